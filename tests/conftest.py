@@ -1,0 +1,23 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: long-running CPU test")
+
+
+@pytest.fixture(scope="session")
+def gpu_lib():
+    """The loaded HIP library; tests marked gpu fail loudly when it cannot be loaded."""
+    from paper_1807_05117_amd import binding
+    lib = binding.load()
+    if not binding.device_available():
+        pytest.fail("no HIP device visible to the library")
+    return lib
