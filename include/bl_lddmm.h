@@ -1,0 +1,220 @@
+/*
+ * bl_lddmm.h -- C interface of the MI355X (gfx950) library for band-limited PDE-constrained
+ * LDDMM on the state equation, optimised by Gauss-Newton-Krylov.
+ *
+ * Paper: M. Hernandez, "Newton-Krylov optimization in PDE-constrained diffeomorphic
+ * registration parameterized in the space of band-limited vector fields" (arXiv:1807.05117).
+ *
+ * Problem statement (Section 3.2, equation BLEnergy and the constraints after it): given a
+ * source image I0 and a target image I1 on a periodic grid, find band-limited velocity
+ * coefficients v~ minimising
+ *     E(v~) = 1/2 <L~ v~, v~>_l2 + sigma^-2 || m(1) - I1 ||^2,
+ *     d_t m + grad m . iota(v~) = 0,  m(0) = I0,
+ * with L = (Id - alpha Lap)^s (Section 2.1) applied diagonally in Fourier.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  Grid      n[0] x n[1] (x n[2]) voxels, x fastest: voxel (x, y, z) is element
+ *            x + n[0] * (y + n[1] * z).  Isotropic voxels of size 1/N_ref with
+ *            N_ref = max_j n[j]; the domain is periodic.  For dim == 2, n[2] and k[2] are
+ *            ignored (treated as 1).
+ *  Images    float32, one value per voxel, prod(n) values.
+ *  Band      float32 complex interleaved (re, im), layout [c][kz][ky][kx], c = 0..dim-1 the
+ *            velocity component along x, y (, z); index j on an axis of size K stands for
+ *            the integer frequency j - K/2, so a band vector holds dim * prod(k) complex
+ *            values (2 * dim * prod(k) floats).  The function it represents is
+ *                v_c(x_i) = Re sum_k v~_c(k) exp(2 pi i sum_j k_j i_j / n_j).
+ *            Inputs are projected onto the admissible set before use: Hermitian
+ *            symmetrisation (v~(k) + conj v~(-k)) / 2 and zero on the unpaired planes
+ *            k_j = -K_j/2.  Outputs are always admissible.
+ *  Inner     <a, b>_l2 = Re sum conj(a) b over the full band; image norms use the unit
+ *  products  volume average (1/prod(n)) sum_i.
+ *  Time      nt uniform semi-Lagrangian steps of length 1/nt; stationary v~.
+ *  Pointers  by default host memory: calls copy inputs to the GPU, compute, copy results
+ *            back and return when done.  With BL_DEVICE_PTRS in problem->flags every image
+ *            and band pointer is device memory of the current HIP device, and work is
+ *            ordered on problem->stream (a hipStream_t, NULL = the null stream).  Scalar
+ *            outputs (energy, stats) are always host memory; calls that produce them wait
+ *            for the stream.  The library keeps no caller pointer after a call returns.
+ *  Errors    every call returns BL_OK (0) or a negative code; bl_lddmm_last_error() gives a
+ *            message for the calling thread.  Arguments are validated on the host before
+ *            any device work.  No C++ exception crosses this interface.
+ *  Results   are deterministic: identical inputs give bitwise identical outputs (fixed
+ *            reduction orders, no atomics in value paths).
+ */
+#ifndef BL_LDDMM_H
+#define BL_LDDMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define BL_OK             0
+#define BL_E_INVALID     -1   /* bad dim, n, k, nt, alpha, s, sigma, opts or NULL pointer     */
+#define BL_E_UNSUPPORTED -2   /* gamma != 0 (incompressible variant) or unknown precision     */
+#define BL_E_NOMEM       -3   /* the working set does not fit in free device memory         */
+#define BL_E_DEVICE      -4   /* a HIP runtime error                                          */
+#define BL_E_NONFINITE   -5   /* NaN/Inf in an input, in E, in the gradient or in H v         */
+
+/* precision forms */
+#define BL_FP32   0   /* FP32 transforms and transports, FP64 reductions                     */
+#define BL_MIXED  1   /* band<->grid contractions on BF16 MFMA with split hi/lo operands and
+                         FP32 accumulation; FP32 transports; FP64 reductions                  */
+
+/* flags */
+#define BL_DEVICE_PTRS 1
+
+/* registration status */
+#define BL_CONVERGED 0
+#define BL_MAXITER   1
+#define BL_STALLED   2
+
+typedef struct {
+  int32_t dim;        /* 2 or 3                                                            */
+  int32_t n[3];       /* grid size per axis (x, y, z), 4 <= n[j] <= 2048                    */
+  int32_t k[3];       /* band size per axis, even, 2 <= k[j] <= n[j]                        */
+  int32_t nt;         /* time steps, 1 <= nt <= 256                                         */
+  double  alpha;      /* L = (Id - alpha Lap)^s: alpha >= 0                                 */
+  int32_t s;          /*                          0 <= s <= 8                               */
+  double  sigma;      /* data weight 1/sigma^2, sigma > 0                                   */
+  int32_t gamma;      /* incompressibility switch of Section 2.2; only 0 is supported      */
+  int32_t precision;  /* BL_FP32 or BL_MIXED                                                */
+  int32_t flags;      /* BL_DEVICE_PTRS or 0                                                */
+  void*   stream;     /* hipStream_t used with BL_DEVICE_PTRS (NULL: null stream)           */
+} bl_problem;
+
+typedef struct {
+  int32_t max_gn;       /* Gauss-Newton iterations, 0 <= max_gn <= BL_MAX_GN (default 10)  */
+  int32_t max_pcg;      /* PCG steps per iteration, >= 1 (default 10)                       */
+  double  gtol;         /* stop when |g|_inf / |g_0|_inf < gtol (default 1e-3)              */
+  double  c1;           /* Armijo constant (default 1e-4)                                   */
+  int32_t max_halvings; /* step halvings in the line search, >= 0 (default 10)              */
+} bl_solver_opts;
+
+#define BL_MAX_GN 64
+
+typedef struct {
+  int32_t status;        /* BL_CONVERGED, BL_MAXITER or BL_STALLED                          */
+  int32_t gn_iters;      /* accepted Gauss-Newton iterations                                */
+  int32_t hessvecs;      /* Hessian-vector products evaluated                               */
+  int32_t gradients;     /* gradients evaluated                                             */
+  int32_t evaluations;   /* energy evaluations (initial + line-search trials)               */
+  int32_t pcg_total;     /* PCG steps over all iterations                                   */
+  double  E[BL_MAX_GN + 1];         /* energy after each accepted iteration (E[0]: start)   */
+  double  mse_rel[BL_MAX_GN + 1];   /* 100 |m(1) - I1|^2 / |I0 - I1|^2 (percent)            */
+  double  ginf_rel[BL_MAX_GN + 1];  /* |g|_inf / |g_0|_inf                                  */
+  int32_t pcg_iters[BL_MAX_GN];     /* PCG steps of each iteration                          */
+  int32_t ls_trials[BL_MAX_GN];     /* line-search trials of each iteration                 */
+  double  eps[BL_MAX_GN];           /* accepted step length (0 when stalled)                */
+  double  seconds;                  /* wall time of the call                                */
+} bl_stats;
+
+typedef struct bl_ctx bl_ctx;
+
+/* Default solver options (10 GN iterations, 10 PCG steps, gtol 1e-3, c1 1e-4, 10 halvings). */
+void bl_lddmm_default_opts(bl_solver_opts* opts);
+
+/*
+ * Gradient of E at v~ (Section 3.2, gradient of the band-limited state-equation method):
+ *     g~ = L^ (.) v~ + pi( int_0^1 lambda grad m dt ),
+ * with lambda the adjoint of Section 2.2 (equation FirstOrder2, final condition
+ * lambda(1) = -(2/sigma^2)(m(1) - I1)), transported backward by semi-Lagrangian steps.
+ *   I0, I1   images (prod(n) floats)          v_hat  band vector (input)
+ *   g_hat    band vector (output)             energy E(v~) (host, may be NULL)
+ */
+int bl_lddmm_gradient(const bl_problem* prob, const float* I0, const float* I1,
+                      const float* v_hat, float* g_hat, double* energy);
+
+/*
+ * Gauss-Newton Hessian-vector product at v~ applied to dv~ (Section 3.2 equation
+ * BLHessianStateEquation with the Gauss-Newton rule of Section 3.4): the incremental state
+ * is transported forward from dm(0) = 0, the incremental adjoint backward from
+ * dlambda(1) = -(2/sigma^2) dm(1), and
+ *     H dv~ = L^ (.) dv~ + pi( int_0^1 dlambda grad m dt ).
+ * The operator is symmetric positive definite up to discretisation error.
+ *   v_hat    point of linearisation        dv_hat  direction        hv_hat  result
+ */
+int bl_lddmm_hessvec(const bl_problem* prob, const float* I0, const float* I1,
+                     const float* v_hat, const float* dv_hat, float* hv_hat);
+
+/*
+ * Registration by reduced-space Gauss-Newton-Krylov in the band (Section 3.4, equations
+ * BLNewton and BLKKT): PCG on H dv~ = -g~ preconditioned by K~ = L~^-1, then
+ * v~ <- v~ + eps dv~ with Armijo backtracking (eps = 1, 1/2, ...).
+ *   opts     solver options (NULL: defaults)
+ *   v_hat    in: initial guess (may be zero); out: result
+ *   warped   out: m(1) = I0 transported by the result (prod(n) floats, may be NULL)
+ *   stats    out: per-iteration statistics (host, may be NULL)
+ */
+int bl_lddmm_register(const bl_problem* prob, const bl_solver_opts* opts, const float* I0,
+                      const float* I1, float* v_hat, float* warped, bl_stats* stats);
+
+/*
+ * Forward state only: warped = m(1), the source transported by the stationary velocity
+ * iota(v~) (Section 2.2 equation StateEquation).  I1 is not needed.
+ */
+int bl_lddmm_warp(const bl_problem* prob, const float* I0, const float* v_hat, float* warped);
+
+/*
+ * Band -> grid (Section 3.1, the inclusion iota) of `ncomp` band components (each prod(k)
+ * complex, projected first) into `ncomp` grid fields (each prod(n) floats).
+ */
+int bl_band_to_grid(const bl_problem* prob, int32_t ncomp, const float* band, float* grid);
+
+/*
+ * Grid -> band (Section 3.1, the projection pi): band = (1/M) sum_i f_i exp(-2 pi i k.i/n),
+ * zero on the unpaired planes, for `ncomp` fields.
+ */
+int bl_grid_to_band(const bl_problem* prob, int32_t ncomp, const float* grid, float* band);
+
+/*
+ * Contexts keep the images and the state of one velocity resident on the device, so that
+ * many Hessian-vector products (as inside PCG) reuse the transported state.
+ *   ctx_create       copies I0, I1 (host or device per prob->flags); owns device memory
+ *                    until ctx_destroy.  *ctx is NULL on error.
+ *   ctx_set_velocity setup + forward state + energy at v~ (energy may be NULL); if g_hat is
+ *                    not NULL also the gradient.
+ *   ctx_hessvec      H dv~ at the velocity last set.  With BL_DEVICE_PTRS it is only
+ *                    enqueued on the stream (no wait).
+ *   ctx_get_field    copy an internal grid field into out (host or device per flags):
+ *                    which = BL_FIELD_* below, index = component or time step.
+ * A context is not thread safe; distinct contexts may be used from distinct threads.
+ */
+int bl_lddmm_ctx_create(const bl_problem* prob, const float* I0, const float* I1, bl_ctx** ctx);
+int bl_lddmm_ctx_set_velocity(bl_ctx* ctx, const float* v_hat, double* energy, float* g_hat);
+int bl_lddmm_ctx_hessvec(bl_ctx* ctx, const float* dv_hat, float* hv_hat);
+int bl_lddmm_ctx_get_field(bl_ctx* ctx, int32_t which, int32_t index, float* out);
+void bl_lddmm_ctx_destroy(bl_ctx* ctx);
+
+#define BL_FIELD_VELOCITY 0   /* iota(v~)_c, index = component                               */
+#define BL_FIELD_DIV      1   /* iota(div~ v~)                                               */
+#define BL_FIELD_X        2   /* forward departure offset (voxels), index = component        */
+#define BL_FIELD_Y        3   /* backward departure offset (voxels), index = component       */
+#define BL_FIELD_A        4   /* adjoint reaction factor                                     */
+#define BL_FIELD_STATE    5   /* m^n, index = time step n in 0..nt                           */
+
+/* Bytes of device memory a context for this problem needs (0 if prob is invalid). */
+uint64_t bl_lddmm_footprint(const bl_problem* prob);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* bl_lddmm_last_error(void);
+
+/* 1 if a HIP device is visible, else 0 (never fails). */
+int bl_lddmm_device_count(void);
+
+/*
+ * Per-kernel timing with HIP events on the library's stream, for benchmarks: while enabled,
+ * every launch of a transport step kernel is bracketed by events; bl_kernel_timing_read
+ * returns the number of launches and the summed milliseconds per kernel class
+ * (0 = forward state step, 1 = incremental forward step, 2 = adjoint step) and resets.
+ */
+int bl_kernel_timing_enable(bl_ctx* ctx, int32_t on);
+int bl_kernel_timing_read(bl_ctx* ctx, int32_t kclass, int64_t* launches, double* ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BL_LDDMM_H */

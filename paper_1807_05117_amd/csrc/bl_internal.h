@@ -1,0 +1,92 @@
+// Internal declarations shared by the HIP translation units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace bl {
+
+// Geometry and weights of one problem, passed by value to every kernel.
+struct Geo {
+  int dim;            // 2 or 3
+  int nx, ny, nz;     // grid (nz == 1 in 2D)
+  int kx, ky, kz;     // band (kz == 1 in 2D)
+  int kzh;            // stored non-negative kz planes: 1 in 2D, kz/2 in 3D
+  int kz0;            // band index of kz = 0: 0 in 2D, kz/2 in 3D
+  int nt;             // time steps
+  int nref;           // max grid size (voxel size 1/nref)
+  int64_t M;          // voxels
+  int64_t B;          // band entries per component (kx*ky*kz)
+  float dt;           // 1/nt
+  float half_nref;    // nref/2 (central difference scale)
+  float lam_scale;    // -2/sigma^2
+};
+
+// Work buffers and twiddle tables of the band<->grid transforms.
+struct DftPlan {
+  float2* tw_x = nullptr;   // [kx][nx]  exp(+2 pi i kx x / nx), kx = j - Kx/2
+  float2* tw_y = nullptr;   // [ky][ny]
+  float2* tw_z = nullptr;   // [kzh][nz] exp(+2 pi i h z / nz), h = 0..kzh-1
+  float2* bufA = nullptr;   // stage buffers, each 4 * kzh * max(ky*nx, ny*nx) complex
+  float2* bufB = nullptr;
+  // split hi/lo bf16 twiddle operands of the mixed-precision path (nullptr in FP32 mode)
+  uint16_t* tz_bf16 = nullptr;
+  int mixed = 0;
+};
+
+constexpr int kMaxKzh = 64;       // register arrays of the z stages: kz <= 128
+constexpr int kRedBlocks = 512;   // partial sums per deterministic FP64 reduction
+
+// ---- transforms (bl_dft.hip)
+void iota(const Geo& g, const DftPlan& p, const float2* band, int C, float* out, hipStream_t s);
+// pi without the 1/M scale: P[c][h][ky][kx] for h = 0..kzh-1 (half spectrum)
+void pi_half(const Geo& g, const DftPlan& p, const float* grid, int C, float2* P, hipStream_t s);
+
+// ---- band kernels (bl_dft.hip)
+// out[c] = projection of raw[c] (c < dim); with_div: out[dim] = spectral divergence.
+// reg_partial (may be null): kRedBlocks partial sums of sum_c Lhat |out_c|^2.
+void band_prep(const Geo& g, const float2* raw, float2* out, int with_div, const double* Lhat64,
+               double* reg_partial, hipStream_t s);
+// out[c][k] = Lhat(k) vproj[c][k] + scale * P (Hermitian-completed), zero on unpaired planes.
+void band_finalize(const Geo& g, int C, const float2* vproj, const float* Lhat,
+                   const float2* P, float scale, float2* out, int* nonfinite, hipStream_t s);
+
+// ---- transports (bl_transport.hip)
+void setup(const Geo& g, const float* v, float* X, float* Y, float* a, hipStream_t s);
+void state_step(const Geo& g, const float* m_in, const float* X, float* m_out, hipStream_t s);
+void energy_partial(const Geo& g, const float* mT, const float* I1, double* partial,
+                    hipStream_t s);
+void terminal(const Geo& g, const float* mT, const float* I1, float* lam, float* b, float w,
+              hipStream_t s);
+void adj_step(const Geo& g, const float* lam_in, const float* Y, const float* a,
+              const float* m_n, float* lam_out, float* b, float w, hipStream_t s);
+void inc_init(const Geo& g, const float* m0, const float* dv, float* t0, hipStream_t s);
+void inc_step(const Geo& g, const float* t_in, const float* X, const float* m_next,
+              const float* dv, float* t_out, hipStream_t s);
+void inc_last(const Geo& g, const float* t_in, const float* X, const float* mT,
+              const float* dv, float* dlam, float* Hb, float w, hipStream_t s);
+
+// ---- reductions and band vector algebra (bl_reduce.hip)
+// out[0] = sum of n partials in a fixed order (one block)
+void reduce_final(const double* partial, int n, double* out, hipStream_t s);
+// kRedBlocks partials of Re sum conj(a) b over n complex entries
+void dot_partial(const float2* a, const float2* b, int64_t n, double* partial, hipStream_t s);
+// kRedBlocks partials of max |a|
+void maxabs_partial(const float2* a, int64_t n, double* partial, hipStream_t s);
+void reduce_max_final(const double* partial, int n, double* out, hipStream_t s);
+// y = alpha x + y
+void axpy(float2* y, const float2* x, double alpha, int64_t n, hipStream_t s);
+// y = x + beta y
+void xpby(float2* y, const float2* x, double beta, int64_t n, hipStream_t s);
+// z = r / Lhat (per component); also kRedBlocks partials of <r, r> (p0) and <r, z> (p1)
+void precond_dots(const Geo& g, const float2* r, const float* Lhat, float2* z, double* p0,
+                  double* p1, hipStream_t s);
+// y = x + eps d
+void add_scaled(float2* y, const float2* x, const float2* d, double eps, int64_t n,
+                hipStream_t s);
+// partials of sum (a - b)^2 over n reals
+void sqdiff_partial(const float* a, const float* b, int64_t n, double* partial, hipStream_t s);
+
+}  // namespace bl

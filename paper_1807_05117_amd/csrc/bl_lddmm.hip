@@ -1,0 +1,915 @@
+// C interface, device contexts and the Gauss-Newton-Krylov driver of the library.
+//
+// Host side of the hot path: argument validation (before any device call), the device
+// arena of one registration problem, the operator sequences of the gradient (paper
+// Section 3.2) and of the Gauss-Newton Hessian-vector product (Section 3.2 equation
+// BLHessianStateEquation with the Gauss-Newton rule of Section 3.4), and the reduced-space
+// solver (Section 3.4 equations BLNewton and BLKKT) with PCG preconditioned by K~ = L~^-1
+// and Armijo backtracking.  All arithmetic runs in the kernels of the other translation
+// units; this file only sequences launches, copies and scalar read-backs.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "bl_internal.h"
+#include "bl_lddmm.h"
+
+namespace {
+
+thread_local std::string t_err;
+
+int fail(int code, const std::string& msg) {
+  t_err = msg;
+  return code;
+}
+
+struct DeviceError {
+  hipError_t e;
+  const char* where;
+};
+
+#define HIP_TRY(expr)                                 \
+  do {                                                \
+    hipError_t e_ = (expr);                           \
+    if (e_ != hipSuccess) throw DeviceError{e_, #expr}; \
+  } while (0)
+
+inline void check_launch(const char* where) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw DeviceError{e, where};
+}
+
+struct NonFinite {
+  const char* what;
+};
+
+// ------------------------------------------------------------------------------ validation
+int validate(const bl_problem* p, bl::Geo* g) {
+  if (!p) return fail(BL_E_INVALID, "problem is NULL");
+  if (p->dim != 2 && p->dim != 3) return fail(BL_E_INVALID, "dim must be 2 or 3");
+  int n[3] = {1, 1, 1}, k[3] = {1, 1, 1};
+  for (int j = 0; j < p->dim; ++j) {
+    n[j] = p->n[j];
+    k[j] = p->k[j];
+    if (n[j] < 4 || n[j] > 2048) return fail(BL_E_INVALID, "grid size n[j] must be in [4, 2048]");
+    if (k[j] < 2 || (k[j] & 1) || k[j] > n[j])
+      return fail(BL_E_INVALID, "band size k[j] must be even, >= 2 and <= n[j]");
+  }
+  if (p->dim == 3 && k[2] > 2 * bl::kMaxKzh)
+    return fail(BL_E_INVALID, "band size k[2] must be <= 128");
+  if (p->nt < 1 || p->nt > 256) return fail(BL_E_INVALID, "nt must be in [1, 256]");
+  if (!std::isfinite(p->alpha) || p->alpha < 0) return fail(BL_E_INVALID, "alpha must be finite and >= 0");
+  if (p->s < 0 || p->s > 8) return fail(BL_E_INVALID, "s must be in [0, 8]");
+  if (!std::isfinite(p->sigma) || !(p->sigma > 0)) return fail(BL_E_INVALID, "sigma must be finite and > 0");
+  if (p->gamma != 0) return fail(BL_E_UNSUPPORTED, "gamma != 0 (incompressible flow) is not supported");
+  if (p->precision != BL_FP32 && p->precision != BL_MIXED)
+    return fail(BL_E_UNSUPPORTED, "precision must be BL_FP32 or BL_MIXED");
+  if (p->flags & ~BL_DEVICE_PTRS) return fail(BL_E_INVALID, "unknown flag bits");
+  if (g) {
+    g->dim = p->dim;
+    g->nx = n[0]; g->ny = n[1]; g->nz = n[2];
+    g->kx = k[0]; g->ky = k[1]; g->kz = k[2];
+    g->kzh = p->dim == 3 ? k[2] / 2 : 1;
+    g->kz0 = p->dim == 3 ? k[2] / 2 : 0;
+    g->nt = p->nt;
+    g->nref = std::max(n[0], std::max(n[1], n[2]));
+    g->M = (int64_t)n[0] * n[1] * n[2];
+    g->B = (int64_t)k[0] * k[1] * k[2];
+    g->dt = (float)(1.0 / p->nt);
+    g->half_nref = 0.5f * (float)g->nref;
+    g->lam_scale = (float)(-2.0 / (p->sigma * p->sigma));
+  }
+  return BL_OK;
+}
+
+int validate_opts(const bl_solver_opts* o) {
+  if (!o) return BL_OK;
+  if (o->max_gn < 0 || o->max_gn > BL_MAX_GN) return fail(BL_E_INVALID, "max_gn must be in [0, 64]");
+  if (o->max_pcg < 1 || o->max_pcg > 1000) return fail(BL_E_INVALID, "max_pcg must be in [1, 1000]");
+  if (!std::isfinite(o->gtol) || o->gtol < 0) return fail(BL_E_INVALID, "gtol must be finite and >= 0");
+  if (!std::isfinite(o->c1) || o->c1 < 0 || o->c1 >= 1) return fail(BL_E_INVALID, "c1 must be in [0, 1)");
+  if (o->max_halvings < 0 || o->max_halvings > 60) return fail(BL_E_INVALID, "max_halvings must be in [0, 60]");
+  return BL_OK;
+}
+
+// ------------------------------------------------------------------------------ arena
+struct Layout {
+  size_t total = 0;
+  size_t take(size_t bytes) {
+    const size_t off = total;
+    total += (bytes + 255) & ~size_t(255);
+    return off;
+  }
+};
+
+enum { RED_REG = 0, RED_DATA, RED_A, RED_B, RED_SLOTS };
+
+}  // namespace
+
+struct bl_ctx {
+  bl::Geo g{};
+  bl_problem prob{};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  bool devptr = false;
+  bool transport = true;
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  // grid fields
+  float* I1 = nullptr;
+  float* m = nullptr;      // (nt + 1) planes, m[0] = I0
+  float* X = nullptr;      // dim planes
+  float* Y = nullptr;      // dim planes
+  float* A = nullptr;
+  float* V = nullptr;      // dim + 1 planes: v, r
+  float* DV = nullptr;     // dim planes
+  float* T0 = nullptr;
+  float* T1 = nullptr;
+  float* Bf = nullptr;     // dim planes: body force
+  // band vectors (complex)
+  float2* braw = nullptr;  // up to 4 components of staging
+  float2* bv = nullptr;    // dim + 1: projected v, divergence
+  float2* bd = nullptr;    // dim: projected dv
+  float2* bout = nullptr;  // dim
+  float2* P = nullptr;     // up to 4 * kzh * ky * kx
+  float* Lhat = nullptr;
+  double* Lhat64 = nullptr;
+  bl::DftPlan plan;
+  double* red = nullptr;   // RED_SLOTS * kRedBlocks partials
+  double* scal = nullptr;  // device scalars
+  double* hscal = nullptr; // pinned host scalars
+  int* flag = nullptr;
+  double* hflag_dummy = nullptr;
+  // state of the last velocity
+  bool have_v = false;
+  double E = 0, reg = 0, data_sum = 0;
+  // solver vectors (dim * B complex each)
+  float2 *sv = nullptr, *sg = nullptr, *sdelta = nullptr, *sr = nullptr, *sz = nullptr,
+         *sp = nullptr, *sHp = nullptr, *stry = nullptr;
+  // kernel timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, int>> ev_used;  // (class, pool index of the start event)
+  size_t ev_next = 0;
+  int64_t t_launch[3] = {0, 0, 0};
+  double t_ms[3] = {0, 0, 0};
+};
+
+namespace {
+
+size_t plane_bytes(const bl::Geo& g) { return (size_t)g.M * sizeof(float); }
+size_t band_bytes(const bl::Geo& g) { return (size_t)g.B * sizeof(float2); }
+size_t stage_elems(const bl::Geo& g) {
+  return (size_t)4 * g.kzh * (size_t)std::max<int64_t>((int64_t)g.ky * g.nx, (int64_t)g.ny * g.nx);
+}
+
+struct Offsets {
+  size_t I1, m, X, Y, A, V, DV, T0, T1, Bf, braw, bv, bd, bout, P, Lhat, Lhat64, tw_x, tw_y,
+      tw_z, bufA, bufB, red, scal, flag, solver;
+  size_t total;
+};
+
+Offsets plan_layout(const bl::Geo& g, bool transport, bool solver) {
+  Layout L;
+  Offsets o{};
+  const size_t pb = plane_bytes(g), bb = band_bytes(g);
+  const int d = g.dim;
+  if (transport) {
+    o.I1 = L.take(pb);
+    o.m = L.take(pb * (g.nt + 1));
+    o.X = L.take(pb * d);
+    o.Y = L.take(pb * d);
+    o.A = L.take(pb);
+    o.V = L.take(pb * (d + 1));
+    o.DV = L.take(pb * d);
+    o.T0 = L.take(pb);
+    o.T1 = L.take(pb);
+    o.Bf = L.take(pb * d);
+  } else {
+    o.V = L.take(pb * 4);
+  }
+  o.braw = L.take(bb * 4);
+  o.bv = L.take(bb * 4);
+  o.bd = L.take(bb * 4);
+  o.bout = L.take(bb * 4);
+  o.P = L.take((size_t)4 * g.kzh * g.ky * g.kx * sizeof(float2));
+  o.Lhat = L.take((size_t)g.B * sizeof(float));
+  o.Lhat64 = L.take((size_t)g.B * sizeof(double));
+  o.tw_x = L.take((size_t)g.kx * g.nx * sizeof(float2));
+  o.tw_y = L.take((size_t)g.ky * g.ny * sizeof(float2));
+  o.tw_z = L.take((size_t)bl::kMaxKzh * g.nz * sizeof(float2));
+  o.bufA = L.take(stage_elems(g) * sizeof(float2));
+  o.bufB = L.take(stage_elems(g) * sizeof(float2));
+  o.red = L.take((size_t)RED_SLOTS * bl::kRedBlocks * sizeof(double));
+  o.scal = L.take(64 * sizeof(double));
+  o.flag = L.take(256);
+  o.solver = solver ? L.take(bb * d * 8) : 0;
+  o.total = L.total;
+  return o;
+}
+
+void twiddles(std::vector<float2>& t, int rows, int K, int N, bool centred) {
+  t.assign((size_t)rows * N, make_float2(0.f, 0.f));
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int j = 0; j < K; ++j) {
+    const long long k = centred ? (long long)j - K / 2 : j;
+    for (int x = 0; x < N; ++x) {
+      long long r = (k * x) % N;
+      if (r < 0) r += N;
+      const double ang = two_pi * (double)r / (double)N;
+      t[(size_t)j * N + x] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
+  }
+}
+
+void destroy_ctx(bl_ctx* c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  if (c->stream) hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
+  if (c->arena) hipFree(c->arena);
+  if (c->hscal) hipHostFree(c->hscal);
+  if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+  delete c;
+}
+
+bl_ctx* create_ctx(const bl_problem* prob, const bl::Geo& g, bool transport, bool solver) {
+  bl_ctx* c = new bl_ctx();
+  try {
+    c->g = g;
+    c->prob = *prob;
+    c->devptr = (prob->flags & BL_DEVICE_PTRS) != 0;
+    c->transport = transport;
+    HIP_TRY(hipGetDevice(&c->device));
+    if (c->devptr) {
+      c->stream = (hipStream_t)prob->stream;
+      c->own_stream = false;
+    } else {
+      HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+      c->own_stream = true;
+    }
+    const Offsets o = plan_layout(g, transport, solver);
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    if (o.total + (64u << 20) > free_b) throw std::bad_alloc();
+    HIP_TRY(hipMalloc(&c->arena, o.total));
+    c->arena_bytes = o.total;
+    char* a = c->arena;
+    auto F = [&](size_t off) { return reinterpret_cast<float*>(a + off); };
+    auto C2 = [&](size_t off) { return reinterpret_cast<float2*>(a + off); };
+    if (transport) {
+      c->I1 = F(o.I1); c->m = F(o.m); c->X = F(o.X); c->Y = F(o.Y); c->A = F(o.A);
+      c->DV = F(o.DV); c->T0 = F(o.T0); c->T1 = F(o.T1); c->Bf = F(o.Bf);
+    }
+    c->V = F(o.V);
+    c->braw = C2(o.braw); c->bv = C2(o.bv); c->bd = C2(o.bd); c->bout = C2(o.bout); c->P = C2(o.P);
+    c->Lhat = F(o.Lhat);
+    c->Lhat64 = reinterpret_cast<double*>(a + o.Lhat64);
+    c->plan.tw_x = C2(o.tw_x); c->plan.tw_y = C2(o.tw_y); c->plan.tw_z = C2(o.tw_z);
+    c->plan.bufA = C2(o.bufA); c->plan.bufB = C2(o.bufB);
+    c->plan.mixed = prob->precision == BL_MIXED;
+    c->red = reinterpret_cast<double*>(a + o.red);
+    c->scal = reinterpret_cast<double*>(a + o.scal);
+    c->flag = reinterpret_cast<int*>(a + o.flag);
+    if (solver) {
+      float2* s = C2(o.solver);
+      const size_t nb = (size_t)g.dim * g.B;
+      c->sv = s; c->sg = s + nb; c->sdelta = s + 2 * nb; c->sr = s + 3 * nb; c->sz = s + 4 * nb;
+      c->sp = s + 5 * nb; c->sHp = s + 6 * nb; c->stry = s + 7 * nb;
+    }
+    HIP_TRY(hipHostMalloc((void**)&c->hscal, 64 * sizeof(double), hipHostMallocDefault));
+    // host tables: twiddles of exactly reduced angles, the symbol of L
+    std::vector<float2> tw;
+    twiddles(tw, g.kx, g.kx, g.nx, true);
+    HIP_TRY(hipMemcpyAsync(c->plan.tw_x, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    twiddles(tw, g.ky, g.ky, g.ny, true);
+    HIP_TRY(hipMemcpyAsync(c->plan.tw_y, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    twiddles(tw, bl::kMaxKzh, g.kzh, g.nz, false);
+    HIP_TRY(hipMemcpyAsync(c->plan.tw_z, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    std::vector<double> L64((size_t)g.B);
+    std::vector<float> L32((size_t)g.B);
+    const double four_pi2 = 39.478417604357434;
+    const int nn[3] = {g.nx, g.ny, g.nz};
+    for (int64_t b = 0; b < g.B; ++b) {
+      const int jx = (int)(b % g.kx), jy = (int)((b / g.kx) % g.ky), jz = (int)(b / ((int64_t)g.kx * g.ky));
+      const int kv[3] = {jx - g.kx / 2, jy - g.ky / 2, jz - g.kz0};
+      double q2 = 0;
+      for (int j = 0; j < g.dim; ++j) {
+        const double q = (double)kv[j] * (double)g.nref / (double)nn[j];
+        q2 += q * q;
+      }
+      const double base = 1.0 + four_pi2 * prob->alpha * q2;
+      double L = 1.0;
+      for (int i = 0; i < prob->s; ++i) L *= base;
+      L64[b] = L;
+      L32[b] = (float)L;
+    }
+    HIP_TRY(hipMemcpyAsync(c->Lhat64, L64.data(), L64.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->Lhat, L32.data(), L32.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemsetAsync(c->flag, 0, 256, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  } catch (...) {
+    destroy_ctx(c);
+    throw;
+  }
+  return c;
+}
+
+inline hipMemcpyKind in_kind(const bl_ctx* c) {
+  return c->devptr ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+}
+void sync(bl_ctx* c) { HIP_TRY(hipStreamSynchronize(c->stream)); }
+
+// -------------------------------------------------------------------------------- timing
+void t_begin(bl_ctx* c, int cls) {
+  if (!c->timing || c->ev_next + 2 > c->ev_pool.size()) return;
+  const int i = (int)c->ev_next;
+  c->ev_next += 2;
+  HIP_TRY(hipEventRecord(c->ev_pool[i], c->stream));
+  c->ev_used.push_back({cls, i});
+}
+void t_end(bl_ctx* c, int cls) {
+  if (!c->timing || c->ev_used.empty()) return;
+  const auto& u = c->ev_used.back();
+  if (u.first != cls) return;
+  HIP_TRY(hipEventRecord(c->ev_pool[u.second + 1], c->stream));
+}
+void t_collect(bl_ctx* c) {
+  if (c->ev_used.empty()) return;
+  sync(c);
+  for (const auto& u : c->ev_used) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, c->ev_pool[u.second], c->ev_pool[u.second + 1]));
+    c->t_launch[u.first] += 1;
+    c->t_ms[u.first] += ms;
+  }
+  c->ev_used.clear();
+  c->ev_next = 0;
+}
+
+// ------------------------------------------------------------------------------ operators
+float trap_w(const bl::Geo& g, int n) { return (n == 0 || n == g.nt) ? 0.5f * g.dt : g.dt; }
+
+double read_scalars(bl_ctx* c, int n) {
+  HIP_TRY(hipMemcpyAsync(c->hscal, c->scal, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  return c->hscal[0];
+}
+
+// setup + forward state + energy at the raw band vector `vraw` (device, dim components)
+void op_set_velocity(bl_ctx* c, const float2* vraw) {
+  const bl::Geo& g = c->g;
+  hipStream_t s = c->stream;
+  double* red_reg = c->red + RED_REG * bl::kRedBlocks;
+  double* red_data = c->red + RED_DATA * bl::kRedBlocks;
+  bl::band_prep(g, vraw, c->bv, 1, c->Lhat64, red_reg, s);
+  bl::iota(g, c->plan, c->bv, g.dim + 1, c->V, s);
+  bl::setup(g, c->V, c->X, c->Y, c->A, s);
+  const size_t M = (size_t)g.M;
+  for (int n = 0; n < g.nt; ++n) {
+    if (c->timing) t_begin(c, 0);
+    bl::state_step(g, c->m + n * M, c->X, c->m + (n + 1) * M, s);
+    if (c->timing) t_end(c, 0);
+  }
+  bl::energy_partial(g, c->m + g.nt * M, c->I1, red_data, s);
+  bl::reduce_final(red_reg, bl::kRedBlocks, c->scal + 0, s);
+  bl::reduce_final(red_data, bl::kRedBlocks, c->scal + 1, s);
+  check_launch("set_velocity");
+  HIP_TRY(hipMemcpyAsync(c->hscal, c->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  sync(c);
+  c->reg = c->hscal[0];
+  c->data_sum = c->hscal[1];
+  const double sig = c->prob.sigma;
+  c->E = 0.5 * c->reg + c->data_sum / (sig * sig * (double)g.M);
+  c->have_v = true;
+  if (!std::isfinite(c->E)) throw NonFinite{"energy"};
+}
+
+// gradient at the current velocity into gout (device, dim components)
+void op_gradient(bl_ctx* c, float2* gout) {
+  const bl::Geo& g = c->g;
+  hipStream_t s = c->stream;
+  const size_t M = (size_t)g.M;
+  bl::terminal(g, c->m + g.nt * M, c->I1, c->T0, c->Bf, trap_w(g, g.nt), s);
+  float* lin = c->T0;
+  float* lout = c->T1;
+  for (int n = g.nt - 1; n >= 0; --n) {
+    if (c->timing) t_begin(c, 2);
+    bl::adj_step(g, lin, c->Y, c->A, c->m + n * M, lout, c->Bf, trap_w(g, n), s);
+    if (c->timing) t_end(c, 2);
+    std::swap(lin, lout);
+  }
+  bl::pi_half(g, c->plan, c->Bf, g.dim, c->P, s);
+  bl::band_finalize(g, g.dim, c->bv, c->Lhat, c->P, (float)(1.0 / (double)g.M), gout, c->flag, s);
+  check_launch("gradient");
+}
+
+// Gauss-Newton Hessian-vector product of the raw direction draw into hout
+void op_hessvec(bl_ctx* c, const float2* draw, float2* hout) {
+  const bl::Geo& g = c->g;
+  hipStream_t s = c->stream;
+  const size_t M = (size_t)g.M;
+  bl::band_prep(g, draw, c->bd, 0, nullptr, nullptr, s);
+  bl::iota(g, c->plan, c->bd, g.dim, c->DV, s);
+  bl::inc_init(g, c->m, c->DV, c->T0, s);
+  float* tin = c->T0;
+  float* tout = c->T1;
+  for (int n = 0; n + 1 < g.nt; ++n) {
+    if (c->timing) t_begin(c, 1);
+    bl::inc_step(g, tin, c->X, c->m + (n + 1) * M, c->DV, tout, s);
+    if (c->timing) t_end(c, 1);
+    std::swap(tin, tout);
+  }
+  bl::inc_last(g, tin, c->X, c->m + g.nt * M, c->DV, tout, c->Bf, trap_w(g, g.nt), s);
+  float* lin = tout;
+  float* lout = tin;
+  for (int n = g.nt - 1; n >= 0; --n) {
+    if (c->timing) t_begin(c, 2);
+    bl::adj_step(g, lin, c->Y, c->A, c->m + n * M, lout, c->Bf, trap_w(g, n), s);
+    if (c->timing) t_end(c, 2);
+    std::swap(lin, lout);
+  }
+  bl::pi_half(g, c->plan, c->Bf, g.dim, c->P, s);
+  bl::band_finalize(g, g.dim, c->bd, c->Lhat, c->P, (float)(1.0 / (double)g.M), hout, c->flag, s);
+  check_launch("hessvec");
+}
+
+void check_flag(bl_ctx* c, const char* what) {
+  int h = 0;
+  HIP_TRY(hipMemcpyAsync(&h, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  if (h) {
+    HIP_TRY(hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
+    sync(c);
+    throw NonFinite{what};
+  }
+}
+
+double dev_dot(bl_ctx* c, const float2* a, const float2* b) {
+  const int64_t n = (int64_t)c->g.dim * c->g.B;
+  double* part = c->red + RED_A * bl::kRedBlocks;
+  bl::dot_partial(a, b, n, part, c->stream);
+  bl::reduce_final(part, bl::kRedBlocks, c->scal + 4, c->stream);
+  HIP_TRY(hipMemcpyAsync(c->hscal + 4, c->scal + 4, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  return c->hscal[4];
+}
+
+double dev_maxabs(bl_ctx* c, const float2* a) {
+  const int64_t n = (int64_t)c->g.dim * c->g.B;
+  double* part = c->red + RED_A * bl::kRedBlocks;
+  bl::maxabs_partial(a, n, part, c->stream);
+  bl::reduce_max_final(part, bl::kRedBlocks, c->scal + 5, c->stream);
+  HIP_TRY(hipMemcpyAsync(c->hscal + 5, c->scal + 5, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  return c->hscal[5];
+}
+
+// z = r / Lhat; returns (<r, r>, <r, z>)
+void dev_precond(bl_ctx* c, const float2* r, float2* z, double* rr, double* rz) {
+  double* p0 = c->red + RED_A * bl::kRedBlocks;
+  double* p1 = c->red + RED_B * bl::kRedBlocks;
+  bl::precond_dots(c->g, r, c->Lhat, z, p0, p1, c->stream);
+  bl::reduce_final(p0, bl::kRedBlocks, c->scal + 6, c->stream);
+  bl::reduce_final(p1, bl::kRedBlocks, c->scal + 7, c->stream);
+  HIP_TRY(hipMemcpyAsync(c->hscal + 6, c->scal + 6, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  *rr = c->hscal[6];
+  *rz = c->hscal[7];
+}
+
+double dev_sqdiff(bl_ctx* c, const float* a, const float* b) {
+  double* part = c->red + RED_A * bl::kRedBlocks;
+  bl::sqdiff_partial(a, b, c->g.M, part, c->stream);
+  bl::reduce_final(part, bl::kRedBlocks, c->scal + 8, c->stream);
+  HIP_TRY(hipMemcpyAsync(c->hscal + 8, c->scal + 8, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  return c->hscal[8];
+}
+
+void load_images(bl_ctx* c, const float* I0, const float* I1) {
+  const size_t pb = plane_bytes(c->g);
+  HIP_TRY(hipMemcpyAsync(c->m, I0, pb, in_kind(c), c->stream));
+  if (I1) HIP_TRY(hipMemcpyAsync(c->I1, I1, pb, in_kind(c), c->stream));
+  else HIP_TRY(hipMemsetAsync(c->I1, 0, pb, c->stream));
+}
+
+void load_band(bl_ctx* c, const float* src, float2* dst, int ncomp) {
+  HIP_TRY(hipMemcpyAsync(dst, src, band_bytes(c->g) * ncomp, in_kind(c), c->stream));
+}
+void store_band(bl_ctx* c, const float2* src, float* dst, int ncomp) {
+  HIP_TRY(hipMemcpyAsync(dst, src, band_bytes(c->g) * ncomp,
+                         c->devptr ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+}
+void store_plane(bl_ctx* c, const float* src, float* dst, size_t nplanes) {
+  HIP_TRY(hipMemcpyAsync(dst, src, plane_bytes(c->g) * nplanes,
+                         c->devptr ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+}
+
+// ------------------------------------------------------------------------------ solver
+void fill_default(bl_solver_opts* o) {
+  o->max_gn = 10;
+  o->max_pcg = 10;
+  o->gtol = 1e-3;
+  o->c1 = 1e-4;
+  o->max_halvings = 10;
+}
+
+// Gauss-Newton-Krylov on the device vectors of the context (reading R-LS / R-PCG):
+// sv holds the initial guess on entry and the result on exit.
+void solve(bl_ctx* c, const bl_solver_opts& o, bl_stats* st) {
+  const bl::Geo& g = c->g;
+  hipStream_t s = c->stream;
+  const int64_t nb = (int64_t)g.dim * g.B;
+  const double den = dev_sqdiff(c, c->m, c->I1);  // |I0 - I1|^2
+  auto mse = [&]() { return den > 0 ? 100.0 * c->data_sum / den : 0.0; };
+
+  op_set_velocity(c, c->sv);
+  HIP_TRY(hipMemcpyAsync(c->sv, c->bv, band_bytes(g) * g.dim, hipMemcpyDeviceToDevice, s));
+  op_gradient(c, c->sg);
+  check_flag(c, "gradient");
+  double E = c->E;
+  const double g0n = std::sqrt(std::max(dev_dot(c, c->sg, c->sg), 0.0));
+  const double ginf0 = dev_maxabs(c, c->sg);
+  st->E[0] = E;
+  st->mse_rel[0] = mse();
+  st->ginf_rel[0] = 1.0;
+  st->gradients = 1;
+  st->evaluations = 1;
+  st->status = BL_MAXITER;
+  if (ginf0 == 0.0) {
+    st->status = BL_CONVERGED;
+    st->ginf_rel[0] = 0.0;
+    return;
+  }
+  double ginf = ginf0;
+  for (int it = 0; it < o.max_gn; ++it) {
+    if (ginf / ginf0 < o.gtol) {
+      st->status = BL_CONVERGED;
+      break;
+    }
+    const double gn = std::sqrt(std::max(dev_dot(c, c->sg, c->sg), 0.0));
+    const double eta = std::min(0.5, std::sqrt(gn / g0n));
+    // PCG on H delta = -g with preconditioner K = 1/Lhat, delta_0 = 0
+    HIP_TRY(hipMemsetAsync(c->sdelta, 0, nb * sizeof(float2), s));
+    HIP_TRY(hipMemsetAsync(c->sr, 0, nb * sizeof(float2), s));
+    bl::axpy(c->sr, c->sg, -1.0, nb, s);  // r = -g
+    double rr, rz;
+    dev_precond(c, c->sr, c->sz, &rr, &rz);
+    HIP_TRY(hipMemcpyAsync(c->sp, c->sz, nb * sizeof(float2), hipMemcpyDeviceToDevice, s));
+    int iters = 0;
+    for (int j = 0; j < o.max_pcg; ++j) {
+      op_hessvec(c, c->sp, c->sHp);
+      st->hessvecs += 1;
+      const double pHp = dev_dot(c, c->sp, c->sHp);
+      if (!(pHp > 0.0)) {
+        if (iters == 0)
+          HIP_TRY(hipMemcpyAsync(c->sdelta, c->sz, nb * sizeof(float2), hipMemcpyDeviceToDevice, s));
+        break;
+      }
+      const double alpha = rz / pHp;
+      bl::axpy(c->sdelta, c->sp, alpha, nb, s);
+      bl::axpy(c->sr, c->sHp, -alpha, nb, s);
+      iters += 1;
+      double rr_new, rz_new;
+      dev_precond(c, c->sr, c->sz, &rr_new, &rz_new);
+      if (std::sqrt(std::max(rr_new, 0.0)) <= eta * gn) break;
+      const double beta = rz_new / rz;
+      rz = rz_new;
+      bl::xpby(c->sp, c->sz, beta, nb, s);  // p = z + beta p
+    }
+    check_launch("pcg");
+    st->pcg_iters[it] = iters;
+    st->pcg_total += iters;
+    // Armijo backtracking on E along delta
+    const double slope = dev_dot(c, c->sg, c->sdelta);
+    double eps = 1.0;
+    bool accepted = false;
+    int trials = 0;
+    for (int t = 0; t <= o.max_halvings; ++t) {
+      trials += 1;
+      bl::add_scaled(c->stry, c->sv, c->sdelta, eps, nb, s);
+      op_set_velocity(c, c->stry);
+      st->evaluations += 1;
+      if (c->E <= E + o.c1 * eps * slope) {
+        accepted = true;
+        break;
+      }
+      eps *= 0.5;
+    }
+    st->ls_trials[it] = trials;
+    if (!accepted) {
+      st->status = BL_STALLED;
+      st->eps[it] = 0.0;
+      op_set_velocity(c, c->sv);  // state of the returned velocity
+      break;
+    }
+    st->eps[it] = eps;
+    HIP_TRY(hipMemcpyAsync(c->sv, c->bv, band_bytes(g) * g.dim, hipMemcpyDeviceToDevice, s));
+    E = c->E;
+    op_gradient(c, c->sg);
+    check_flag(c, "gradient");
+    st->gradients += 1;
+    st->gn_iters += 1;
+    ginf = dev_maxabs(c, c->sg);
+    st->E[st->gn_iters] = E;
+    st->mse_rel[st->gn_iters] = mse();
+    st->ginf_rel[st->gn_iters] = ginf / ginf0;
+    if (it + 1 == o.max_gn && ginf / ginf0 < o.gtol) st->status = BL_CONVERGED;
+  }
+}
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const DeviceError& e) {
+    return fail(BL_E_DEVICE, std::string("HIP error in ") + e.where + ": " + hipGetErrorString(e.e));
+  } catch (const NonFinite& e) {
+    return fail(BL_E_NONFINITE, std::string("non-finite value in ") + e.what);
+  } catch (const std::bad_alloc&) {
+    return fail(BL_E_NOMEM, "device working set does not fit in free memory");
+  } catch (...) {
+    return fail(BL_E_DEVICE, "unexpected internal error");
+  }
+}
+
+struct CtxHolder {
+  bl_ctx* c = nullptr;
+  ~CtxHolder() { destroy_ctx(c); }
+};
+
+}  // namespace
+
+// ================================================================================ C-ABI
+extern "C" {
+
+void bl_lddmm_default_opts(bl_solver_opts* opts) {
+  if (opts) fill_default(opts);
+}
+
+const char* bl_lddmm_last_error(void) { return t_err.c_str(); }
+
+int bl_lddmm_device_count(void) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess) return 0;
+  return n;
+}
+
+uint64_t bl_lddmm_footprint(const bl_problem* prob) {
+  bl::Geo g;
+  if (validate(prob, &g) != BL_OK) return 0;
+  return (uint64_t)plan_layout(g, true, true).total;
+}
+
+int bl_lddmm_ctx_create(const bl_problem* prob, const float* I0, const float* I1, bl_ctx** out) {
+  t_err.clear();
+  if (out) *out = nullptr;
+  bl::Geo g;
+  if (int r = validate(prob, &g)) return r;
+  if (!out || !I0 || !I1) return fail(BL_E_INVALID, "NULL pointer argument");
+  return guarded([&]() {
+    CtxHolder h;
+    h.c = create_ctx(prob, g, true, true);
+    load_images(h.c, I0, I1);
+    sync(h.c);
+    *out = h.c;
+    h.c = nullptr;
+    return BL_OK;
+  });
+}
+
+void bl_lddmm_ctx_destroy(bl_ctx* ctx) { destroy_ctx(ctx); }
+
+int bl_lddmm_ctx_set_velocity(bl_ctx* c, const float* v_hat, double* energy, float* g_hat) {
+  t_err.clear();
+  if (!c || !v_hat) return fail(BL_E_INVALID, "NULL pointer argument");
+  return guarded([&]() {
+    HIP_TRY(hipSetDevice(c->device));
+    load_band(c, v_hat, c->braw, c->g.dim);
+    op_set_velocity(c, c->braw);
+    if (energy) *energy = c->E;
+    if (g_hat) {
+      op_gradient(c, c->bout);
+      store_band(c, c->bout, g_hat, c->g.dim);
+      check_flag(c, "gradient");
+    }
+    t_collect(c);
+    return BL_OK;
+  });
+}
+
+int bl_lddmm_ctx_hessvec(bl_ctx* c, const float* dv_hat, float* hv_hat) {
+  t_err.clear();
+  if (!c || !dv_hat || !hv_hat) return fail(BL_E_INVALID, "NULL pointer argument");
+  if (!c->have_v) return fail(BL_E_INVALID, "no velocity set on this context");
+  return guarded([&]() {
+    HIP_TRY(hipSetDevice(c->device));
+    if (c->devptr) {
+      op_hessvec(c, reinterpret_cast<const float2*>(dv_hat), reinterpret_cast<float2*>(hv_hat));
+      return BL_OK;
+    }
+    load_band(c, dv_hat, c->braw, c->g.dim);
+    op_hessvec(c, c->braw, c->bout);
+    store_band(c, c->bout, hv_hat, c->g.dim);
+    check_flag(c, "Hessian-vector product");
+    t_collect(c);
+    return BL_OK;
+  });
+}
+
+int bl_lddmm_ctx_get_field(bl_ctx* c, int32_t which, int32_t index, float* out) {
+  t_err.clear();
+  if (!c || !out) return fail(BL_E_INVALID, "NULL pointer argument");
+  const bl::Geo& g = c->g;
+  const float* src = nullptr;
+  const size_t M = (size_t)g.M;
+  switch (which) {
+    case BL_FIELD_VELOCITY: if (index >= 0 && index < g.dim) src = c->V + index * M; break;
+    case BL_FIELD_DIV: if (index == 0) src = c->V + g.dim * M; break;
+    case BL_FIELD_X: if (index >= 0 && index < g.dim) src = c->X + index * M; break;
+    case BL_FIELD_Y: if (index >= 0 && index < g.dim) src = c->Y + index * M; break;
+    case BL_FIELD_A: if (index == 0) src = c->A; break;
+    case BL_FIELD_STATE: if (index >= 0 && index <= g.nt) src = c->m + index * M; break;
+    default: break;
+  }
+  if (!src) return fail(BL_E_INVALID, "unknown field or index out of range");
+  if (!c->have_v && which != BL_FIELD_STATE) return fail(BL_E_INVALID, "no velocity set on this context");
+  return guarded([&]() {
+    HIP_TRY(hipSetDevice(c->device));
+    store_plane(c, src, out, 1);
+    sync(c);
+    return BL_OK;
+  });
+}
+
+int bl_lddmm_gradient(const bl_problem* prob, const float* I0, const float* I1,
+                      const float* v_hat, float* g_hat, double* energy) {
+  t_err.clear();
+  bl::Geo g;
+  if (int r = validate(prob, &g)) return r;
+  if (!I0 || !I1 || !v_hat || !g_hat) return fail(BL_E_INVALID, "NULL pointer argument");
+  return guarded([&]() {
+    CtxHolder h;
+    h.c = create_ctx(prob, g, true, false);
+    load_images(h.c, I0, I1);
+    load_band(h.c, v_hat, h.c->braw, g.dim);
+    op_set_velocity(h.c, h.c->braw);
+    op_gradient(h.c, h.c->bout);
+    store_band(h.c, h.c->bout, g_hat, g.dim);
+    check_flag(h.c, "gradient");
+    if (energy) *energy = h.c->E;
+    return BL_OK;
+  });
+}
+
+int bl_lddmm_hessvec(const bl_problem* prob, const float* I0, const float* I1,
+                     const float* v_hat, const float* dv_hat, float* hv_hat) {
+  t_err.clear();
+  bl::Geo g;
+  if (int r = validate(prob, &g)) return r;
+  if (!I0 || !I1 || !v_hat || !dv_hat || !hv_hat) return fail(BL_E_INVALID, "NULL pointer argument");
+  return guarded([&]() {
+    CtxHolder h;
+    h.c = create_ctx(prob, g, true, false);
+    load_images(h.c, I0, I1);
+    load_band(h.c, v_hat, h.c->braw, g.dim);
+    op_set_velocity(h.c, h.c->braw);
+    load_band(h.c, dv_hat, h.c->braw, g.dim);
+    op_hessvec(h.c, h.c->braw, h.c->bout);
+    store_band(h.c, h.c->bout, hv_hat, g.dim);
+    check_flag(h.c, "Hessian-vector product");
+    return BL_OK;
+  });
+}
+
+int bl_lddmm_warp(const bl_problem* prob, const float* I0, const float* v_hat, float* warped) {
+  t_err.clear();
+  bl::Geo g;
+  if (int r = validate(prob, &g)) return r;
+  if (!I0 || !v_hat || !warped) return fail(BL_E_INVALID, "NULL pointer argument");
+  return guarded([&]() {
+    CtxHolder h;
+    h.c = create_ctx(prob, g, true, false);
+    load_images(h.c, I0, nullptr);
+    load_band(h.c, v_hat, h.c->braw, g.dim);
+    op_set_velocity(h.c, h.c->braw);
+    store_plane(h.c, h.c->m + (size_t)g.nt * g.M, warped, 1);
+    sync(h.c);
+    return BL_OK;
+  });
+}
+
+int bl_lddmm_register(const bl_problem* prob, const bl_solver_opts* opts, const float* I0,
+                      const float* I1, float* v_hat, float* warped, bl_stats* stats) {
+  t_err.clear();
+  bl::Geo g;
+  if (int r = validate(prob, &g)) return r;
+  if (int r = validate_opts(opts)) return r;
+  if (!I0 || !I1 || !v_hat) return fail(BL_E_INVALID, "NULL pointer argument");
+  bl_solver_opts o;
+  if (opts) o = *opts; else fill_default(&o);
+  return guarded([&]() {
+    const auto t0 = std::chrono::steady_clock::now();
+    bl_stats local;
+    std::memset(&local, 0, sizeof(local));
+    CtxHolder h;
+    h.c = create_ctx(prob, g, true, true);
+    load_images(h.c, I0, I1);
+    load_band(h.c, v_hat, h.c->sv, g.dim);
+    solve(h.c, o, &local);
+    store_band(h.c, h.c->sv, v_hat, g.dim);
+    if (warped) store_plane(h.c, h.c->m + (size_t)g.nt * g.M, warped, 1);
+    sync(h.c);
+    local.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = local;
+    return BL_OK;
+  });
+}
+
+int bl_band_to_grid(const bl_problem* prob, int32_t ncomp, const float* band, float* grid) {
+  t_err.clear();
+  bl::Geo g;
+  if (int r = validate(prob, &g)) return r;
+  if (ncomp < 1 || ncomp > 4) return fail(BL_E_INVALID, "ncomp must be in [1, 4]");
+  if (!band || !grid) return fail(BL_E_INVALID, "NULL pointer argument");
+  return guarded([&]() {
+    CtxHolder h;
+    h.c = create_ctx(prob, g, false, false);
+    bl_ctx* c = h.c;
+    // project each component separately through the prep kernel (it handles dim components)
+    bl::Geo g1 = g;
+    g1.dim = 1;
+    for (int i = 0; i < ncomp; ++i) {
+      load_band(c, band + (size_t)2 * g.B * i, c->braw, 1);
+      bl::band_prep(g1, c->braw, c->bv + (size_t)g.B * i, 0, nullptr, nullptr, c->stream);
+    }
+    bl::iota(g, c->plan, c->bv, ncomp, c->V, c->stream);
+    check_launch("band_to_grid");
+    store_plane(c, c->V, grid, ncomp);
+    sync(c);
+    return BL_OK;
+  });
+}
+
+int bl_grid_to_band(const bl_problem* prob, int32_t ncomp, const float* grid, float* band) {
+  t_err.clear();
+  bl::Geo g;
+  if (int r = validate(prob, &g)) return r;
+  if (ncomp < 1 || ncomp > 4) return fail(BL_E_INVALID, "ncomp must be in [1, 4]");
+  if (!band || !grid) return fail(BL_E_INVALID, "NULL pointer argument");
+  return guarded([&]() {
+    CtxHolder h;
+    h.c = create_ctx(prob, g, false, false);
+    bl_ctx* c = h.c;
+    HIP_TRY(hipMemcpyAsync(c->V, grid, plane_bytes(g) * ncomp, in_kind(c), c->stream));
+    bl::pi_half(g, c->plan, c->V, ncomp, c->P, c->stream);
+    bl::band_finalize(g, ncomp, nullptr, c->Lhat, c->P, (float)(1.0 / (double)g.M), c->bout,
+                      c->flag, c->stream);
+    check_launch("grid_to_band");
+    store_band(c, c->bout, band, ncomp);
+    sync(c);
+    return BL_OK;
+  });
+}
+
+int bl_kernel_timing_enable(bl_ctx* c, int32_t on) {
+  t_err.clear();
+  if (!c) return fail(BL_E_INVALID, "NULL context");
+  return guarded([&]() {
+    HIP_TRY(hipSetDevice(c->device));
+    if (on && c->ev_pool.empty()) {
+      c->ev_pool.resize(8192);
+      for (auto& e : c->ev_pool) HIP_TRY(hipEventCreate(&e));
+    }
+    t_collect(c);
+    c->timing = on != 0;
+    return BL_OK;
+  });
+}
+
+int bl_kernel_timing_read(bl_ctx* c, int32_t kclass, int64_t* launches, double* ms) {
+  t_err.clear();
+  if (!c || !launches || !ms) return fail(BL_E_INVALID, "NULL pointer argument");
+  if (kclass < 0 || kclass > 2) return fail(BL_E_INVALID, "kernel class must be 0, 1 or 2");
+  return guarded([&]() {
+    HIP_TRY(hipSetDevice(c->device));
+    t_collect(c);
+    *launches = c->t_launch[kclass];
+    *ms = c->t_ms[kclass];
+    c->t_launch[kclass] = 0;
+    c->t_ms[kclass] = 0;
+    return BL_OK;
+  });
+}
+
+}  // extern "C"

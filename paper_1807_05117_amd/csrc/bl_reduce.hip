@@ -1,0 +1,191 @@
+// Deterministic FP64 reductions and band-vector algebra for the Gauss-Newton-Krylov solver
+// (paper Section 3.4: PCG on H dv~ = -g~ with preconditioner K~ = L~^-1).
+//
+// Every reduction runs on a fixed grid of kRedBlocks blocks of 256 threads; each thread
+// accumulates a fixed strided subset in FP64, each block reduces through a fixed LDS tree,
+// and one block sums the partials in order.  No atomics, so results are bitwise repeatable.
+#include "bl_internal.h"
+
+namespace bl {
+namespace {
+
+__device__ __forceinline__ void block_sum_store(double acc, double* __restrict__ partial) {
+  __shared__ double sh[256];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__device__ __forceinline__ void block_max_store(double acc, double* __restrict__ partial) {
+  __shared__ double sh[256];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+#define GRID_STRIDE(i, n) \
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < (n); i += (int64_t)gridDim.x * 256)
+
+__global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__ partial, int n,
+                                                      double* __restrict__ out) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += partial[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_reduce_max_final(const double* __restrict__ partial,
+                                                          int n, double* __restrict__ out) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc = fmax(acc, partial[i]);
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_dot_partial(const float2* __restrict__ a,
+                                                     const float2* __restrict__ b, int64_t n,
+                                                     double* __restrict__ partial) {
+  double acc = 0.0;
+  GRID_STRIDE(i, n) {
+    const float2 x = a[i], y = b[i];
+    acc = fma((double)x.x, (double)y.x, acc);
+    acc = fma((double)x.y, (double)y.y, acc);
+  }
+  block_sum_store(acc, partial);
+}
+
+__global__ __launch_bounds__(256) void k_maxabs_partial(const float2* __restrict__ a, int64_t n,
+                                                        double* __restrict__ partial) {
+  double acc = 0.0;
+  GRID_STRIDE(i, n) {
+    const float2 x = a[i];
+    acc = fmax(acc, sqrt((double)x.x * x.x + (double)x.y * x.y));
+  }
+  block_max_store(acc, partial);
+}
+
+__global__ __launch_bounds__(256) void k_axpy(float2* __restrict__ y, const float2* __restrict__ x,
+                                              double alpha, int64_t n) {
+  GRID_STRIDE(i, n) {
+    const float2 a = x[i];
+    float2 b = y[i];
+    b.x = (float)fma(alpha, (double)a.x, (double)b.x);
+    b.y = (float)fma(alpha, (double)a.y, (double)b.y);
+    y[i] = b;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_xpby(float2* __restrict__ y, const float2* __restrict__ x,
+                                              double beta, int64_t n) {
+  GRID_STRIDE(i, n) {
+    const float2 a = x[i];
+    float2 b = y[i];
+    b.x = (float)fma(beta, (double)b.x, (double)a.x);
+    b.y = (float)fma(beta, (double)b.y, (double)a.y);
+    y[i] = b;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_add_scaled(float2* __restrict__ y,
+                                                    const float2* __restrict__ x,
+                                                    const float2* __restrict__ d, double eps,
+                                                    int64_t n) {
+  GRID_STRIDE(i, n) {
+    const float2 a = x[i], b = d[i];
+    y[i] = make_float2((float)fma(eps, (double)b.x, (double)a.x),
+                       (float)fma(eps, (double)b.y, (double)a.y));
+  }
+}
+
+__global__ __launch_bounds__(256) void k_precond_dots(Geo g, const float2* __restrict__ r,
+                                                      const float* __restrict__ Lhat,
+                                                      float2* __restrict__ z,
+                                                      double* __restrict__ p0,
+                                                      double* __restrict__ p1) {
+  const int64_t n = (int64_t)g.dim * g.B;
+  double rr = 0.0, rz = 0.0;
+  GRID_STRIDE(i, n) {
+    const int64_t b = i % g.B;
+    const float2 x = r[i];
+    const float inv = 1.0f / Lhat[b];
+    const float2 w = make_float2(x.x * inv, x.y * inv);
+    z[i] = w;
+    rr = fma((double)x.x, (double)x.x, rr);
+    rr = fma((double)x.y, (double)x.y, rr);
+    rz = fma((double)x.x, (double)w.x, rz);
+    rz = fma((double)x.y, (double)w.y, rz);
+  }
+  block_sum_store(rr, p0);
+  __syncthreads();
+  block_sum_store(rz, p1);
+}
+
+__global__ __launch_bounds__(256) void k_sqdiff_partial(const float* __restrict__ a,
+                                                        const float* __restrict__ b, int64_t n,
+                                                        double* __restrict__ partial) {
+  double acc = 0.0;
+  GRID_STRIDE(i, n) {
+    const double d = (double)a[i] - (double)b[i];
+    acc = fma(d, d, acc);
+  }
+  block_sum_store(acc, partial);
+}
+
+inline int blocks_for(int64_t n) {
+  (void)n;
+  return kRedBlocks;
+}
+
+}  // namespace
+
+void reduce_final(const double* partial, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, partial, n, out);
+}
+void reduce_max_final(const double* partial, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_max_final, dim3(1), dim3(256), 0, s, partial, n, out);
+}
+void dot_partial(const float2* a, const float2* b, int64_t n, double* partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(kRedBlocks), dim3(256), 0, s, a, b, n, partial);
+}
+void maxabs_partial(const float2* a, int64_t n, double* partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_maxabs_partial, dim3(kRedBlocks), dim3(256), 0, s, a, n, partial);
+}
+void axpy(float2* y, const float2* x, double alpha, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy, dim3(blocks_for(n)), dim3(256), 0, s, y, x, alpha, n);
+}
+void xpby(float2* y, const float2* x, double beta, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_xpby, dim3(blocks_for(n)), dim3(256), 0, s, y, x, beta, n);
+}
+void add_scaled(float2* y, const float2* x, const float2* d, double eps, int64_t n,
+                hipStream_t s) {
+  hipLaunchKernelGGL(k_add_scaled, dim3(blocks_for(n)), dim3(256), 0, s, y, x, d, eps, n);
+}
+void precond_dots(const Geo& g, const float2* r, const float* Lhat, float2* z, double* p0,
+                  double* p1, hipStream_t s) {
+  hipLaunchKernelGGL(k_precond_dots, dim3(kRedBlocks), dim3(256), 0, s, g, r, Lhat, z, p0, p1);
+}
+void sqdiff_partial(const float* a, const float* b, int64_t n, double* partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_sqdiff_partial, dim3(kRedBlocks), dim3(256), 0, s, a, b, n, partial);
+}
+
+}  // namespace bl

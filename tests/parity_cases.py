@@ -1,0 +1,78 @@
+"""Seeded parity cases shared by the GPU tests: inputs from the phantom generators, targets
+and expected values from the FP64 oracle only (nothing here comes from the HIP path)."""
+from __future__ import annotations
+
+import functools
+
+import numpy as np
+
+import oracle as O
+from paper_1807_05117_amd import binding as B
+from paper_1807_05117_amd import phantoms
+
+# name: (dim, n, k, nt, max displacement in voxels, phantom classes)
+CASES = {
+    # 2D plain method: 64^2 blobs, band 16^2, Nt = 10, 4 px
+    "c1_2d": (2, (64, 64), (16, 16), 10, 4.0, 0),
+    # ragged 3D: x spans two 64-wide tiles with a tail, y five 4-high tiles with a tail
+    "ragged_3d": (3, (72, 21, 13), (16, 10, 8), 5, 3.0, 3),
+    # non-cubic brain-like shape at reduced size (l_j differ per axis)
+    "brainlike_small": (3, (40, 48, 40), (10, 12, 10), 6, 3.0, 5),
+    # the 128^3 workload: band 32^3, Nt = 10, 6 voxels
+    "c2_full": (3, (128, 128, 128), (32, 32, 32), 10, 6.0, 3),
+}
+
+
+@functools.lru_cache(maxsize=None)
+def case(name, seed=0):
+    dim, n, k, nt, disp, ncls = CASES[name]
+    prob = O.Problem(dim, n, k, nt, alpha=1e-3, s=2, sigma=1.0)
+    if dim == 2:
+        I0 = phantoms.blobs_2d(seed, n[0])[: n[1], : n[0]]
+    else:
+        I0 = phantoms.shells_3d(seed, n, n_classes=ncls)
+    I0 = I0.astype(np.float32).astype(np.float64)
+    vs = O.project(phantoms.raw_band_velocity(seed, dim, k), prob)
+    vs *= disp / O.max_displacement_voxels(vs, prob)
+    vs = vs.astype(np.complex64).astype(np.complex128)
+    I1 = O.warp(I0, vs, prob).astype(np.float32).astype(np.float64)
+    vh = (0.5 * vs).astype(np.complex64).astype(np.complex128)        # mid-optimisation point
+    dv = O.project(phantoms.random_band_direction(seed + 1, dim, k), prob)
+    dv = (dv / np.abs(dv).max()).astype(np.complex64).astype(np.complex128)
+    return prob, I0, I1, vs, vh, dv
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_state(name, seed=0):
+    prob, I0, I1, vs, vh, dv = case(name, seed)
+    return O.evaluate(vh, I0, I1, prob)
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_gradient(name, seed=0):
+    return O.gradient(oracle_state(name, seed))
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_hessvec(name, seed=0):
+    prob, I0, I1, vs, vh, dv = case(name, seed)
+    return O.hessvec(oracle_state(name, seed), dv)
+
+
+def bl_problem(prob, precision=B.BL_FP32, **kw):
+    return B.make_problem(prob.dim, prob.n, prob.k, prob.nt, alpha=prob.alpha, s=prob.s,
+                          sigma=prob.sigma, precision=precision, **kw)
+
+
+def rel2(a, b):
+    return float(np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel())
+                 / np.linalg.norm(np.asarray(b).ravel()))
+
+
+def grad_error(g_gpu, g_ref, prob, vh):
+    """|g - g_ref|_2 / (|L v|_2 + |pi(b)|_2): the regulariser and the data part are normalised
+    separately so that their cancellation near an optimum does not inflate the error."""
+    Lv = O.L_hat(prob)[None] * O.project(vh, prob)
+    pb = g_ref - Lv
+    den = np.linalg.norm(Lv.ravel()) + np.linalg.norm(pb.ravel())
+    return float(np.linalg.norm((np.asarray(g_gpu) - g_ref).ravel()) / den)

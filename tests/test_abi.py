@@ -1,0 +1,124 @@
+"""C-interface contract checks that need no GPU: the library loads, exports every function
+that include/bl_lddmm.h declares, and rejects invalid arguments on the host before any
+device call."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from paper_1807_05117_amd import binding as B
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return B.load()
+
+
+def test_header_functions_are_exported(lib):
+    names = B.header_functions()
+    assert len(names) >= 17
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_struct_layouts_match_c_abi():
+    # field offsets of the C structs under the x86-64 SysV ABI
+    assert B.Problem.alpha.offset == 32 and B.Problem.sigma.offset == 48
+    assert B.Problem.stream.offset == 72 and C.sizeof(B.Problem) == 80
+    assert C.sizeof(B.SolverOpts) == 32
+    assert B.Stats.E.offset == 24
+
+
+def _p(**kw):
+    base = dict(dim=3, n=(16, 12, 10), k=(8, 6, 4), nt=4)
+    base.update(kw)
+    return B.make_problem(**base)
+
+
+BAD = [
+    (dict(dim=4), B.BL_E_INVALID),
+    (dict(dim=1), B.BL_E_INVALID),
+    (dict(n=(2, 12, 10)), B.BL_E_INVALID),
+    (dict(n=(4096, 12, 10)), B.BL_E_INVALID),
+    (dict(k=(7, 6, 4)), B.BL_E_INVALID),
+    (dict(k=(0, 6, 4)), B.BL_E_INVALID),
+    (dict(k=(18, 6, 4)), B.BL_E_INVALID),
+    (dict(nt=0), B.BL_E_INVALID),
+    (dict(nt=1000), B.BL_E_INVALID),
+    (dict(alpha=-1.0), B.BL_E_INVALID),
+    (dict(alpha=float("nan")), B.BL_E_INVALID),
+    (dict(s=-1), B.BL_E_INVALID),
+    (dict(s=9), B.BL_E_INVALID),
+    (dict(sigma=0.0), B.BL_E_INVALID),
+    (dict(sigma=float("inf")), B.BL_E_INVALID),
+    (dict(gamma=1), B.BL_E_UNSUPPORTED),
+    (dict(precision=7), B.BL_E_UNSUPPORTED),
+]
+
+
+@pytest.mark.parametrize("kw,code", BAD)
+def test_invalid_problem_rejected_before_device_work(lib, kw, code):
+    p = _p(**kw)
+    shp = (10, 12, 16)
+    I = np.zeros(shp, np.float32)
+    v = np.zeros((3, 4, 6, 8), np.complex64)
+    g = np.zeros_like(v)
+    E = C.c_double()
+    rc = lib.bl_lddmm_gradient(C.byref(p), I.ctypes.data, I.ctypes.data, v.ctypes.data,
+                               g.ctypes.data, C.byref(E))
+    assert rc == code
+    assert lib.bl_lddmm_last_error().decode() != ""
+    assert lib.bl_lddmm_footprint(C.byref(p)) == 0
+
+
+def test_null_pointers_rejected(lib):
+    p = _p()
+    I = np.zeros((10, 12, 16), np.float32)
+    v = np.zeros((3, 4, 6, 8), np.complex64)
+    assert lib.bl_lddmm_gradient(C.byref(p), None, I.ctypes.data, v.ctypes.data, v.ctypes.data,
+                                 None) == B.BL_E_INVALID
+    assert lib.bl_lddmm_hessvec(C.byref(p), I.ctypes.data, I.ctypes.data, v.ctypes.data, None,
+                                v.ctypes.data) == B.BL_E_INVALID
+    assert lib.bl_lddmm_gradient(None, None, None, None, None, None) == B.BL_E_INVALID
+    assert "NULL" in lib.bl_lddmm_last_error().decode()
+    h = C.c_void_p(123)
+    assert lib.bl_lddmm_ctx_create(C.byref(p), None, None, C.byref(h)) == B.BL_E_INVALID
+    assert h.value is None
+    assert lib.bl_lddmm_ctx_hessvec(None, None, None) == B.BL_E_INVALID
+    assert lib.bl_lddmm_ctx_set_velocity(None, None, None, None) == B.BL_E_INVALID
+    lib.bl_lddmm_ctx_destroy(None)   # no-op
+
+
+def test_bad_solver_options_rejected(lib):
+    p = _p()
+    I = np.zeros((10, 12, 16), np.float32)
+    v = np.zeros((3, 4, 6, 8), np.complex64)
+    for kw in (dict(max_gn=-1), dict(max_gn=65), dict(max_pcg=0), dict(c1=1.5),
+               dict(gtol=float("nan")), dict(max_halvings=-2)):
+        o = B.opts_struct(**kw)
+        rc = lib.bl_lddmm_register(C.byref(p), C.byref(o), I.ctypes.data, I.ctypes.data,
+                                   v.ctypes.data, None, None)
+        assert rc == B.BL_E_INVALID, kw
+
+
+def test_band_utility_arguments_rejected(lib):
+    p = _p()
+    x = np.zeros(16, np.float32)
+    assert lib.bl_band_to_grid(C.byref(p), 0, x.ctypes.data, x.ctypes.data) == B.BL_E_INVALID
+    assert lib.bl_grid_to_band(C.byref(p), 5, x.ctypes.data, x.ctypes.data) == B.BL_E_INVALID
+
+
+def test_footprint_scales_with_problem(lib):
+    small = lib.bl_lddmm_footprint(C.byref(_p()))
+    c2 = lib.bl_lddmm_footprint(C.byref(B.make_problem(3, (128,) * 3, (32,) * 3, 10)))
+    assert small > 0 and c2 > 100 * small
+    # (nt + 1) state planes + 2 * dim offsets + reaction + 2 * (dim + 1) + 2 + dim fields
+    M = 128 ** 3
+    assert c2 >= (11 + 3 + 3 + 1 + 4 + 3 + 2 + 3 + 1) * 4 * M
+
+
+def test_default_opts(lib):
+    o = B.SolverOpts()
+    lib.bl_lddmm_default_opts(C.byref(o))
+    assert (o.max_gn, o.max_pcg, o.max_halvings) == (10, 10, 10)
+    assert o.gtol == 1e-3 and o.c1 == 1e-4
