@@ -1,0 +1,262 @@
+"""Benchmark of band-limited PDE-LDDMM (state equation, Gauss-Newton-Krylov) on one MI355X.
+
+Workload: a synthetic 128^3 brain-like phantom (3 nested ellipsoidal tissue shells,
+intensities 0.2/0.5/0.8, Gaussian smoothing sigma = 1 voxel, N(0, 0.01^2) noise), target =
+the phantom warped by a random band-limited velocity (band 32^3, coefficients
+N(0,1)/(1 + |k|^2), 6 voxels maximal displacement), band 32^3, Nt = 10, alpha = 1e-3,
+s = 2, sigma = 1.  One step = one full registration (10 Gauss-Newton iterations with at
+most 10 PCG steps each), which runs every stage of the path: band<->grid transforms,
+departure-point setup, forward state, energy, adjoint and body force, incremental state,
+incremental adjoint, regulariser, PCG and line search.
+
+Printed: one JSON line with registrations/min as the value, plus Gauss-Newton
+Hessian-vector products per second (200 products at a cached mid-optimisation state),
+per-registration and per-product p50/p99 latency, the roofline of the dominant kernel
+(timed with HIP events on the library's stream) and the FP64 oracle's rate on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_1807_05117_amd import binding as B  # noqa: E402
+from paper_1807_05117_amd import phantoms  # noqa: E402
+
+GRID = (128, 128, 128)
+BAND = (32, 32, 32)
+NT = 10
+DISP = 6.0
+HBM_PEAK_GBS = 8000.0
+# algorithmic FP32 bytes per voxel of one launch of each transport step kernel:
+#   state step      X (12) + m^n (4) read, m^{n+1} (4) written                 = 20
+#   incremental     X (12) + t^n (4) + m^{n+1} (4) + dv (12) read, t^{n+1} (4)  = 36
+#   adjoint step    Y (12) + a (4) + lambda^{n+1} (4) + m^n (4) read,
+#                   lambda^n (4) written (body force kept on chip)             = 28
+KCLASS = {0: ("state_step", 20), 1: ("inc_step", 36), 2: ("adj_step", 28)}
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def percentile(xs, q):
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else None
+
+
+def make_inputs(seed=0):
+    I0 = phantoms.shells_3d(seed, GRID, n_classes=3).astype(np.float32)
+    raw = phantoms.raw_band_velocity(seed, 3, BAND).astype(np.complex64)
+    p = B.make_problem(3, GRID, BAND, NT)
+    v = B.bl_band_to_grid(p, raw)                       # projected inside the library
+    vmax = float(np.sqrt((v.astype(np.float64) ** 2).sum(axis=0)).max()) * max(GRID)
+    vs = (raw * (DISP / vmax)).astype(np.complex64)
+    I1 = B.bl_lddmm_warp(p, I0, vs)
+    return I0, I1, vs
+
+
+def gpu_leg(steps, warmup, n_hv=200):
+    import torch
+
+    p = B.make_problem(3, GRID, BAND, NT)
+    I0, I1, vs = make_inputs(0)
+    v0 = np.zeros_like(vs)
+    progress("inputs ready; warmup")
+    for _ in range(warmup):
+        B.bl_lddmm_register(p, I0, I1, v0)
+    torch.cuda.synchronize()
+    lat = []
+    stats = None
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        _, warped, stats = B.bl_lddmm_register(p, I0, I1, v0)
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    progress(f"{steps} registrations in {elapsed:.3f} s; Hessian-vector products")
+
+    # Hessian-vector products at a cached mid-optimisation state, device pointers on the
+    # library's own context stream = torch's current stream
+    stream = torch.cuda.current_stream()
+    pd = B.make_problem(3, GRID, BAND, NT, device=True, stream=stream.cuda_stream)
+    dI0 = torch.from_numpy(I0).cuda()
+    dI1 = torch.from_numpy(I1).cuda()
+    ctx = B.Ctx(pd, dI0, dI1)
+    vh = torch.from_numpy(np.ascontiguousarray(0.5 * vs)).cuda()
+    gen = np.random.default_rng(1)
+    dvn = (gen.standard_normal(vs.shape) + 1j * gen.standard_normal(vs.shape)).astype(np.complex64)
+    dv = torch.from_numpy(dvn).cuda()
+    out = torch.empty_like(dv)
+    E, g = ctx.bl_lddmm_ctx_set_velocity(vh)
+    for _ in range(20):
+        ctx.bl_lddmm_ctx_hessvec(dv, out)
+    torch.cuda.synchronize()
+    # throughput: back-to-back products
+    t1 = time.perf_counter()
+    for _ in range(n_hv):
+        ctx.bl_lddmm_ctx_hessvec(dv, out)
+    torch.cuda.synchronize()
+    hv_s = n_hv / (time.perf_counter() - t1)
+    # latency: one product at a time, HIP events on the same stream
+    hv_lat = []
+    for _ in range(50):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.bl_lddmm_ctx_hessvec(dv, out)
+        e1.record(stream)
+        e1.synchronize()
+        hv_lat.append(e0.elapsed_time(e1))
+    # gradients per second (set_velocity + gradient)
+    t2 = time.perf_counter()
+    for _ in range(20):
+        ctx.bl_lddmm_ctx_set_velocity(vh)
+    torch.cuda.synchronize()
+    grad_s = 20 / (time.perf_counter() - t2)
+    # per-kernel durations with HIP events on the context's stream
+    ctx.bl_kernel_timing_enable(True)
+    ctx.bl_lddmm_ctx_set_velocity(vh)
+    for _ in range(20):
+        ctx.bl_lddmm_ctx_hessvec(dv, out)
+    torch.cuda.synchronize()
+    kern = {}
+    for k in (0, 1, 2):
+        n, ms = ctx.bl_kernel_timing_read(k)
+        kern[k] = (n, ms)
+    ctx.bl_kernel_timing_enable(False)
+    ctx.close()
+    # achievable HBM bandwidth: a plain 1 GiB device-to-device copy (also the reference
+    # kernel for scaling the FETCH_SIZE / WRITE_SIZE counters)
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    copy_gbs = 10 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) / 1000.0) / 1e9
+    del src, dst
+    return dict(copy_gbs=copy_gbs, elapsed=elapsed, lat=lat, stats=stats, hv_s=hv_s, hv_lat=hv_lat, grad_s=grad_s,
+                kern=kern, E=E)
+
+
+def cpu_leg(stats):
+    """The FP64 oracle on the host: one energy evaluation, one gradient and one
+    Hessian-vector product at 128^3, scaled by the registration's operation counts."""
+    from threadpoolctl import threadpool_limits
+
+    import oracle as O
+
+    with threadpool_limits(limits=1):
+        prob = O.Problem(3, GRID, BAND, NT)
+        I0 = phantoms.shells_3d(0, GRID, n_classes=3).astype(np.float32).astype(np.float64)
+        vs = O.project(phantoms.raw_band_velocity(0, 3, BAND), prob)
+        vs *= DISP / O.max_displacement_voxels(vs, prob)
+        I1 = O.warp(I0, vs, prob).astype(np.float32).astype(np.float64)
+        t = time.perf_counter()
+        st = O.evaluate(0.5 * vs, I0, I1, prob)
+        t_eval = time.perf_counter() - t
+        t = time.perf_counter()
+        O.gradient(st)
+        t_grad = time.perf_counter() - t
+        d = O.project(phantoms.random_band_direction(1, 3, BAND), prob)
+        t = time.perf_counter()
+        O.hessvec(st, d)
+        t_hv = time.perf_counter() - t
+    progress(f"oracle: evaluation {t_eval:.1f} s, gradient {t_grad:.1f} s, product {t_hv:.1f} s")
+    t_reg = (stats["evaluations"] * t_eval + stats["gradients"] * t_grad
+             + stats["hessvecs"] * t_hv)
+    return {"value": 60.0 / t_reg, "unit": "registrations/min", "cores": 1, "kind": "oracle",
+            "sample": (f"one energy evaluation ({t_eval:.1f} s), one gradient ({t_grad:.1f} s) "
+                       f"and one Hessian-vector product ({t_hv:.1f} s) at 128^3/32^3/Nt=10, "
+                       f"FP64 NumPy on 1 thread, scaled by the registration's counts "
+                       f"({stats['evaluations']} evaluations, {stats['gradients']} gradients, "
+                       f"{stats['hessvecs']} products)"),
+            "hv_per_s": 1.0 / t_hv}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the registration path has no multi-GPU mode "
+              "(pairs are independent; see the design notes for how it would shard).",
+              file=sys.stderr)
+        sys.exit(2)
+    B.load()
+    if not B.device_available():
+        raise RuntimeError("no HIP device visible")
+    r = gpu_leg(args.steps, args.warmup)
+    ms_step = 1000.0 * r["elapsed"] / args.steps
+    value = 60000.0 / ms_step
+    M = GRID[0] * GRID[1] * GRID[2]
+    # dominant kernel: largest total time among the transport step kernels
+    kc = max(r["kern"], key=lambda k: r["kern"][k][1])
+    n_launch, ms_tot = r["kern"][kc]
+    name, bpv = KCLASS[kc]
+    avg_s = ms_tot / 1000.0 / max(n_launch, 1)
+    achieved = bpv * M / avg_s / 1e9
+    hv_bytes = (64 * NT + 36) * M
+    line = {
+        "metric": "GN Hessian-vec products/s and registrations/min at 128^3; p50/p99 latency",
+        "value": value,
+        "unit": "registrations/min",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "registration of a 128^3 3-class shell phantom to its warp "
+                               "(6 vox), band 32^3, Nt=10, 10 GN x <=10 PCG",
+                   "grid": list(GRID), "band": list(BAND), "nt": NT, "alpha": 1e-3, "s": 2,
+                   "sigma": 1.0, "precision": "fp32", "parallelism": "single GPU"},
+        "registration": {"p50_ms": 1000 * percentile(r["lat"], 50),
+                         "p99_ms": 1000 * percentile(r["lat"], 99),
+                         "gn_iters": r["stats"]["gn_iters"], "hessvecs": r["stats"]["hessvecs"],
+                         "gradients": r["stats"]["gradients"],
+                         "evaluations": r["stats"]["evaluations"],
+                         "final_mse_rel": r["stats"]["mse_rel"][-1],
+                         "status": r["stats"]["status"]},
+        "hv_per_s": r["hv_s"],
+        "hv_p50_ms": percentile(r["hv_lat"], 50),
+        "hv_p99_ms": percentile(r["hv_lat"], 99),
+        "hv_hbm_gbs_algorithmic": hv_bytes * r["hv_s"] / 1e9,
+        "gradients_per_s": r["grad_s"],
+        "kernels": {KCLASS[k][0]: {"launches": r["kern"][k][0],
+                                   "avg_us": 1000.0 * r["kern"][k][1] / max(r["kern"][k][0], 1)}
+                    for k in r["kern"]},
+        "roofline": {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_voxel": bpv, "avg_launch_us": avg_s * 1e6,
+                     "copy_gbs": r["copy_gbs"], "frac_of_copy": achieved / r["copy_gbs"]},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu:
+        progress("oracle baseline on the host")
+        line["cpu_baseline"] = cpu_leg(r["stats"])
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -74,8 +74,8 @@ extern "C" {
 
 typedef struct {
   int32_t dim;        /* 2 or 3                                                            */
-  int32_t n[3];       /* grid size per axis (x, y, z), 4 <= n[j] <= 2048                    */
-  int32_t k[3];       /* band size per axis, even, 2 <= k[j] <= n[j]                        */
+  int32_t n[3];       /* grid size per axis (x, y, z), 4 <= n[j] <= 2048, prod <= 2^30       */
+  int32_t k[3];       /* band size per axis, even, 2 <= k[j] <= n[j], k[2] <= 128             */
   int32_t nt;         /* time steps, 1 <= nt <= 256                                         */
   double  alpha;      /* L = (Id - alpha Lap)^s: alpha >= 0                                 */
   int32_t s;          /*                          0 <= s <= 8                               */

@@ -70,10 +70,20 @@ _P = C.c_void_p
 
 
 def load():
-    """Load the library (fails loudly when it has not been built)."""
+    """Load the library (fails loudly when it has not been built).
+
+    torch wheels ship their own HIP runtime under the same soname as /opt/rocm's.  Two
+    runtimes in one process cannot share the GPU, so torch is imported first: the library's
+    libamdhip64.so.7 dependency then resolves to the runtime torch already loaded and device
+    pointers, streams and events are shared.
+    """
     global _lib
     if _lib is not None:
         return _lib
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1807_05117_amd/build.py")
     lib = C.CDLL(LIB_PATH)

@@ -39,7 +39,14 @@ __device__ __forceinline__ void cmac_conj(float2& acc, float2 a, float2 b) {
   acc.y = fmaf(-a.x, b.y, acc.y);
 }
 
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // ---------------------------------------------------------------------------- iota stages
+// All contraction loops run in chunks of kU terms: the kU operand loads of a chunk are
+// issued before its arithmetic, so kU memory latencies overlap.  Chunks past the end of an
+// axis read clamped (in-bounds) data against zero-padded twiddle rows.
+
+// x stage: one thread per (x, ky, c*kzh + h); the band row is uniform across the block.
 __global__ __launch_bounds__(64) void k_iota_x(Geo g, const float2* __restrict__ band,
                                                const float2* __restrict__ tw_x,
                                                float2* __restrict__ F1) {
@@ -49,27 +56,59 @@ __global__ __launch_bounds__(64) void k_iota_x(Geo g, const float2* __restrict__
   if (x >= g.nx) return;
   const int c = ch / g.kzh, h = ch - c * g.kzh;
   const float2* row = band + ((size_t)(c * g.kz + g.kz0 + h) * g.ky + jy) * g.kx;
-  float2 acc = make_float2(0.f, 0.f);
-  for (int jx = 0; jx < g.kx; ++jx) cmac(acc, row[jx], tw_x[(size_t)jx * g.nx + x]);
-  F1[((size_t)ch * g.ky + jy) * g.nx + x] = acc;
+  float2 a0 = make_float2(0.f, 0.f), a1 = a0;
+  for (int j0 = 0; j0 < g.kx; j0 += kU) {
+    float2 b[kU], t[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      b[u] = row[min(j0 + u, g.kx - 1)];
+      t[u] = tw_x[(size_t)(j0 + u) * g.nx + x];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; u += 2) {
+      cmac(a0, b[u], t[u]);
+      cmac(a1, b[u + 1], t[u + 1]);
+    }
+  }
+  F1[((size_t)ch * g.ky + jy) * g.nx + x] = make_float2(a0.x + a1.x, a0.y + a1.y);
 }
 
+// y stage: one thread per (x, group of kYG y values, c*kzh + h); the F1 column is read once
+// per group and the twiddles of the group are wave-uniform (scalar loads).
 __global__ __launch_bounds__(64) void k_iota_y(Geo g, const float2* __restrict__ F1,
-                                               const float2* __restrict__ tw_y,
+                                               const float2* __restrict__ tw_y, int nyp,
                                                float2* __restrict__ F2) {
   const int x = blockIdx.x * 64 + threadIdx.x;
-  const int y = blockIdx.y;
+  const int y0 = blockIdx.y * kYG;
   const int ch = blockIdx.z;
   if (x >= g.nx) return;
   const float2* col = F1 + (size_t)ch * g.ky * g.nx + x;
-  float2 acc = make_float2(0.f, 0.f);
-  for (int jy = 0; jy < g.ky; ++jy) cmac(acc, col[(size_t)jy * g.nx], tw_y[(size_t)jy * g.ny + y]);
-  F2[((size_t)ch * g.ny + y) * g.nx + x] = acc;
+  float2 acc[kYG];
+#pragma unroll
+  for (int u = 0; u < kYG; ++u) acc[u] = make_float2(0.f, 0.f);
+  for (int j0 = 0; j0 < g.ky; j0 += kU) {
+    float2 f[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) f[u] = col[(size_t)min(j0 + u, g.ky - 1) * g.nx];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const float2* tw = tw_y + (size_t)(j0 + u) * nyp + y0;
+#pragma unroll
+      for (int v = 0; v < kYG; ++v) cmac(acc[v], f[u], tw[v]);
+    }
+  }
+  float2* dst = F2 + ((size_t)ch * g.ny + y0) * g.nx + x;
+#pragma unroll
+  for (int u = 0; u < kYG; ++u)
+    if (y0 + u < g.ny) dst[(size_t)u * g.nx] = acc[u];
 }
 
+// z stage (real output): one thread per (column q, chunk of z, component); the half-spectrum
+// column is held in registers, the twiddle rows of four z planes at a time are
+// wave-uniform.  zchunk is a multiple of 4.
 template <int KZH>
 __global__ __launch_bounds__(256) void k_iota_z(Geo g, const float2* __restrict__ F2,
-                                                const float2* __restrict__ tw_z,
+                                                const float2* __restrict__ tw_zT,
                                                 float* __restrict__ out, int zchunk) {
   const int nq = g.nx * g.ny;
   const int q = blockIdx.x * 256 + threadIdx.x;
@@ -79,68 +118,93 @@ __global__ __launch_bounds__(256) void k_iota_z(Geo g, const float2* __restrict_
   const float2* src = F2 + (size_t)c * g.kzh * nq + q;
 #pragma unroll
   for (int h = 0; h < KZH; ++h) {
-    float2 v = h < g.kzh ? src[(size_t)h * nq] : make_float2(0.f, 0.f);
-    if (h > 0) { v.x *= 2.f; v.y *= 2.f; }
-    f[h] = v;
+    const int hc = h < g.kzh ? h : g.kzh - 1;   // clamped, always in bounds
+    float2 v = src[(size_t)hc * nq];
+    const float sc = h >= g.kzh ? 0.f : (h > 0 ? 2.f : 1.f);
+    f[h] = make_float2(sc * v.x, sc * v.y);
   }
   const int z0 = blockIdx.y * zchunk;
   const int z1 = min(g.nz, z0 + zchunk);
   float* dst = out + (size_t)c * g.M + q;
-  for (int z = z0; z < z1; ++z) {
-    float acc0 = f[0].x, acc1 = 0.f;
+  for (int z = z0; z < z1; z += 4) {
+    float acc[4][2];
 #pragma unroll
-    for (int h = 1; h < KZH; ++h) {
-      const float2 t = tw_z[(size_t)h * g.nz + z];
-      acc0 = fmaf(f[h].x, t.x, acc0);
-      acc1 = fmaf(-f[h].y, t.y, acc1);
+    for (int u = 0; u < 4; ++u) {
+      const float2* tw = tw_zT + (size_t)(z + u) * kZP;   // rows up to nzp are allocated
+      acc[u][0] = 0.f;
+      acc[u][1] = 0.f;
+#pragma unroll
+      for (int h = 0; h < KZH; ++h) {
+        const float2 t = tw[h];
+        acc[u][0] = fmaf(f[h].x, t.x, acc[u][0]);
+        acc[u][1] = fmaf(-f[h].y, t.y, acc[u][1]);
+      }
     }
-    dst[(size_t)z * nq] = acc0 + acc1;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (z + u < z1) dst[(size_t)(z + u) * nq] = acc[u][0] + acc[u][1];
   }
 }
 
 // ------------------------------------------------------------------------------ pi stages
+// z stage: block of 64 columns x kNW wavefronts; in every round of kZU kNW planes wavefront
+// w sums the planes w + u kNW (u < kZU) with wave-uniform twiddle rows -- kZU loads in
+// flight per wavefront -- then the kNW partial sums are added in LDS in a fixed order.
+constexpr int kNW = 8;
+constexpr int kZU = 16;
+
 template <int KZH>
-__global__ __launch_bounds__(256) void k_pi_z(Geo g, const float* __restrict__ f,
-                                              const float2* __restrict__ tw_z,
-                                              float2* __restrict__ G) {
+__global__ __launch_bounds__(64 * kNW) void k_pi_z(Geo g, const float* __restrict__ f,
+                                                   const float2* __restrict__ tw_zT,
+                                                   float2* __restrict__ G) {
   constexpr int CH = (KZH % 8 == 0) ? 8 : ((KZH % 4 == 0) ? 4 : 1);
-  __shared__ float2 sh[3][CH][64];
+  __shared__ float2 sh[kNW - 1][CH][64];
   const int nq = g.nx * g.ny;
-  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int tx = threadIdx.x;
+  const int w = wave_uniform(threadIdx.y);
   const int q = blockIdx.x * 64 + tx;
   const int c = blockIdx.y;
+  const int qc = q < nq ? q : nq - 1;   // clamped column: loads stay in bounds
   float2 acc[KZH];
 #pragma unroll
   for (int h = 0; h < KZH; ++h) acc[h] = make_float2(0.f, 0.f);
-  if (q < nq) {
-    const float* src = f + (size_t)c * g.M + q;
-    for (int z = ty; z < g.nz; z += 4) {
-      const float v = src[(size_t)z * nq];
+  const float* src = f + (size_t)c * g.M + qc;
+  for (int zb = 0; zb < g.nz; zb += kZU * kNW) {
+    float v[kZU];
+#pragma unroll
+    for (int u = 0; u < kZU; ++u) v[u] = src[(size_t)min(zb + w + u * kNW, g.nz - 1) * nq];
+#pragma unroll
+    for (int u = 0; u < kZU; ++u) {
+      const float2* t = tw_zT + (size_t)(zb + w + u * kNW) * kZP;   // zero rows past nz
 #pragma unroll
       for (int h = 0; h < KZH; ++h) {
-        const float2 t = tw_z[(size_t)h * g.nz + z];
-        acc[h].x = fmaf(v, t.x, acc[h].x);
-        acc[h].y = fmaf(-v, t.y, acc[h].y);
+        acc[h].x = fmaf(v[u], t[h].x, acc[h].x);
+        acc[h].y = fmaf(-v[u], t[h].y, acc[h].y);
       }
     }
   }
 #pragma unroll
   for (int h0 = 0; h0 < KZH; h0 += CH) {
-    if (ty > 0) {
+    if (w > 0) {
 #pragma unroll
-      for (int hh = 0; hh < CH; ++hh) sh[ty - 1][hh][tx] = acc[h0 + hh];
+      for (int hh = 0; hh < CH; ++hh) sh[w - 1][hh][tx] = acc[h0 + hh];
     }
     __syncthreads();
-    if (ty == 0) {
+    if (w == 0) {
 #pragma unroll
       for (int hh = 0; hh < CH; ++hh) {
-        acc[h0 + hh].x += (sh[0][hh][tx].x + sh[1][hh][tx].x) + sh[2][hh][tx].x;
-        acc[h0 + hh].y += (sh[0][hh][tx].y + sh[1][hh][tx].y) + sh[2][hh][tx].y;
+        float2 s = acc[h0 + hh];
+#pragma unroll
+        for (int o = 0; o < kNW - 1; ++o) {
+          s.x += sh[o][hh][tx].x;
+          s.y += sh[o][hh][tx].y;
+        }
+        acc[h0 + hh] = s;
       }
     }
     __syncthreads();
   }
-  if (ty == 0 && q < nq) {
+  if (w == 0 && q < nq) {
     float2* dst = G + (size_t)c * g.kzh * nq + q;
 #pragma unroll
     for (int h = 0; h < KZH; ++h)
@@ -148,71 +212,132 @@ __global__ __launch_bounds__(256) void k_pi_z(Geo g, const float* __restrict__ f
   }
 }
 
-__global__ __launch_bounds__(64) void k_pi_y(Geo g, const float2* __restrict__ G,
-                                             const float2* __restrict__ tw_y,
-                                             float2* __restrict__ H) {
-  const int x = blockIdx.x * 64 + threadIdx.x;
-  const int jy = blockIdx.y;
+// y stage: block of 64 x-columns x kYS wavefronts for one group of kJG ky outputs; wavefront
+// s sums a contiguous quarter of the y planes in chunks of kU, the partial sums are added in
+// LDS in a fixed order.
+constexpr int kYS = 4;
+
+__global__ __launch_bounds__(64 * kYS) void k_pi_y(Geo g, const float2* __restrict__ G,
+                                                   const float2* __restrict__ tw_yT, int kyp,
+                                                   int yseg, float2* __restrict__ H) {
+  __shared__ float2 sh[kYS - 1][kJG][64];
+  const int tx = threadIdx.x;
+  const int sgm = wave_uniform(threadIdx.y);
+  const int x = blockIdx.x * 64 + tx;
+  const int j0 = blockIdx.y * kJG;
   const int ch = blockIdx.z;
-  if (x >= g.nx) return;
-  const float2* col = G + (size_t)ch * g.ny * g.nx + x;
-  const float2* tw = tw_y + (size_t)jy * g.ny;
-  float2 acc = make_float2(0.f, 0.f);
-  for (int y = 0; y < g.ny; ++y) cmac_conj(acc, col[(size_t)y * g.nx], tw[y]);
-  H[((size_t)ch * g.ky + jy) * g.nx + x] = acc;
+  const int xc = x < g.nx ? x : g.nx - 1;
+  const float2* col = G + (size_t)ch * g.ny * g.nx + xc;
+  float2 acc[kJG];
+#pragma unroll
+  for (int u = 0; u < kJG; ++u) acc[u] = make_float2(0.f, 0.f);
+  const int ya = sgm * yseg;
+  const int yb = min(g.ny, ya + yseg);
+  for (int y0 = ya; y0 < yb; y0 += kUY) {
+    float2 v[kUY];
+#pragma unroll
+    for (int u = 0; u < kUY; ++u) v[u] = col[(size_t)min(y0 + u, g.ny - 1) * g.nx];
+#pragma unroll
+    for (int u = 0; u < kUY; ++u) {
+      // rows past the segment end belong to the next segment: weight them by zero
+      const float keep = (y0 + u < yb) ? 1.f : 0.f;
+      const float2 vv = make_float2(keep * v[u].x, keep * v[u].y);
+      const float2* tw = tw_yT + (size_t)(y0 + u) * kyp + j0;
+#pragma unroll
+      for (int w = 0; w < kJG; ++w) cmac_conj(acc[w], vv, tw[w]);
+    }
+  }
+  if (sgm > 0) {
+#pragma unroll
+    for (int w = 0; w < kJG; ++w) sh[sgm - 1][w][tx] = acc[w];
+  }
+  __syncthreads();
+  if (sgm == 0 && x < g.nx) {
+    float2* dst = H + ((size_t)ch * g.ky + j0) * g.nx + x;
+#pragma unroll
+    for (int w = 0; w < kJG; ++w) {
+      float2 s = acc[w];
+#pragma unroll
+      for (int o = 0; o < kYS - 1; ++o) {
+        s.x += sh[o][w][tx].x;
+        s.y += sh[o][w][tx].y;
+      }
+      if (j0 + w < g.ky) dst[(size_t)w * g.nx] = s;
+    }
+  }
 }
 
-__global__ __launch_bounds__(64) void k_pi_x(Geo g, const float2* __restrict__ H,
-                                             const float2* __restrict__ tw_x,
-                                             float2* __restrict__ P) {
-  const int jx = blockIdx.x * 64 + threadIdx.x;
-  const int jy = blockIdx.y;
-  const int ch = blockIdx.z;
-  if (jx >= g.kx) return;
-  const float2* row = H + ((size_t)ch * g.ky + jy) * g.nx;
-  const float2* tw = tw_x + (size_t)jx * g.nx;
-  float2 acc = make_float2(0.f, 0.f);
-  for (int x = 0; x < g.nx; ++x) cmac_conj(acc, row[x], tw[x]);
-  P[((size_t)ch * g.ky + jy) * g.kx + jx] = acc;
+// x stage: one thread per (kx, row) over the flattened rows (c*kzh + h, ky); H rows and the
+// transposed twiddles are read in chunks of kU.
+__global__ __launch_bounds__(256) void k_pi_x(Geo g, int rows, const float2* __restrict__ H,
+                                              const float2* __restrict__ tw_xT,
+                                              float2* __restrict__ P) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  const int r = t / g.kx;
+  const int jx = t - r * g.kx;
+  if (r >= rows) return;
+  const float2* row = H + (size_t)r * g.nx;
+  float2 a0 = make_float2(0.f, 0.f), a1 = a0;
+  for (int x0 = 0; x0 < g.nx; x0 += kU) {
+    float2 hv[kU], tv[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      hv[u] = row[min(x0 + u, g.nx - 1)];
+      tv[u] = tw_xT[(size_t)(x0 + u) * g.kx + jx];   // zero rows past nx
+    }
+#pragma unroll
+    for (int u = 0; u < kU; u += 2) {
+      cmac_conj(a0, hv[u], tv[u]);
+      cmac_conj(a1, hv[u + 1], tv[u + 1]);
+    }
+  }
+  P[(size_t)r * g.kx + jx] = make_float2(a0.x + a1.x, a0.y + a1.y);
 }
 
 // ---------------------------------------------------------------------------- band kernels
-__device__ __forceinline__ void band_index(const Geo& g, int64_t b, int& jx, int& jy, int& jz) {
-  jx = (int)(b % g.kx);
-  const int64_t r = b / g.kx;
-  jy = (int)(r % g.ky);
-  jz = (int)(r / g.ky);
+__device__ __forceinline__ void band_index(const Geo& g, int b, int& jx, int& jy, int& jz) {
+  const int r = b / g.kx;
+  jx = b - r * g.kx;
+  jz = r / g.ky;
+  jy = r - jz * g.ky;
 }
 __device__ __forceinline__ bool unpaired(const Geo& g, int jx, int jy, int jz) {
   return jx == 0 || jy == 0 || (g.kz > 1 && jz == 0);
 }
-__device__ __forceinline__ int64_t mirror(const Geo& g, int jx, int jy, int jz) {
+__device__ __forceinline__ int mirror(const Geo& g, int jx, int jy, int jz) {
   const int mx = g.kx - jx, my = g.ky - jy, mz = g.kz > 1 ? g.kz - jz : 0;
-  return ((int64_t)mz * g.ky + my) * g.kx + mx;
+  return (mz * g.ky + my) * g.kx + mx;
 }
 
+template <int DIM>
 __global__ __launch_bounds__(256) void k_band_prep(Geo g, const float2* __restrict__ raw,
                                                    float2* __restrict__ out, int with_div,
                                                    const double* __restrict__ Lhat64,
                                                    double* __restrict__ reg_partial) {
   __shared__ double sh[256];
   double acc = 0.0;
-  for (int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x; b < g.B;
-       b += (int64_t)gridDim.x * 256) {
+  const int B = (int)g.B;
+  for (int b = blockIdx.x * 256 + threadIdx.x; b < B; b += gridDim.x * 256) {
     int jx, jy, jz;
     band_index(g, b, jx, jy, jz);
     const bool up = unpaired(g, jx, jy, jz);
-    const int64_t mb = up ? b : mirror(g, jx, jy, jz);
-    float2 o[3];
-    for (int c = 0; c < g.dim; ++c) {
-      if (up) {
-        o[c] = make_float2(0.f, 0.f);
-      } else {
-        const float2 a = raw[c * g.B + b], m = raw[c * g.B + mb];
-        o[c] = make_float2(0.5f * (a.x + m.x), 0.5f * (a.y - m.y));
-      }
-      out[c * g.B + b] = o[c];
-      if (reg_partial) acc += Lhat64[b] * ((double)o[c].x * o[c].x + (double)o[c].y * o[c].y);
+    const int mb = up ? b : mirror(g, jx, jy, jz);
+    float2 a[DIM], m[DIM], o[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      a[c] = raw[c * B + b];
+      m[c] = raw[c * B + mb];
+    }
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      o[c] = up ? make_float2(0.f, 0.f)
+                : make_float2(0.5f * (a[c].x + m[c].x), 0.5f * (a[c].y - m[c].y));
+      out[c * B + b] = o[c];
+    }
+    if (reg_partial) {
+      const double l = Lhat64[b];
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) acc += l * ((double)o[c].x * o[c].x + (double)o[c].y * o[c].y);
     }
     if (with_div) {
       // r~ = sum_c 2 pi i (k_c / l_c) v~_c with l_c = n_c / N_ref
@@ -220,12 +345,13 @@ __global__ __launch_bounds__(256) void k_band_prep(Geo g, const float2* __restri
       const int kv[3] = {jx - g.kx / 2, jy - g.ky / 2, jz - g.kz0};
       const int nn[3] = {g.nx, g.ny, g.nz};
       float2 d = make_float2(0.f, 0.f);
-      for (int c = 0; c < g.dim; ++c) {
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) {
         const float qc = two_pi * (float)kv[c] * ((float)g.nref / (float)nn[c]);
         d.x = fmaf(-qc, o[c].y, d.x);
         d.y = fmaf(qc, o[c].x, d.y);
       }
-      out[g.dim * g.B + b] = d;
+      out[DIM * B + b] = d;
     }
   }
   if (reg_partial) {
@@ -245,11 +371,11 @@ __global__ __launch_bounds__(256) void k_band_finalize(Geo g, int C,
                                                        const float2* __restrict__ P,
                                                        float scale, float2* __restrict__ out,
                                                        int* __restrict__ nonfinite) {
-  const int64_t total = (int64_t)C * g.B;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * 256) {
-    const int c = (int)(i / g.B);
-    const int64_t b = i - (int64_t)c * g.B;
+  const int B = (int)g.B;
+  const int total = C * B;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < total; i += gridDim.x * 256) {
+    const int c = i / B;
+    const int b = i - c * B;
     int jx, jy, jz;
     band_index(g, b, jx, jy, jz);
     float2 o = make_float2(0.f, 0.f);
@@ -271,7 +397,7 @@ __global__ __launch_bounds__(256) void k_band_finalize(Geo g, int C,
       o = make_float2(scale * pv.x, scale * pv.y);
       if (vproj) {
         const float l = Lhat[b];
-        const float2 v = vproj[(size_t)c * g.B + b];
+        const float2 v = vproj[c * B + b];
         o.x = fmaf(l, v.x, o.x);
         o.y = fmaf(l, v.y, o.y);
       }
@@ -289,13 +415,14 @@ void launch_z_pair(const Geo& g, const DftPlan& p, const float2* F2, float* out,
     // split z into chunks so that a launch has enough blocks to fill the chip
     const int qblocks = (nq + 255) / 256;
     int nchunk = 1;
-    while (qblocks * nchunk * C < 2048 && nchunk < g.nz) nchunk *= 2;
-    const int zchunk = (g.nz + nchunk - 1) / nchunk;
+    while (qblocks * nchunk * C < 768 && nchunk * 16 < g.nz) nchunk *= 2;
+    const int zchunk = ((g.nz + nchunk - 1) / nchunk + 3) / 4 * 4;
     nchunk = (g.nz + zchunk - 1) / zchunk;
     hipLaunchKernelGGL(k_iota_z<KZH>, dim3(qblocks, nchunk, C), dim3(256), 0, s, g, F2,
-                       p.tw_z, out, zchunk);
+                       p.tw_zT, out, zchunk);
   } else {
-    hipLaunchKernelGGL(k_pi_z<KZH>, dim3((nq + 63) / 64, C), dim3(64, 4), 0, s, g, f, p.tw_z, G);
+    hipLaunchKernelGGL(k_pi_z<KZH>, dim3((nq + 63) / 64, C), dim3(64, kNW), 0, s, g, f,
+                       p.tw_zT, G);
   }
 }
 
@@ -303,6 +430,7 @@ void z_stage(const Geo& g, const DftPlan& p, const float2* F2, float* out, int C
              const float* f, float2* G, hipStream_t s, bool inverse) {
   const int k = g.kzh;
   if (k <= 1) launch_z_pair<1>(g, p, F2, out, C, f, G, s, inverse);
+  else if (k <= 4) launch_z_pair<4>(g, p, F2, out, C, f, G, s, inverse);
   else if (k <= 8) launch_z_pair<8>(g, p, F2, out, C, f, G, s, inverse);
   else if (k <= 12) launch_z_pair<12>(g, p, F2, out, C, f, G, s, inverse);
   else if (k <= 16) launch_z_pair<16>(g, p, F2, out, C, f, G, s, inverse);
@@ -318,28 +446,42 @@ void z_stage(const Geo& g, const DftPlan& p, const float2* F2, float* out, int C
 void iota(const Geo& g, const DftPlan& p, const float2* band, int C, float* out, hipStream_t s) {
   const int xb = (g.nx + 63) / 64;
   hipLaunchKernelGGL(k_iota_x, dim3(xb, g.ky, C * g.kzh), dim3(64), 0, s, g, band, p.tw_x, p.bufA);
-  hipLaunchKernelGGL(k_iota_y, dim3(xb, g.ny, C * g.kzh), dim3(64), 0, s, g, p.bufA, p.tw_y, p.bufB);
+  hipLaunchKernelGGL(k_iota_y, dim3(xb, p.nyp / kYG, C * g.kzh), dim3(64), 0, s, g, p.bufA, p.tw_y,
+                     p.nyp, p.bufB);
   z_stage(g, p, p.bufB, out, C, nullptr, nullptr, s, true);
 }
 
 void pi_half(const Geo& g, const DftPlan& p, const float* grid, int C, float2* P, hipStream_t s) {
   const int xb = (g.nx + 63) / 64;
   z_stage(g, p, nullptr, nullptr, C, grid, p.bufA, s, false);
-  hipLaunchKernelGGL(k_pi_y, dim3(xb, g.ky, C * g.kzh), dim3(64), 0, s, g, p.bufA, p.tw_y, p.bufB);
-  hipLaunchKernelGGL(k_pi_x, dim3((g.kx + 63) / 64, g.ky, C * g.kzh), dim3(64), 0, s, g, p.bufB,
-                     p.tw_x, P);
+  const int yseg = ((g.ny + kYS - 1) / kYS + kUY - 1) / kUY * kUY;
+  hipLaunchKernelGGL(k_pi_y, dim3(xb, p.kyp / kJG, C * g.kzh), dim3(64, kYS), 0, s, g, p.bufA,
+                     p.tw_yT, p.kyp, yseg, p.bufB);
+  const int rows = C * g.kzh * g.ky;
+  hipLaunchKernelGGL(k_pi_x, dim3((rows * g.kx + 255) / 256), dim3(256), 0, s, g, rows, p.bufB,
+                     p.tw_xT, P);
 }
 
 void band_prep(const Geo& g, const float2* raw, float2* out, int with_div, const double* Lhat64,
                double* reg_partial, hipStream_t s) {
-  hipLaunchKernelGGL(k_band_prep, dim3(kRedBlocks), dim3(256), 0, s, g, raw, out, with_div,
-                     Lhat64, reg_partial);
+  // the regulariser sum needs the fixed kRedBlocks grid; the plain projection one thread per
+  // band entry
+  const int blocks = reg_partial ? kRedBlocks : (int)((g.B + 255) / 256);
+  if (g.dim == 3)
+    hipLaunchKernelGGL(k_band_prep<3>, dim3(blocks), dim3(256), 0, s, g, raw, out, with_div,
+                       Lhat64, reg_partial);
+  else if (g.dim == 2)
+    hipLaunchKernelGGL(k_band_prep<2>, dim3(blocks), dim3(256), 0, s, g, raw, out, with_div,
+                       Lhat64, reg_partial);
+  else
+    hipLaunchKernelGGL(k_band_prep<1>, dim3(blocks), dim3(256), 0, s, g, raw, out, with_div,
+                       Lhat64, reg_partial);
 }
 
 void band_finalize(const Geo& g, int C, const float2* vproj, const float* Lhat,
                    const float2* P, float scale, float2* out, int* nonfinite, hipStream_t s) {
-  const int64_t total = (int64_t)C * g.B;
-  const int blocks = (int)std::min<int64_t>(4096, (total + 255) / 256);
+  const int total = C * (int)g.B;
+  const int blocks = std::min(4096, (total + 255) / 256);
   hipLaunchKernelGGL(k_band_finalize, dim3(blocks), dim3(256), 0, s, g, C, vproj, Lhat, P,
                      scale, out, nonfinite);
 }

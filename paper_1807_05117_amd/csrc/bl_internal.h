@@ -25,10 +25,21 @@ struct Geo {
 };
 
 // Work buffers and twiddle tables of the band<->grid transforms.
+constexpr int kYG = 8;     // y outputs per thread in the iota y stage
+constexpr int kJG = 16;    // ky outputs per thread in the pi y stage
+constexpr int kZP = 64;    // padded row length of the z twiddle table
+constexpr int kU = 8;      // loads in flight per thread in the contraction loops
+constexpr int kUY = 16;    // loads in flight per thread in the pi y stage
+
+// Twiddle tables are zero-padded so that every chunk of kU loads stays in bounds:
+// padded extents: kx, nx rounded up to 8, ny to 16, ky to kJG, nz to 128.
 struct DftPlan {
-  float2* tw_x = nullptr;   // [kx][nx]  exp(+2 pi i kx x / nx), kx = j - Kx/2
-  float2* tw_y = nullptr;   // [ky][ny]
-  float2* tw_z = nullptr;   // [kzh][nz] exp(+2 pi i h z / nz), h = 0..kzh-1
+  float2* tw_x = nullptr;   // [kxp][nx]   exp(+2 pi i kx x / nx), kx = j - Kx/2; zero rows >= Kx
+  float2* tw_xT = nullptr;  // [nxp][kx]   the same, transposed; zero rows >= nx
+  float2* tw_y = nullptr;   // [kyp][nyp]  exp(+2 pi i ky y / ny); zero outside
+  float2* tw_yT = nullptr;  // [nyp][kyp]  the same, transposed
+  float2* tw_zT = nullptr;  // [nzp][kZP]  exp(+2 pi i h z / nz), h = 0..kzh-1; zero outside
+  int kxp = 0, nxp = 0, kyp = 0, nyp = 0, nzp = 0;
   float2* bufA = nullptr;   // stage buffers, each 4 * kzh * max(ky*nx, ny*nx) complex
   float2* bufB = nullptr;
   // split hi/lo bf16 twiddle operands of the mixed-precision path (nullptr in FP32 mode)
@@ -58,15 +69,16 @@ void setup(const Geo& g, const float* v, float* X, float* Y, float* a, hipStream
 void state_step(const Geo& g, const float* m_in, const float* X, float* m_out, hipStream_t s);
 void energy_partial(const Geo& g, const float* mT, const float* I1, double* partial,
                     hipStream_t s);
-void terminal(const Geo& g, const float* mT, const float* I1, float* lam, float* b, float w,
+void terminal(const Geo& g, const float* mT, const float* I1, float* lam, hipStream_t s);
+void adj_step(const Geo& g, const float* lam_in, const float* Y, const float* a, float* lam_out,
               hipStream_t s);
-void adj_step(const Geo& g, const float* lam_in, const float* Y, const float* a,
-              const float* m_n, float* lam_out, float* b, float w, hipStream_t s);
+// b_c = sum_n w_n lam^n d_c m^n over nt + 1 stored planes of lam and m
+void body_force(const Geo& g, const float* lam, const float* m, float* b, hipStream_t s);
 void inc_init(const Geo& g, const float* m0, const float* dv, float* t0, hipStream_t s);
 void inc_step(const Geo& g, const float* t_in, const float* X, const float* m_next,
               const float* dv, float* t_out, hipStream_t s);
 void inc_last(const Geo& g, const float* t_in, const float* X, const float* mT,
-              const float* dv, float* dlam, float* Hb, float w, hipStream_t s);
+              const float* dv, float* dlam, hipStream_t s);
 
 // ---- reductions and band vector algebra (bl_reduce.hip)
 // out[0] = sum of n partials in a fixed order (one block)

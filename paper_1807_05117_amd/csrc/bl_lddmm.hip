@@ -62,6 +62,8 @@ int validate(const bl_problem* p, bl::Geo* g) {
   }
   if (p->dim == 3 && k[2] > 2 * bl::kMaxKzh)
     return fail(BL_E_INVALID, "band size k[2] must be <= 128");
+  if ((int64_t)n[0] * n[1] * n[2] > (int64_t(1) << 30))
+    return fail(BL_E_INVALID, "grid must have at most 2^30 voxels");
   if (p->nt < 1 || p->nt > 256) return fail(BL_E_INVALID, "nt must be in [1, 256]");
   if (!std::isfinite(p->alpha) || p->alpha < 0) return fail(BL_E_INVALID, "alpha must be finite and >= 0");
   if (p->s < 0 || p->s > 8) return fail(BL_E_INVALID, "s must be in [0, 8]");
@@ -131,6 +133,7 @@ struct bl_ctx {
   float* DV = nullptr;     // dim planes
   float* T0 = nullptr;
   float* T1 = nullptr;
+  float* L = nullptr;      // (nt + 1) planes: adjoint or incremental adjoint
   float* Bf = nullptr;     // dim planes: body force
   // band vectors (complex)
   float2* braw = nullptr;  // up to 4 components of staging
@@ -169,9 +172,16 @@ size_t stage_elems(const bl::Geo& g) {
   return (size_t)4 * g.kzh * (size_t)std::max<int64_t>((int64_t)g.ky * g.nx, (int64_t)g.ny * g.nx);
 }
 
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+int nyp_of(const bl::Geo& g) { return round_up(g.ny, 16); }
+int kyp_of(const bl::Geo& g) { return round_up(g.ky, bl::kJG); }
+int kxp_of(const bl::Geo& g) { return round_up(g.kx, 8); }
+int nxp_of(const bl::Geo& g) { return round_up(g.nx, 8); }
+int nzp_of(const bl::Geo& g) { return round_up(g.nz, 128); }
+
 struct Offsets {
-  size_t I1, m, X, Y, A, V, DV, T0, T1, Bf, braw, bv, bd, bout, P, Lhat, Lhat64, tw_x, tw_y,
-      tw_z, bufA, bufB, red, scal, flag, solver;
+  size_t I1, m, X, Y, A, V, DV, T0, T1, L, Bf, braw, bv, bd, bout, P, Lhat, Lhat64, tw_x, tw_xT,
+      tw_y, tw_yT, tw_zT, bufA, bufB, red, scal, flag, solver;
   size_t total;
 };
 
@@ -190,6 +200,7 @@ Offsets plan_layout(const bl::Geo& g, bool transport, bool solver) {
     o.DV = L.take(pb * d);
     o.T0 = L.take(pb);
     o.T1 = L.take(pb);
+    o.L = L.take(pb * (g.nt + 1));
     o.Bf = L.take(pb * d);
   } else {
     o.V = L.take(pb * 4);
@@ -201,9 +212,11 @@ Offsets plan_layout(const bl::Geo& g, bool transport, bool solver) {
   o.P = L.take((size_t)4 * g.kzh * g.ky * g.kx * sizeof(float2));
   o.Lhat = L.take((size_t)g.B * sizeof(float));
   o.Lhat64 = L.take((size_t)g.B * sizeof(double));
-  o.tw_x = L.take((size_t)g.kx * g.nx * sizeof(float2));
-  o.tw_y = L.take((size_t)g.ky * g.ny * sizeof(float2));
-  o.tw_z = L.take((size_t)bl::kMaxKzh * g.nz * sizeof(float2));
+  o.tw_x = L.take((size_t)kxp_of(g) * g.nx * sizeof(float2));
+  o.tw_xT = L.take((size_t)nxp_of(g) * g.kx * sizeof(float2));
+  o.tw_y = L.take((size_t)kyp_of(g) * nyp_of(g) * sizeof(float2));
+  o.tw_yT = L.take((size_t)nyp_of(g) * kyp_of(g) * sizeof(float2));
+  o.tw_zT = L.take((size_t)bl::kZP * nzp_of(g) * sizeof(float2));
   o.bufA = L.take(stage_elems(g) * sizeof(float2));
   o.bufB = L.take(stage_elems(g) * sizeof(float2));
   o.red = L.take((size_t)RED_SLOTS * bl::kRedBlocks * sizeof(double));
@@ -214,18 +227,27 @@ Offsets plan_layout(const bl::Geo& g, bool transport, bool solver) {
   return o;
 }
 
-void twiddles(std::vector<float2>& t, int rows, int K, int N, bool centred) {
-  t.assign((size_t)rows * N, make_float2(0.f, 0.f));
+// exp(+2 pi i k x / N) for centred (k = j - K/2) or plain (k = j) frequency indices, from the
+// exactly reduced angle 2 pi ((k x) mod N) / N in FP64.
+float2 twiddle(int j, int K, int x, int N, bool centred) {
   const double two_pi = 6.283185307179586476925286766559;
-  for (int j = 0; j < K; ++j) {
-    const long long k = centred ? (long long)j - K / 2 : j;
+  const long long k = centred ? (long long)j - K / 2 : j;
+  long long r = (k * x) % N;
+  if (r < 0) r += N;
+  const double ang = two_pi * (double)r / (double)N;
+  return make_float2((float)std::cos(ang), (float)std::sin(ang));
+}
+
+// table[row][col] with `rows` x `cols` entries, zero outside j < K, x < N; transposed tables
+// index [x][j].
+void twiddles(std::vector<float2>& t, int rows, int cols, int K, int N, bool centred,
+              bool transposed) {
+  t.assign((size_t)rows * cols, make_float2(0.f, 0.f));
+  for (int j = 0; j < K; ++j)
     for (int x = 0; x < N; ++x) {
-      long long r = (k * x) % N;
-      if (r < 0) r += N;
-      const double ang = two_pi * (double)r / (double)N;
-      t[(size_t)j * N + x] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+      const size_t i = transposed ? (size_t)x * cols + j : (size_t)j * cols + x;
+      t[i] = twiddle(j, K, x, N, centred);
     }
-  }
 }
 
 void destroy_ctx(bl_ctx* c) {
@@ -265,13 +287,16 @@ bl_ctx* create_ctx(const bl_problem* prob, const bl::Geo& g, bool transport, boo
     auto C2 = [&](size_t off) { return reinterpret_cast<float2*>(a + off); };
     if (transport) {
       c->I1 = F(o.I1); c->m = F(o.m); c->X = F(o.X); c->Y = F(o.Y); c->A = F(o.A);
-      c->DV = F(o.DV); c->T0 = F(o.T0); c->T1 = F(o.T1); c->Bf = F(o.Bf);
+      c->DV = F(o.DV); c->T0 = F(o.T0); c->T1 = F(o.T1); c->L = F(o.L); c->Bf = F(o.Bf);
     }
     c->V = F(o.V);
     c->braw = C2(o.braw); c->bv = C2(o.bv); c->bd = C2(o.bd); c->bout = C2(o.bout); c->P = C2(o.P);
     c->Lhat = F(o.Lhat);
     c->Lhat64 = reinterpret_cast<double*>(a + o.Lhat64);
-    c->plan.tw_x = C2(o.tw_x); c->plan.tw_y = C2(o.tw_y); c->plan.tw_z = C2(o.tw_z);
+    c->plan.tw_x = C2(o.tw_x); c->plan.tw_xT = C2(o.tw_xT);
+    c->plan.tw_y = C2(o.tw_y); c->plan.tw_yT = C2(o.tw_yT); c->plan.tw_zT = C2(o.tw_zT);
+    c->plan.nyp = nyp_of(g); c->plan.kyp = kyp_of(g); c->plan.kxp = kxp_of(g);
+    c->plan.nxp = nxp_of(g); c->plan.nzp = nzp_of(g);
     c->plan.bufA = C2(o.bufA); c->plan.bufB = C2(o.bufB);
     c->plan.mixed = prob->precision == BL_MIXED;
     c->red = reinterpret_cast<double*>(a + o.red);
@@ -286,15 +311,20 @@ bl_ctx* create_ctx(const bl_problem* prob, const bl::Geo& g, bool transport, boo
     HIP_TRY(hipHostMalloc((void**)&c->hscal, 64 * sizeof(double), hipHostMallocDefault));
     // host tables: twiddles of exactly reduced angles, the symbol of L
     std::vector<float2> tw;
-    twiddles(tw, g.kx, g.kx, g.nx, true);
-    HIP_TRY(hipMemcpyAsync(c->plan.tw_x, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    twiddles(tw, g.ky, g.ky, g.ny, true);
-    HIP_TRY(hipMemcpyAsync(c->plan.tw_y, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    twiddles(tw, bl::kMaxKzh, g.kzh, g.nz, false);
-    HIP_TRY(hipMemcpyAsync(c->plan.tw_z, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    auto upload = [&](float2* dst) {
+      HIP_TRY(hipMemcpyAsync(dst, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice, c->stream));
+      HIP_TRY(hipStreamSynchronize(c->stream));
+    };
+    twiddles(tw, c->plan.kxp, g.nx, g.kx, g.nx, true, false);
+    upload(c->plan.tw_x);
+    twiddles(tw, c->plan.nxp, g.kx, g.kx, g.nx, true, true);
+    upload(c->plan.tw_xT);
+    twiddles(tw, c->plan.kyp, c->plan.nyp, g.ky, g.ny, true, false);
+    upload(c->plan.tw_y);
+    twiddles(tw, c->plan.nyp, c->plan.kyp, g.ky, g.ny, true, true);
+    upload(c->plan.tw_yT);
+    twiddles(tw, c->plan.nzp, bl::kZP, g.kzh, g.nz, false, true);
+    upload(c->plan.tw_zT);
     std::vector<double> L64((size_t)g.B);
     std::vector<float> L32((size_t)g.B);
     const double four_pi2 = 39.478417604357434;
@@ -357,8 +387,6 @@ void t_collect(bl_ctx* c) {
 }
 
 // ------------------------------------------------------------------------------ operators
-float trap_w(const bl::Geo& g, int n) { return (n == 0 || n == g.nt) ? 0.5f * g.dt : g.dt; }
-
 double read_scalars(bl_ctx* c, int n) {
   HIP_TRY(hipMemcpyAsync(c->hscal, c->scal, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   sync(c);
@@ -394,20 +422,26 @@ void op_set_velocity(bl_ctx* c, const float2* vraw) {
   if (!std::isfinite(c->E)) throw NonFinite{"energy"};
 }
 
+// backward transport of L[nt] down to L[0], then the body force b = sum_n w_n L[n] grad m^n
+void backward_and_body_force(bl_ctx* c) {
+  const bl::Geo& g = c->g;
+  hipStream_t s = c->stream;
+  const size_t M = (size_t)g.M;
+  for (int n = g.nt - 1; n >= 0; --n) {
+    if (c->timing) t_begin(c, 2);
+    bl::adj_step(g, c->L + (n + 1) * M, c->Y, c->A, c->L + n * M, s);
+    if (c->timing) t_end(c, 2);
+  }
+  bl::body_force(g, c->L, c->m, c->Bf, s);
+}
+
 // gradient at the current velocity into gout (device, dim components)
 void op_gradient(bl_ctx* c, float2* gout) {
   const bl::Geo& g = c->g;
   hipStream_t s = c->stream;
   const size_t M = (size_t)g.M;
-  bl::terminal(g, c->m + g.nt * M, c->I1, c->T0, c->Bf, trap_w(g, g.nt), s);
-  float* lin = c->T0;
-  float* lout = c->T1;
-  for (int n = g.nt - 1; n >= 0; --n) {
-    if (c->timing) t_begin(c, 2);
-    bl::adj_step(g, lin, c->Y, c->A, c->m + n * M, lout, c->Bf, trap_w(g, n), s);
-    if (c->timing) t_end(c, 2);
-    std::swap(lin, lout);
-  }
+  bl::terminal(g, c->m + g.nt * M, c->I1, c->L + g.nt * M, s);
+  backward_and_body_force(c);
   bl::pi_half(g, c->plan, c->Bf, g.dim, c->P, s);
   bl::band_finalize(g, g.dim, c->bv, c->Lhat, c->P, (float)(1.0 / (double)g.M), gout, c->flag, s);
   check_launch("gradient");
@@ -429,15 +463,8 @@ void op_hessvec(bl_ctx* c, const float2* draw, float2* hout) {
     if (c->timing) t_end(c, 1);
     std::swap(tin, tout);
   }
-  bl::inc_last(g, tin, c->X, c->m + g.nt * M, c->DV, tout, c->Bf, trap_w(g, g.nt), s);
-  float* lin = tout;
-  float* lout = tin;
-  for (int n = g.nt - 1; n >= 0; --n) {
-    if (c->timing) t_begin(c, 2);
-    bl::adj_step(g, lin, c->Y, c->A, c->m + n * M, lout, c->Bf, trap_w(g, n), s);
-    if (c->timing) t_end(c, 2);
-    std::swap(lin, lout);
-  }
+  bl::inc_last(g, tin, c->X, c->m + g.nt * M, c->DV, c->L + g.nt * M, s);
+  backward_and_body_force(c);
   bl::pi_half(g, c->plan, c->Bf, g.dim, c->P, s);
   bl::band_finalize(g, g.dim, c->bd, c->Lhat, c->P, (float)(1.0 / (double)g.M), hout, c->flag, s);
   check_launch("hessvec");

@@ -8,7 +8,7 @@
 //   Y = +(u + Interp(u, i + u)) / 2         backward characteristic (Heun)
 //   a = 1 + dt/2 [R + (1 + dt R) r],  R = Interp(r, i + Y),  r = div v
 //   m^{n+1} = Interp(m^n, i + X)
-//   lambda^n = a Interp(lambda^{n+1}, i + Y),  b += w_n lambda^n grad m^n
+//   lambda^n = a Interp(lambda^{n+1}, i + Y),  b = sum_n w_n lambda^n grad m^n
 //   t^0 = dt/2 f^0, t^{n+1} = Interp(t^n, i + X) + dt f^{n+1},
 //   dm^Nt = Interp(t^{Nt-1}, i + X) + dt/2 f^Nt,  f^n = -grad m^n . dv
 // with periodic d-linear interpolation, central differences grad f = (f(i+e) - f(i-e)) N_ref/2
@@ -41,9 +41,11 @@ __device__ __forceinline__ void split(float o, int base, int n, int& i0, int& i1
   i1 = (i0 + 1 == n) ? 0 : i0 + 1;
 }
 
+// All in-volume indices are 32-bit (the host guarantees prod(n) <= 2^30); plane offsets are
+// applied to the base pointers.
 template <int DIM>
 struct Tap {
-  size_t r00, r01, r10, r11;  // row starts (z0,y0) (z0,y1) (z1,y0) (z1,y1)
+  uint32_t r00, r01, r10, r11;  // row starts (z0,y0) (z0,y1) (z1,y0) (z1,y1)
   int x0, x1;
   float wx, wy, wz;
 };
@@ -58,14 +60,14 @@ __device__ __forceinline__ Tap<DIM> make_tap(const Geo& g, int x, int y, int z, 
   if (DIM == 3) {
     int z0, z1;
     split(oz, z, g.nz, z0, z1, t.wz);
-    t.r00 = ((size_t)z0 * g.ny + y0) * g.nx;
-    t.r01 = ((size_t)z0 * g.ny + y1) * g.nx;
-    t.r10 = ((size_t)z1 * g.ny + y0) * g.nx;
-    t.r11 = ((size_t)z1 * g.ny + y1) * g.nx;
+    t.r00 = ((uint32_t)z0 * g.ny + y0) * g.nx;
+    t.r01 = ((uint32_t)z0 * g.ny + y1) * g.nx;
+    t.r10 = ((uint32_t)z1 * g.ny + y0) * g.nx;
+    t.r11 = ((uint32_t)z1 * g.ny + y1) * g.nx;
   } else {
     t.wz = 0.0f;
-    t.r00 = (size_t)y0 * g.nx;
-    t.r01 = (size_t)y1 * g.nx;
+    t.r00 = (uint32_t)y0 * g.nx;
+    t.r01 = (uint32_t)y1 * g.nx;
     t.r10 = t.r00;
     t.r11 = t.r01;
   }
@@ -91,28 +93,44 @@ __device__ __forceinline__ float apply(const float* __restrict__ f, const Tap<DI
 // Central differences of f at voxel (x, y, z), scaled by N_ref / 2.
 template <int DIM>
 __device__ __forceinline__ void grad_c(const Geo& g, const float* __restrict__ f, int x, int y,
-                                       int z, size_t p, float* gr) {
+                                       int z, uint32_t p, float* gr) {
   const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x + 1 == g.nx ? 0 : x + 1;
-  const size_t row = p - x;
+  const uint32_t row = p - x;
   gr[0] = (f[row + xp] - f[row + xm]) * g.half_nref;
-  const size_t sy = g.nx;
-  const size_t pym = y == 0 ? p + (size_t)(g.ny - 1) * sy : p - sy;
-  const size_t pyp = y + 1 == g.ny ? p - (size_t)(g.ny - 1) * sy : p + sy;
+  const uint32_t sy = g.nx;
+  const uint32_t pym = y == 0 ? p + (uint32_t)(g.ny - 1) * sy : p - sy;
+  const uint32_t pyp = y + 1 == g.ny ? p - (uint32_t)(g.ny - 1) * sy : p + sy;
   gr[1] = (f[pyp] - f[pym]) * g.half_nref;
   if (DIM == 3) {
-    const size_t sz = (size_t)g.nx * g.ny;
-    const size_t pzm = z == 0 ? p + (size_t)(g.nz - 1) * sz : p - sz;
-    const size_t pzp = z + 1 == g.nz ? p - (size_t)(g.nz - 1) * sz : p + sz;
+    const uint32_t sz = (uint32_t)g.nx * g.ny;
+    const uint32_t pzm = z == 0 ? p + (uint32_t)(g.nz - 1) * sz : p - sz;
+    const uint32_t pzp = z + 1 == g.nz ? p - (uint32_t)(g.nz - 1) * sz : p + sz;
     gr[2] = (f[pzp] - f[pzm]) * g.half_nref;
   }
 }
+
+// Kernels that take ZV voxels per thread along z: z is clamped to the grid so that every load
+// stays in bounds and the ZV voxels' loads can be issued together; only the stores are
+// guarded.
+#define VOXEL_XY                                         \
+  const int x = blockIdx.x * BX + threadIdx.x;           \
+  const int y = blockIdx.y * BY + threadIdx.y;           \
+  if (x >= g.nx || y >= g.ny) return;                    \
+  const size_t M = (size_t)g.M;                          \
+  (void)M;
+#define VOXEL_Z(zz)                                      \
+  const int zr = blockIdx.z * ZV + (zz);                 \
+  const int z = zr < g.nz ? zr : g.nz - 1;               \
+  const bool live = zr < g.nz;                           \
+  const uint32_t p = ((uint32_t)z * g.ny + y) * g.nx + x;\
+  (void)live;
 
 #define VOXEL_PROLOGUE                                   \
   const int x = blockIdx.x * BX + threadIdx.x;           \
   const int y = blockIdx.y * BY + threadIdx.y;           \
   const int z = blockIdx.z;                              \
   if (x >= g.nx || y >= g.ny) return;                    \
-  const size_t p = ((size_t)z * g.ny + y) * g.nx + x;    \
+  const uint32_t p = ((uint32_t)z * g.ny + y) * g.nx + x; \
   const size_t M = (size_t)g.M;                          \
   (void)M;
 
@@ -145,49 +163,65 @@ __global__ __launch_bounds__(BX* BY) void k_setup(Geo g, const float* __restrict
   A[p] = 1.0f + 0.5f * g.dt * (R + (1.0f + g.dt * R) * ri);
 }
 
-template <int DIM>
+template <int DIM, int ZV>
 __global__ __launch_bounds__(BX* BY) void k_state_step(Geo g, const float* __restrict__ m_in,
                                                        const float* __restrict__ X,
                                                        float* __restrict__ m_out) {
-  VOXEL_PROLOGUE
-  const float ox = X[p], oy = X[M + p], oz = DIM == 3 ? X[2 * M + p] : 0.f;
-  m_out[p] = apply<DIM>(m_in, make_tap<DIM>(g, x, y, z, ox, oy, oz));
+  VOXEL_XY
+#pragma unroll
+  for (int zz = 0; zz < ZV; ++zz) {
+    VOXEL_Z(zz)
+    const float ox = X[p], oy = X[M + p], oz = DIM == 3 ? X[2 * M + p] : 0.f;
+    const float v = apply<DIM>(m_in, make_tap<DIM>(g, x, y, z, ox, oy, oz));
+    if (live) m_out[p] = v;
+  }
 }
 
 template <int DIM>
 __global__ __launch_bounds__(BX* BY) void k_terminal(Geo g, const float* __restrict__ mT,
                                                      const float* __restrict__ I1,
-                                                     float* __restrict__ lam,
-                                                     float* __restrict__ b, float w) {
+                                                     float* __restrict__ lam) {
   VOXEL_PROLOGUE
-  const float l = g.lam_scale * (mT[p] - I1[p]);
-  lam[p] = l;
-  float gr[3];
-  grad_c<DIM>(g, mT, x, y, z, p, gr);
-  for (int c = 0; c < DIM; ++c) b[c * M + p] = w * l * gr[c];
+  lam[p] = g.lam_scale * (mT[p] - I1[p]);
 }
 
-template <int DIM>
+template <int DIM, int ZV>
 __global__ __launch_bounds__(BX* BY) void k_adj_step(Geo g, const float* __restrict__ lam_in,
                                                      const float* __restrict__ Y,
                                                      const float* __restrict__ A,
-                                                     const float* __restrict__ m_n,
-                                                     float* __restrict__ lam_out,
-                                                     float* __restrict__ b, float w) {
+                                                     float* __restrict__ lam_out) {
+  VOXEL_XY
+#pragma unroll
+  for (int zz = 0; zz < ZV; ++zz) {
+    VOXEL_Z(zz)
+    const float ox = Y[p], oy = Y[M + p], oz = DIM == 3 ? Y[2 * M + p] : 0.f;
+    const float v = A[p] * apply<DIM>(lam_in, make_tap<DIM>(g, x, y, z, ox, oy, oz));
+    if (live) lam_out[p] = v;
+  }
+}
+
+// b = sum_n w_n lambda^n grad m^n over the stored adjoint and state planes (trapezoid in
+// time), one pass after the backward transport.
+template <int DIM>
+__global__ __launch_bounds__(BX* BY) void k_body_force(Geo g, const float* __restrict__ lam,
+                                                       const float* __restrict__ m,
+                                                       float* __restrict__ b) {
   VOXEL_PROLOGUE
-  const float ox = Y[p], oy = Y[M + p], oz = DIM == 3 ? Y[2 * M + p] : 0.f;
-  const float l = A[p] * apply<DIM>(lam_in, make_tap<DIM>(g, x, y, z, ox, oy, oz));
-  lam_out[p] = l;
-  float gr[3];
-  grad_c<DIM>(g, m_n, x, y, z, p, gr);
-  const float wl = w * l;
-  for (int c = 0; c < DIM; ++c) b[c * M + p] = fmaf(wl, gr[c], b[c * M + p]);
+  float acc[3] = {0.f, 0.f, 0.f};
+  for (int n = 0; n <= g.nt; ++n) {
+    const float w = (n == 0 || n == g.nt) ? 0.5f * g.dt : g.dt;
+    float gr[3];
+    grad_c<DIM>(g, m + (size_t)n * M, x, y, z, p, gr);
+    const float wl = w * lam[(size_t)n * M + p];
+    for (int c = 0; c < DIM; ++c) acc[c] = fmaf(wl, gr[c], acc[c]);
+  }
+  for (int c = 0; c < DIM; ++c) b[c * M + p] = acc[c];
 }
 
 template <int DIM>
 __device__ __forceinline__ float source_f(const Geo& g, const float* __restrict__ m,
                                           const float* __restrict__ dv, int x, int y, int z,
-                                          size_t p) {
+                                          uint32_t p) {
   float gr[3];
   grad_c<DIM>(g, m, x, y, z, p, gr);
   const size_t M = (size_t)g.M;
@@ -205,16 +239,21 @@ __global__ __launch_bounds__(BX* BY) void k_inc_init(Geo g, const float* __restr
   t0[p] = 0.5f * g.dt * source_f<DIM>(g, m0, dv, x, y, z, p);
 }
 
-template <int DIM>
+template <int DIM, int ZV>
 __global__ __launch_bounds__(BX* BY) void k_inc_step(Geo g, const float* __restrict__ t_in,
                                                      const float* __restrict__ X,
                                                      const float* __restrict__ m_next,
                                                      const float* __restrict__ dv,
                                                      float* __restrict__ t_out) {
-  VOXEL_PROLOGUE
-  const float ox = X[p], oy = X[M + p], oz = DIM == 3 ? X[2 * M + p] : 0.f;
-  const float tr = apply<DIM>(t_in, make_tap<DIM>(g, x, y, z, ox, oy, oz));
-  t_out[p] = fmaf(g.dt, source_f<DIM>(g, m_next, dv, x, y, z, p), tr);
+  VOXEL_XY
+#pragma unroll
+  for (int zz = 0; zz < ZV; ++zz) {
+    VOXEL_Z(zz)
+    const float ox = X[p], oy = X[M + p], oz = DIM == 3 ? X[2 * M + p] : 0.f;
+    const float tr = apply<DIM>(t_in, make_tap<DIM>(g, x, y, z, ox, oy, oz));
+    const float v = fmaf(g.dt, source_f<DIM>(g, m_next, dv, x, y, z, p), tr);
+    if (live) t_out[p] = v;
+  }
 }
 
 template <int DIM>
@@ -222,17 +261,12 @@ __global__ __launch_bounds__(BX* BY) void k_inc_last(Geo g, const float* __restr
                                                      const float* __restrict__ X,
                                                      const float* __restrict__ mT,
                                                      const float* __restrict__ dv,
-                                                     float* __restrict__ dlam,
-                                                     float* __restrict__ Hb, float w) {
+                                                     float* __restrict__ dlam) {
   VOXEL_PROLOGUE
   const float ox = X[p], oy = X[M + p], oz = DIM == 3 ? X[2 * M + p] : 0.f;
   const float tr = apply<DIM>(t_in, make_tap<DIM>(g, x, y, z, ox, oy, oz));
   const float dm = fmaf(0.5f * g.dt, source_f<DIM>(g, mT, dv, x, y, z, p), tr);
-  const float l = g.lam_scale * dm;
-  dlam[p] = l;
-  float gr[3];
-  grad_c<DIM>(g, mT, x, y, z, p, gr);
-  for (int c = 0; c < DIM; ++c) Hb[c * M + p] = w * l * gr[c];
+  dlam[p] = g.lam_scale * dm;
 }
 
 // Deterministic partial sums of (mT - I1)^2: a fixed grid of kRedBlocks blocks, each thread
@@ -256,7 +290,9 @@ __global__ __launch_bounds__(256) void k_energy_partial(int64_t n, const float* 
   if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
 }
 
-inline dim3 vox_grid(const Geo& g) { return dim3((g.nx + BX - 1) / BX, (g.ny + BY - 1) / BY, g.nz); }
+inline dim3 vox_grid(const Geo& g, int zv = 1) {
+  return dim3((g.nx + BX - 1) / BX, (g.ny + BY - 1) / BY, (g.nz + zv - 1) / zv);
+}
 inline dim3 vox_block() { return dim3(BX, BY, 1); }
 
 }  // namespace
@@ -269,30 +305,41 @@ inline dim3 vox_block() { return dim3(BX, BY, 1); }
       hipLaunchKernelGGL(KERNEL<2>, vox_grid(g), vox_block(), 0, s, __VA_ARGS__);   \
   } while (0)
 
+// two voxels per thread along z in 3D, one in 2D
+#define DISPATCH_ZV(KERNEL, ...)                                                          \
+  do {                                                                                    \
+    if (g.dim == 3)                                                                       \
+      hipLaunchKernelGGL((KERNEL<3, 2>), vox_grid(g, 2), vox_block(), 0, s, __VA_ARGS__); \
+    else                                                                                  \
+      hipLaunchKernelGGL((KERNEL<2, 1>), vox_grid(g, 1), vox_block(), 0, s, __VA_ARGS__); \
+  } while (0)
+
 void setup(const Geo& g, const float* v, float* X, float* Y, float* a, hipStream_t s) {
   DISPATCH(k_setup, g, v, X, Y, a);
 }
 void state_step(const Geo& g, const float* m_in, const float* X, float* m_out, hipStream_t s) {
-  DISPATCH(k_state_step, g, m_in, X, m_out);
+  DISPATCH_ZV(k_state_step, g, m_in, X, m_out);
 }
-void terminal(const Geo& g, const float* mT, const float* I1, float* lam, float* b, float w,
+void terminal(const Geo& g, const float* mT, const float* I1, float* lam, hipStream_t s) {
+  DISPATCH(k_terminal, g, mT, I1, lam);
+}
+void adj_step(const Geo& g, const float* lam_in, const float* Y, const float* a, float* lam_out,
               hipStream_t s) {
-  DISPATCH(k_terminal, g, mT, I1, lam, b, w);
+  DISPATCH_ZV(k_adj_step, g, lam_in, Y, a, lam_out);
 }
-void adj_step(const Geo& g, const float* lam_in, const float* Y, const float* a,
-              const float* m_n, float* lam_out, float* b, float w, hipStream_t s) {
-  DISPATCH(k_adj_step, g, lam_in, Y, a, m_n, lam_out, b, w);
+void body_force(const Geo& g, const float* lam, const float* m, float* b, hipStream_t s) {
+  DISPATCH(k_body_force, g, lam, m, b);
 }
 void inc_init(const Geo& g, const float* m0, const float* dv, float* t0, hipStream_t s) {
   DISPATCH(k_inc_init, g, m0, dv, t0);
 }
 void inc_step(const Geo& g, const float* t_in, const float* X, const float* m_next,
               const float* dv, float* t_out, hipStream_t s) {
-  DISPATCH(k_inc_step, g, t_in, X, m_next, dv, t_out);
+  DISPATCH_ZV(k_inc_step, g, t_in, X, m_next, dv, t_out);
 }
 void inc_last(const Geo& g, const float* t_in, const float* X, const float* mT,
-              const float* dv, float* dlam, float* Hb, float w, hipStream_t s) {
-  DISPATCH(k_inc_last, g, t_in, X, mT, dv, dlam, Hb, w);
+              const float* dv, float* dlam, hipStream_t s) {
+  DISPATCH(k_inc_last, g, t_in, X, mT, dv, dlam);
 }
 void energy_partial(const Geo& g, const float* mT, const float* I1, double* partial,
                     hipStream_t s) {

@@ -112,9 +112,9 @@ def test_footprint_scales_with_problem(lib):
     small = lib.bl_lddmm_footprint(C.byref(_p()))
     c2 = lib.bl_lddmm_footprint(C.byref(B.make_problem(3, (128,) * 3, (32,) * 3, 10)))
     assert small > 0 and c2 > 100 * small
-    # (nt + 1) state planes + 2 * dim offsets + reaction + 2 * (dim + 1) + 2 + dim fields
+    # (nt + 1) state and adjoint planes, offsets, reaction, velocity, ping-pong, body force
     M = 128 ** 3
-    assert c2 >= (11 + 3 + 3 + 1 + 4 + 3 + 2 + 3 + 1) * 4 * M
+    assert c2 >= (11 + 11 + 3 + 3 + 1 + 4 + 3 + 2 + 3 + 1) * 4 * M
 
 
 def test_default_opts(lib):

@@ -211,3 +211,28 @@ def test_nonfinite_input_reported(gpu_lib):
     with pytest.raises(B.BLError) as e:
         B.bl_lddmm_gradient(bl_problem(prob), I0, bad, vh)
     assert e.value.code == B.BL_E_NONFINITE
+
+
+def test_device_pointer_mode_matches_host_mode(gpu_lib):
+    """torch tensors and a torch stream through BL_DEVICE_PTRS give the host-mode results
+    bit for bit (same kernels, same launch configuration)."""
+    import torch
+
+    prob, I0, I1, vs, vh, dv = case("ragged_3d")
+    host = B.Ctx(bl_problem(prob), I0, I1)
+    Eh, gh = host.bl_lddmm_ctx_set_velocity(vh.astype(np.complex64))
+    Hh = host.bl_lddmm_ctx_hessvec(dv.astype(np.complex64))
+    host.close()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        p = bl_problem(prob, device=True, stream=stream.cuda_stream)
+        dI0 = torch.from_numpy(I0.astype(np.float32)).cuda()
+        dI1 = torch.from_numpy(I1.astype(np.float32)).cuda()
+        ctx = B.Ctx(p, dI0, dI1)
+        Ed, gd = ctx.bl_lddmm_ctx_set_velocity(torch.from_numpy(vh.astype(np.complex64)).cuda())
+        Hd = ctx.bl_lddmm_ctx_hessvec(torch.from_numpy(dv.astype(np.complex64)).cuda())
+        stream.synchronize()
+        ctx.close()
+    assert Ed == Eh
+    assert np.array_equal(gd.cpu().numpy(), gh)
+    assert np.array_equal(Hd.cpu().numpy(), Hh)
