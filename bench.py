@@ -62,11 +62,11 @@ def make_inputs(seed=0):
     return I0, I1, vs
 
 
-def gpu_leg(steps, warmup, n_hv=200):
+def gpu_leg(steps, warmup, n_hv=200, n_lat=50, n_grad=20, precision=B.BL_FP32, inputs=None):
     import torch
 
-    p = B.make_problem(3, GRID, BAND, NT)
-    I0, I1, vs = make_inputs(0)
+    p = B.make_problem(3, GRID, BAND, NT, precision=precision)
+    I0, I1, vs = inputs if inputs is not None else make_inputs(0)
     v0 = np.zeros_like(vs)
     progress("inputs ready; warmup")
     for _ in range(warmup):
@@ -86,7 +86,8 @@ def gpu_leg(steps, warmup, n_hv=200):
     # Hessian-vector products at a cached mid-optimisation state, device pointers on the
     # library's own context stream = torch's current stream
     stream = torch.cuda.current_stream()
-    pd = B.make_problem(3, GRID, BAND, NT, device=True, stream=stream.cuda_stream)
+    pd = B.make_problem(3, GRID, BAND, NT, device=True, stream=stream.cuda_stream,
+                        precision=precision)
     dI0 = torch.from_numpy(I0).cuda()
     dI1 = torch.from_numpy(I1).cuda()
     ctx = B.Ctx(pd, dI0, dI1)
@@ -107,7 +108,7 @@ def gpu_leg(steps, warmup, n_hv=200):
     hv_s = n_hv / (time.perf_counter() - t1)
     # latency: one product at a time, HIP events on the same stream
     hv_lat = []
-    for _ in range(50):
+    for _ in range(n_lat):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -117,10 +118,10 @@ def gpu_leg(steps, warmup, n_hv=200):
         hv_lat.append(e0.elapsed_time(e1))
     # gradients per second (set_velocity + gradient)
     t2 = time.perf_counter()
-    for _ in range(20):
+    for _ in range(n_grad):
         ctx.bl_lddmm_ctx_set_velocity(vh)
     torch.cuda.synchronize()
-    grad_s = 20 / (time.perf_counter() - t2)
+    grad_s = n_grad / (time.perf_counter() - t2)
     # per-kernel durations with HIP events on the context's stream
     ctx.bl_kernel_timing_enable(True)
     ctx.bl_lddmm_ctx_set_velocity(vh)
@@ -133,6 +134,9 @@ def gpu_leg(steps, warmup, n_hv=200):
         kern[k] = (n, ms)
     ctx.bl_kernel_timing_enable(False)
     ctx.close()
+    if precision != B.BL_FP32:
+        return dict(elapsed=elapsed, lat=lat, stats=stats, hv_s=hv_s, hv_lat=hv_lat,
+                    grad_s=grad_s, kern=kern, E=E, inputs=(I0, I1, vs), warped=warped)
     # achievable HBM bandwidth: a plain 1 GiB device-to-device copy (also the reference
     # kernel for scaling the FETCH_SIZE / WRITE_SIZE counters)
     src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -149,7 +153,7 @@ def gpu_leg(steps, warmup, n_hv=200):
     e1.synchronize()
     copy_gbs = 10 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) / 1000.0) / 1e9
     del src, dst
-    return dict(copy_gbs=copy_gbs, elapsed=elapsed, lat=lat, stats=stats, hv_s=hv_s, hv_lat=hv_lat, grad_s=grad_s,
+    return dict(copy_gbs=copy_gbs, inputs=(I0, I1, vs), warped=warped, elapsed=elapsed, lat=lat, stats=stats, hv_s=hv_s, hv_lat=hv_lat, grad_s=grad_s,
                 kern=kern, E=E)
 
 
@@ -188,12 +192,31 @@ def cpu_leg(stats):
             "hv_per_s": 1.0 / t_hv}
 
 
+def traffic_record(kernel):
+    """Per-launch HBM bytes of `kernel` from the committed counter summary, if it was taken on
+    the kernel source that is built now (else None)."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic_c2_128cube_fp32.json")
+    src = os.path.join(ROOT, "paper_1807_05117_amd", "csrc", "bl_transport.hip")
+    try:
+        rec = json.load(open(path))
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("transport_source_sha256") != digest or kernel not in rec.get("kernels", {}):
+        return None
+    return rec["kernels"][kernel]["bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
+    ap.add_argument("--quick", action="store_true",
+                    help="fewer Hessian-vector repetitions (for profiler passes)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the registration path has no multi-GPU mode "
@@ -203,7 +226,10 @@ def main():
     B.load()
     if not B.device_available():
         raise RuntimeError("no HIP device visible")
-    r = gpu_leg(args.steps, args.warmup)
+    reps = (20, 5, 2) if args.quick else (200, 50, 20)
+    r = gpu_leg(args.steps, args.warmup, *reps)
+    progress("mixed-precision form")
+    rm = gpu_leg(max(1, args.steps // 2), 1, *reps, precision=B.BL_MIXED, inputs=r["inputs"])
     ms_step = 1000.0 * r["elapsed"] / args.steps
     value = 60000.0 / ms_step
     M = GRID[0] * GRID[1] * GRID[2]
@@ -246,8 +272,17 @@ def main():
         "kernels": {KCLASS[k][0]: {"launches": r["kern"][k][0],
                                    "avg_us": 1000.0 * r["kern"][k][1] / max(r["kern"][k][0], 1)}
                     for k in r["kern"]},
+        "mixed": {"precision": "bf16 split hi/lo MFMA band<->grid z contractions, fp32 "
+                               "transports, fp64 reductions",
+                  "registrations_per_min": 60000.0 / (1000.0 * rm["elapsed"] / max(1, args.steps // 2)),
+                  "hv_per_s": rm["hv_s"], "hv_p50_ms": percentile(rm["hv_lat"], 50),
+                  "hv_p99_ms": percentile(rm["hv_lat"], 99), "gradients_per_s": rm["grad_s"],
+                  "final_mse_rel": rm["stats"]["mse_rel"][-1],
+                  "final_mse_rel_fp32": r["stats"]["mse_rel"][-1],
+                  "warped_max_abs_diff_vs_fp32": float(np.abs(rm["warped"] - r["warped"]).max())},
         "roofline": {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic_record(name),
                      "bytes_per_voxel": bpv, "avg_launch_us": avg_s * 1e6,
                      "copy_gbs": r["copy_gbs"], "frac_of_copy": achieved / r["copy_gbs"]},
         "cpu_baseline": None,

@@ -74,7 +74,7 @@ extern "C" {
 
 typedef struct {
   int32_t dim;        /* 2 or 3                                                            */
-  int32_t n[3];       /* grid size per axis (x, y, z), 4 <= n[j] <= 2048, prod <= 2^30       */
+  int32_t n[3];       /* grid size per axis (x, y, z), 4 <= n[j] <= 2048, prod < 2^30        */
   int32_t k[3];       /* band size per axis, even, 2 <= k[j] <= n[j], k[2] <= 128             */
   int32_t nt;         /* time steps, 1 <= nt <= 256                                         */
   double  alpha;      /* L = (Id - alpha Lap)^s: alpha >= 0                                 */
@@ -207,7 +207,8 @@ int bl_lddmm_device_count(void);
 
 /*
  * Per-kernel timing with HIP events on the library's stream, for benchmarks: while enabled,
- * every launch of a transport step kernel is bracketed by events; bl_kernel_timing_read
+ * each run of consecutive launches of a transport step kernel is bracketed by one event
+ * pair (no per-launch event overhead); bl_kernel_timing_read
  * returns the number of launches and the summed milliseconds per kernel class
  * (0 = forward state step, 1 = incremental forward step, 2 = adjoint step) and resets.
  */

@@ -448,12 +448,18 @@ void iota(const Geo& g, const DftPlan& p, const float2* band, int C, float* out,
   hipLaunchKernelGGL(k_iota_x, dim3(xb, g.ky, C * g.kzh), dim3(64), 0, s, g, band, p.tw_x, p.bufA);
   hipLaunchKernelGGL(k_iota_y, dim3(xb, p.nyp / kYG, C * g.kzh), dim3(64), 0, s, g, p.bufA, p.tw_y,
                      p.nyp, p.bufB);
-  z_stage(g, p, p.bufB, out, C, nullptr, nullptr, s, true);
+  if (p.mixed)
+    iota_z_mixed(g, p, p.bufB, C, out, s);
+  else
+    z_stage(g, p, p.bufB, out, C, nullptr, nullptr, s, true);
 }
 
 void pi_half(const Geo& g, const DftPlan& p, const float* grid, int C, float2* P, hipStream_t s) {
   const int xb = (g.nx + 63) / 64;
-  z_stage(g, p, nullptr, nullptr, C, grid, p.bufA, s, false);
+  if (p.mixed)
+    pi_z_mixed(g, p, grid, C, p.bufA, s);
+  else
+    z_stage(g, p, nullptr, nullptr, C, grid, p.bufA, s, false);
   const int yseg = ((g.ny + kYS - 1) / kYS + kUY - 1) / kUY * kUY;
   hipLaunchKernelGGL(k_pi_y, dim3(xb, p.kyp / kJG, C * g.kzh), dim3(64, kYS), 0, s, g, p.bufA,
                      p.tw_yT, p.kyp, yseg, p.bufB);

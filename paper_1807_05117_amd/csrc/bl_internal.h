@@ -42,8 +42,10 @@ struct DftPlan {
   int kxp = 0, nxp = 0, kyp = 0, nyp = 0, nzp = 0;
   float2* bufA = nullptr;   // stage buffers, each 4 * kzh * max(ky*nx, ny*nx) complex
   float2* bufB = nullptr;
-  // split hi/lo bf16 twiddle operands of the mixed-precision path (nullptr in FP32 mode)
-  uint16_t* tz_bf16 = nullptr;
+  // split hi/lo BF16 twiddle matrices of the mixed-precision z stages (FP32 mode: unused)
+  unsigned short* wi_bf16 = nullptr;   // [2][nzp32][mixed_kp]    iota: (hi, lo)
+  unsigned short* wp_bf16 = nullptr;   // [2][32 mixed_jt][nzp16] pi:   (hi, lo)
+  int nzp32 = 0, nzp16 = 0;
   int mixed = 0;
 };
 
@@ -51,9 +53,17 @@ constexpr int kMaxKzh = 64;       // register arrays of the z stages: kz <= 128
 constexpr int kRedBlocks = 512;   // partial sums per deterministic FP64 reduction
 
 // ---- transforms (bl_dft.hip)
+// out: C planes
 void iota(const Geo& g, const DftPlan& p, const float2* band, int C, float* out, hipStream_t s);
 // pi without the 1/M scale: P[c][h][ky][kx] for h = 0..kzh-1 (half spectrum)
 void pi_half(const Geo& g, const DftPlan& p, const float* grid, int C, float2* P, hipStream_t s);
+
+// ---- mixed-precision z stages on BF16 matrix cores (bl_mixed.hip)
+int mixed_kp(const Geo& g);   // padded contraction length of the iota z stage: 2 kzh -> x16
+int mixed_jt(const Geo& g);   // 32-row output tiles of the pi z stage
+void iota_z_mixed(const Geo& g, const DftPlan& p, const float2* F2, int C, float* out,
+                  hipStream_t s);
+void pi_z_mixed(const Geo& g, const DftPlan& p, const float* f, int C, float2* G, hipStream_t s);
 
 // ---- band kernels (bl_dft.hip)
 // out[c] = projection of raw[c] (c < dim); with_div: out[dim] = spectral divergence.
@@ -65,12 +75,13 @@ void band_finalize(const Geo& g, int C, const float2* vproj, const float* Lhat,
                    const float2* P, float scale, float2* out, int* nonfinite, hipStream_t s);
 
 // ---- transports (bl_transport.hip)
-void setup(const Geo& g, const float* v, float* X, float* Y, float* a, hipStream_t s);
+// X: dim planes of forward offsets; YA = (Y, a) backward offsets and reaction factor
+void setup(const Geo& g, const float* v, float* X, float4* YA, hipStream_t s);
 void state_step(const Geo& g, const float* m_in, const float* X, float* m_out, hipStream_t s);
 void energy_partial(const Geo& g, const float* mT, const float* I1, double* partial,
                     hipStream_t s);
 void terminal(const Geo& g, const float* mT, const float* I1, float* lam, hipStream_t s);
-void adj_step(const Geo& g, const float* lam_in, const float* Y, const float* a, float* lam_out,
+void adj_step(const Geo& g, const float* lam_in, const float4* YA, float* lam_out,
               hipStream_t s);
 // b_c = sum_n w_n lam^n d_c m^n over nt + 1 stored planes of lam and m
 void body_force(const Geo& g, const float* lam, const float* m, float* b, hipStream_t s);
@@ -79,6 +90,8 @@ void inc_step(const Geo& g, const float* t_in, const float* X, const float* m_ne
               const float* dv, float* t_out, hipStream_t s);
 void inc_last(const Geo& g, const float* t_in, const float* X, const float* mT,
               const float* dv, float* dlam, hipStream_t s);
+// one component of packed float4 voxels into a plane
+void unpack4(const Geo& g, int comp, const float4* in, float* plane, hipStream_t s);
 
 // ---- reductions and band vector algebra (bl_reduce.hip)
 // out[0] = sum of n partials in a fixed order (one block)

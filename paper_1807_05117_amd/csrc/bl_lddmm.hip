@@ -62,8 +62,8 @@ int validate(const bl_problem* p, bl::Geo* g) {
   }
   if (p->dim == 3 && k[2] > 2 * bl::kMaxKzh)
     return fail(BL_E_INVALID, "band size k[2] must be <= 128");
-  if ((int64_t)n[0] * n[1] * n[2] > (int64_t(1) << 30))
-    return fail(BL_E_INVALID, "grid must have at most 2^30 voxels");
+  if ((int64_t)n[0] * n[1] * n[2] >= (int64_t(1) << 30))
+    return fail(BL_E_INVALID, "grid must have fewer than 2^30 voxels");
   if (p->nt < 1 || p->nt > 256) return fail(BL_E_INVALID, "nt must be in [1, 256]");
   if (!std::isfinite(p->alpha) || p->alpha < 0) return fail(BL_E_INVALID, "alpha must be finite and >= 0");
   if (p->s < 0 || p->s > 8) return fail(BL_E_INVALID, "s must be in [0, 8]");
@@ -126,11 +126,10 @@ struct bl_ctx {
   // grid fields
   float* I1 = nullptr;
   float* m = nullptr;      // (nt + 1) planes, m[0] = I0
-  float* X = nullptr;      // dim planes
-  float* Y = nullptr;      // dim planes
-  float* A = nullptr;
+  float* X = nullptr;      // dim planes: forward departure offsets
+  float4* YA = nullptr;    // (Y, a): backward offsets and adjoint reaction factor
   float* V = nullptr;      // dim + 1 planes: v, r
-  float* DV = nullptr;     // dim planes
+  float* DV = nullptr;     // dim planes: dv
   float* T0 = nullptr;
   float* T1 = nullptr;
   float* L = nullptr;      // (nt + 1) planes: adjoint or incremental adjoint
@@ -158,8 +157,10 @@ struct bl_ctx {
   // kernel timing
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
-  std::vector<std::pair<int, int>> ev_used;  // (class, pool index of the start event)
+  struct Run { int cls, ev, count; };
+  std::vector<Run> ev_used;  // timed runs: class, pool index of the start event, launches
   size_t ev_next = 0;
+  int ev_open = -1;
   int64_t t_launch[3] = {0, 0, 0};
   double t_ms[3] = {0, 0, 0};
 };
@@ -180,12 +181,12 @@ int nxp_of(const bl::Geo& g) { return round_up(g.nx, 8); }
 int nzp_of(const bl::Geo& g) { return round_up(g.nz, 128); }
 
 struct Offsets {
-  size_t I1, m, X, Y, A, V, DV, T0, T1, L, Bf, braw, bv, bd, bout, P, Lhat, Lhat64, tw_x, tw_xT,
-      tw_y, tw_yT, tw_zT, bufA, bufB, red, scal, flag, solver;
+  size_t I1, m, X, YA, V, DV, T0, T1, L, Bf, braw, bv, bd, bout, P, Lhat, Lhat64, tw_x, tw_xT,
+      tw_y, tw_yT, tw_zT, wi, wp, bufA, bufB, red, scal, flag, solver;
   size_t total;
 };
 
-Offsets plan_layout(const bl::Geo& g, bool transport, bool solver) {
+Offsets plan_layout(const bl::Geo& g, bool transport, bool solver, bool mixed) {
   Layout L;
   Offsets o{};
   const size_t pb = plane_bytes(g), bb = band_bytes(g);
@@ -194,8 +195,7 @@ Offsets plan_layout(const bl::Geo& g, bool transport, bool solver) {
     o.I1 = L.take(pb);
     o.m = L.take(pb * (g.nt + 1));
     o.X = L.take(pb * d);
-    o.Y = L.take(pb * d);
-    o.A = L.take(pb);
+    o.YA = L.take(pb * 4);
     o.V = L.take(pb * (d + 1));
     o.DV = L.take(pb * d);
     o.T0 = L.take(pb);
@@ -217,6 +217,10 @@ Offsets plan_layout(const bl::Geo& g, bool transport, bool solver) {
   o.tw_y = L.take((size_t)kyp_of(g) * nyp_of(g) * sizeof(float2));
   o.tw_yT = L.take((size_t)nyp_of(g) * kyp_of(g) * sizeof(float2));
   o.tw_zT = L.take((size_t)bl::kZP * nzp_of(g) * sizeof(float2));
+  if (mixed) {
+    o.wi = L.take((size_t)2 * round_up(g.nz, 32) * bl::mixed_kp(g) * sizeof(unsigned short));
+    o.wp = L.take((size_t)2 * 32 * bl::mixed_jt(g) * round_up(g.nz, 16) * sizeof(unsigned short));
+  }
   o.bufA = L.take(stage_elems(g) * sizeof(float2));
   o.bufB = L.take(stage_elems(g) * sizeof(float2));
   o.red = L.take((size_t)RED_SLOTS * bl::kRedBlocks * sizeof(double));
@@ -250,6 +254,57 @@ void twiddles(std::vector<float2>& t, int rows, int cols, int K, int N, bool cen
     }
 }
 
+// FP32 value -> BF16 bits, round to nearest even
+unsigned short bf16_bits(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+double bf16_value(unsigned short h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+// split hi/lo BF16 pair of an FP64 value
+void split_bf16(double t, unsigned short& hi, unsigned short& lo) {
+  hi = bf16_bits((float)t);
+  lo = bf16_bits((float)(t - bf16_value(hi)));
+}
+
+// Matrices of the mixed-precision z stages (exactly reduced angles in FP64, split to BF16):
+//   Wi[z][2h] = s_h cos(2 pi h z / nz), Wi[z][2h+1] = -s_h sin(..), s_0 = 1, s_h = 2, rows
+//   z < round_up(nz, 32), columns < mixed_kp;  Wp[2h][z] = cos(..), Wp[2h+1][z] = -sin(..),
+//   rows < 32 mixed_jt, columns z < round_up(nz, 16).  Each as a hi table followed by a lo
+//   table; entries outside h < kzh, z < nz are zero.
+void mixed_tables(const bl::Geo& g, std::vector<unsigned short>& wi,
+                  std::vector<unsigned short>& wp) {
+  const double two_pi = 6.283185307179586476925286766559;
+  const int kp = bl::mixed_kp(g), zi = round_up(g.nz, 32);
+  const int jr = 32 * bl::mixed_jt(g), zp = round_up(g.nz, 16);
+  wi.assign((size_t)2 * zi * kp, 0);
+  wp.assign((size_t)2 * jr * zp, 0);
+  for (int z = 0; z < g.nz; ++z)
+    for (int h = 0; h < g.kzh; ++h) {
+      long long r = ((long long)h * z) % g.nz;
+      const double ang = two_pi * (double)r / (double)g.nz;
+      const double cs = std::cos(ang), sn = std::sin(ang), sh = h == 0 ? 1.0 : 2.0;
+      unsigned short hi, lo;
+      split_bf16(sh * cs, hi, lo);
+      wi[(size_t)z * kp + 2 * h] = hi;
+      wi[(size_t)zi * kp + (size_t)z * kp + 2 * h] = lo;
+      split_bf16(-sh * sn, hi, lo);
+      wi[(size_t)z * kp + 2 * h + 1] = hi;
+      wi[(size_t)zi * kp + (size_t)z * kp + 2 * h + 1] = lo;
+      split_bf16(cs, hi, lo);
+      wp[(size_t)(2 * h) * zp + z] = hi;
+      wp[(size_t)jr * zp + (size_t)(2 * h) * zp + z] = lo;
+      split_bf16(-sn, hi, lo);
+      wp[(size_t)(2 * h + 1) * zp + z] = hi;
+      wp[(size_t)jr * zp + (size_t)(2 * h + 1) * zp + z] = lo;
+    }
+}
+
 void destroy_ctx(bl_ctx* c) {
   if (!c) return;
   hipSetDevice(c->device);
@@ -276,7 +331,8 @@ bl_ctx* create_ctx(const bl_problem* prob, const bl::Geo& g, bool transport, boo
       HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
       c->own_stream = true;
     }
-    const Offsets o = plan_layout(g, transport, solver);
+    const bool mixed = prob->precision == BL_MIXED;
+    const Offsets o = plan_layout(g, transport, solver, mixed);
     size_t free_b = 0, total_b = 0;
     HIP_TRY(hipMemGetInfo(&free_b, &total_b));
     if (o.total + (64u << 20) > free_b) throw std::bad_alloc();
@@ -286,8 +342,11 @@ bl_ctx* create_ctx(const bl_problem* prob, const bl::Geo& g, bool transport, boo
     auto F = [&](size_t off) { return reinterpret_cast<float*>(a + off); };
     auto C2 = [&](size_t off) { return reinterpret_cast<float2*>(a + off); };
     if (transport) {
-      c->I1 = F(o.I1); c->m = F(o.m); c->X = F(o.X); c->Y = F(o.Y); c->A = F(o.A);
-      c->DV = F(o.DV); c->T0 = F(o.T0); c->T1 = F(o.T1); c->L = F(o.L); c->Bf = F(o.Bf);
+      c->I1 = F(o.I1); c->m = F(o.m);
+      c->X = F(o.X);
+      c->YA = reinterpret_cast<float4*>(a + o.YA);
+      c->DV = F(o.DV);
+      c->T0 = F(o.T0); c->T1 = F(o.T1); c->L = F(o.L); c->Bf = F(o.Bf);
     }
     c->V = F(o.V);
     c->braw = C2(o.braw); c->bv = C2(o.bv); c->bd = C2(o.bd); c->bout = C2(o.bout); c->P = C2(o.P);
@@ -298,7 +357,13 @@ bl_ctx* create_ctx(const bl_problem* prob, const bl::Geo& g, bool transport, boo
     c->plan.nyp = nyp_of(g); c->plan.kyp = kyp_of(g); c->plan.kxp = kxp_of(g);
     c->plan.nxp = nxp_of(g); c->plan.nzp = nzp_of(g);
     c->plan.bufA = C2(o.bufA); c->plan.bufB = C2(o.bufB);
-    c->plan.mixed = prob->precision == BL_MIXED;
+    c->plan.mixed = mixed;
+    if (mixed) {
+      c->plan.wi_bf16 = reinterpret_cast<unsigned short*>(a + o.wi);
+      c->plan.wp_bf16 = reinterpret_cast<unsigned short*>(a + o.wp);
+      c->plan.nzp32 = round_up(g.nz, 32);
+      c->plan.nzp16 = round_up(g.nz, 16);
+    }
     c->red = reinterpret_cast<double*>(a + o.red);
     c->scal = reinterpret_cast<double*>(a + o.scal);
     c->flag = reinterpret_cast<int*>(a + o.flag);
@@ -325,6 +390,13 @@ bl_ctx* create_ctx(const bl_problem* prob, const bl::Geo& g, bool transport, boo
     upload(c->plan.tw_yT);
     twiddles(tw, c->plan.nzp, bl::kZP, g.kzh, g.nz, false, true);
     upload(c->plan.tw_zT);
+    if (mixed) {
+      std::vector<unsigned short> wi, wp;
+      mixed_tables(g, wi, wp);
+      HIP_TRY(hipMemcpyAsync(c->plan.wi_bf16, wi.data(), wi.size() * 2, hipMemcpyHostToDevice, c->stream));
+      HIP_TRY(hipMemcpyAsync(c->plan.wp_bf16, wp.data(), wp.size() * 2, hipMemcpyHostToDevice, c->stream));
+      HIP_TRY(hipStreamSynchronize(c->stream));
+    }
     std::vector<double> L64((size_t)g.B);
     std::vector<float> L32((size_t)g.B);
     const double four_pi2 = 39.478417604357434;
@@ -360,27 +432,31 @@ inline hipMemcpyKind in_kind(const bl_ctx* c) {
 void sync(bl_ctx* c) { HIP_TRY(hipStreamSynchronize(c->stream)); }
 
 // -------------------------------------------------------------------------------- timing
-void t_begin(bl_ctx* c, int cls) {
-  if (!c->timing || c->ev_next + 2 > c->ev_pool.size()) return;
-  const int i = (int)c->ev_next;
+// A run of `count` consecutive launches of one kernel class is bracketed by one event pair,
+// so the per-launch average carries no event overhead.
+void t_begin(bl_ctx* c) {
+  if (!c->timing || c->ev_next + 2 > c->ev_pool.size()) {
+    c->ev_open = -1;
+    return;
+  }
+  c->ev_open = (int)c->ev_next;
   c->ev_next += 2;
-  HIP_TRY(hipEventRecord(c->ev_pool[i], c->stream));
-  c->ev_used.push_back({cls, i});
+  HIP_TRY(hipEventRecord(c->ev_pool[c->ev_open], c->stream));
 }
-void t_end(bl_ctx* c, int cls) {
-  if (!c->timing || c->ev_used.empty()) return;
-  const auto& u = c->ev_used.back();
-  if (u.first != cls) return;
-  HIP_TRY(hipEventRecord(c->ev_pool[u.second + 1], c->stream));
+void t_end(bl_ctx* c, int cls, int count) {
+  if (!c->timing || c->ev_open < 0) return;
+  HIP_TRY(hipEventRecord(c->ev_pool[c->ev_open + 1], c->stream));
+  c->ev_used.push_back({cls, c->ev_open, count});
+  c->ev_open = -1;
 }
 void t_collect(bl_ctx* c) {
   if (c->ev_used.empty()) return;
   sync(c);
   for (const auto& u : c->ev_used) {
     float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, c->ev_pool[u.second], c->ev_pool[u.second + 1]));
-    c->t_launch[u.first] += 1;
-    c->t_ms[u.first] += ms;
+    HIP_TRY(hipEventElapsedTime(&ms, c->ev_pool[u.ev], c->ev_pool[u.ev + 1]));
+    c->t_launch[u.cls] += u.count;
+    c->t_ms[u.cls] += ms;
   }
   c->ev_used.clear();
   c->ev_next = 0;
@@ -401,13 +477,11 @@ void op_set_velocity(bl_ctx* c, const float2* vraw) {
   double* red_data = c->red + RED_DATA * bl::kRedBlocks;
   bl::band_prep(g, vraw, c->bv, 1, c->Lhat64, red_reg, s);
   bl::iota(g, c->plan, c->bv, g.dim + 1, c->V, s);
-  bl::setup(g, c->V, c->X, c->Y, c->A, s);
+  bl::setup(g, c->V, c->X, c->YA, s);
   const size_t M = (size_t)g.M;
-  for (int n = 0; n < g.nt; ++n) {
-    if (c->timing) t_begin(c, 0);
-    bl::state_step(g, c->m + n * M, c->X, c->m + (n + 1) * M, s);
-    if (c->timing) t_end(c, 0);
-  }
+  if (c->timing) t_begin(c);
+  for (int n = 0; n < g.nt; ++n) bl::state_step(g, c->m + n * M, c->X, c->m + (n + 1) * M, s);
+  if (c->timing) t_end(c, 0, g.nt);
   bl::energy_partial(g, c->m + g.nt * M, c->I1, red_data, s);
   bl::reduce_final(red_reg, bl::kRedBlocks, c->scal + 0, s);
   bl::reduce_final(red_data, bl::kRedBlocks, c->scal + 1, s);
@@ -427,11 +501,9 @@ void backward_and_body_force(bl_ctx* c) {
   const bl::Geo& g = c->g;
   hipStream_t s = c->stream;
   const size_t M = (size_t)g.M;
-  for (int n = g.nt - 1; n >= 0; --n) {
-    if (c->timing) t_begin(c, 2);
-    bl::adj_step(g, c->L + (n + 1) * M, c->Y, c->A, c->L + n * M, s);
-    if (c->timing) t_end(c, 2);
-  }
+  if (c->timing) t_begin(c);
+  for (int n = g.nt - 1; n >= 0; --n) bl::adj_step(g, c->L + (n + 1) * M, c->YA, c->L + n * M, s);
+  if (c->timing) t_end(c, 2, g.nt);
   bl::body_force(g, c->L, c->m, c->Bf, s);
 }
 
@@ -457,12 +529,12 @@ void op_hessvec(bl_ctx* c, const float2* draw, float2* hout) {
   bl::inc_init(g, c->m, c->DV, c->T0, s);
   float* tin = c->T0;
   float* tout = c->T1;
+  if (c->timing && g.nt > 1) t_begin(c);
   for (int n = 0; n + 1 < g.nt; ++n) {
-    if (c->timing) t_begin(c, 1);
     bl::inc_step(g, tin, c->X, c->m + (n + 1) * M, c->DV, tout, s);
-    if (c->timing) t_end(c, 1);
     std::swap(tin, tout);
   }
+  if (c->timing && g.nt > 1) t_end(c, 1, g.nt - 1);
   bl::inc_last(g, tin, c->X, c->m + g.nt * M, c->DV, c->L + g.nt * M, s);
   backward_and_body_force(c);
   bl::pi_half(g, c->plan, c->Bf, g.dim, c->P, s);
@@ -695,7 +767,7 @@ int bl_lddmm_device_count(void) {
 uint64_t bl_lddmm_footprint(const bl_problem* prob) {
   bl::Geo g;
   if (validate(prob, &g) != BL_OK) return 0;
-  return (uint64_t)plan_layout(g, true, true).total;
+  return (uint64_t)plan_layout(g, true, true, prob->precision == BL_MIXED).total;
 }
 
 int bl_lddmm_ctx_create(const bl_problem* prob, const float* I0, const float* I1, bl_ctx** out) {
@@ -759,20 +831,27 @@ int bl_lddmm_ctx_get_field(bl_ctx* c, int32_t which, int32_t index, float* out) 
   if (!c || !out) return fail(BL_E_INVALID, "NULL pointer argument");
   const bl::Geo& g = c->g;
   const float* src = nullptr;
+  const float4* packed = nullptr;
+  int comp = 0;
   const size_t M = (size_t)g.M;
   switch (which) {
     case BL_FIELD_VELOCITY: if (index >= 0 && index < g.dim) src = c->V + index * M; break;
     case BL_FIELD_DIV: if (index == 0) src = c->V + g.dim * M; break;
     case BL_FIELD_X: if (index >= 0 && index < g.dim) src = c->X + index * M; break;
-    case BL_FIELD_Y: if (index >= 0 && index < g.dim) src = c->Y + index * M; break;
-    case BL_FIELD_A: if (index == 0) src = c->A; break;
+    case BL_FIELD_Y: if (index >= 0 && index < g.dim) { packed = c->YA; comp = index; } break;
+    case BL_FIELD_A: if (index == 0) { packed = c->YA; comp = 3; } break;
     case BL_FIELD_STATE: if (index >= 0 && index <= g.nt) src = c->m + index * M; break;
     default: break;
   }
-  if (!src) return fail(BL_E_INVALID, "unknown field or index out of range");
+  if (!src && !packed) return fail(BL_E_INVALID, "unknown field or index out of range");
   if (!c->have_v && which != BL_FIELD_STATE) return fail(BL_E_INVALID, "no velocity set on this context");
   return guarded([&]() {
     HIP_TRY(hipSetDevice(c->device));
+    if (packed) {
+      bl::unpack4(g, comp, packed, c->T0, c->stream);   // T0 is free between operations
+      check_launch("get_field");
+      src = c->T0;
+    }
     store_plane(c, src, out, 1);
     sync(c);
     return BL_OK;

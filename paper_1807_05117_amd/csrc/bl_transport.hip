@@ -14,15 +14,17 @@
 // with periodic d-linear interpolation, central differences grad f = (f(i+e) - f(i-e)) N_ref/2
 // and trapezoid weights w_n in time.
 //
-// Layout: every grid field is float32 with x fastest; vector fields are `dim` consecutive
-// planes of M floats.  One thread per voxel, 64 x 4 threads per block along (x, y), one
-// grid layer of blocks per z plane, so wavefronts read and write whole x rows.
+// Layout: grid fields are float32 planes with x fastest; vector fields are dim consecutive
+// planes.  The backward offsets and the reaction factor are packed into one 16-byte voxel,
+// YA = (Y, a), which costs no extra bytes and saves three loads.  The kernels stream at the
+// HBM rate, so they read every field once per voxel (12 + 4 + ... bytes) and nothing more;
+// the two x-neighbours of every interpolation row come in one 8-byte load.
 #include "bl_internal.h"
 
 namespace bl {
 namespace {
 
-constexpr int BX = 64, BY = 4;
+constexpr int BX = 64;
 
 __device__ __forceinline__ int wrap(int i, int n) {
   if ((unsigned)i < (unsigned)n) return i;
@@ -41,8 +43,30 @@ __device__ __forceinline__ void split(float o, int base, int n, int& i0, int& i1
   i1 = (i0 + 1 == n) ? 0 : i0 + 1;
 }
 
-// All in-volume indices are 32-bit (the host guarantees prod(n) <= 2^30); plane offsets are
-// applied to the base pointers.
+// Interpolation rows are read through a raw buffer resource: an 8-byte load of two
+// consecutive floats needs only 4-byte alignment there (global loads would be split), and the
+// hardware range check returns 0 for any dword past the buffer instead of faulting.
+typedef float f2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t field_rsrc(const float* f, const Geo& g) {
+  const uint64_t bytes = (uint64_t)g.M * 4u;   // < 2^32: the host limits prod(n) to < 2^30
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(f), (short)0, (int)(uint32_t)bytes,
+                                           0x00020000);
+}
+
+// f[row + x0] and f[row + x1] where x1 is x0 + 1 or the periodic wrap to 0.
+__device__ __forceinline__ void load_pair(__amdgpu_buffer_rsrc_t rs, uint32_t row, int x0,
+                                          int x1, float& v0, float& v1) {
+  const f2v v = __builtin_bit_cast(
+      f2v, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)((row + (uint32_t)x0) * 4u), 0, 0));
+  v0 = v.x;
+  v1 = v.y;
+  if (x1 != x0 + 1)
+    v1 = __builtin_bit_cast(
+        float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)((row + (uint32_t)x1) * 4u), 0, 0));
+}
+
+// All in-volume indices are 32-bit (the host guarantees prod(n) <= 2^30).
 template <int DIM>
 struct Tap {
   uint32_t r00, r01, r10, r11;  // row starts (z0,y0) (z0,y1) (z1,y0) (z1,y1)
@@ -75,21 +99,139 @@ __device__ __forceinline__ Tap<DIM> make_tap(const Geo& g, int x, int y, int z, 
 }
 
 template <int DIM>
-__device__ __forceinline__ float apply(const float* __restrict__ f, const Tap<DIM>& t) {
-  const float a0 = f[t.r00 + t.x0], a1 = f[t.r00 + t.x1];
-  const float b0 = f[t.r01 + t.x0], b1 = f[t.r01 + t.x1];
+__device__ __forceinline__ float apply(__amdgpu_buffer_rsrc_t f, const Tap<DIM>& t) {
+  float a0, a1, b0, b1;
+  load_pair(f, t.r00, t.x0, t.x1, a0, a1);
+  load_pair(f, t.r01, t.x0, t.x1, b0, b1);
   const float ra = fmaf(t.wx, a1 - a0, a0);
   const float rb = fmaf(t.wx, b1 - b0, b0);
   const float pa = fmaf(t.wy, rb - ra, ra);
   if (DIM == 2) return pa;
-  const float c0 = f[t.r10 + t.x0], c1 = f[t.r10 + t.x1];
-  const float d0 = f[t.r11 + t.x0], d1 = f[t.r11 + t.x1];
+  float c0, c1, d0, d1;
+  load_pair(f, t.r10, t.x0, t.x1, c0, c1);
+  load_pair(f, t.r11, t.x0, t.x1, d0, d1);
   const float rc = fmaf(t.wx, c1 - c0, c0);
   const float rd = fmaf(t.wx, d1 - d0, d0);
   const float pb = fmaf(t.wy, rd - rc, rc);
   return fmaf(t.wz, pb - pa, pa);
 }
 
+// ------------------------------------------------------------------ gather kernels (64 x 4)
+// One thread per ZV voxels along z; z is clamped to the grid so that every load stays in
+// bounds and the ZV voxels' loads can be issued together; only the stores are guarded.
+constexpr int GBY = 4;
+
+// XCD-aware tile order: the hardware deals consecutive workgroups round-robin to the 8
+// XCDs, each with its own L2.  The launch is 1D with a multiple of 8 workgroups and workgroup
+// b works on tile (b % 8) * (nb / 8) + b / 8 of the x-fastest tile order, so every XCD sweeps
+// one contiguous slab of the volume and the y / z neighbours that gathers and central
+// differences touch are mostly in its own L2.
+constexpr int kXCD = 8;
+
+struct TileIdx {
+  int bx, by, bz;
+  bool valid;
+};
+
+__device__ __forceinline__ TileIdx xcd_tile(int gx, int gy, int gz) {
+  const int nb = gridDim.x;                 // multiple of kXCD
+  const int b = blockIdx.x;
+  const int t = (b % kXCD) * (nb / kXCD) + b / kXCD;
+  TileIdx r;
+  r.bx = t % gx;
+  r.by = (t / gx) % gy;
+  r.bz = t / (gx * gy);
+  r.valid = r.bz < gz;
+  return r;
+}
+
+#define GATHER_XY                                                                \
+  const TileIdx tile = xcd_tile((g.nx + BX - 1) / BX, (g.ny + GBY - 1) / GBY,    \
+                                (g.nz + ZV - 1) / ZV);                           \
+  if (!tile.valid) return;                                                       \
+  const int x = tile.bx * BX + threadIdx.x;                                      \
+  const int y = tile.by * GBY + threadIdx.y;                                     \
+  if (x >= g.nx || y >= g.ny) return;
+#define GATHER_Z(zz)                                     \
+  const int zr = tile.bz * ZV + (zz);                    \
+  const int z = zr < g.nz ? zr : g.nz - 1;               \
+  const bool live = zr < g.nz;                           \
+  const uint32_t p = ((uint32_t)z * g.ny + y) * g.nx + x;
+
+template <int DIM>
+__global__ __launch_bounds__(BX* GBY) void k_setup(Geo g, const float* __restrict__ v,
+                                                   float* __restrict__ X,
+                                                   float4* __restrict__ YA) {
+  constexpr int ZV = 1;
+  GATHER_XY
+  GATHER_Z(0)
+  (void)live;
+  const size_t M = (size_t)g.M;
+  const float s = g.dt * (float)g.nref;
+  float u[3] = {0.f, 0.f, 0.f};
+  for (int c = 0; c < DIM; ++c) u[c] = s * v[c * M + p];
+  // forward: X = -(u + Interp(u, i - u)) / 2
+  const Tap<DIM> tf = make_tap<DIM>(g, x, y, z, -u[0], -u[1], -u[2]);
+  // backward: Y = +(u + Interp(u, i + u)) / 2
+  const Tap<DIM> tb = make_tap<DIM>(g, x, y, z, u[0], u[1], u[2]);
+  float xo[3] = {0.f, 0.f, 0.f}, yo[3] = {0.f, 0.f, 0.f};
+  for (int c = 0; c < DIM; ++c) {
+    const __amdgpu_buffer_rsrc_t vc = field_rsrc(v + c * M, g);
+    xo[c] = -0.5f * (u[c] + s * apply<DIM>(vc, tf));
+    yo[c] = 0.5f * (u[c] + s * apply<DIM>(vc, tb));
+  }
+  // reaction factor of the adjoint along the backward characteristic (Heun)
+  const float* r = v + DIM * M;
+  const Tap<DIM> ty = make_tap<DIM>(g, x, y, z, yo[0], yo[1], yo[2]);
+  const float R = apply<DIM>(field_rsrc(r, g), ty);
+  const float ri = r[p];
+  const float a = 1.0f + 0.5f * g.dt * (R + (1.0f + g.dt * R) * ri);
+  for (int c = 0; c < DIM; ++c) X[c * M + p] = xo[c];
+  YA[p] = make_float4(yo[0], yo[1], yo[2], a);
+}
+
+template <int DIM, int ZV>
+__global__ __launch_bounds__(BX* GBY) void k_state_step(Geo g, const float* __restrict__ m_in,
+                                                        const float* __restrict__ X,
+                                                        float* __restrict__ m_out) {
+  GATHER_XY
+  const size_t M = (size_t)g.M;
+#pragma unroll
+  for (int zz = 0; zz < ZV; ++zz) {
+    GATHER_Z(zz)
+    const float ox = X[p], oy = X[M + p], oz = DIM == 3 ? X[2 * M + p] : 0.f;
+    const float v = apply<DIM>(field_rsrc(m_in, g), make_tap<DIM>(g, x, y, z, ox, oy, oz));
+    if (live) m_out[p] = v;
+  }
+}
+
+template <int DIM, int ZV>
+__global__ __launch_bounds__(BX* GBY) void k_adj_step(Geo g, const float* __restrict__ lam_in,
+                                                      const float4* __restrict__ YA,
+                                                      float* __restrict__ lam_out) {
+  GATHER_XY
+#pragma unroll
+  for (int zz = 0; zz < ZV; ++zz) {
+    GATHER_Z(zz)
+    const float4 o = YA[p];
+    const float v =
+        o.w * apply<DIM>(field_rsrc(lam_in, g), make_tap<DIM>(g, x, y, z, o.x, o.y, o.z));
+    if (live) lam_out[p] = v;
+  }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(BX* GBY) void k_terminal(Geo g, const float* __restrict__ mT,
+                                                      const float* __restrict__ I1,
+                                                      float* __restrict__ lam) {
+  constexpr int ZV = 1;
+  GATHER_XY
+  GATHER_Z(0)
+  (void)live;
+  lam[p] = g.lam_scale * (mT[p] - I1[p]);
+}
+
+// ---------------------------------------------------------------- stencil + gather kernels
 // Central differences of f at voxel (x, y, z), scaled by N_ref / 2.
 template <int DIM>
 __device__ __forceinline__ void grad_c(const Geo& g, const float* __restrict__ f, int x, int y,
@@ -109,115 +251,7 @@ __device__ __forceinline__ void grad_c(const Geo& g, const float* __restrict__ f
   }
 }
 
-// Kernels that take ZV voxels per thread along z: z is clamped to the grid so that every load
-// stays in bounds and the ZV voxels' loads can be issued together; only the stores are
-// guarded.
-#define VOXEL_XY                                         \
-  const int x = blockIdx.x * BX + threadIdx.x;           \
-  const int y = blockIdx.y * BY + threadIdx.y;           \
-  if (x >= g.nx || y >= g.ny) return;                    \
-  const size_t M = (size_t)g.M;                          \
-  (void)M;
-#define VOXEL_Z(zz)                                      \
-  const int zr = blockIdx.z * ZV + (zz);                 \
-  const int z = zr < g.nz ? zr : g.nz - 1;               \
-  const bool live = zr < g.nz;                           \
-  const uint32_t p = ((uint32_t)z * g.ny + y) * g.nx + x;\
-  (void)live;
-
-#define VOXEL_PROLOGUE                                   \
-  const int x = blockIdx.x * BX + threadIdx.x;           \
-  const int y = blockIdx.y * BY + threadIdx.y;           \
-  const int z = blockIdx.z;                              \
-  if (x >= g.nx || y >= g.ny) return;                    \
-  const uint32_t p = ((uint32_t)z * g.ny + y) * g.nx + x; \
-  const size_t M = (size_t)g.M;                          \
-  (void)M;
-
-template <int DIM>
-__global__ __launch_bounds__(BX* BY) void k_setup(Geo g, const float* __restrict__ v,
-                                                  float* __restrict__ X, float* __restrict__ Y,
-                                                  float* __restrict__ A) {
-  VOXEL_PROLOGUE
-  const float s = g.dt * (float)g.nref;
-  float u[3] = {0.f, 0.f, 0.f};
-  for (int c = 0; c < DIM; ++c) u[c] = s * v[c * M + p];
-  // forward: X = -(u + Interp(u, i - u)) / 2
-  const Tap<DIM> tf = make_tap<DIM>(g, x, y, z, -u[0], -u[1], -u[2]);
-  // backward: Y = +(u + Interp(u, i + u)) / 2
-  const Tap<DIM> tb = make_tap<DIM>(g, x, y, z, u[0], u[1], u[2]);
-  float yo[3] = {0.f, 0.f, 0.f};
-  for (int c = 0; c < DIM; ++c) {
-    const float* vc = v + c * M;
-    const float uf = s * apply<DIM>(vc, tf);
-    const float ub = s * apply<DIM>(vc, tb);
-    X[c * M + p] = -0.5f * (u[c] + uf);
-    yo[c] = 0.5f * (u[c] + ub);
-    Y[c * M + p] = yo[c];
-  }
-  // reaction factor of the adjoint along the backward characteristic (Heun)
-  const float* r = v + DIM * M;
-  const Tap<DIM> ty = make_tap<DIM>(g, x, y, z, yo[0], yo[1], yo[2]);
-  const float R = apply<DIM>(r, ty);
-  const float ri = r[p];
-  A[p] = 1.0f + 0.5f * g.dt * (R + (1.0f + g.dt * R) * ri);
-}
-
-template <int DIM, int ZV>
-__global__ __launch_bounds__(BX* BY) void k_state_step(Geo g, const float* __restrict__ m_in,
-                                                       const float* __restrict__ X,
-                                                       float* __restrict__ m_out) {
-  VOXEL_XY
-#pragma unroll
-  for (int zz = 0; zz < ZV; ++zz) {
-    VOXEL_Z(zz)
-    const float ox = X[p], oy = X[M + p], oz = DIM == 3 ? X[2 * M + p] : 0.f;
-    const float v = apply<DIM>(m_in, make_tap<DIM>(g, x, y, z, ox, oy, oz));
-    if (live) m_out[p] = v;
-  }
-}
-
-template <int DIM>
-__global__ __launch_bounds__(BX* BY) void k_terminal(Geo g, const float* __restrict__ mT,
-                                                     const float* __restrict__ I1,
-                                                     float* __restrict__ lam) {
-  VOXEL_PROLOGUE
-  lam[p] = g.lam_scale * (mT[p] - I1[p]);
-}
-
-template <int DIM, int ZV>
-__global__ __launch_bounds__(BX* BY) void k_adj_step(Geo g, const float* __restrict__ lam_in,
-                                                     const float* __restrict__ Y,
-                                                     const float* __restrict__ A,
-                                                     float* __restrict__ lam_out) {
-  VOXEL_XY
-#pragma unroll
-  for (int zz = 0; zz < ZV; ++zz) {
-    VOXEL_Z(zz)
-    const float ox = Y[p], oy = Y[M + p], oz = DIM == 3 ? Y[2 * M + p] : 0.f;
-    const float v = A[p] * apply<DIM>(lam_in, make_tap<DIM>(g, x, y, z, ox, oy, oz));
-    if (live) lam_out[p] = v;
-  }
-}
-
-// b = sum_n w_n lambda^n grad m^n over the stored adjoint and state planes (trapezoid in
-// time), one pass after the backward transport.
-template <int DIM>
-__global__ __launch_bounds__(BX* BY) void k_body_force(Geo g, const float* __restrict__ lam,
-                                                       const float* __restrict__ m,
-                                                       float* __restrict__ b) {
-  VOXEL_PROLOGUE
-  float acc[3] = {0.f, 0.f, 0.f};
-  for (int n = 0; n <= g.nt; ++n) {
-    const float w = (n == 0 || n == g.nt) ? 0.5f * g.dt : g.dt;
-    float gr[3];
-    grad_c<DIM>(g, m + (size_t)n * M, x, y, z, p, gr);
-    const float wl = w * lam[(size_t)n * M + p];
-    for (int c = 0; c < DIM; ++c) acc[c] = fmaf(wl, gr[c], acc[c]);
-  }
-  for (int c = 0; c < DIM; ++c) b[c * M + p] = acc[c];
-}
-
+// f = -grad m . dv at voxel p (dv: dim planes)
 template <int DIM>
 __device__ __forceinline__ float source_f(const Geo& g, const float* __restrict__ m,
                                           const float* __restrict__ dv, int x, int y, int z,
@@ -231,42 +265,77 @@ __device__ __forceinline__ float source_f(const Geo& g, const float* __restrict_
   return -s;
 }
 
-template <int DIM>
-__global__ __launch_bounds__(BX* BY) void k_inc_init(Geo g, const float* __restrict__ m0,
-                                                     const float* __restrict__ dv,
-                                                     float* __restrict__ t0) {
-  VOXEL_PROLOGUE
-  t0[p] = 0.5f * g.dt * source_f<DIM>(g, m0, dv, x, y, z, p);
+template <int DIM, int ZV>
+__global__ __launch_bounds__(BX* GBY) void k_inc_init(Geo g, const float* __restrict__ m0,
+                                                      const float* __restrict__ dv,
+                                                      float* __restrict__ t0) {
+  GATHER_XY
+#pragma unroll
+  for (int zz = 0; zz < ZV; ++zz) {
+    GATHER_Z(zz)
+    const float v = 0.5f * g.dt * source_f<DIM>(g, m0, dv, x, y, z, p);
+    if (live) t0[p] = v;
+  }
 }
 
 template <int DIM, int ZV>
-__global__ __launch_bounds__(BX* BY) void k_inc_step(Geo g, const float* __restrict__ t_in,
-                                                     const float* __restrict__ X,
-                                                     const float* __restrict__ m_next,
-                                                     const float* __restrict__ dv,
-                                                     float* __restrict__ t_out) {
-  VOXEL_XY
+__global__ __launch_bounds__(BX* GBY) void k_inc_step(Geo g, const float* __restrict__ t_in,
+                                                      const float* __restrict__ X,
+                                                      const float* __restrict__ m_next,
+                                                      const float* __restrict__ dv,
+                                                      float* __restrict__ t_out) {
+  GATHER_XY
+  const size_t M = (size_t)g.M;
 #pragma unroll
   for (int zz = 0; zz < ZV; ++zz) {
-    VOXEL_Z(zz)
+    GATHER_Z(zz)
     const float ox = X[p], oy = X[M + p], oz = DIM == 3 ? X[2 * M + p] : 0.f;
-    const float tr = apply<DIM>(t_in, make_tap<DIM>(g, x, y, z, ox, oy, oz));
+    const float tr = apply<DIM>(field_rsrc(t_in, g), make_tap<DIM>(g, x, y, z, ox, oy, oz));
     const float v = fmaf(g.dt, source_f<DIM>(g, m_next, dv, x, y, z, p), tr);
     if (live) t_out[p] = v;
   }
 }
 
-template <int DIM>
-__global__ __launch_bounds__(BX* BY) void k_inc_last(Geo g, const float* __restrict__ t_in,
-                                                     const float* __restrict__ X,
-                                                     const float* __restrict__ mT,
-                                                     const float* __restrict__ dv,
-                                                     float* __restrict__ dlam) {
-  VOXEL_PROLOGUE
-  const float ox = X[p], oy = X[M + p], oz = DIM == 3 ? X[2 * M + p] : 0.f;
-  const float tr = apply<DIM>(t_in, make_tap<DIM>(g, x, y, z, ox, oy, oz));
-  const float dm = fmaf(0.5f * g.dt, source_f<DIM>(g, mT, dv, x, y, z, p), tr);
-  dlam[p] = g.lam_scale * dm;
+template <int DIM, int ZV>
+__global__ __launch_bounds__(BX* GBY) void k_inc_last(Geo g, const float* __restrict__ t_in,
+                                                      const float* __restrict__ X,
+                                                      const float* __restrict__ mT,
+                                                      const float* __restrict__ dv,
+                                                      float* __restrict__ dlam) {
+  GATHER_XY
+  const size_t M = (size_t)g.M;
+#pragma unroll
+  for (int zz = 0; zz < ZV; ++zz) {
+    GATHER_Z(zz)
+    const float ox = X[p], oy = X[M + p], oz = DIM == 3 ? X[2 * M + p] : 0.f;
+    const float tr = apply<DIM>(field_rsrc(t_in, g), make_tap<DIM>(g, x, y, z, ox, oy, oz));
+    const float dm = fmaf(0.5f * g.dt, source_f<DIM>(g, mT, dv, x, y, z, p), tr);
+    if (live) dlam[p] = g.lam_scale * dm;
+  }
+}
+
+// b = sum_n w_n lambda^n grad m^n over the stored adjoint and state planes (trapezoid in
+// time), one pass after the backward transport.
+template <int DIM, int ZV>
+__global__ __launch_bounds__(BX* GBY) void k_body_force(Geo g, const float* __restrict__ lam,
+                                                        const float* __restrict__ m,
+                                                        float* __restrict__ b) {
+  GATHER_XY
+  const size_t M = (size_t)g.M;
+#pragma unroll
+  for (int zz = 0; zz < ZV; ++zz) {
+    GATHER_Z(zz)
+    float acc[3] = {0.f, 0.f, 0.f};
+    for (int n = 0; n <= g.nt; ++n) {
+      const float w = (n == 0 || n == g.nt) ? 0.5f * g.dt : g.dt;
+      float gr[3];
+      grad_c<DIM>(g, m + n * M, x, y, z, p, gr);
+      const float wl = w * lam[n * M + p];
+      for (int c = 0; c < DIM; ++c) acc[c] = fmaf(wl, gr[c], acc[c]);
+    }
+    if (live)
+      for (int c = 0; c < DIM; ++c) b[c * M + p] = acc[c];
+  }
 }
 
 // Deterministic partial sums of (mT - I1)^2: a fixed grid of kRedBlocks blocks, each thread
@@ -290,60 +359,78 @@ __global__ __launch_bounds__(256) void k_energy_partial(int64_t n, const float* 
   if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
 }
 
-inline dim3 vox_grid(const Geo& g, int zv = 1) {
-  return dim3((g.nx + BX - 1) / BX, (g.ny + BY - 1) / BY, (g.nz + zv - 1) / zv);
+// One component of packed float4 data into a plane.
+__global__ __launch_bounds__(256) void k_unpack4(int64_t n, int comp,
+                                                 const float4* __restrict__ src,
+                                                 float* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float4 v = src[i];
+  dst[i] = comp == 0 ? v.x : comp == 1 ? v.y : comp == 2 ? v.z : v.w;
 }
-inline dim3 vox_block() { return dim3(BX, BY, 1); }
 
+inline dim3 gather_grid(const Geo& g, int zv) {
+  const long long nb = (long long)((g.nx + BX - 1) / BX) * ((g.ny + GBY - 1) / GBY) *
+                       ((g.nz + zv - 1) / zv);
+  return dim3((unsigned)((nb + kXCD - 1) / kXCD * kXCD));
+}
 }  // namespace
 
-#define DISPATCH(KERNEL, ...)                                                       \
-  do {                                                                              \
-    if (g.dim == 3)                                                                 \
-      hipLaunchKernelGGL(KERNEL<3>, vox_grid(g), vox_block(), 0, s, __VA_ARGS__);   \
-    else                                                                            \
-      hipLaunchKernelGGL(KERNEL<2>, vox_grid(g), vox_block(), 0, s, __VA_ARGS__);   \
+#define DISPATCH_GATHER(KERNEL, ...)                                                            \
+  do {                                                                                          \
+    if (g.dim == 3)                                                                             \
+      hipLaunchKernelGGL((KERNEL<3, 2>), gather_grid(g, 2), dim3(BX, GBY), 0, s, __VA_ARGS__);  \
+    else                                                                                        \
+      hipLaunchKernelGGL((KERNEL<2, 1>), gather_grid(g, 1), dim3(BX, GBY), 0, s, __VA_ARGS__);  \
   } while (0)
-
-// two voxels per thread along z in 3D, one in 2D
-#define DISPATCH_ZV(KERNEL, ...)                                                          \
-  do {                                                                                    \
-    if (g.dim == 3)                                                                       \
-      hipLaunchKernelGGL((KERNEL<3, 2>), vox_grid(g, 2), vox_block(), 0, s, __VA_ARGS__); \
-    else                                                                                  \
-      hipLaunchKernelGGL((KERNEL<2, 1>), vox_grid(g, 1), vox_block(), 0, s, __VA_ARGS__); \
+#define DISPATCH_GATHER1(KERNEL, ...)                                                           \
+  do {                                                                                          \
+    if (g.dim == 3)                                                                             \
+      hipLaunchKernelGGL((KERNEL<3, 1>), gather_grid(g, 1), dim3(BX, GBY), 0, s, __VA_ARGS__);  \
+    else                                                                                        \
+      hipLaunchKernelGGL((KERNEL<2, 1>), gather_grid(g, 1), dim3(BX, GBY), 0, s, __VA_ARGS__);  \
   } while (0)
-
-void setup(const Geo& g, const float* v, float* X, float* Y, float* a, hipStream_t s) {
-  DISPATCH(k_setup, g, v, X, Y, a);
+#define DISPATCH_ONE(KERNEL, ...)                                                          \
+  do {                                                                                     \
+    if (g.dim == 3)                                                                        \
+      hipLaunchKernelGGL(KERNEL<3>, gather_grid(g, 1), dim3(BX, GBY), 0, s, __VA_ARGS__);  \
+    else                                                                                   \
+      hipLaunchKernelGGL(KERNEL<2>, gather_grid(g, 1), dim3(BX, GBY), 0, s, __VA_ARGS__);  \
+  } while (0)
+void setup(const Geo& g, const float* v, float* X, float4* YA, hipStream_t s) {
+  DISPATCH_ONE(k_setup, g, v, X, YA);
 }
 void state_step(const Geo& g, const float* m_in, const float* X, float* m_out, hipStream_t s) {
-  DISPATCH_ZV(k_state_step, g, m_in, X, m_out);
+  DISPATCH_GATHER(k_state_step, g, m_in, X, m_out);
 }
 void terminal(const Geo& g, const float* mT, const float* I1, float* lam, hipStream_t s) {
-  DISPATCH(k_terminal, g, mT, I1, lam);
+  DISPATCH_ONE(k_terminal, g, mT, I1, lam);
 }
-void adj_step(const Geo& g, const float* lam_in, const float* Y, const float* a, float* lam_out,
+void adj_step(const Geo& g, const float* lam_in, const float4* YA, float* lam_out,
               hipStream_t s) {
-  DISPATCH_ZV(k_adj_step, g, lam_in, Y, a, lam_out);
+  DISPATCH_GATHER(k_adj_step, g, lam_in, YA, lam_out);
 }
 void body_force(const Geo& g, const float* lam, const float* m, float* b, hipStream_t s) {
-  DISPATCH(k_body_force, g, lam, m, b);
+  DISPATCH_GATHER1(k_body_force, g, lam, m, b);
 }
 void inc_init(const Geo& g, const float* m0, const float* dv, float* t0, hipStream_t s) {
-  DISPATCH(k_inc_init, g, m0, dv, t0);
+  DISPATCH_GATHER(k_inc_init, g, m0, dv, t0);
 }
 void inc_step(const Geo& g, const float* t_in, const float* X, const float* m_next,
               const float* dv, float* t_out, hipStream_t s) {
-  DISPATCH_ZV(k_inc_step, g, t_in, X, m_next, dv, t_out);
+  DISPATCH_GATHER(k_inc_step, g, t_in, X, m_next, dv, t_out);
 }
 void inc_last(const Geo& g, const float* t_in, const float* X, const float* mT,
               const float* dv, float* dlam, hipStream_t s) {
-  DISPATCH(k_inc_last, g, t_in, X, mT, dv, dlam);
+  DISPATCH_GATHER(k_inc_last, g, t_in, X, mT, dv, dlam);
 }
 void energy_partial(const Geo& g, const float* mT, const float* I1, double* partial,
                     hipStream_t s) {
   hipLaunchKernelGGL(k_energy_partial, dim3(kRedBlocks), dim3(256), 0, s, g.M, mT, I1, partial);
+}
+void unpack4(const Geo& g, int comp, const float4* in, float* plane, hipStream_t s) {
+  hipLaunchKernelGGL(k_unpack4, dim3((unsigned)((g.M + 255) / 256)), dim3(256), 0, s, g.M, comp,
+                     in, plane);
 }
 
 }  // namespace bl

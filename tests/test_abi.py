@@ -114,7 +114,7 @@ def test_footprint_scales_with_problem(lib):
     assert small > 0 and c2 > 100 * small
     # (nt + 1) state and adjoint planes, offsets, reaction, velocity, ping-pong, body force
     M = 128 ** 3
-    assert c2 >= (11 + 11 + 3 + 3 + 1 + 4 + 3 + 2 + 3 + 1) * 4 * M
+    assert c2 >= (11 + 11 + 3 + 4 + 4 + 3 + 2 + 3 + 1) * 4 * M
 
 
 def test_default_opts(lib):
