@@ -58,6 +58,7 @@ extern "C" {
 #define BL_E_NOMEM       -3   /* the working set does not fit in free device memory         */
 #define BL_E_DEVICE      -4   /* a HIP runtime error                                          */
 #define BL_E_NONFINITE   -5   /* NaN/Inf in an input, in E, in the gradient or in H v         */
+/* -6 (BL_E_CANCELLED) and 1 (BL_PENDING) belong to the serving calls below                   */
 
 /* precision forms */
 #define BL_FP32   0   /* FP32 transforms and transports, FP64 reductions                     */
@@ -214,6 +215,59 @@ int bl_lddmm_device_count(void);
  */
 int bl_kernel_timing_enable(bl_ctx* ctx, int32_t on);
 int bl_kernel_timing_read(bl_ctx* ctx, int32_t kclass, int64_t* launches, double* ms);
+
+/*
+ * Serving: a request loop for many registrations on one GPU (continuous batching).
+ *
+ * Requests (bl_lddmm_register problems, host pointers, any mix of grid sizes, band sizes,
+ * time steps and precisions) enter a FIFO queue.  The head of the queue is admitted as soon
+ * as a slot is free and its device footprint (bl_lddmm_footprint) fits in the remaining
+ * budget; each slot registers its pair on its own HIP stream in a device arena it reuses, so
+ * the work of all resident pairs overlaps on the device and a slot takes the next request
+ * the moment its pair finishes.  Every result is identical to bl_lddmm_register's on the same
+ * inputs (same kernels, same launch shapes, fixed-order reductions).
+ *   server_create   budget_bytes: device memory the resident pairs may use (0: 80% of free);
+ *                   max_slots: pairs resident at once (1..64)
+ *   server_submit   validates, copies I0, I1 (and v_hat if not NULL: initial guess; zero
+ *                   otherwise) and returns a ticket; opts may be NULL (defaults); flags must
+ *                   not contain BL_DEVICE_PTRS.  BL_E_NOMEM if the footprint exceeds the budget.
+ *   server_wait     waits up to timeout_s (< 0: forever) for the request; on completion copies
+ *                   v_hat, warped (each may be NULL), stats and times (may be NULL), releases
+ *                   the ticket and returns the registration's return code; BL_PENDING if it
+ *                   is still queued or running when the timeout expires.
+ *   server_cancel   removes a queued request (its wait returns BL_E_CANCELLED); a running one
+ *                   completes.
+ *   server_destroy  lets running requests finish, drops queued ones, frees everything.
+ * Times are seconds since server_create (steady clock).
+ */
+#define BL_PENDING        1
+#define BL_E_CANCELLED   -6
+
+typedef struct bl_server bl_server;
+
+typedef struct {
+  double submitted;   /* bl_server_submit returned                                         */
+  double admitted;    /* taken by a slot (budget and slot available)                        */
+  double finished;    /* result ready                                                       */
+  int32_t slot;       /* slot that ran it                                                   */
+} bl_request_times;
+
+typedef struct {
+  uint64_t budget_bytes;     /* admission budget                                             */
+  uint64_t peak_bytes;       /* largest sum of footprints resident at once                  */
+  int32_t  max_slots;
+  int32_t  peak_resident;    /* most pairs resident at once                                  */
+  int64_t  submitted, completed, failed, cancelled;
+} bl_server_info;
+
+int bl_server_create(uint64_t budget_bytes, int32_t max_slots, bl_server** server);
+int bl_server_submit(bl_server* server, const bl_problem* prob, const bl_solver_opts* opts,
+                     const float* I0, const float* I1, const float* v_hat, uint64_t* ticket);
+int bl_server_wait(bl_server* server, uint64_t ticket, double timeout_s, float* v_hat,
+                   float* warped, bl_stats* stats, bl_request_times* times);
+int bl_server_cancel(bl_server* server, uint64_t ticket);
+int bl_server_info_get(bl_server* server, bl_server_info* info);
+void bl_server_destroy(bl_server* server);
 
 #ifdef __cplusplus
 }

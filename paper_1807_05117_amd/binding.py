@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libbl_lddmm.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "bl_lddmm.h")
 
 BL_OK, BL_E_INVALID, BL_E_UNSUPPORTED, BL_E_NOMEM, BL_E_DEVICE, BL_E_NONFINITE = 0, -1, -2, -3, -4, -5
+BL_PENDING, BL_E_CANCELLED = 1, -6
 BL_FP32, BL_MIXED = 0, 1
 BL_DEVICE_PTRS = 1
 BL_CONVERGED, BL_MAXITER, BL_STALLED = 0, 1, 2
@@ -65,6 +66,18 @@ class Stats(C.Structure):
                 "eps": list(self.eps[:nit]), "seconds": self.seconds}
 
 
+class RequestTimes(C.Structure):
+    _fields_ = [("submitted", C.c_double), ("admitted", C.c_double), ("finished", C.c_double),
+                ("slot", C.c_int32)]
+
+
+class ServerInfo(C.Structure):
+    _fields_ = [("budget_bytes", C.c_uint64), ("peak_bytes", C.c_uint64),
+                ("max_slots", C.c_int32), ("peak_resident", C.c_int32),
+                ("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("cancelled", C.c_int64)]
+
+
 _lib = None
 _P = C.c_void_p
 
@@ -106,6 +119,14 @@ def load():
         "bl_lddmm_default_opts": (None, [C.POINTER(SolverOpts)]),
         "bl_kernel_timing_enable": (C.c_int, [_P, C.c_int32]),
         "bl_kernel_timing_read": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+        "bl_server_create": (C.c_int, [C.c_uint64, C.c_int32, C.POINTER(C.c_void_p)]),
+        "bl_server_submit": (C.c_int, [_P, PP, C.POINTER(SolverOpts), _P, _P, _P,
+                                       C.POINTER(C.c_uint64)]),
+        "bl_server_wait": (C.c_int, [_P, C.c_uint64, C.c_double, _P, _P, C.POINTER(Stats),
+                                     C.POINTER(RequestTimes)]),
+        "bl_server_cancel": (C.c_int, [_P, C.c_uint64]),
+        "bl_server_info_get": (C.c_int, [_P, C.POINTER(ServerInfo)]),
+        "bl_server_destroy": (None, [_P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -328,3 +349,63 @@ class Ctx:
         ms = C.c_double()
         _check(self.lib.bl_kernel_timing_read(self.h, kclass, C.byref(n), C.byref(ms)))
         return n.value, ms.value
+
+
+# ----------------------------------------------------------------------------- serving
+class Server:
+    """The registration request loop (bl_server_*): submit returns a ticket immediately;
+    wait returns (rc, v_hat, warped, stats, times)."""
+
+    def __init__(self, budget_bytes=0, max_slots=4):
+        self.lib = load()
+        h = C.c_void_p()
+        _check(self.lib.bl_server_create(int(budget_bytes), int(max_slots), C.byref(h)))
+        self.h = h
+        self._shapes = {}
+
+    def submit(self, p, I0, I1, v0=None, opts=None):
+        I0 = _f32(I0, grid_shape(p))
+        I1 = _f32(I1, grid_shape(p))
+        v = _c64(v0, band_shape(p)) if v0 is not None else None
+        t = C.c_uint64()
+        o = C.byref(opts) if opts is not None else None
+        _check(self.lib.bl_server_submit(self.h, C.byref(p), o, _ptr(I0), _ptr(I1),
+                                         _ptr(v) if v is not None else None, C.byref(t)))
+        self._shapes[t.value] = (grid_shape(p), band_shape(p))
+        return t.value
+
+    def wait(self, ticket, timeout=-1.0):
+        gs, bs = self._shapes[ticket]
+        v = np.empty(bs, np.complex64)
+        w = np.empty(gs, np.float32)
+        st = Stats()
+        tm = RequestTimes()
+        rc = self.lib.bl_server_wait(self.h, ticket, float(timeout), _ptr(v), _ptr(w),
+                                     C.byref(st), C.byref(tm))
+        if rc == BL_PENDING:
+            return rc, None, None, None, None
+        self._shapes.pop(ticket, None)
+        times = {"submitted": tm.submitted, "admitted": tm.admitted, "finished": tm.finished,
+                 "slot": tm.slot}
+        if rc != BL_OK:
+            return rc, None, None, None, times
+        return rc, v, w, st.to_dict(), times
+
+    def cancel(self, ticket):
+        return self.lib.bl_server_cancel(self.h, ticket)
+
+    def info(self):
+        i = ServerInfo()
+        _check(self.lib.bl_server_info_get(self.h, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in ServerInfo._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.bl_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,133 @@
+// Host-side internals shared by the C-interface translation units: the device context of one
+// registration problem, validation, transfers and the Gauss-Newton-Krylov driver.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "bl_internal.h"
+#include "bl_lddmm.h"
+
+namespace bl {
+namespace host {
+
+struct DeviceError {
+  hipError_t e;
+  const char* where;
+};
+
+#define HIP_TRY(expr)                                 \
+  do {                                                \
+    hipError_t e_ = (expr);                           \
+    if (e_ != hipSuccess) throw DeviceError{e_, #expr}; \
+  } while (0)
+
+inline void check_launch(const char* where) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw DeviceError{e, where};
+}
+
+struct NonFinite {
+  const char* what;
+};
+
+enum { RED_REG = 0, RED_DATA, RED_A, RED_B, RED_SLOTS };
+
+int fail(int code, const std::string& msg);
+int validate(const bl_problem* p, Geo* g);
+int validate_opts(const bl_solver_opts* o);
+void fill_default(bl_solver_opts* o);
+
+}  // namespace host
+}  // namespace bl
+
+struct bl_ctx {
+  bl::Geo g{};
+  bl_problem prob{};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  bool devptr = false;
+  bool transport = true;
+  char* arena = nullptr;
+  bool own_arena = true;
+  size_t arena_bytes = 0;
+  // grid fields
+  float* I1 = nullptr;
+  float* m = nullptr;      // (nt + 1) planes, m[0] = I0
+  float* X = nullptr;      // dim planes: forward departure offsets
+  float4* YA = nullptr;    // (Y, a): backward offsets and adjoint reaction factor
+  float* V = nullptr;      // dim + 1 planes: v, r
+  float* DV = nullptr;     // dim planes: dv
+  float* T0 = nullptr;
+  float* T1 = nullptr;
+  float* L = nullptr;      // (nt + 1) planes: adjoint or incremental adjoint
+  float* Bf = nullptr;     // dim planes: body force
+  // band vectors (complex)
+  float2* braw = nullptr;  // up to 4 components of staging
+  float2* bv = nullptr;    // dim + 1: projected v, divergence
+  float2* bd = nullptr;    // dim: projected dv
+  float2* bout = nullptr;  // dim
+  float2* P = nullptr;     // up to 4 * kzh * ky * kx
+  float* Lhat = nullptr;
+  double* Lhat64 = nullptr;
+  bl::DftPlan plan;
+  double* red = nullptr;   // RED_SLOTS * kRedBlocks partials
+  double* scal = nullptr;  // device scalars
+  double* hscal = nullptr; // pinned host scalars
+  bool own_hscal = true;
+  int* flag = nullptr;
+  double* hflag_dummy = nullptr;
+  // state of the last velocity
+  bool have_v = false;
+  double E = 0, reg = 0, data_sum = 0;
+  // solver vectors (dim * B complex each)
+  float2 *sv = nullptr, *sg = nullptr, *sdelta = nullptr, *sr = nullptr, *sz = nullptr,
+         *sp = nullptr, *sHp = nullptr, *stry = nullptr;
+  // kernel timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  struct Run { int cls, ev, count; };
+  std::vector<Run> ev_used;  // timed runs: class, pool index of the start event, launches
+  size_t ev_next = 0;
+  int ev_open = -1;
+  int64_t t_launch[3] = {0, 0, 0};
+  double t_ms[3] = {0, 0, 0};
+};
+
+namespace bl {
+namespace host {
+
+// Device bytes of a context (transport fields, solver vectors, mixed-precision tables).
+size_t ctx_bytes(const Geo& g, bool transport, bool solver, bool mixed);
+// A context on the current device.  With arena != nullptr the caller provides (and keeps
+// owning) at least ctx_bytes() of device memory and the stream, and host_scalars (64 pinned
+// doubles) if not NULL; nothing is allocated then.
+bl_ctx* create_ctx(const bl_problem* prob, const Geo& g, bool transport, bool solver,
+                   void* arena = nullptr, size_t arena_bytes = 0, hipStream_t stream = nullptr,
+                   double* host_scalars = nullptr);
+void destroy_ctx(bl_ctx* c);
+void sync(bl_ctx* c);
+void load_images(bl_ctx* c, const float* I0, const float* I1);
+void load_band(bl_ctx* c, const float* src, float2* dst, int ncomp);
+void store_band(bl_ctx* c, const float2* src, float* dst, int ncomp);
+void store_plane(bl_ctx* c, const float* src, float* dst, size_t nplanes);
+void solve(bl_ctx* c, const bl_solver_opts& o, bl_stats* st);
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const DeviceError& e) {
+    return fail(BL_E_DEVICE, std::string("HIP error in ") + e.where + ": " + hipGetErrorString(e.e));
+  } catch (const NonFinite& e) {
+    return fail(BL_E_NONFINITE, std::string("non-finite value in ") + e.what);
+  } catch (const std::bad_alloc&) {
+    return fail(BL_E_NOMEM, "device working set does not fit in free memory");
+  } catch (...) {
+    return fail(BL_E_DEVICE, "unexpected internal error");
+  }
+}
+
+}  // namespace host
+}  // namespace bl

@@ -16,10 +16,10 @@
 #include <string>
 #include <vector>
 
-#include "bl_internal.h"
-#include "bl_lddmm.h"
+#include "bl_host.h"
 
-namespace {
+namespace bl {
+namespace host {
 
 thread_local std::string t_err;
 
@@ -27,26 +27,6 @@ int fail(int code, const std::string& msg) {
   t_err = msg;
   return code;
 }
-
-struct DeviceError {
-  hipError_t e;
-  const char* where;
-};
-
-#define HIP_TRY(expr)                                 \
-  do {                                                \
-    hipError_t e_ = (expr);                           \
-    if (e_ != hipSuccess) throw DeviceError{e_, #expr}; \
-  } while (0)
-
-inline void check_launch(const char* where) {
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) throw DeviceError{e, where};
-}
-
-struct NonFinite {
-  const char* what;
-};
 
 // ------------------------------------------------------------------------------ validation
 int validate(const bl_problem* p, bl::Geo* g) {
@@ -109,63 +89,13 @@ struct Layout {
   }
 };
 
-enum { RED_REG = 0, RED_DATA, RED_A, RED_B, RED_SLOTS };
 
-}  // namespace
+}  // namespace host
+}  // namespace bl
 
-struct bl_ctx {
-  bl::Geo g{};
-  bl_problem prob{};
-  int device = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  bool devptr = false;
-  bool transport = true;
-  char* arena = nullptr;
-  size_t arena_bytes = 0;
-  // grid fields
-  float* I1 = nullptr;
-  float* m = nullptr;      // (nt + 1) planes, m[0] = I0
-  float* X = nullptr;      // dim planes: forward departure offsets
-  float4* YA = nullptr;    // (Y, a): backward offsets and adjoint reaction factor
-  float* V = nullptr;      // dim + 1 planes: v, r
-  float* DV = nullptr;     // dim planes: dv
-  float* T0 = nullptr;
-  float* T1 = nullptr;
-  float* L = nullptr;      // (nt + 1) planes: adjoint or incremental adjoint
-  float* Bf = nullptr;     // dim planes: body force
-  // band vectors (complex)
-  float2* braw = nullptr;  // up to 4 components of staging
-  float2* bv = nullptr;    // dim + 1: projected v, divergence
-  float2* bd = nullptr;    // dim: projected dv
-  float2* bout = nullptr;  // dim
-  float2* P = nullptr;     // up to 4 * kzh * ky * kx
-  float* Lhat = nullptr;
-  double* Lhat64 = nullptr;
-  bl::DftPlan plan;
-  double* red = nullptr;   // RED_SLOTS * kRedBlocks partials
-  double* scal = nullptr;  // device scalars
-  double* hscal = nullptr; // pinned host scalars
-  int* flag = nullptr;
-  double* hflag_dummy = nullptr;
-  // state of the last velocity
-  bool have_v = false;
-  double E = 0, reg = 0, data_sum = 0;
-  // solver vectors (dim * B complex each)
-  float2 *sv = nullptr, *sg = nullptr, *sdelta = nullptr, *sr = nullptr, *sz = nullptr,
-         *sp = nullptr, *sHp = nullptr, *stry = nullptr;
-  // kernel timing
-  bool timing = false;
-  std::vector<hipEvent_t> ev_pool;
-  struct Run { int cls, ev, count; };
-  std::vector<Run> ev_used;  // timed runs: class, pool index of the start event, launches
-  size_t ev_next = 0;
-  int ev_open = -1;
-  int64_t t_launch[3] = {0, 0, 0};
-  double t_ms[3] = {0, 0, 0};
-};
 
-namespace {
+namespace bl {
+namespace host {
 
 size_t plane_bytes(const bl::Geo& g) { return (size_t)g.M * sizeof(float); }
 size_t band_bytes(const bl::Geo& g) { return (size_t)g.B * sizeof(float2); }
@@ -310,13 +240,14 @@ void destroy_ctx(bl_ctx* c) {
   hipSetDevice(c->device);
   if (c->stream) hipStreamSynchronize(c->stream);
   for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
-  if (c->arena) hipFree(c->arena);
-  if (c->hscal) hipHostFree(c->hscal);
+  if (c->arena && c->own_arena) hipFree(c->arena);
+  if (c->hscal && c->own_hscal) hipHostFree(c->hscal);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   delete c;
 }
 
-bl_ctx* create_ctx(const bl_problem* prob, const bl::Geo& g, bool transport, bool solver) {
+bl_ctx* create_ctx(const bl_problem* prob, const bl::Geo& g, bool transport, bool solver,
+                   void* arena, size_t arena_bytes, hipStream_t stream, double* host_scalars) {
   bl_ctx* c = new bl_ctx();
   try {
     c->g = g;
@@ -324,7 +255,10 @@ bl_ctx* create_ctx(const bl_problem* prob, const bl::Geo& g, bool transport, boo
     c->devptr = (prob->flags & BL_DEVICE_PTRS) != 0;
     c->transport = transport;
     HIP_TRY(hipGetDevice(&c->device));
-    if (c->devptr) {
+    if (arena) {
+      c->stream = stream;          // caller-owned arena and stream
+      c->own_stream = false;
+    } else if (c->devptr) {
       c->stream = (hipStream_t)prob->stream;
       c->own_stream = false;
     } else {
@@ -333,10 +267,17 @@ bl_ctx* create_ctx(const bl_problem* prob, const bl::Geo& g, bool transport, boo
     }
     const bool mixed = prob->precision == BL_MIXED;
     const Offsets o = plan_layout(g, transport, solver, mixed);
-    size_t free_b = 0, total_b = 0;
-    HIP_TRY(hipMemGetInfo(&free_b, &total_b));
-    if (o.total + (64u << 20) > free_b) throw std::bad_alloc();
-    HIP_TRY(hipMalloc(&c->arena, o.total));
+    if (arena) {
+      if (arena_bytes < o.total) throw std::bad_alloc();
+      c->arena = static_cast<char*>(arena);
+      c->own_arena = false;
+    } else {
+      size_t free_b = 0, total_b = 0;
+      HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+      if (o.total + (64u << 20) > free_b) throw std::bad_alloc();
+      HIP_TRY(hipMalloc(&c->arena, o.total));
+      c->own_arena = true;
+    }
     c->arena_bytes = o.total;
     char* a = c->arena;
     auto F = [&](size_t off) { return reinterpret_cast<float*>(a + off); };
@@ -373,7 +314,12 @@ bl_ctx* create_ctx(const bl_problem* prob, const bl::Geo& g, bool transport, boo
       c->sv = s; c->sg = s + nb; c->sdelta = s + 2 * nb; c->sr = s + 3 * nb; c->sz = s + 4 * nb;
       c->sp = s + 5 * nb; c->sHp = s + 6 * nb; c->stry = s + 7 * nb;
     }
-    HIP_TRY(hipHostMalloc((void**)&c->hscal, 64 * sizeof(double), hipHostMallocDefault));
+    if (host_scalars) {
+      c->hscal = host_scalars;
+      c->own_hscal = false;
+    } else {
+      HIP_TRY(hipHostMalloc((void**)&c->hscal, 64 * sizeof(double), hipHostMallocDefault));
+    }
     // host tables: twiddles of exactly reduced angles, the symbol of L
     std::vector<float2> tw;
     auto upload = [&](float2* dst) {
@@ -727,19 +673,8 @@ void solve(bl_ctx* c, const bl_solver_opts& o, bl_stats* st) {
   }
 }
 
-template <class F>
-int guarded(F&& f) {
-  try {
-    return f();
-  } catch (const DeviceError& e) {
-    return fail(BL_E_DEVICE, std::string("HIP error in ") + e.where + ": " + hipGetErrorString(e.e));
-  } catch (const NonFinite& e) {
-    return fail(BL_E_NONFINITE, std::string("non-finite value in ") + e.what);
-  } catch (const std::bad_alloc&) {
-    return fail(BL_E_NOMEM, "device working set does not fit in free memory");
-  } catch (...) {
-    return fail(BL_E_DEVICE, "unexpected internal error");
-  }
+size_t ctx_bytes(const bl::Geo& g, bool transport, bool solver, bool mixed) {
+  return plan_layout(g, transport, solver, mixed).total;
 }
 
 struct CtxHolder {
@@ -747,9 +682,12 @@ struct CtxHolder {
   ~CtxHolder() { destroy_ctx(c); }
 };
 
-}  // namespace
+}  // namespace host
+}  // namespace bl
 
 // ================================================================================ C-ABI
+using namespace bl::host;
+
 extern "C" {
 
 void bl_lddmm_default_opts(bl_solver_opts* opts) {

@@ -89,39 +89,52 @@ __global__ __launch_bounds__(256) void k_iota_z_mfma(Geo g, const float2* __rest
   const u16x8* Whi = reinterpret_cast<const u16x8*>(Wi);
   const u16x8* Wlo = reinterpret_cast<const u16x8*>(Wi + (size_t)nzp32 * KP);
   float* dst = out + (size_t)c * g.M + qc;
-  for (int zt = 0; zt * 32 < g.nz; ++zt) {
-    f32x16 acc;
+  // z tiles four at a time: the A operands of the four tiles are loaded before any product
+  for (int zt0 = 0; zt0 * 32 < g.nz; zt0 += 4) {
+    bf16x8 ahi[4][KS], alo[4][KS];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-    const int zrow = zt * 32 + col;   // A row of this lane (zero-padded table rows)
+    for (int u = 0; u < 4; ++u) {
+      // A row of this lane; rows past the table (tiles beyond nz) reuse row 0, never stored
+      const int zrow = (zt0 + u) * 32 < g.nz ? (zt0 + u) * 32 + col : col;
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      const size_t ai = ((size_t)zrow * KP + 16 * s + 8 * kq) / 8;
-      const bf16x8 ahi = __builtin_bit_cast(bf16x8, Whi[ai]);
-      const bf16x8 alo = __builtin_bit_cast(bf16x8, Wlo[ai]);
-      acc = mfma3(ahi, alo, bhi[s], blo[s], acc);
+      for (int s = 0; s < KS; ++s) {
+        const size_t ai = ((size_t)zrow * KP + 16 * s + 8 * kq) / 8;
+        ahi[u][s] = __builtin_bit_cast(bf16x8, Whi[ai]);
+        alo[u][s] = __builtin_bit_cast(bf16x8, Wlo[ai]);
+      }
     }
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int z = zt * 32 + 8 * (r >> 2) + 4 * kq + (r & 3);
-      if (z < g.nz && q < nq) dst[(size_t)z * nq] = acc[r];
+    for (int u = 0; u < 4; ++u) {
+      const int zt = zt0 + u;
+      if (zt * 32 >= g.nz) break;
+      f32x16 acc;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+#pragma unroll
+      for (int s = 0; s < KS; ++s) acc = mfma3(ahi[u][s], alo[u][s], bhi[s], blo[s], acc);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int z = zt * 32 + 8 * (r >> 2) + 4 * kq + (r & 3);
+        if (z < g.nz && q < nq) dst[(size_t)z * nq] = acc[r];
+      }
     }
   }
 }
 
-// pi z stage.  One wavefront per (component, 32 columns); the wavefront walks z in steps of
-// 16 planes, splitting its B operand on the fly, for JT 32-row tiles of (Re, Im) outputs.
-// Wp is [2][32 JT][nzp16] BF16 (hi table then lo table).
+// pi z stage.  One block of four wavefronts per (component, 32 columns); wavefront w takes
+// the 16-plane steps w, w + 4, ... two at a time (16 loads in flight), splitting its B operand
+// on the fly, for JT 32-row tiles of (Re, Im) outputs; the four partial accumulators are
+// added in LDS in a fixed order.  Wp is [2][32 JT][nzp16] BF16 (hi table then lo table).
 template <int JT>
 __global__ __launch_bounds__(256) void k_pi_z_mfma(Geo g, const float* __restrict__ f,
                                                    const unsigned short* __restrict__ Wp,
-                                                   int nzp16, float2* __restrict__ G, int nqt) {
+                                                   int nzp16, float2* __restrict__ G) {
+  __shared__ float red[3][JT][16][64];
   const int lane = threadIdx.x & 63;
-  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nq = g.nx * g.ny;
   const int c = blockIdx.y;
-  if (wave >= nqt) return;
-  const int q0 = wave * 32;
+  const int q0 = blockIdx.x * 32;
   const int col = lane & 31, kq = lane >> 5;
   const int q = q0 + col;
   const int qc = q < nq ? q : nq - 1;
@@ -133,31 +146,52 @@ __global__ __launch_bounds__(256) void k_pi_z_mfma(Geo g, const float* __restric
   const float* src = f + (size_t)c * g.M + qc;
   const u16x8* Whi = reinterpret_cast<const u16x8*>(Wp);
   const u16x8* Wlo = reinterpret_cast<const u16x8*>(Wp + (size_t)32 * JT * nzp16);
-  for (int z0 = 0; z0 < g.nz; z0 += 16) {
-    float v[8];
+  const int nsteps = (g.nz + 15) / 16;
+  for (int s0 = w; s0 < nsteps; s0 += 8) {
+    float v[2][8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int z = z0 + 8 * kq + e;
-      v[e] = src[(size_t)(z < g.nz ? z : g.nz - 1) * nq];
-      if (z >= g.nz || q >= nq) v[e] = 0.f;
-    }
-    u16x8 hv, lv;
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      unsigned short a, b;
-      split_bf16(v[e], a, b);
-      hv[e] = a;
-      lv[e] = b;
-    }
-    const bf16x8 bhi = __builtin_bit_cast(bf16x8, hv);
-    const bf16x8 blo = __builtin_bit_cast(bf16x8, lv);
+      for (int e = 0; e < 8; ++e) {
+        const int z = 16 * (s0 + 4 * u) + 8 * kq + e;
+        v[u][e] = src[(size_t)(z < g.nz ? z : g.nz - 1) * nq];
+        if (z >= g.nz || q >= nq) v[u][e] = 0.f;
+      }
 #pragma unroll
-    for (int t = 0; t < JT; ++t) {
-      const size_t ai = ((size_t)(32 * t + col) * nzp16 + z0 + 8 * kq) / 8;
-      acc[t] = mfma3(__builtin_bit_cast(bf16x8, Whi[ai]), __builtin_bit_cast(bf16x8, Wlo[ai]),
-                     bhi, blo, acc[t]);
+    for (int u = 0; u < 2; ++u) {
+      const int z0 = 16 * (s0 + 4 * u);
+      if (z0 >= g.nz) break;
+      u16x8 hv, lv;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        unsigned short a, b;
+        split_bf16(v[u][e], a, b);
+        hv[e] = a;
+        lv[e] = b;
+      }
+      const bf16x8 bhi = __builtin_bit_cast(bf16x8, hv);
+      const bf16x8 blo = __builtin_bit_cast(bf16x8, lv);
+#pragma unroll
+      for (int t = 0; t < JT; ++t) {
+        const size_t ai = ((size_t)(32 * t + col) * nzp16 + z0 + 8 * kq) / 8;
+        acc[t] = mfma3(__builtin_bit_cast(bf16x8, Whi[ai]), __builtin_bit_cast(bf16x8, Wlo[ai]),
+                       bhi, blo, acc[t]);
+      }
     }
   }
+  if (w > 0) {
+#pragma unroll
+    for (int t = 0; t < JT; ++t)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) red[w - 1][t][r][lane] = acc[t][r];
+  }
+  __syncthreads();
+  if (w != 0) return;
+#pragma unroll
+  for (int t = 0; t < JT; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      acc[t][r] = ((acc[t][r] + red[0][t][r][lane]) + red[1][t][r][lane]) + red[2][t][r][lane];
   // rows j = 8 (r / 4) + 4 kq + r % 4: registers (r, r + 1) with r % 4 in {0, 2} hold the
   // (Re, Im) pair of h = j / 2
   float2* dst = G + (size_t)c * g.kzh * nq + qc;
@@ -200,20 +234,19 @@ void iota_z_mixed(const Geo& g, const DftPlan& p, const float2* F2, int C, float
 
 void pi_z_mixed(const Geo& g, const DftPlan& p, const float* f, int C, float2* G, hipStream_t s) {
   const int nq = g.nx * g.ny;
-  const int nqt = (nq + 31) / 32;
-  const dim3 grid((nqt + 3) / 4, C);
+  const dim3 grid((nq + 31) / 32, C);
   switch (mixed_jt(g)) {
     case 1:
-      hipLaunchKernelGGL(k_pi_z_mfma<1>, grid, dim3(256), 0, s, g, f, p.wp_bf16, p.nzp16, G, nqt);
+      hipLaunchKernelGGL(k_pi_z_mfma<1>, grid, dim3(256), 0, s, g, f, p.wp_bf16, p.nzp16, G);
       break;
     case 2:
-      hipLaunchKernelGGL(k_pi_z_mfma<2>, grid, dim3(256), 0, s, g, f, p.wp_bf16, p.nzp16, G, nqt);
+      hipLaunchKernelGGL(k_pi_z_mfma<2>, grid, dim3(256), 0, s, g, f, p.wp_bf16, p.nzp16, G);
       break;
     case 3:
-      hipLaunchKernelGGL(k_pi_z_mfma<3>, grid, dim3(256), 0, s, g, f, p.wp_bf16, p.nzp16, G, nqt);
+      hipLaunchKernelGGL(k_pi_z_mfma<3>, grid, dim3(256), 0, s, g, f, p.wp_bf16, p.nzp16, G);
       break;
     default:
-      hipLaunchKernelGGL(k_pi_z_mfma<4>, grid, dim3(256), 0, s, g, f, p.wp_bf16, p.nzp16, G, nqt);
+      hipLaunchKernelGGL(k_pi_z_mfma<4>, grid, dim3(256), 0, s, g, f, p.wp_bf16, p.nzp16, G);
       break;
   }
 }

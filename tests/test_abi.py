@@ -122,3 +122,16 @@ def test_default_opts(lib):
     lib.bl_lddmm_default_opts(C.byref(o))
     assert (o.max_gn, o.max_pcg, o.max_halvings) == (10, 10, 10)
     assert o.gtol == 1e-3 and o.c1 == 1e-4
+
+
+def test_server_arguments_rejected(lib):
+    h = C.c_void_p()
+    assert lib.bl_server_create(0, 0, C.byref(h)) == B.BL_E_INVALID
+    assert lib.bl_server_create(0, 65, C.byref(h)) == B.BL_E_INVALID
+    assert lib.bl_server_create(0, 2, None) == B.BL_E_INVALID
+    t = C.c_uint64()
+    p = _p()
+    assert lib.bl_server_submit(None, C.byref(p), None, None, None, None, C.byref(t)) == B.BL_E_INVALID
+    assert lib.bl_server_wait(None, 1, 0.0, None, None, None, None) == B.BL_E_INVALID
+    assert lib.bl_server_cancel(None, 1) == B.BL_E_INVALID
+    lib.bl_server_destroy(None)
