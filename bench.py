@@ -192,6 +192,91 @@ def cpu_leg(stats):
             "hv_per_s": 1.0 / t_hv}
 
 
+SERVE_SIZES = [(96, 96, 96), (128, 128, 128), (160, 192, 160)]
+
+
+def serve_leg(n_pairs=64, rate=4.0, slots=8, seed=1000):
+    """Continuous-batching request loop on a stream of registration pairs of mixed sizes:
+    grids uniform over 96^3, 128^3 and 160x192x160, band = grid/4 per axis, Nt in {5, 10},
+    per-pair velocity seeds (6 voxels).  Three runs over the same pairs: sequential plain FP32
+    (one bl_lddmm_register after the other), saturated mixed-precision serving (all pairs
+    queued at t = 0) and open-loop mixed-precision serving with Poisson arrivals."""
+    rng = np.random.default_rng(seed)
+    base = {}
+    for i, shp in enumerate(SERVE_SIZES):
+        base[shp] = phantoms.shells_3d(seed + i, shp, n_classes=3 if i < 2 else 5).astype(np.float32)
+    pairs = []
+    for i in range(n_pairs):
+        shp = SERVE_SIZES[int(rng.integers(len(SERVE_SIZES)))]
+        nt = int(rng.choice([5, 10]))
+        band = tuple(n // 4 for n in shp)
+        raw = phantoms.raw_band_velocity(seed + 10 + i, 3, band).astype(np.complex64)
+        p = B.make_problem(3, shp, band, nt)
+        v = B.bl_band_to_grid(p, raw)
+        vmax = float(np.sqrt((v.astype(np.float64) ** 2).sum(axis=0)).max()) * max(shp)
+        I1 = B.bl_lddmm_warp(p, base[shp], (raw * (DISP / vmax)).astype(np.complex64))
+        pairs.append((shp, band, nt, base[shp], I1))
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_pairs))
+    progress(f"serving: {n_pairs} pairs ready; sequential FP32")
+
+    def prob(i, precision):
+        shp, band, nt, _, _ = pairs[i]
+        return B.make_problem(3, shp, band, nt, precision=precision)
+
+    seq_mse = []
+    t0 = time.perf_counter()
+    for i, (shp, band, nt, I0, I1) in enumerate(pairs):
+        v0 = np.zeros(B.band_shape(prob(i, B.BL_FP32)), np.complex64)
+        _, _, st = B.bl_lddmm_register(prob(i, B.BL_FP32), I0, I1, v0)
+        seq_mse.append(st["mse_rel"][-1])
+    t_seq = time.perf_counter() - t0
+
+    def serve(arrive):
+        srv = B.Server(max_slots=slots)
+        t_start = time.perf_counter()
+        tickets = []
+        for i, (shp, band, nt, I0, I1) in enumerate(pairs):
+            if arrive is not None:
+                delay = arrive[i] - (time.perf_counter() - t_start)
+                if delay > 0:
+                    time.sleep(delay)
+            tickets.append(srv.submit(prob(i, B.BL_MIXED), I0, I1))
+        lat, mse = [], []
+        for t in tickets:
+            rc, _, _, st, tm = srv.wait(t)
+            if rc != B.BL_OK:
+                raise RuntimeError(f"serving request failed: {rc}")
+            lat.append(tm["finished"] - tm["submitted"])
+            mse.append(st["mse_rel"][-1])
+        wall = time.perf_counter() - t_start
+        info = srv.info()
+        srv.close()
+        return wall, lat, mse, info
+
+    progress("serving: saturated")
+    w_sat, lat_sat, mse_sat, info_sat = serve(None)
+    progress("serving: Poisson arrivals")
+    w_poi, lat_poi, mse_poi, info_poi = serve(arrivals)
+    dm = [abs(a - b) / max(abs(b), 1e-12) for a, b in zip(mse_sat, seq_mse)]
+    return {
+        "pairs": n_pairs, "slots": slots,
+        "grids": [list(g) for g in SERVE_SIZES], "band": "grid/4", "nt": [5, 10],
+        "sequential_fp32": {"registrations_per_min": 60.0 * n_pairs / t_seq, "seconds": t_seq},
+        "saturated_mixed": {"registrations_per_min": 60.0 * n_pairs / w_sat, "seconds": w_sat,
+                            "p50_ms": 1000 * percentile(lat_sat, 50),
+                            "p99_ms": 1000 * percentile(lat_sat, 99),
+                            "peak_resident": info_sat["peak_resident"],
+                            "peak_gb": info_sat["peak_bytes"] / 1e9},
+        "poisson_mixed": {"rate_per_s": rate, "seconds": w_poi,
+                          "registrations_per_min": 60.0 * n_pairs / w_poi,
+                          "p50_ms": 1000 * percentile(lat_poi, 50),
+                          "p99_ms": 1000 * percentile(lat_poi, 99),
+                          "peak_resident": info_poi["peak_resident"]},
+        "speedup_saturated_vs_sequential_fp32": t_seq / w_sat,
+        "final_mse_rel_max_rel_diff_vs_fp32": max(dm),
+    }
+
+
 def traffic_record(kernel):
     """Per-launch HBM bytes of `kernel` from the committed counter summary, if it was taken on
     the kernel source that is built now (else None)."""
@@ -217,6 +302,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
     ap.add_argument("--quick", action="store_true",
                     help="fewer Hessian-vector repetitions (for profiler passes)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the registration path has no multi-GPU mode "
@@ -287,6 +373,8 @@ def main():
                      "copy_gbs": r["copy_gbs"], "frac_of_copy": achieved / r["copy_gbs"]},
         "cpu_baseline": None,
     }
+    if not args.no_serve:
+        line["serving"] = serve_leg()
     if not args.no_cpu:
         progress("oracle baseline on the host")
         line["cpu_baseline"] = cpu_leg(r["stats"])

@@ -57,7 +57,7 @@ import numpy as np
 
 __all__ = [
     "Problem", "band_freqs", "project", "zero_unpaired", "iota", "pi_", "L_hat",
-    "div_band", "interp", "grad_c", "trapezoid_weights", "setup", "forward_state",
+    "div_band", "iota_at", "pi_at", "interp", "grad_c", "trapezoid_weights", "setup", "forward_state",
     "energy", "State", "evaluate", "gradient", "hessvec", "warp", "dot", "norm2",
     "norm_inf", "mse_rel", "register", "SolverOpts", "CONVERGED", "MAXITER", "STALLED",
     "max_displacement_voxels",
@@ -182,6 +182,47 @@ def pi_(f: np.ndarray, prob: Problem) -> np.ndarray:
     else:
         out = np.einsum("zc,yb,xa,zyx->cba", E[2], E[1], E[0], f, optimize=True)
     return zero_unpaired(out / prob.M, prob)
+
+
+def iota_at(vh: np.ndarray, prob: Problem, points) -> np.ndarray:
+    """iota of one component at selected grid points only (same definition as iota, R4).
+
+    points: integer array (P, dim) of NumPy-order grid indices ([z,] y, x).  Used to check
+    single outputs of grids too large for the full transform.
+    """
+    vh = np.asarray(vh, dtype=np.complex128)
+    pts = np.asarray(points, dtype=np.int64).reshape(-1, prob.dim)
+    out = np.empty(len(pts))
+    for p, idx in enumerate(pts):
+        acc = vh
+        for a in range(prob.dim - 1, -1, -1):  # contract the last band axis first
+            N, K = prob.shape[a], prob.bshape[a]
+            e = np.exp(2j * np.pi * idx[a] * band_freqs(K) / N)
+            acc = acc @ e
+        out[p] = acc.real
+    return out
+
+
+def pi_at(f: np.ndarray, prob: Problem, kidx) -> np.ndarray:
+    """pi of one grid field at selected band indices only (same definition as pi_, R4).
+
+    kidx: integer array (P, dim) of NumPy-order band indices (index j <-> k = j - K/2);
+    entries on an unpaired plane are zero.
+    """
+    f = np.asarray(f, dtype=np.float64)
+    ks = np.asarray(kidx, dtype=np.int64).reshape(-1, prob.dim)
+    out = np.empty(len(ks), dtype=np.complex128)
+    for p, kk in enumerate(ks):
+        if np.any(kk == 0):
+            out[p] = 0.0
+            continue
+        acc = f
+        for a in range(prob.dim - 1, -1, -1):
+            N, K = prob.shape[a], prob.bshape[a]
+            e = np.exp(-2j * np.pi * np.arange(N) * (kk[a] - K // 2) / N)
+            acc = acc @ e
+        out[p] = acc / prob.M
+    return out
 
 
 def _kl(prob: Problem):

@@ -119,6 +119,7 @@ def load():
         "bl_lddmm_default_opts": (None, [C.POINTER(SolverOpts)]),
         "bl_kernel_timing_enable": (C.c_int, [_P, C.c_int32]),
         "bl_kernel_timing_read": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+        "bl_lddmm_ctx_launch_shapes": (C.c_int, [_P, C.POINTER(C.c_int32)]),
         "bl_server_create": (C.c_int, [C.c_uint64, C.c_int32, C.POINTER(C.c_void_p)]),
         "bl_server_submit": (C.c_int, [_P, PP, C.POINTER(SolverOpts), _P, _P, _P,
                                        C.POINTER(C.c_uint64)]),
@@ -349,6 +350,13 @@ class Ctx:
         ms = C.c_double()
         _check(self.lib.bl_kernel_timing_read(self.h, kclass, C.byref(n), C.byref(ms)))
         return n.value, ms.value
+
+    def bl_lddmm_ctx_launch_shapes(self):
+        """voxels per thread along z of the transport launches: state, incremental, adjoint,
+        body force"""
+        out = (C.c_int32 * 4)()
+        _check(self.lib.bl_lddmm_ctx_launch_shapes(self.h, out))
+        return tuple(out)
 
 
 # ----------------------------------------------------------------------------- serving

@@ -32,6 +32,10 @@ struct NonFinite {
 };
 
 enum { RED_REG = 0, RED_DATA, RED_A, RED_B, RED_SLOTS };
+// slots of the device scalars (bl_ctx::scal) and of their host-mapped mirror (bl_ctx::hscal)
+enum {
+  S_REG = 0, S_DATA, S_GG, S_GINF, S_PHP, S_SLOPE, S_RR, S_RZ0, S_RZ1, S_SQD, S_FLAG, S_SLOTS
+};
 
 int fail(int code, const std::string& msg);
 int validate(const bl_problem* p, Geo* g);
@@ -74,10 +78,13 @@ struct bl_ctx {
   bl::DftPlan plan;
   double* red = nullptr;   // RED_SLOTS * kRedBlocks partials
   double* scal = nullptr;  // device scalars
-  double* hscal = nullptr; // pinned host scalars
+  double* hscal = nullptr; // pinned, coherent host scalars (64 doubles) written by kernels
+  double* hdev = nullptr;  // device address of hscal
   bool own_hscal = true;
   int* flag = nullptr;
   double* hflag_dummy = nullptr;
+  // transport launch shapes chosen for this grid shape (Geo::zv)
+  bool tuned = false;
   // state of the last velocity
   bool have_v = false;
   double E = 0, reg = 0, data_sum = 0;
@@ -101,12 +108,14 @@ namespace host {
 // Device bytes of a context (transport fields, solver vectors, mixed-precision tables).
 size_t ctx_bytes(const Geo& g, bool transport, bool solver, bool mixed);
 // A context on the current device.  With arena != nullptr the caller provides (and keeps
-// owning) at least ctx_bytes() of device memory and the stream, and host_scalars (64 pinned
-// doubles) if not NULL; nothing is allocated then.
+// owning) at least ctx_bytes() of device memory and the stream, and host_scalars (64 doubles
+// from alloc_host_scalars) if not NULL; nothing is allocated then.
 bl_ctx* create_ctx(const bl_problem* prob, const Geo& g, bool transport, bool solver,
                    void* arena = nullptr, size_t arena_bytes = 0, hipStream_t stream = nullptr,
                    double* host_scalars = nullptr);
 void destroy_ctx(bl_ctx* c);
+// 64 doubles of pinned, coherent, device-mapped host memory for published scalars
+double* alloc_host_scalars();
 void sync(bl_ctx* c);
 void load_images(bl_ctx* c, const float* I0, const float* I1);
 void load_band(bl_ctx* c, const float* src, float2* dst, int ncomp);

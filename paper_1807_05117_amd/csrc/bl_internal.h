@@ -22,7 +22,13 @@ struct Geo {
   float dt;           // 1/nt
   float half_nref;    // nref/2 (central difference scale)
   float lam_scale;    // -2/sigma^2
+  // voxels per thread along z of the transport launches, per kernel class (TR_*): a launch
+  // shape only, every choice computes bitwise the same values
+  int zv[4];
 };
+
+// kernel classes of the transport launch shapes (Geo::zv)
+enum { TR_STATE = 0, TR_INC, TR_ADJ, TR_FORCE };
 
 // Work buffers and twiddle tables of the band<->grid transforms.
 constexpr int kYG = 8;     // y outputs per thread in the iota y stage
@@ -94,17 +100,27 @@ void inc_last(const Geo& g, const float* t_in, const float* X, const float* mT,
 void unpack4(const Geo& g, int comp, const float4* in, float* plane, hipStream_t s);
 
 // ---- reductions and band vector algebra (bl_reduce.hip)
-// out[0] = sum of n partials in a fixed order (one block)
-void reduce_final(const double* partial, int n, double* out, hipStream_t s);
+// out[0] = sum of n partials in a fixed order (one block); also stored to host[0] (host-mapped
+// pinned memory) when host != NULL, and *flag published to host_flag[0] when flag != NULL
+void reduce_final(const double* partial, int n, double* out, hipStream_t s,
+                  double* host = nullptr, const int* flag = nullptr, double* host_flag = nullptr);
 // kRedBlocks partials of Re sum conj(a) b over n complex entries
 void dot_partial(const float2* a, const float2* b, int64_t n, double* partial, hipStream_t s);
 // kRedBlocks partials of max |a|
 void maxabs_partial(const float2* a, int64_t n, double* partial, hipStream_t s);
-void reduce_max_final(const double* partial, int n, double* out, hipStream_t s);
+void reduce_max_final(const double* partial, int n, double* out, hipStream_t s,
+                      double* host = nullptr, const int* flag = nullptr,
+                      double* host_flag = nullptr);
 // y = alpha x + y
 void axpy(float2* y, const float2* x, double alpha, int64_t n, hipStream_t s);
 // y = x + beta y
 void xpby(float2* y, const float2* x, double beta, int64_t n, hipStream_t s);
+// y += sign * (num[0] / den[0]) x with device scalars (no update unless den[0] > 0)
+void axpy_dev(float2* y, const float2* x, const double* num, const double* den, double sign,
+              int64_t n, hipStream_t s);
+// y = x + (num[0] / den[0]) y with device scalars
+void xpby_dev(float2* y, const float2* x, const double* num, const double* den, int64_t n,
+              hipStream_t s);
 // z = r / Lhat (per component); also kRedBlocks partials of <r, r> (p0) and <r, z> (p1)
 void precond_dots(const Geo& g, const float2* r, const float* Lhat, float2* z, double* p0,
                   double* p1, hipStream_t s);

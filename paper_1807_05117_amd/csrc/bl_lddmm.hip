@@ -8,10 +8,14 @@
 // and Armijo backtracking.  All arithmetic runs in the kernels of the other translation
 // units; this file only sequences launches, copies and scalar read-backs.
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -65,6 +69,11 @@ int validate(const bl_problem* p, bl::Geo* g) {
     g->dt = (float)(1.0 / p->nt);
     g->half_nref = 0.5f * (float)g->nref;
     g->lam_scale = (float)(-2.0 / (p->sigma * p->sigma));
+    const bool d3 = p->dim == 3;
+    g->zv[bl::TR_STATE] = d3 ? 2 : 1;
+    g->zv[bl::TR_INC] = d3 ? 2 : 1;
+    g->zv[bl::TR_ADJ] = d3 ? 2 : 1;
+    g->zv[bl::TR_FORCE] = 1;
   }
   return BL_OK;
 }
@@ -235,6 +244,14 @@ void mixed_tables(const bl::Geo& g, std::vector<unsigned short>& wi,
     }
 }
 
+double* alloc_host_scalars() {
+  // coherent: kernels store straight to host memory, visible once the stream has synchronised
+  double* h = nullptr;
+  HIP_TRY(hipHostMalloc((void**)&h, 64 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
+  for (int i = 0; i < 64; ++i) h[i] = 0.0;
+  return h;
+}
+
 void destroy_ctx(bl_ctx* c) {
   if (!c) return;
   hipSetDevice(c->device);
@@ -318,8 +335,9 @@ bl_ctx* create_ctx(const bl_problem* prob, const bl::Geo& g, bool transport, boo
       c->hscal = host_scalars;
       c->own_hscal = false;
     } else {
-      HIP_TRY(hipHostMalloc((void**)&c->hscal, 64 * sizeof(double), hipHostMallocDefault));
+      c->hscal = alloc_host_scalars();
     }
+    HIP_TRY(hipHostGetDevicePointer((void**)&c->hdev, c->hscal, 0));
     // host tables: twiddles of exactly reduced angles, the symbol of L
     std::vector<float2> tw;
     auto upload = [&](float2* dst) {
@@ -409,10 +427,76 @@ void t_collect(bl_ctx* c) {
 }
 
 // ------------------------------------------------------------------------------ operators
-double read_scalars(bl_ctx* c, int n) {
-  HIP_TRY(hipMemcpyAsync(c->hscal, c->scal, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  sync(c);
-  return c->hscal[0];
+// ------------------------------------------------------------------ transport launch shapes
+// Tiles of 64 x 4 x zv voxels; zv only changes how many voxels one thread handles, never the
+// arithmetic of a voxel.  Candidates are timed on the context's own offset fields right after
+// the first setup on a grid shape (the gathers' cache behaviour depends on the real offsets);
+// the planes they write (T0, T1, Bf) are work space that every operation rewrites before use.
+std::mutex g_shape_mu;
+std::map<std::array<int, 4>, std::array<int, 4>> g_shapes;
+
+void choose_launch_shapes(bl_ctx* c) {
+  c->tuned = true;
+  bl::Geo& g = c->g;
+  if (g.dim != 3 || !c->transport) return;
+  const char* env = std::getenv("BL_TRANSPORT_ZV");
+  if (env && *env) {
+    const int v = std::atoi(env);
+    if (v == 1 || v == 2 || v == 4)
+      for (int k = 0; k < 4; ++k) g.zv[k] = v;
+    return;  // any other value keeps the defaults
+  }
+  const std::array<int, 4> key = {g.dim, g.nx, g.ny, g.nz};
+  {
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    auto it = g_shapes.find(key);
+    if (it != g_shapes.end()) {
+      for (int k = 0; k < 4; ++k) g.zv[k] = it->second[k];
+      return;
+    }
+  }
+  hipStream_t s = c->stream;
+  const size_t M = (size_t)g.M;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  struct Ev {
+    hipEvent_t a, b;
+    ~Ev() { hipEventDestroy(a); hipEventDestroy(b); }
+  } ev{e0, e1};
+  auto launch = [&](int cls) {
+    switch (cls) {
+      case bl::TR_STATE: bl::state_step(g, c->m, c->X, c->T0, s); break;
+      case bl::TR_INC: bl::inc_step(g, c->T0, c->X, c->m + M, c->DV, c->T1, s); break;
+      case bl::TR_ADJ: bl::adj_step(g, c->T0, c->YA, c->T1, s); break;
+      default: bl::body_force(g, c->L, c->m, c->Bf, s); break;
+    }
+  };
+  constexpr int kReps = 4;
+  std::array<int, 4> best;
+  for (int cls = 0; cls < 4; ++cls) {
+    const int dflt = g.zv[cls];
+    float t_best = 0.f;
+    best[cls] = dflt;
+    for (int zv : {dflt, 1, 2, 4}) {
+      if (zv == dflt && t_best > 0.f) continue;
+      g.zv[cls] = zv;
+      launch(cls);  // warm-up
+      HIP_TRY(hipEventRecord(e0, s));
+      for (int r = 0; r < kReps; ++r) launch(cls);
+      HIP_TRY(hipEventRecord(e1, s));
+      check_launch("launch shape timing");
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      // another shape must beat the default by 3% to replace it (timing noise)
+      if (zv == dflt) t_best = ms;
+      else if (ms < 0.97f * t_best) { t_best = ms; best[cls] = zv; }
+    }
+    g.zv[cls] = best[cls];
+  }
+  std::lock_guard<std::mutex> lk(g_shape_mu);
+  g_shapes.emplace(key, best);
 }
 
 // setup + forward state + energy at the raw band vector `vraw` (device, dim components)
@@ -424,18 +508,18 @@ void op_set_velocity(bl_ctx* c, const float2* vraw) {
   bl::band_prep(g, vraw, c->bv, 1, c->Lhat64, red_reg, s);
   bl::iota(g, c->plan, c->bv, g.dim + 1, c->V, s);
   bl::setup(g, c->V, c->X, c->YA, s);
+  if (!c->tuned) choose_launch_shapes(c);
   const size_t M = (size_t)g.M;
   if (c->timing) t_begin(c);
   for (int n = 0; n < g.nt; ++n) bl::state_step(g, c->m + n * M, c->X, c->m + (n + 1) * M, s);
   if (c->timing) t_end(c, 0, g.nt);
   bl::energy_partial(g, c->m + g.nt * M, c->I1, red_data, s);
-  bl::reduce_final(red_reg, bl::kRedBlocks, c->scal + 0, s);
-  bl::reduce_final(red_data, bl::kRedBlocks, c->scal + 1, s);
+  bl::reduce_final(red_reg, bl::kRedBlocks, c->scal + S_REG, s, c->hdev + S_REG);
+  bl::reduce_final(red_data, bl::kRedBlocks, c->scal + S_DATA, s, c->hdev + S_DATA);
   check_launch("set_velocity");
-  HIP_TRY(hipMemcpyAsync(c->hscal, c->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
   sync(c);
-  c->reg = c->hscal[0];
-  c->data_sum = c->hscal[1];
+  c->reg = c->hscal[S_REG];
+  c->data_sum = c->hscal[S_DATA];
   const double sig = c->prob.sigma;
   c->E = 0.5 * c->reg + c->data_sum / (sig * sig * (double)g.M);
   c->have_v = true;
@@ -499,46 +583,43 @@ void check_flag(bl_ctx* c, const char* what) {
   }
 }
 
-double dev_dot(bl_ctx* c, const float2* a, const float2* b) {
+// <g, g>, max |g| and the non-finite flag of the last band kernels, in one synchronisation
+void grad_stats(bl_ctx* c, const float2* gvec, double* gg, double* ginf) {
   const int64_t n = (int64_t)c->g.dim * c->g.B;
-  double* part = c->red + RED_A * bl::kRedBlocks;
-  bl::dot_partial(a, b, n, part, c->stream);
-  bl::reduce_final(part, bl::kRedBlocks, c->scal + 4, c->stream);
-  HIP_TRY(hipMemcpyAsync(c->hscal + 4, c->scal + 4, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  double* pa = c->red + RED_A * bl::kRedBlocks;
+  double* pb = c->red + RED_B * bl::kRedBlocks;
+  bl::dot_partial(gvec, gvec, n, pa, c->stream);
+  bl::reduce_final(pa, bl::kRedBlocks, c->scal + S_GG, c->stream, c->hdev + S_GG);
+  bl::maxabs_partial(gvec, n, pb, c->stream);
+  bl::reduce_max_final(pb, bl::kRedBlocks, c->scal + S_GINF, c->stream, c->hdev + S_GINF, c->flag,
+                       c->hdev + S_FLAG);
+  check_launch("gradient norms");
   sync(c);
-  return c->hscal[4];
+  if (c->hscal[S_FLAG] != 0.0) {
+    HIP_TRY(hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
+    sync(c);
+    throw NonFinite{"gradient"};
+  }
+  *gg = c->hscal[S_GG];
+  *ginf = c->hscal[S_GINF];
 }
 
-double dev_maxabs(bl_ctx* c, const float2* a) {
-  const int64_t n = (int64_t)c->g.dim * c->g.B;
-  double* part = c->red + RED_A * bl::kRedBlocks;
-  bl::maxabs_partial(a, n, part, c->stream);
-  bl::reduce_max_final(part, bl::kRedBlocks, c->scal + 5, c->stream);
-  HIP_TRY(hipMemcpyAsync(c->hscal + 5, c->scal + 5, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  sync(c);
-  return c->hscal[5];
-}
-
-// z = r / Lhat; returns (<r, r>, <r, z>)
-void dev_precond(bl_ctx* c, const float2* r, float2* z, double* rr, double* rz) {
-  double* p0 = c->red + RED_A * bl::kRedBlocks;
-  double* p1 = c->red + RED_B * bl::kRedBlocks;
-  bl::precond_dots(c->g, r, c->Lhat, z, p0, p1, c->stream);
-  bl::reduce_final(p0, bl::kRedBlocks, c->scal + 6, c->stream);
-  bl::reduce_final(p1, bl::kRedBlocks, c->scal + 7, c->stream);
-  HIP_TRY(hipMemcpyAsync(c->hscal + 6, c->scal + 6, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  sync(c);
-  *rr = c->hscal[6];
-  *rz = c->hscal[7];
+// enqueue z = r / Lhat with <r, r> -> slot S_RR (also published) and <r, z> -> slot rz_slot
+void enqueue_precond(bl_ctx* c, int rz_slot) {
+  double* pa = c->red + RED_A * bl::kRedBlocks;
+  double* pb = c->red + RED_B * bl::kRedBlocks;
+  bl::precond_dots(c->g, c->sr, c->Lhat, c->sz, pa, pb, c->stream);
+  bl::reduce_final(pa, bl::kRedBlocks, c->scal + S_RR, c->stream, c->hdev + S_RR);
+  bl::reduce_final(pb, bl::kRedBlocks, c->scal + rz_slot, c->stream);
 }
 
 double dev_sqdiff(bl_ctx* c, const float* a, const float* b) {
   double* part = c->red + RED_A * bl::kRedBlocks;
   bl::sqdiff_partial(a, b, c->g.M, part, c->stream);
-  bl::reduce_final(part, bl::kRedBlocks, c->scal + 8, c->stream);
-  HIP_TRY(hipMemcpyAsync(c->hscal + 8, c->scal + 8, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  bl::reduce_final(part, bl::kRedBlocks, c->scal + S_SQD, c->stream, c->hdev + S_SQD);
+  check_launch("sqdiff");
   sync(c);
-  return c->hscal[8];
+  return c->hscal[S_SQD];
 }
 
 void load_images(bl_ctx* c, const float* I0, const float* I1) {
@@ -572,19 +653,23 @@ void fill_default(bl_solver_opts* o) {
 // Gauss-Newton-Krylov on the device vectors of the context (reading R-LS / R-PCG):
 // sv holds the initial guess on entry and the result on exit.
 void solve(bl_ctx* c, const bl_solver_opts& o, bl_stats* st) {
+  // Scalars stay on the device wherever only kernels consume them (the PCG step length and
+  // direction update); the host synchronises once per PCG step for its stopping test, once per
+  // line-search trial for E, and once per gradient for its norms and the non-finite flag.
   const bl::Geo& g = c->g;
   hipStream_t s = c->stream;
   const int64_t nb = (int64_t)g.dim * g.B;
+  double* pa = c->red + RED_A * bl::kRedBlocks;
   const double den = dev_sqdiff(c, c->m, c->I1);  // |I0 - I1|^2
   auto mse = [&]() { return den > 0 ? 100.0 * c->data_sum / den : 0.0; };
 
   op_set_velocity(c, c->sv);
   HIP_TRY(hipMemcpyAsync(c->sv, c->bv, band_bytes(g) * g.dim, hipMemcpyDeviceToDevice, s));
   op_gradient(c, c->sg);
-  check_flag(c, "gradient");
+  double gg, ginf0;
+  grad_stats(c, c->sg, &gg, &ginf0);
   double E = c->E;
-  const double g0n = std::sqrt(std::max(dev_dot(c, c->sg, c->sg), 0.0));
-  const double ginf0 = dev_maxabs(c, c->sg);
+  const double g0n = std::sqrt(std::max(gg, 0.0));
   st->E[0] = E;
   st->mse_rel[0] = mse();
   st->ginf_rel[0] = 1.0;
@@ -602,41 +687,44 @@ void solve(bl_ctx* c, const bl_solver_opts& o, bl_stats* st) {
       st->status = BL_CONVERGED;
       break;
     }
-    const double gn = std::sqrt(std::max(dev_dot(c, c->sg, c->sg), 0.0));
+    const double gn = std::sqrt(std::max(gg, 0.0));
     const double eta = std::min(0.5, std::sqrt(gn / g0n));
     // PCG on H delta = -g with preconditioner K = 1/Lhat, delta_0 = 0
     HIP_TRY(hipMemsetAsync(c->sdelta, 0, nb * sizeof(float2), s));
     HIP_TRY(hipMemsetAsync(c->sr, 0, nb * sizeof(float2), s));
     bl::axpy(c->sr, c->sg, -1.0, nb, s);  // r = -g
-    double rr, rz;
-    dev_precond(c, c->sr, c->sz, &rr, &rz);
+    int rz_cur = S_RZ0, rz_next = S_RZ1;
+    enqueue_precond(c, rz_cur);
     HIP_TRY(hipMemcpyAsync(c->sp, c->sz, nb * sizeof(float2), hipMemcpyDeviceToDevice, s));
     int iters = 0;
     for (int j = 0; j < o.max_pcg; ++j) {
       op_hessvec(c, c->sp, c->sHp);
       st->hessvecs += 1;
-      const double pHp = dev_dot(c, c->sp, c->sHp);
+      bl::dot_partial(c->sp, c->sHp, nb, pa, s);
+      bl::reduce_final(pa, bl::kRedBlocks, c->scal + S_PHP, s, c->hdev + S_PHP);
+      // alpha = <r, z> / <p, Hp>, zero when <p, Hp> <= 0 (then neither vector moves)
+      bl::axpy_dev(c->sdelta, c->sp, c->scal + rz_cur, c->scal + S_PHP, 1.0, nb, s);
+      bl::axpy_dev(c->sr, c->sHp, c->scal + rz_cur, c->scal + S_PHP, -1.0, nb, s);
+      enqueue_precond(c, rz_next);
+      check_launch("pcg");
+      sync(c);
+      const double pHp = c->hscal[S_PHP];
       if (!(pHp > 0.0)) {
-        if (iters == 0)
+        if (iters == 0)  // z = K r of the unchanged r: the preconditioned steepest-descent step
           HIP_TRY(hipMemcpyAsync(c->sdelta, c->sz, nb * sizeof(float2), hipMemcpyDeviceToDevice, s));
         break;
       }
-      const double alpha = rz / pHp;
-      bl::axpy(c->sdelta, c->sp, alpha, nb, s);
-      bl::axpy(c->sr, c->sHp, -alpha, nb, s);
       iters += 1;
-      double rr_new, rz_new;
-      dev_precond(c, c->sr, c->sz, &rr_new, &rz_new);
-      if (std::sqrt(std::max(rr_new, 0.0)) <= eta * gn) break;
-      const double beta = rz_new / rz;
-      rz = rz_new;
-      bl::xpby(c->sp, c->sz, beta, nb, s);  // p = z + beta p
+      if (std::sqrt(std::max(c->hscal[S_RR], 0.0)) <= eta * gn) break;
+      bl::xpby_dev(c->sp, c->sz, c->scal + rz_next, c->scal + rz_cur, nb, s);  // p = z + beta p
+      std::swap(rz_cur, rz_next);
     }
     check_launch("pcg");
     st->pcg_iters[it] = iters;
     st->pcg_total += iters;
-    // Armijo backtracking on E along delta
-    const double slope = dev_dot(c, c->sg, c->sdelta);
+    // Armijo backtracking on E along delta; the slope <g, delta> arrives with the first trial
+    bl::dot_partial(c->sg, c->sdelta, nb, pa, s);
+    bl::reduce_final(pa, bl::kRedBlocks, c->scal + S_SLOPE, s, c->hdev + S_SLOPE);
     double eps = 1.0;
     bool accepted = false;
     int trials = 0;
@@ -645,6 +733,7 @@ void solve(bl_ctx* c, const bl_solver_opts& o, bl_stats* st) {
       bl::add_scaled(c->stry, c->sv, c->sdelta, eps, nb, s);
       op_set_velocity(c, c->stry);
       st->evaluations += 1;
+      const double slope = c->hscal[S_SLOPE];
       if (c->E <= E + o.c1 * eps * slope) {
         accepted = true;
         break;
@@ -662,10 +751,9 @@ void solve(bl_ctx* c, const bl_solver_opts& o, bl_stats* st) {
     HIP_TRY(hipMemcpyAsync(c->sv, c->bv, band_bytes(g) * g.dim, hipMemcpyDeviceToDevice, s));
     E = c->E;
     op_gradient(c, c->sg);
-    check_flag(c, "gradient");
+    grad_stats(c, c->sg, &gg, &ginf);
     st->gradients += 1;
     st->gn_iters += 1;
-    ginf = dev_maxabs(c, c->sg);
     st->E[st->gn_iters] = E;
     st->mse_rel[st->gn_iters] = mse();
     st->ginf_rel[st->gn_iters] = ginf / ginf0;
@@ -924,6 +1012,13 @@ int bl_grid_to_band(const bl_problem* prob, int32_t ncomp, const float* grid, fl
     sync(c);
     return BL_OK;
   });
+}
+
+int bl_lddmm_ctx_launch_shapes(bl_ctx* c, int32_t zv_out[4]) {
+  t_err.clear();
+  if (!c || !zv_out) return fail(BL_E_INVALID, "NULL pointer argument");
+  for (int k = 0; k < 4; ++k) zv_out[k] = c->g.dim == 3 ? c->g.zv[k] : 1;
+  return BL_OK;
 }
 
 int bl_kernel_timing_enable(bl_ctx* c, int32_t on) {

@@ -34,32 +34,62 @@ __device__ __forceinline__ void block_max_store(double acc, double* __restrict__
 #define GRID_STRIDE(i, n) \
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < (n); i += (int64_t)gridDim.x * 256)
 
+// Final pass of a reduction: one block sums (or maxes) the partials in a fixed order and
+// stores the result in device memory and, when `host` is not NULL, also in host-mapped pinned
+// memory, so the host reads it after a stream synchronisation without a separate copy.  With
+// `flag` not NULL the non-finite flag of the band kernels is published beside it as a double.
+template <bool MAX>
 __global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__ partial, int n,
-                                                      double* __restrict__ out) {
+                                                      double* __restrict__ out,
+                                                      double* __restrict__ host,
+                                                      const int* __restrict__ flag,
+                                                      double* __restrict__ host_flag) {
   __shared__ double sh[256];
   double acc = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) acc += partial[i];
+  for (int i = threadIdx.x; i < n; i += 256) acc = MAX ? fmax(acc, partial[i]) : acc + partial[i];
   sh[threadIdx.x] = acc;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    if ((int)threadIdx.x < o)
+      sh[threadIdx.x] = MAX ? fmax(sh[threadIdx.x], sh[threadIdx.x + o]) : sh[threadIdx.x] + sh[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = sh[0];
+  if (threadIdx.x == 0) {
+    out[0] = sh[0];
+    if (host) host[0] = sh[0];
+    if (flag) host_flag[0] = (double)flag[0];
+  }
 }
 
-__global__ __launch_bounds__(256) void k_reduce_max_final(const double* __restrict__ partial,
-                                                          int n, double* __restrict__ out) {
-  __shared__ double sh[256];
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) acc = fmax(acc, partial[i]);
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
-    __syncthreads();
+// y += s * (num / den) x with the quotient taken on the device (0 unless den > 0): the PCG step
+// length alpha = <r, z> / <p, Hp> without a round trip to the host.
+__global__ __launch_bounds__(256) void k_axpy_dev(float2* __restrict__ y, const float2* __restrict__ x,
+                                                  const double* __restrict__ num,
+                                                  const double* __restrict__ den, double sign,
+                                                  int64_t n) {
+  const double d = den[0];
+  const double alpha = d > 0.0 ? sign * (num[0] / d) : 0.0;
+  GRID_STRIDE(i, n) {
+    const float2 a = x[i];
+    float2 b = y[i];
+    b.x = (float)fma(alpha, (double)a.x, (double)b.x);
+    b.y = (float)fma(alpha, (double)a.y, (double)b.y);
+    y[i] = b;
   }
-  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// y = x + (num / den) y: the PCG direction update with beta = <r', z'> / <r, z> on the device
+__global__ __launch_bounds__(256) void k_xpby_dev(float2* __restrict__ y, const float2* __restrict__ x,
+                                                  const double* __restrict__ num,
+                                                  const double* __restrict__ den, int64_t n) {
+  const double beta = num[0] / den[0];
+  GRID_STRIDE(i, n) {
+    const float2 a = x[i];
+    float2 b = y[i];
+    b.x = (float)fma(beta, (double)b.x, (double)a.x);
+    b.y = (float)fma(beta, (double)b.y, (double)a.y);
+    y[i] = b;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_dot_partial(const float2* __restrict__ a,
@@ -158,11 +188,23 @@ inline int blocks_for(int64_t n) {
 
 }  // namespace
 
-void reduce_final(const double* partial, int n, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, partial, n, out);
+void reduce_final(const double* partial, int n, double* out, hipStream_t s, double* host,
+                  const int* flag, double* host_flag) {
+  hipLaunchKernelGGL(k_reduce_final<false>, dim3(1), dim3(256), 0, s, partial, n, out, host, flag,
+                     host_flag);
 }
-void reduce_max_final(const double* partial, int n, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_max_final, dim3(1), dim3(256), 0, s, partial, n, out);
+void reduce_max_final(const double* partial, int n, double* out, hipStream_t s, double* host,
+                      const int* flag, double* host_flag) {
+  hipLaunchKernelGGL(k_reduce_final<true>, dim3(1), dim3(256), 0, s, partial, n, out, host, flag,
+                     host_flag);
+}
+void axpy_dev(float2* y, const float2* x, const double* num, const double* den, double sign,
+              int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy_dev, dim3(blocks_for(n)), dim3(256), 0, s, y, x, num, den, sign, n);
+}
+void xpby_dev(float2* y, const float2* x, const double* num, const double* den, int64_t n,
+              hipStream_t s) {
+  hipLaunchKernelGGL(k_xpby_dev, dim3(blocks_for(n)), dim3(256), 0, s, y, x, num, den, n);
 }
 void dot_partial(const float2* a, const float2* b, int64_t n, double* partial, hipStream_t s) {
   hipLaunchKernelGGL(k_dot_partial, dim3(kRedBlocks), dim3(256), 0, s, a, b, n, partial);

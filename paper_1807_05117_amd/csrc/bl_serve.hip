@@ -163,7 +163,7 @@ int bl_server_create(uint64_t budget_bytes, int32_t max_slots, bl_server** out) 
     s->slots.resize(max_slots);
     for (auto& sl : s->slots) {
       HIP_TRY(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
-      HIP_TRY(hipHostMalloc((void**)&sl.hscal, 64 * sizeof(double), hipHostMallocDefault));
+      sl.hscal = alloc_host_scalars();
     }
     bl_server* raw = s.get();
     for (int i = 0; i < max_slots; ++i) raw->slots[i].th = std::thread(worker, raw, i);

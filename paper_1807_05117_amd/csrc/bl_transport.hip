@@ -376,19 +376,20 @@ inline dim3 gather_grid(const Geo& g, int zv) {
 }
 }  // namespace
 
-#define DISPATCH_GATHER(KERNEL, ...)                                                            \
+// 3D launches take the class's voxels per thread along z (1, 2 or 4); 2D runs one per thread
+#define DISPATCH_GATHER(KERNEL, CLS, ...)                                                       \
   do {                                                                                          \
-    if (g.dim == 3)                                                                             \
-      hipLaunchKernelGGL((KERNEL<3, 2>), gather_grid(g, 2), dim3(BX, GBY), 0, s, __VA_ARGS__);  \
-    else                                                                                        \
+    if (g.dim == 3) {                                                                           \
+      const int zv_ = g.zv[CLS];                                                                \
+      if (zv_ == 4)                                                                             \
+        hipLaunchKernelGGL((KERNEL<3, 4>), gather_grid(g, 4), dim3(BX, GBY), 0, s, __VA_ARGS__); \
+      else if (zv_ == 2)                                                                        \
+        hipLaunchKernelGGL((KERNEL<3, 2>), gather_grid(g, 2), dim3(BX, GBY), 0, s, __VA_ARGS__); \
+      else                                                                                      \
+        hipLaunchKernelGGL((KERNEL<3, 1>), gather_grid(g, 1), dim3(BX, GBY), 0, s, __VA_ARGS__); \
+    } else {                                                                                    \
       hipLaunchKernelGGL((KERNEL<2, 1>), gather_grid(g, 1), dim3(BX, GBY), 0, s, __VA_ARGS__);  \
-  } while (0)
-#define DISPATCH_GATHER1(KERNEL, ...)                                                           \
-  do {                                                                                          \
-    if (g.dim == 3)                                                                             \
-      hipLaunchKernelGGL((KERNEL<3, 1>), gather_grid(g, 1), dim3(BX, GBY), 0, s, __VA_ARGS__);  \
-    else                                                                                        \
-      hipLaunchKernelGGL((KERNEL<2, 1>), gather_grid(g, 1), dim3(BX, GBY), 0, s, __VA_ARGS__);  \
+    }                                                                                           \
   } while (0)
 #define DISPATCH_ONE(KERNEL, ...)                                                          \
   do {                                                                                     \
@@ -401,28 +402,28 @@ void setup(const Geo& g, const float* v, float* X, float4* YA, hipStream_t s) {
   DISPATCH_ONE(k_setup, g, v, X, YA);
 }
 void state_step(const Geo& g, const float* m_in, const float* X, float* m_out, hipStream_t s) {
-  DISPATCH_GATHER(k_state_step, g, m_in, X, m_out);
+  DISPATCH_GATHER(k_state_step, TR_STATE, g, m_in, X, m_out);
 }
 void terminal(const Geo& g, const float* mT, const float* I1, float* lam, hipStream_t s) {
   DISPATCH_ONE(k_terminal, g, mT, I1, lam);
 }
 void adj_step(const Geo& g, const float* lam_in, const float4* YA, float* lam_out,
               hipStream_t s) {
-  DISPATCH_GATHER(k_adj_step, g, lam_in, YA, lam_out);
+  DISPATCH_GATHER(k_adj_step, TR_ADJ, g, lam_in, YA, lam_out);
 }
 void body_force(const Geo& g, const float* lam, const float* m, float* b, hipStream_t s) {
-  DISPATCH_GATHER1(k_body_force, g, lam, m, b);
+  DISPATCH_GATHER(k_body_force, TR_FORCE, g, lam, m, b);
 }
 void inc_init(const Geo& g, const float* m0, const float* dv, float* t0, hipStream_t s) {
-  DISPATCH_GATHER(k_inc_init, g, m0, dv, t0);
+  DISPATCH_GATHER(k_inc_init, TR_INC, g, m0, dv, t0);
 }
 void inc_step(const Geo& g, const float* t_in, const float* X, const float* m_next,
               const float* dv, float* t_out, hipStream_t s) {
-  DISPATCH_GATHER(k_inc_step, g, t_in, X, m_next, dv, t_out);
+  DISPATCH_GATHER(k_inc_step, TR_INC, g, t_in, X, m_next, dv, t_out);
 }
 void inc_last(const Geo& g, const float* t_in, const float* X, const float* mT,
               const float* dv, float* dlam, hipStream_t s) {
-  DISPATCH_GATHER(k_inc_last, g, t_in, X, mT, dv, dlam);
+  DISPATCH_GATHER(k_inc_last, TR_INC, g, t_in, X, mT, dv, dlam);
 }
 void energy_partial(const Geo& g, const float* mT, const float* I1, double* partial,
                     hipStream_t s) {

@@ -20,6 +20,8 @@ CASES = {
     "brainlike_small": (3, (40, 48, 40), (10, 12, 10), 6, 3.0, 5),
     # the 128^3 workload: band 32^3, Nt = 10, 6 voxels
     "c2_full": (3, (128, 128, 128), (32, 32, 32), 10, 6.0, 3),
+    # brain-shaped 160x192x160: band 40x48x40, Nt = 10, five classes, 6 voxels
+    "c3_full": (3, (160, 192, 160), (40, 48, 40), 10, 6.0, 5),
 }
 
 

@@ -85,6 +85,43 @@ def test_iota_pi_bruteforce(dim, n, k):
     assert np.max(np.abs(got_p - ref_p)) <= 1e-13 * np.max(np.abs(ref_p))
 
 
+@pytest.mark.parametrize("dim,n,k", [(2, (8, 6), (4, 4)), (3, (8, 6, 4), (4, 4, 4))])
+def test_point_sampled_transforms_bruteforce(dim, n, k):
+    """iota_at / pi_at (single outputs of grids too large for the full transform) against the
+    double sum written out term by term"""
+    prob = O.Problem(dim, n, k, 4)
+    vh = rand_band(prob, 3, admissible=False)[0]
+    f = RNG.standard_normal(prob.shape)
+    pts = [idx for idx in np.ndindex(prob.shape)][::3]
+    kids = [kidx for kidx in np.ndindex(prob.bshape)]
+    for idx, got in zip(pts, O.iota_at(vh, prob, pts)):
+        ref = sum(vh[kidx] * cmath.exp(2j * math.pi * sum(
+            (kidx[::-1][j] - k[j] // 2) * idx[::-1][j] / n[j] for j in range(dim))) for kidx in kids)
+        assert abs(got - ref.real) <= 1e-13 * np.abs(vh).sum()
+    for kidx, got in zip(kids, O.pi_at(f, prob, kids)):
+        if 0 in kidx:
+            assert got == 0
+            continue
+        ref = sum(f[idx] * cmath.exp(-2j * math.pi * sum(
+            (kidx[::-1][j] - k[j] // 2) * idx[::-1][j] / n[j] for j in range(dim)))
+            for idx in np.ndindex(prob.shape)) / prob.M
+        assert abs(got - ref) <= 1e-14 * np.abs(f).sum()
+
+
+def test_point_sampled_transforms_numpy_fft():
+    prob = O.Problem(3, (40, 24, 18), (16, 12, 6), 4)
+    vh = rand_band(prob, 9)[0]
+    grid = fft_iota(vh, prob).real
+    f = RNG.standard_normal(prob.shape)
+    band = fft_pi(f, prob)
+    rng = np.random.default_rng(17)
+    pts = np.stack([rng.integers(0, N, 50) for N in prob.shape], axis=1)
+    kids = np.stack([rng.integers(0, K, 50) for K in prob.bshape], axis=1)
+    assert np.allclose(O.iota_at(vh, prob, pts), grid[tuple(pts.T)], rtol=0,
+                       atol=1e-13 * np.abs(grid).max())
+    assert np.allclose(O.pi_at(f, prob, kids), band[tuple(kids.T)], rtol=0, atol=1e-14)
+
+
 @pytest.mark.parametrize("dim,n,k", [(2, (64, 48), (16, 12)), (3, (20, 16, 12), (8, 6, 4))])
 def test_iota_pi_numpy_fft(dim, n, k):
     prob = O.Problem(dim, n, k, 4)
