@@ -200,6 +200,17 @@ void bl_lddmm_ctx_destroy(bl_ctx* ctx);
 /* Bytes of device memory a context for this problem needs (0 if prob is invalid). */
 uint64_t bl_lddmm_footprint(const bl_problem* prob);
 
+/*
+ * The one-shot calls (bl_lddmm_register, _gradient, _hessvec, _warp) keep the device context
+ * of a successful call (its footprint) and reuse it for the next call on the same problem
+ * (same grid, band, nt, alpha, s, sigma, precision, flags, device), so repeated calls
+ * allocate no device memory and rebuild no tables.  At most 8 idle contexts and 32 GiB are
+ * kept; a call that finds too little free memory frees them first.  Concurrent calls never
+ * share a context.  This call frees every idle cached context (it waits for nothing: cached
+ * contexts have no work in flight).
+ */
+void bl_lddmm_release_cached(void);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char* bl_lddmm_last_error(void);
 

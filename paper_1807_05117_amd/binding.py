@@ -114,6 +114,7 @@ def load():
         "bl_lddmm_ctx_get_field": (C.c_int, [_P, C.c_int32, C.c_int32, _P]),
         "bl_lddmm_ctx_destroy": (None, [_P]),
         "bl_lddmm_footprint": (C.c_uint64, [PP]),
+        "bl_lddmm_release_cached": (None, []),
         "bl_lddmm_last_error": (C.c_char_p, []),
         "bl_lddmm_device_count": (C.c_int, []),
         "bl_lddmm_default_opts": (None, [C.POINTER(SolverOpts)]),
@@ -239,6 +240,25 @@ def bl_lddmm_register(p, I0, I1, v0, opts=None):
     _check(lib.bl_lddmm_register(C.byref(p), C.byref(o), _ptr(I0), _ptr(I1), _ptr(v), _ptr(w),
                                  C.byref(st)))
     return v, w, st.to_dict()
+
+
+def bl_lddmm_register_device(p, I0, I1, v, warped=None, opts=None):
+    """bl_lddmm_register on device memory (p made with device=True): I0, I1, warped are torch
+    float32 tensors of the grid shape, v a complex64 tensor of the band shape, updated in
+    place; stream-ordered on p.stream, and the call returns after its work is complete."""
+    lib = load()
+    for t in (I0, I1, v) + ((warped,) if warped is not None else ()):
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("device tensors must be contiguous GPU tensors")
+    st = Stats()
+    o = opts if opts is not None else opts_struct()
+    _check(lib.bl_lddmm_register(C.byref(p), C.byref(o), _tptr(I0), _tptr(I1), _tptr(v),
+                                 _tptr(warped) if warped is not None else None, C.byref(st)))
+    return st.to_dict()
+
+
+def bl_lddmm_release_cached():
+    load().bl_lddmm_release_cached()
 
 
 def bl_lddmm_warp(p, I0, v_hat):

@@ -104,45 +104,53 @@ __global__ __launch_bounds__(64) void k_iota_y(Geo g, const float2* __restrict__
 }
 
 // z stage (real output): one thread per (column q, chunk of z, component); the half-spectrum
-// column is held in registers, the twiddle rows of four z planes at a time are
-// wave-uniform.  zchunk is a multiple of 4.
+// column is held in registers.  Planes z and nz - z share their twiddles up to conjugation,
+// so one pass over z <= nz/2 forms A = sum_h f.x t.x and B = sum_h f.y t.y and writes A - B
+// to plane z and A + B to plane nz - z.  The block's twiddle rows are staged once in LDS;
+// every lane of a wavefront reads the same entry (a broadcast), 16 bytes at a time.
 template <int KZH>
 __global__ __launch_bounds__(256) void k_iota_z(Geo g, const float2* __restrict__ F2,
                                                 const float2* __restrict__ tw_zT,
                                                 float* __restrict__ out, int zchunk) {
+  extern __shared__ float4 tws4[];   // zchunk rows of KZH (even) or 2 (KZH == 1) float2
+  constexpr int RW = KZH == 1 ? 2 : KZH;   // row width in float2
+  float2* tws = reinterpret_cast<float2*>(tws4);
   const int nq = g.nx * g.ny;
   const int q = blockIdx.x * 256 + threadIdx.x;
   const int c = blockIdx.z;
+  const int zmax = g.nz / 2;
+  const int z0 = blockIdx.y * zchunk;
+  for (int i = threadIdx.x; i < zchunk * RW; i += 256) {
+    const int r = i / RW, h = i - r * RW;
+    tws[i] = h < KZH ? tw_zT[(size_t)min(z0 + r, zmax) * kZP + h] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
   if (q >= nq) return;
-  float2 f[KZH];
+  float2 f[RW];
   const float2* src = F2 + (size_t)c * g.kzh * nq + q;
 #pragma unroll
-  for (int h = 0; h < KZH; ++h) {
+  for (int h = 0; h < RW; ++h) {
     const int hc = h < g.kzh ? h : g.kzh - 1;   // clamped, always in bounds
     float2 v = src[(size_t)hc * nq];
     const float sc = h >= g.kzh ? 0.f : (h > 0 ? 2.f : 1.f);
     f[h] = make_float2(sc * v.x, sc * v.y);
   }
-  const int z0 = blockIdx.y * zchunk;
-  const int z1 = min(g.nz, z0 + zchunk);
+  const int z1 = min(zmax + 1, z0 + zchunk);
   float* dst = out + (size_t)c * g.M + q;
-  for (int z = z0; z < z1; z += 4) {
-    float acc[4][2];
+  for (int z = z0; z < z1; ++z) {
+    const float4* t4 = tws4 + (size_t)(z - z0) * (RW / 2);
+    float a = 0.f, b = 0.f;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const float2* tw = tw_zT + (size_t)(z + u) * kZP;   // rows up to nzp are allocated
-      acc[u][0] = 0.f;
-      acc[u][1] = 0.f;
-#pragma unroll
-      for (int h = 0; h < KZH; ++h) {
-        const float2 t = tw[h];
-        acc[u][0] = fmaf(f[h].x, t.x, acc[u][0]);
-        acc[u][1] = fmaf(-f[h].y, t.y, acc[u][1]);
-      }
+    for (int h2 = 0; h2 < RW / 2; ++h2) {
+      const float4 t = t4[h2];
+      a = fmaf(f[2 * h2].x, t.x, a);
+      b = fmaf(f[2 * h2].y, t.y, b);
+      a = fmaf(f[2 * h2 + 1].x, t.z, a);
+      b = fmaf(f[2 * h2 + 1].y, t.w, b);
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (z + u < z1) dst[(size_t)(z + u) * nq] = acc[u][0] + acc[u][1];
+    dst[(size_t)z * nq] = a - b;
+    const int zm = g.nz - z;
+    if (z > 0 && zm != z) dst[(size_t)zm * nq] = a + b;
   }
 }
 
@@ -213,9 +221,9 @@ __global__ __launch_bounds__(64 * kNW) void k_pi_z(Geo g, const float* __restric
 }
 
 // y stage: block of 64 x-columns x kYS wavefronts for one group of kJG ky outputs; wavefront
-// s sums a contiguous quarter of the y planes in chunks of kU, the partial sums are added in
+// s sums a contiguous 1/kYS of the y planes in chunks of kUY, the partial sums are added in
 // LDS in a fixed order.
-constexpr int kYS = 4;
+constexpr int kYS = 8;
 
 __global__ __launch_bounds__(64 * kYS) void k_pi_y(Geo g, const float2* __restrict__ G,
                                                    const float2* __restrict__ tw_yT, int kyp,
@@ -267,22 +275,33 @@ __global__ __launch_bounds__(64 * kYS) void k_pi_y(Geo g, const float2* __restri
   }
 }
 
-// x stage: one thread per (kx, row) over the flattened rows (c*kzh + h, ky); H rows and the
-// transposed twiddles are read in chunks of kU.
-__global__ __launch_bounds__(256) void k_pi_x(Geo g, int rows, const float2* __restrict__ H,
-                                              const float2* __restrict__ tw_xT,
-                                              float2* __restrict__ P) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
+// x stage: one output (kx, row) per column of a 64 x kXS block over the flattened rows
+// (c*kzh + h, ky); wavefront s sums a contiguous 1/kXS of x in chunks of kU (H rows and the
+// transposed twiddles), the partial sums are added in LDS in a fixed order.
+constexpr int kXS = 4;
+
+__global__ __launch_bounds__(64 * kXS) void k_pi_x(Geo g, int rows, int xseg,
+                                                   const float2* __restrict__ H,
+                                                   const float2* __restrict__ tw_xT,
+                                                   float2* __restrict__ P) {
+  __shared__ float2 sh[kXS - 1][64];
+  const int tx = threadIdx.x;
+  const int sgm = wave_uniform(threadIdx.y);
+  const int t = blockIdx.x * 64 + tx;
   const int r = t / g.kx;
   const int jx = t - r * g.kx;
-  if (r >= rows) return;
-  const float2* row = H + (size_t)r * g.nx;
+  const int rc = r < rows ? r : rows - 1;   // clamped row: loads stay in bounds
+  const float2* row = H + (size_t)rc * g.nx;
+  const int xa = sgm * xseg;
+  const int xb = min(g.nx, xa + xseg);
   float2 a0 = make_float2(0.f, 0.f), a1 = a0;
-  for (int x0 = 0; x0 < g.nx; x0 += kU) {
+  for (int x0 = xa; x0 < xb; x0 += kU) {
     float2 hv[kU], tv[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-      hv[u] = row[min(x0 + u, g.nx - 1)];
+      const float keep = (x0 + u < xb) ? 1.f : 0.f;   // the next segment's columns
+      const float2 v = row[min(x0 + u, g.nx - 1)];
+      hv[u] = make_float2(keep * v.x, keep * v.y);
       tv[u] = tw_xT[(size_t)(x0 + u) * g.kx + jx];   // zero rows past nx
     }
 #pragma unroll
@@ -291,7 +310,17 @@ __global__ __launch_bounds__(256) void k_pi_x(Geo g, int rows, const float2* __r
       cmac_conj(a1, hv[u + 1], tv[u + 1]);
     }
   }
-  P[(size_t)r * g.kx + jx] = make_float2(a0.x + a1.x, a0.y + a1.y);
+  float2 acc = make_float2(a0.x + a1.x, a0.y + a1.y);
+  if (sgm > 0) sh[sgm - 1][tx] = acc;
+  __syncthreads();
+  if (sgm == 0 && r < rows) {
+#pragma unroll
+    for (int o = 0; o < kXS - 1; ++o) {
+      acc.x += sh[o][tx].x;
+      acc.y += sh[o][tx].y;
+    }
+    P[(size_t)r * g.kx + jx] = acc;
+  }
 }
 
 // ---------------------------------------------------------------------------- band kernels
@@ -413,12 +442,16 @@ void launch_z_pair(const Geo& g, const DftPlan& p, const float2* F2, float* out,
   const int nq = g.nx * g.ny;
   if (inverse) {
     // split z into chunks so that a launch has enough blocks to fill the chip
+    // (z, nz - z) pairs: z = 0 .. nz/2, in chunks of at most 64 (LDS: 64 twiddle rows)
+    // split further until the launch has enough blocks to fill the chip
+    const int npair = g.nz / 2 + 1;
     const int qblocks = (nq + 255) / 256;
-    int nchunk = 1;
-    while (qblocks * nchunk * C < 768 && nchunk * 16 < g.nz) nchunk *= 2;
-    const int zchunk = ((g.nz + nchunk - 1) / nchunk + 3) / 4 * 4;
-    nchunk = (g.nz + zchunk - 1) / zchunk;
-    hipLaunchKernelGGL(k_iota_z<KZH>, dim3(qblocks, nchunk, C), dim3(256), 0, s, g, F2,
+    int nchunk = (npair + 63) / 64;
+    while (qblocks * nchunk * C < 768 && nchunk * 8 < npair) nchunk *= 2;
+    const int zchunk = (npair + nchunk - 1) / nchunk;
+    nchunk = (npair + zchunk - 1) / zchunk;
+    const size_t lds = (size_t)zchunk * (KZH == 1 ? 2 : KZH) * sizeof(float2);
+    hipLaunchKernelGGL(k_iota_z<KZH>, dim3(qblocks, nchunk, C), dim3(256), lds, s, g, F2,
                        p.tw_zT, out, zchunk);
   } else {
     hipLaunchKernelGGL(k_pi_z<KZH>, dim3((nq + 63) / 64, C), dim3(64, kNW), 0, s, g, f,
@@ -464,8 +497,9 @@ void pi_half(const Geo& g, const DftPlan& p, const float* grid, int C, float2* P
   hipLaunchKernelGGL(k_pi_y, dim3(xb, p.kyp / kJG, C * g.kzh), dim3(64, kYS), 0, s, g, p.bufA,
                      p.tw_yT, p.kyp, yseg, p.bufB);
   const int rows = C * g.kzh * g.ky;
-  hipLaunchKernelGGL(k_pi_x, dim3((rows * g.kx + 255) / 256), dim3(256), 0, s, g, rows, p.bufB,
-                     p.tw_xT, P);
+  const int xseg = ((g.nx + kXS - 1) / kXS + kU - 1) / kU * kU;
+  hipLaunchKernelGGL(k_pi_x, dim3((rows * g.kx + 63) / 64), dim3(64, kXS), 0, s, g, rows, xseg,
+                     p.bufB, p.tw_xT, P);
 }
 
 void band_prep(const Geo& g, const float2* raw, float2* out, int with_div, const double* Lhat64,

@@ -31,8 +31,8 @@ struct Geo {
 enum { TR_STATE = 0, TR_INC, TR_ADJ, TR_FORCE };
 
 // Work buffers and twiddle tables of the band<->grid transforms.
-constexpr int kYG = 8;     // y outputs per thread in the iota y stage
-constexpr int kJG = 16;    // ky outputs per thread in the pi y stage
+constexpr int kYG = 4;     // y outputs per thread in the iota y stage
+constexpr int kJG = 8;     // ky outputs per thread in the pi y stage
 constexpr int kZP = 64;    // padded row length of the z twiddle table
 constexpr int kU = 8;      // loads in flight per thread in the contraction loops
 constexpr int kUY = 16;    // loads in flight per thread in the pi y stage

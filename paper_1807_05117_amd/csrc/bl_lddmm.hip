@@ -770,6 +770,100 @@ struct CtxHolder {
   ~CtxHolder() { destroy_ctx(c); }
 };
 
+// ---------------------------------------------------------------- idle context cache
+// The one-shot calls (register, gradient, H v, warp) take an idle context of the same problem
+// on the same device if one is cached and hand it back after a successful call (their work is
+// complete then: each ends with a host synchronisation), so repeated calls on one problem
+// shape allocate no device memory and rebuild no tables.  At most kCacheMax idle contexts and
+// kCacheBytes of device memory are kept; bl_lddmm_release_cached frees them.
+constexpr size_t kCacheMax = 8;
+constexpr size_t kCacheBytes = size_t(32) << 30;
+std::mutex g_cache_mu;
+std::vector<bl_ctx*> g_idle;   // oldest first
+
+bool same_problem(const bl_ctx* c, const bl_problem* p, int device, bool solver) {
+  const bl_problem& q = c->prob;
+  if (c->device != device || !c->transport || (c->sv != nullptr) != solver) return false;
+  if (q.dim != p->dim || q.nt != p->nt || q.s != p->s || q.gamma != p->gamma ||
+      q.precision != p->precision || q.flags != p->flags)
+    return false;
+  for (int j = 0; j < 3; ++j)
+    if (q.n[j] != p->n[j] || q.k[j] != p->k[j]) return false;
+  return q.alpha == p->alpha && q.sigma == p->sigma;
+}
+
+void free_idle(std::vector<bl_ctx*>& v) {
+  int dev = 0;
+  const bool have_dev = hipGetDevice(&dev) == hipSuccess;
+  for (bl_ctx* c : v) destroy_ctx(c);   // switches to each context's device
+  v.clear();
+  if (have_dev) hipSetDevice(dev);
+}
+
+struct CachedCtx {
+  bl_ctx* c = nullptr;
+  bool ok = false;
+  CachedCtx(const bl_problem* prob, const bl::Geo& g, bool solver) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    {
+      std::lock_guard<std::mutex> lk(g_cache_mu);
+      for (size_t i = 0; i < g_idle.size(); ++i)
+        if (same_problem(g_idle[i], prob, dev, solver)) {
+          c = g_idle[i];
+          g_idle.erase(g_idle.begin() + i);
+          break;
+        }
+    }
+    if (c) {
+      if (c->devptr) c->stream = (hipStream_t)prob->stream;
+      c->have_v = false;
+      return;
+    }
+    try {
+      c = create_ctx(prob, g, true, solver);
+    } catch (const std::bad_alloc&) {
+      // idle cached contexts may hold the memory: free them and try once more
+      std::vector<bl_ctx*> drop;
+      {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        drop.swap(g_idle);
+      }
+      free_idle(drop);
+      c = create_ctx(prob, g, true, solver);
+    }
+  }
+  ~CachedCtx() {
+    if (!c) return;
+    if (!ok) {
+      destroy_ctx(c);
+      return;
+    }
+    if (c->timing) {
+      for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
+      c->ev_pool.clear();
+      c->ev_used.clear();
+      c->ev_next = 0;
+      c->ev_open = -1;
+      c->timing = false;
+    }
+    if (c->devptr) c->stream = nullptr;   // the caller's stream is not kept
+    std::vector<bl_ctx*> drop;
+    {
+      std::lock_guard<std::mutex> lk(g_cache_mu);
+      g_idle.push_back(c);
+      size_t bytes = 0;
+      for (bl_ctx* x : g_idle) bytes += x->arena_bytes;
+      while (g_idle.size() > kCacheMax || (bytes > kCacheBytes && g_idle.size() > 1)) {
+        bytes -= g_idle.front()->arena_bytes;
+        drop.push_back(g_idle.front());
+        g_idle.erase(g_idle.begin());
+      }
+    }
+    free_idle(drop);
+  }
+};
+
 }  // namespace host
 }  // namespace bl
 
@@ -788,6 +882,15 @@ int bl_lddmm_device_count(void) {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess) return 0;
   return n;
+}
+
+void bl_lddmm_release_cached(void) {
+  std::vector<bl_ctx*> drop;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    drop.swap(g_idle);
+  }
+  free_idle(drop);
 }
 
 uint64_t bl_lddmm_footprint(const bl_problem* prob) {
@@ -891,8 +994,7 @@ int bl_lddmm_gradient(const bl_problem* prob, const float* I0, const float* I1,
   if (int r = validate(prob, &g)) return r;
   if (!I0 || !I1 || !v_hat || !g_hat) return fail(BL_E_INVALID, "NULL pointer argument");
   return guarded([&]() {
-    CtxHolder h;
-    h.c = create_ctx(prob, g, true, false);
+    CachedCtx h(prob, g, false);
     load_images(h.c, I0, I1);
     load_band(h.c, v_hat, h.c->braw, g.dim);
     op_set_velocity(h.c, h.c->braw);
@@ -900,6 +1002,7 @@ int bl_lddmm_gradient(const bl_problem* prob, const float* I0, const float* I1,
     store_band(h.c, h.c->bout, g_hat, g.dim);
     check_flag(h.c, "gradient");
     if (energy) *energy = h.c->E;
+    h.ok = true;
     return BL_OK;
   });
 }
@@ -911,8 +1014,7 @@ int bl_lddmm_hessvec(const bl_problem* prob, const float* I0, const float* I1,
   if (int r = validate(prob, &g)) return r;
   if (!I0 || !I1 || !v_hat || !dv_hat || !hv_hat) return fail(BL_E_INVALID, "NULL pointer argument");
   return guarded([&]() {
-    CtxHolder h;
-    h.c = create_ctx(prob, g, true, false);
+    CachedCtx h(prob, g, false);
     load_images(h.c, I0, I1);
     load_band(h.c, v_hat, h.c->braw, g.dim);
     op_set_velocity(h.c, h.c->braw);
@@ -920,6 +1022,7 @@ int bl_lddmm_hessvec(const bl_problem* prob, const float* I0, const float* I1,
     op_hessvec(h.c, h.c->braw, h.c->bout);
     store_band(h.c, h.c->bout, hv_hat, g.dim);
     check_flag(h.c, "Hessian-vector product");
+    h.ok = true;
     return BL_OK;
   });
 }
@@ -930,13 +1033,13 @@ int bl_lddmm_warp(const bl_problem* prob, const float* I0, const float* v_hat, f
   if (int r = validate(prob, &g)) return r;
   if (!I0 || !v_hat || !warped) return fail(BL_E_INVALID, "NULL pointer argument");
   return guarded([&]() {
-    CtxHolder h;
-    h.c = create_ctx(prob, g, true, false);
+    CachedCtx h(prob, g, false);
     load_images(h.c, I0, nullptr);
     load_band(h.c, v_hat, h.c->braw, g.dim);
     op_set_velocity(h.c, h.c->braw);
     store_plane(h.c, h.c->m + (size_t)g.nt * g.M, warped, 1);
     sync(h.c);
+    h.ok = true;
     return BL_OK;
   });
 }
@@ -954,8 +1057,7 @@ int bl_lddmm_register(const bl_problem* prob, const bl_solver_opts* opts, const 
     const auto t0 = std::chrono::steady_clock::now();
     bl_stats local;
     std::memset(&local, 0, sizeof(local));
-    CtxHolder h;
-    h.c = create_ctx(prob, g, true, true);
+    CachedCtx h(prob, g, true);
     load_images(h.c, I0, I1);
     load_band(h.c, v_hat, h.c->sv, g.dim);
     solve(h.c, o, &local);
@@ -964,6 +1066,7 @@ int bl_lddmm_register(const bl_problem* prob, const bl_solver_opts* opts, const 
     sync(h.c);
     local.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (stats) *stats = local;
+    h.ok = true;
     return BL_OK;
   });
 }
