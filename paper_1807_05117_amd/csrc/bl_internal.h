@@ -38,7 +38,7 @@ constexpr int kU = 8;      // loads in flight per thread in the contraction loop
 constexpr int kUY = 16;    // loads in flight per thread in the pi y stage
 
 // Twiddle tables are zero-padded so that every chunk of kU loads stays in bounds:
-// padded extents: kx, nx rounded up to 8, ny to 16, ky to kJG, nz to 128.
+// padded extents: kx, nx rounded up to 8, ny to 32, ky to kJG, nz to 128.
 struct DftPlan {
   float2* tw_x = nullptr;   // [kxp][nx]   exp(+2 pi i kx x / nx), kx = j - Kx/2; zero rows >= Kx
   float2* tw_xT = nullptr;  // [nxp][kx]   the same, transposed; zero rows >= nx

@@ -113,7 +113,7 @@ size_t stage_elems(const bl::Geo& g) {
 }
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
-int nyp_of(const bl::Geo& g) { return round_up(g.ny, 16); }
+int nyp_of(const bl::Geo& g) { return round_up(g.ny, 32); }
 int kyp_of(const bl::Geo& g) { return round_up(g.ky, bl::kJG); }
 int kxp_of(const bl::Geo& g) { return round_up(g.kx, 8); }
 int nxp_of(const bl::Geo& g) { return round_up(g.nx, 8); }

@@ -48,6 +48,7 @@ struct Slot {
   void* arena = nullptr;
   size_t arena_bytes = 0;
   double* hscal = nullptr;
+  bl_ctx* ctx = nullptr;   // the last request's context (tables built), reused for the same problem
 };
 
 }  // namespace
@@ -73,21 +74,46 @@ struct bl_server {
 namespace {
 
 // Run one request on a slot: context in the slot's arena, registration, results to host.
+bool same_request_problem(const bl_problem& a, const bl_problem& b) {
+  if (a.dim != b.dim || a.nt != b.nt || a.s != b.s || a.gamma != b.gamma ||
+      a.precision != b.precision || a.flags != b.flags || a.alpha != b.alpha || a.sigma != b.sigma)
+    return false;
+  for (int j = 0; j < 3; ++j)
+    if (a.n[j] != b.n[j] || a.k[j] != b.k[j]) return false;
+  return true;
+}
+
 void run_request(bl_server* srv, Slot& slot, int slot_index, Request* r) {
   r->rc = guarded([&]() {
-    if (slot.arena_bytes < r->bytes) {
-      if (slot.arena) HIP_TRY(hipFree(slot.arena));
-      slot.arena = nullptr;
-      slot.arena_bytes = 0;
-      HIP_TRY(hipMalloc(&slot.arena, r->bytes));
-      slot.arena_bytes = r->bytes;
+    // a context of the same problem as the slot's last one is reused as it is (its tables
+    // and launch shapes); any other problem gets a new context in the slot's arena
+    if (slot.ctx && !same_request_problem(slot.ctx->prob, r->prob)) {
+      destroy_ctx(slot.ctx);
+      slot.ctx = nullptr;
     }
-    bl_ctx* c = create_ctx(&r->prob, r->g, true, true, slot.arena, slot.arena_bytes, slot.stream,
-                           slot.hscal);
-    struct Guard {
-      bl_ctx* c;
-      ~Guard() { destroy_ctx(c); }
-    } guard{c};
+    if (!slot.ctx) {
+      if (slot.arena_bytes < r->bytes) {
+        if (slot.arena) HIP_TRY(hipFree(slot.arena));
+        slot.arena = nullptr;
+        slot.arena_bytes = 0;
+        HIP_TRY(hipMalloc(&slot.arena, r->bytes));
+        slot.arena_bytes = r->bytes;
+      }
+      slot.ctx = create_ctx(&r->prob, r->g, true, true, slot.arena, slot.arena_bytes, slot.stream,
+                            slot.hscal);
+    }
+    bl_ctx* c = slot.ctx;
+    c->have_v = false;
+    struct Guard {   // a failed request leaves no context behind
+      Slot& sl;
+      bool ok = false;
+      ~Guard() {
+        if (!ok) {
+          destroy_ctx(sl.ctx);
+          sl.ctx = nullptr;
+        }
+      }
+    } guard{slot};
     load_images(c, r->I0.data(), r->I1.data());
     load_band(c, r->v.data(), c->sv, r->g.dim);
     std::memset(&r->stats, 0, sizeof(r->stats));
@@ -98,6 +124,7 @@ void run_request(bl_server* srv, Slot& slot, int slot_index, Request* r) {
     store_plane(c, c->m + (size_t)r->g.nt * r->g.M, r->warped.data(), 1);
     sync(c);
     r->stats.seconds = std::chrono::duration<double>(Clock::now() - ts).count();
+    guard.ok = true;
     return BL_OK;
   });
   if (r->rc != BL_OK) r->err = bl_lddmm_last_error();
@@ -280,6 +307,8 @@ void bl_server_destroy(bl_server* srv) {
   hipSetDevice(srv->device);
   for (auto& sl : srv->slots) {
     if (sl.stream) hipStreamSynchronize(sl.stream);
+    destroy_ctx(sl.ctx);   // does not own the arena, stream or host scalars
+    sl.ctx = nullptr;
     if (sl.arena) hipFree(sl.arena);
     if (sl.hscal) hipHostFree(sl.hscal);
     if (sl.stream) hipStreamDestroy(sl.stream);
