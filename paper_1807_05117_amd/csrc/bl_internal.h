@@ -115,9 +115,11 @@ void reduce_max_final(const double* partial, int n, double* out, hipStream_t s,
 void axpy(float2* y, const float2* x, double alpha, int64_t n, hipStream_t s);
 // y = x + beta y
 void xpby(float2* y, const float2* x, double beta, int64_t n, hipStream_t s);
-// y += sign * (num[0] / den[0]) x with device scalars (no update unless den[0] > 0)
-void axpy_dev(float2* y, const float2* x, const double* num, const double* den, double sign,
-              int64_t n, hipStream_t s);
+// one PCG step: alpha = rz / pHp (0 unless pHp > 0), delta += alpha p, r -= alpha Hp,
+// z = r / Lhat, kRedBlocks partials of <r, r> (p0) and <r, z> (p1)
+void pcg_step(const Geo& g, const float2* p, const float2* Hp, const double* rz,
+              const double* pHp, float2* delta, float2* r, const float* Lhat, float2* z,
+              double* p0, double* p1, hipStream_t s);
 // y = x + (num[0] / den[0]) y with device scalars
 void xpby_dev(float2* y, const float2* x, const double* num, const double* den, int64_t n,
               hipStream_t s);

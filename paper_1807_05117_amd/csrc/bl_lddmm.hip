@@ -660,6 +660,7 @@ void solve(bl_ctx* c, const bl_solver_opts& o, bl_stats* st) {
   hipStream_t s = c->stream;
   const int64_t nb = (int64_t)g.dim * g.B;
   double* pa = c->red + RED_A * bl::kRedBlocks;
+  double* pb = c->red + RED_B * bl::kRedBlocks;
   const double den = dev_sqdiff(c, c->m, c->I1);  // |I0 - I1|^2
   auto mse = [&]() { return den > 0 ? 100.0 * c->data_sum / den : 0.0; };
 
@@ -702,10 +703,12 @@ void solve(bl_ctx* c, const bl_solver_opts& o, bl_stats* st) {
       st->hessvecs += 1;
       bl::dot_partial(c->sp, c->sHp, nb, pa, s);
       bl::reduce_final(pa, bl::kRedBlocks, c->scal + S_PHP, s, c->hdev + S_PHP);
-      // alpha = <r, z> / <p, Hp>, zero when <p, Hp> <= 0 (then neither vector moves)
-      bl::axpy_dev(c->sdelta, c->sp, c->scal + rz_cur, c->scal + S_PHP, 1.0, nb, s);
-      bl::axpy_dev(c->sr, c->sHp, c->scal + rz_cur, c->scal + S_PHP, -1.0, nb, s);
-      enqueue_precond(c, rz_next);
+      // alpha = <r, z> / <p, Hp>, zero when <p, Hp> <= 0 (then neither vector moves);
+      // delta, r, z = K r and the partials of <r, r>, <r, z> in one launch
+      bl::pcg_step(g, c->sp, c->sHp, c->scal + rz_cur, c->scal + S_PHP, c->sdelta, c->sr, c->Lhat,
+                   c->sz, pa, pb, s);
+      bl::reduce_final(pa, bl::kRedBlocks, c->scal + S_RR, s, c->hdev + S_RR);
+      bl::reduce_final(pb, bl::kRedBlocks, c->scal + rz_next, s);
       check_launch("pcg");
       sync(c);
       const double pHp = c->hscal[S_PHP];

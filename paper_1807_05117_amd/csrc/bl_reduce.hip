@@ -61,21 +61,45 @@ __global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__
   }
 }
 
-// y += s * (num / den) x with the quotient taken on the device (0 unless den > 0): the PCG step
-// length alpha = <r, z> / <p, Hp> without a round trip to the host.
-__global__ __launch_bounds__(256) void k_axpy_dev(float2* __restrict__ y, const float2* __restrict__ x,
-                                                  const double* __restrict__ num,
-                                                  const double* __restrict__ den, double sign,
-                                                  int64_t n) {
-  const double d = den[0];
-  const double alpha = d > 0.0 ? sign * (num[0] / d) : 0.0;
+// One PCG step after the product Hp, in one launch: alpha = rz / pHp (0 unless pHp > 0),
+// delta += alpha p, r -= alpha Hp, z = r / Lhat, and the block partials of <r, r> (p0) and
+// <r, z> (p1).  Per element the arithmetic of axpy and precond_dots, in the same grid.
+__global__ __launch_bounds__(256) void k_pcg_step(Geo g, const float2* __restrict__ p,
+                                                  const float2* __restrict__ Hp,
+                                                  const double* __restrict__ rz,
+                                                  const double* __restrict__ pHp,
+                                                  float2* __restrict__ delta,
+                                                  float2* __restrict__ r,
+                                                  const float* __restrict__ Lhat,
+                                                  float2* __restrict__ z,
+                                                  double* __restrict__ p0,
+                                                  double* __restrict__ p1) {
+  const int64_t n = (int64_t)g.dim * g.B;
+  const double d = pHp[0];
+  const double alpha = d > 0.0 ? rz[0] / d : 0.0;
+  const double nalpha = d > 0.0 ? -1.0 * (rz[0] / d) : 0.0;
+  double rr = 0.0, rzn = 0.0;
   GRID_STRIDE(i, n) {
-    const float2 a = x[i];
-    float2 b = y[i];
-    b.x = (float)fma(alpha, (double)a.x, (double)b.x);
-    b.y = (float)fma(alpha, (double)a.y, (double)b.y);
-    y[i] = b;
+    const float2 pi = p[i], hi = Hp[i];
+    float2 di = delta[i], ri = r[i];
+    di.x = (float)fma(alpha, (double)pi.x, (double)di.x);
+    di.y = (float)fma(alpha, (double)pi.y, (double)di.y);
+    ri.x = (float)fma(nalpha, (double)hi.x, (double)ri.x);
+    ri.y = (float)fma(nalpha, (double)hi.y, (double)ri.y);
+    delta[i] = di;
+    r[i] = ri;
+    const int64_t b = i % g.B;
+    const float inv = 1.0f / Lhat[b];
+    const float2 w = make_float2(ri.x * inv, ri.y * inv);
+    z[i] = w;
+    rr = fma((double)ri.x, (double)ri.x, rr);
+    rr = fma((double)ri.y, (double)ri.y, rr);
+    rzn = fma((double)ri.x, (double)w.x, rzn);
+    rzn = fma((double)ri.y, (double)w.y, rzn);
   }
+  block_sum_store(rr, p0);
+  __syncthreads();
+  block_sum_store(rzn, p1);
 }
 
 // y = x + (num / den) y: the PCG direction update with beta = <r', z'> / <r, z> on the device
@@ -198,9 +222,11 @@ void reduce_max_final(const double* partial, int n, double* out, hipStream_t s, 
   hipLaunchKernelGGL(k_reduce_final<true>, dim3(1), dim3(256), 0, s, partial, n, out, host, flag,
                      host_flag);
 }
-void axpy_dev(float2* y, const float2* x, const double* num, const double* den, double sign,
-              int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_axpy_dev, dim3(blocks_for(n)), dim3(256), 0, s, y, x, num, den, sign, n);
+void pcg_step(const Geo& g, const float2* p, const float2* Hp, const double* rz,
+              const double* pHp, float2* delta, float2* r, const float* Lhat, float2* z,
+              double* p0, double* p1, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_step, dim3(kRedBlocks), dim3(256), 0, s, g, p, Hp, rz, pHp, delta, r,
+                     Lhat, z, p0, p1);
 }
 void xpby_dev(float2* y, const float2* x, const double* num, const double* den, int64_t n,
               hipStream_t s) {
