@@ -229,11 +229,11 @@ int bl_kernel_timing_read(bl_ctx* ctx, int32_t kclass, int64_t* launches, double
 
 /*
  * Launch shapes of the transport kernels.  A 3D transport launch runs tiles of 64 x 4 x zv
- * voxels (zv voxels per thread along z, zv in {1, 2, 4}) per kernel class: zv_out[0] forward
+ * voxels (zv voxels per thread along z, zv in {1, 2, 4, 8}) per kernel class: zv_out[0] forward
  * state step, [1] incremental state, [2] adjoint steps, [3] body force.  Every shape computes
  * bitwise the same values.  The library times the candidates on the context's own fields at
  * the first velocity set on a grid shape and keeps the fastest per shape for the process; the
- * environment variable BL_TRANSPORT_ZV = 1, 2 or 4 forces one shape for all classes, and 0
+ * environment variable BL_TRANSPORT_ZV = 1, 2, 4 or 8 forces one shape for all classes, and 0
  * keeps the built-in defaults without timing.  Reads the shapes in use (all 1 in 2D, and the
  * defaults before the first velocity).  Errors: BL_E_INVALID for NULL arguments.
  */

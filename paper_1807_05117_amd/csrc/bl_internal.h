@@ -22,6 +22,7 @@ struct Geo {
   float dt;           // 1/nt
   float half_nref;    // nref/2 (central difference scale)
   float lam_scale;    // -2/sigma^2
+  float inv_nx, inv_ny, inv_nz;   // 1/n per axis (periodic index wrap)
   // voxels per thread along z of the transport launches, per kernel class (TR_*): a launch
   // shape only, every choice computes bitwise the same values
   int zv[4];

@@ -69,6 +69,9 @@ int validate(const bl_problem* p, bl::Geo* g) {
     g->dt = (float)(1.0 / p->nt);
     g->half_nref = 0.5f * (float)g->nref;
     g->lam_scale = (float)(-2.0 / (p->sigma * p->sigma));
+    g->inv_nx = 1.0f / (float)n[0];
+    g->inv_ny = 1.0f / (float)n[1];
+    g->inv_nz = 1.0f / (float)n[2];
     const bool d3 = p->dim == 3;
     g->zv[bl::TR_STATE] = d3 ? 2 : 1;
     g->zv[bl::TR_INC] = d3 ? 2 : 1;
@@ -442,7 +445,7 @@ void choose_launch_shapes(bl_ctx* c) {
   const char* env = std::getenv("BL_TRANSPORT_ZV");
   if (env && *env) {
     const int v = std::atoi(env);
-    if (v == 1 || v == 2 || v == 4)
+    if (v == 1 || v == 2 || v == 4 || v == 8)
       for (int k = 0; k < 4; ++k) g.zv[k] = v;
     return;  // any other value keeps the defaults
   }
@@ -478,7 +481,7 @@ void choose_launch_shapes(bl_ctx* c) {
     const int dflt = g.zv[cls];
     float t_best = 0.f;
     best[cls] = dflt;
-    for (int zv : {dflt, 1, 2, 4}) {
+    for (int zv : {dflt, 1, 2, 4, 8}) {
       if (zv == dflt && t_best > 0.f) continue;
       g.zv[cls] = zv;
       launch(cls);  // warm-up

@@ -26,20 +26,26 @@ namespace {
 
 constexpr int BX = 64;
 
-__device__ __forceinline__ int wrap(int i, int n) {
-  if ((unsigned)i < (unsigned)n) return i;
-  int r = i % n;
-  return r < 0 ? r + n : r;
+// Periodic index without branches (|i| < 2^21, so i is exact in float): the quotient from
+// i * (1/n) may be off by one near multiples of n, which the two selects correct.  No branch
+// keeps the voxels of a thread in one basic block, so their loads can all be in flight.
+__device__ __forceinline__ int wrap(int i, int n, float inv_n) {
+  const int q = (int)floorf((float)i * inv_n);
+  int r = i - q * n;
+  r += r < 0 ? n : 0;
+  r -= r >= n ? n : 0;
+  return r;
 }
 
 // Split an offset into the lower cell index (periodic) and the fractional weight.  Offsets
 // are clamped to +-2^20 voxels and non-finite offsets are mapped to 0, so every index that
 // reaches memory lies in [0, n).
-__device__ __forceinline__ void split(float o, int base, int n, int& i0, int& i1, float& w) {
+__device__ __forceinline__ void split(float o, int base, int n, float inv_n, int& i0, int& i1,
+                                      float& w) {
   if (!(fabsf(o) <= 1048576.0f)) o = 0.0f;
   const float f = floorf(o);
   w = o - f;
-  i0 = wrap(base + (int)f, n);
+  i0 = wrap(base + (int)f, n, inv_n);
   i1 = (i0 + 1 == n) ? 0 : i0 + 1;
 }
 
@@ -54,16 +60,20 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t field_rsrc(const float* f, con
                                            0x00020000);
 }
 
-// f[row + x0] and f[row + x1] where x1 is x0 + 1 or the periodic wrap to 0.
+// f[row + x0] and f[row + x1] where x1 is x0 + 1 or the periodic wrap to 0.  The wrapped
+// value comes from a second load that every lane issues; lanes that do not wrap point it past
+// the end of the buffer, where the range check returns 0 without touching memory.  No branch.
+constexpr uint32_t kPastEnd = 0xFFFFFFFCu;   // >= the byte size of any field (< 2^32)
+
 __device__ __forceinline__ void load_pair(__amdgpu_buffer_rsrc_t rs, uint32_t row, int x0,
                                           int x1, float& v0, float& v1) {
   const f2v v = __builtin_bit_cast(
       f2v, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)((row + (uint32_t)x0) * 4u), 0, 0));
+  const bool wrapped = x1 != x0 + 1;
+  const uint32_t off = wrapped ? (row + (uint32_t)x1) * 4u : kPastEnd;
+  const float w = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0));
   v0 = v.x;
-  v1 = v.y;
-  if (x1 != x0 + 1)
-    v1 = __builtin_bit_cast(
-        float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)((row + (uint32_t)x1) * 4u), 0, 0));
+  v1 = wrapped ? w : v.y;
 }
 
 // All in-volume indices are 32-bit (the host guarantees prod(n) <= 2^30).
@@ -79,11 +89,11 @@ __device__ __forceinline__ Tap<DIM> make_tap(const Geo& g, int x, int y, int z, 
                                              float oy, float oz) {
   Tap<DIM> t;
   int y0, y1;
-  split(ox, x, g.nx, t.x0, t.x1, t.wx);
-  split(oy, y, g.ny, y0, y1, t.wy);
+  split(ox, x, g.nx, g.inv_nx, t.x0, t.x1, t.wx);
+  split(oy, y, g.ny, g.inv_ny, y0, y1, t.wy);
   if (DIM == 3) {
     int z0, z1;
-    split(oz, z, g.nz, z0, z1, t.wz);
+    split(oz, z, g.nz, g.inv_nz, z0, z1, t.wz);
     t.r00 = ((uint32_t)z0 * g.ny + y0) * g.nx;
     t.r01 = ((uint32_t)z0 * g.ny + y1) * g.nx;
     t.r10 = ((uint32_t)z1 * g.ny + y0) * g.nx;
@@ -157,6 +167,13 @@ __device__ __forceinline__ TileIdx xcd_tile(int gx, int gy, int gz) {
   const int z = zr < g.nz ? zr : g.nz - 1;               \
   const bool live = zr < g.nz;                           \
   const uint32_t p = ((uint32_t)z * g.ny + y) * g.nx + x;
+// The values of a thread's ZV voxels are computed first and stored afterwards, so no store
+// sits between the voxels' loads.
+#define STORE_ZV(out, val)                                 \
+  _Pragma("unroll") for (int zz = 0; zz < ZV; ++zz) {      \
+    GATHER_Z(zz)                                           \
+    if (live) (out)[p] = (val)[zz];                        \
+  }
 
 template <int DIM>
 __global__ __launch_bounds__(BX* GBY) void k_setup(Geo g, const float* __restrict__ v,
@@ -196,13 +213,15 @@ __global__ __launch_bounds__(BX* GBY) void k_state_step(Geo g, const float* __re
                                                         float* __restrict__ m_out) {
   GATHER_XY
   const size_t M = (size_t)g.M;
+  float val[ZV];
 #pragma unroll
   for (int zz = 0; zz < ZV; ++zz) {
     GATHER_Z(zz)
+    (void)live;
     const float ox = X[p], oy = X[M + p], oz = DIM == 3 ? X[2 * M + p] : 0.f;
-    const float v = apply<DIM>(field_rsrc(m_in, g), make_tap<DIM>(g, x, y, z, ox, oy, oz));
-    if (live) m_out[p] = v;
+    val[zz] = apply<DIM>(field_rsrc(m_in, g), make_tap<DIM>(g, x, y, z, ox, oy, oz));
   }
+  STORE_ZV(m_out, val)
 }
 
 template <int DIM, int ZV>
@@ -210,14 +229,15 @@ __global__ __launch_bounds__(BX* GBY) void k_adj_step(Geo g, const float* __rest
                                                       const float4* __restrict__ YA,
                                                       float* __restrict__ lam_out) {
   GATHER_XY
+  float val[ZV];
 #pragma unroll
   for (int zz = 0; zz < ZV; ++zz) {
     GATHER_Z(zz)
+    (void)live;
     const float4 o = YA[p];
-    const float v =
-        o.w * apply<DIM>(field_rsrc(lam_in, g), make_tap<DIM>(g, x, y, z, o.x, o.y, o.z));
-    if (live) lam_out[p] = v;
+    val[zz] = o.w * apply<DIM>(field_rsrc(lam_in, g), make_tap<DIM>(g, x, y, z, o.x, o.y, o.z));
   }
+  STORE_ZV(lam_out, val)
 }
 
 template <int DIM>
@@ -270,12 +290,14 @@ __global__ __launch_bounds__(BX* GBY) void k_inc_init(Geo g, const float* __rest
                                                       const float* __restrict__ dv,
                                                       float* __restrict__ t0) {
   GATHER_XY
+  float val[ZV];
 #pragma unroll
   for (int zz = 0; zz < ZV; ++zz) {
     GATHER_Z(zz)
-    const float v = 0.5f * g.dt * source_f<DIM>(g, m0, dv, x, y, z, p);
-    if (live) t0[p] = v;
+    (void)live;
+    val[zz] = 0.5f * g.dt * source_f<DIM>(g, m0, dv, x, y, z, p);
   }
+  STORE_ZV(t0, val)
 }
 
 template <int DIM, int ZV>
@@ -286,14 +308,16 @@ __global__ __launch_bounds__(BX* GBY) void k_inc_step(Geo g, const float* __rest
                                                       float* __restrict__ t_out) {
   GATHER_XY
   const size_t M = (size_t)g.M;
+  float val[ZV];
 #pragma unroll
   for (int zz = 0; zz < ZV; ++zz) {
     GATHER_Z(zz)
+    (void)live;
     const float ox = X[p], oy = X[M + p], oz = DIM == 3 ? X[2 * M + p] : 0.f;
     const float tr = apply<DIM>(field_rsrc(t_in, g), make_tap<DIM>(g, x, y, z, ox, oy, oz));
-    const float v = fmaf(g.dt, source_f<DIM>(g, m_next, dv, x, y, z, p), tr);
-    if (live) t_out[p] = v;
+    val[zz] = fmaf(g.dt, source_f<DIM>(g, m_next, dv, x, y, z, p), tr);
   }
+  STORE_ZV(t_out, val)
 }
 
 template <int DIM, int ZV>
@@ -304,14 +328,17 @@ __global__ __launch_bounds__(BX* GBY) void k_inc_last(Geo g, const float* __rest
                                                       float* __restrict__ dlam) {
   GATHER_XY
   const size_t M = (size_t)g.M;
+  float val[ZV];
 #pragma unroll
   for (int zz = 0; zz < ZV; ++zz) {
     GATHER_Z(zz)
+    (void)live;
     const float ox = X[p], oy = X[M + p], oz = DIM == 3 ? X[2 * M + p] : 0.f;
     const float tr = apply<DIM>(field_rsrc(t_in, g), make_tap<DIM>(g, x, y, z, ox, oy, oz));
     const float dm = fmaf(0.5f * g.dt, source_f<DIM>(g, mT, dv, x, y, z, p), tr);
-    if (live) dlam[p] = g.lam_scale * dm;
+    val[zz] = g.lam_scale * dm;
   }
+  STORE_ZV(dlam, val)
 }
 
 // b = sum_n w_n lambda^n grad m^n over the stored adjoint and state planes (trapezoid in
@@ -376,12 +403,14 @@ inline dim3 gather_grid(const Geo& g, int zv) {
 }
 }  // namespace
 
-// 3D launches take the class's voxels per thread along z (1, 2 or 4); 2D runs one per thread
+// 3D launches take the class's voxels per thread along z (1, 2, 4 or 8); 2D runs one per thread
 #define DISPATCH_GATHER(KERNEL, CLS, ...)                                                       \
   do {                                                                                          \
     if (g.dim == 3) {                                                                           \
       const int zv_ = g.zv[CLS];                                                                \
-      if (zv_ == 4)                                                                             \
+      if (zv_ == 8)                                                                             \
+        hipLaunchKernelGGL((KERNEL<3, 8>), gather_grid(g, 8), dim3(BX, GBY), 0, s, __VA_ARGS__); \
+      else if (zv_ == 4)                                                                        \
         hipLaunchKernelGGL((KERNEL<3, 4>), gather_grid(g, 4), dim3(BX, GBY), 0, s, __VA_ARGS__); \
       else if (zv_ == 2)                                                                        \
         hipLaunchKernelGGL((KERNEL<3, 2>), gather_grid(g, 2), dim3(BX, GBY), 0, s, __VA_ARGS__); \

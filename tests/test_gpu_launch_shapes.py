@@ -38,8 +38,8 @@ def _run(name, zv):
 def test_every_launch_shape_gives_identical_results(gpu_lib, name):
     ref = _run(name, None)
     print(name, "tuned launch shapes", ref[3], flush=True)
-    assert all(z in (1, 2, 4) for z in ref[3])
-    for zv in (1, 2, 4):
+    assert all(z in (1, 2, 4, 8) for z in ref[3])
+    for zv in (1, 2, 4, 8):
         E, g, H, shapes = _run(name, zv)
         assert shapes == (zv,) * 4
         assert E == ref[0], zv
