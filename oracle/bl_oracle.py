@@ -45,7 +45,11 @@ notes):
   R-GN Gauss-Newton = the Eulerian incremental system with every residual-proportional
       term dropped (symmetric positive definite);
   R-LS update v~ <- v~ + eps dv~ (Hdv~ = -g is a descent direction), Armijo backtracking;
-  R-PCG dv~_0 = 0, at most max_pcg steps, forcing eta = min(0.5, sqrt(|g| / |g_0|)).
+  R-PCG dv~_0 = 0, at most max_pcg steps, forcing eta = min(0.5, sqrt(|g| / |g_0|));
+  R-gamma gamma = 1 (incompressible flow, Section 2.2 constraint, Section 3.2 band form):
+      v~ restricted to divergence-free band vectors; the multiplier terms of the gradient and
+      Hessian make them divergence-free, i.e. both are the per-index orthogonal projections
+      I - q q^T / |q|^2 (q_j = 2 pi k_j / l_j) of the gamma = 0 expressions; inputs projected.
 """
 from __future__ import annotations
 
@@ -57,7 +61,7 @@ import numpy as np
 
 __all__ = [
     "Problem", "band_freqs", "project", "zero_unpaired", "iota", "pi_", "L_hat",
-    "div_band", "iota_at", "pi_at", "interp", "grad_c", "trapezoid_weights", "setup", "forward_state",
+    "div_band", "leray", "iota_at", "pi_at", "interp", "grad_c", "trapezoid_weights", "setup", "forward_state",
     "energy", "State", "evaluate", "gradient", "hessvec", "warp", "dot", "norm2",
     "norm_inf", "mse_rel", "register", "SolverOpts", "CONVERGED", "MAXITER", "STALLED",
     "max_displacement_voxels",
@@ -79,6 +83,7 @@ class Problem:
     alpha: float = 1e-3
     s: int = 2
     sigma: float = 1.0
+    gamma: int = 0
 
     def __post_init__(self):
         if self.dim not in (2, 3):
@@ -90,6 +95,8 @@ class Problem:
                 raise ValueError("band sizes must be even, >= 2 and <= grid size")
         if self.nt < 1 or self.sigma <= 0 or self.alpha < 0 or self.s < 0:
             raise ValueError("bad nt / sigma / alpha / s")
+        if self.gamma not in (0, 1):
+            raise ValueError("gamma must be 0 or 1")
 
     @property
     def shape(self):
@@ -136,7 +143,9 @@ def zero_unpaired(vh: np.ndarray, prob: Problem) -> np.ndarray:
 
 def project(vh: np.ndarray, prob: Problem) -> np.ndarray:
     """Projection onto admissible coefficients: (v~(k) + conj v~(-k)) / 2 on paired
-    indices, zero on unpaired planes (R3).  Works on one component or on a stack."""
+    indices, zero on unpaired planes (R3).  Works on one component or on a stack; a velocity
+    stack (dim components) of an incompressible problem (gamma = 1) is then also made
+    divergence-free (leray, reading R-gamma)."""
     vh = np.asarray(vh, dtype=np.complex128)
     out = np.zeros_like(vh)
     lead = vh.ndim - prob.dim
@@ -144,7 +153,23 @@ def project(vh: np.ndarray, prob: Problem) -> np.ndarray:
     rev = (slice(None),) * lead + (slice(None, None, -1),) * prob.dim
     w = vh[inner]
     out[inner] = 0.5 * (w + np.conj(w[rev]))
+    if prob.gamma == 1 and lead == 1 and vh.shape[0] == prob.dim:
+        out = leray(out, prob)
     return out
+
+
+def leray(vh: np.ndarray, prob: Problem) -> np.ndarray:
+    """Orthogonal projection of a band velocity (dim components) onto the divergence-free
+    band vectors, per index k: v~ - q (q . v~) / |q|^2 with q_j = 2 pi k_j / l_j, the symbol of
+    the spectral divergence up to the factor i; identity at k = 0 (reading R-gamma: the
+    multiplier term gamma grad~ p~ of the gradient and Hessian of Section 3.2 is what makes
+    them divergence-free, i.e. these projections)."""
+    vh = np.asarray(vh, dtype=np.complex128)
+    q = [2.0 * np.pi * x for x in _kl(prob)]
+    qq = sum(x * x for x in q)
+    s = sum(q[j] * vh[j] for j in range(prob.dim))
+    inv = np.divide(1.0, qq, out=np.zeros_like(qq), where=qq > 0)
+    return np.stack([vh[j] - q[j] * s * inv for j in range(prob.dim)])
 
 
 def _emat(N: int, K: int, sign: float) -> np.ndarray:
@@ -371,7 +396,7 @@ def gradient(st: State) -> np.ndarray:
         for j in range(d):
             b[j] += w[n] * lam * gm[j]
     Lh = L_hat(prob)
-    return np.stack([Lh * st.geo["vh"][j] + pi_(b[j], prob) for j in range(d)])
+    return _constrained(np.stack([Lh * st.geo["vh"][j] + pi_(b[j], prob) for j in range(d)]), prob)
 
 
 def hessvec(st: State, dvh: np.ndarray) -> np.ndarray:
@@ -409,7 +434,13 @@ def hessvec(st: State, dvh: np.ndarray) -> np.ndarray:
         for j in range(d):
             Hb[j] += w[n] * dlam * gm[j]
     Lh = L_hat(prob)
-    return np.stack([Lh * dvh[j] + pi_(Hb[j], prob) for j in range(d)])
+    return _constrained(np.stack([Lh * dvh[j] + pi_(Hb[j], prob) for j in range(d)]), prob)
+
+
+def _constrained(g: np.ndarray, prob: Problem) -> np.ndarray:
+    """gamma = 1: the gradient or Hessian product with its multiplier term, i.e. the
+    divergence-free part (reading R-gamma); gamma = 0: unchanged."""
+    return leray(g, prob) if prob.gamma == 1 else g
 
 
 def warp(I0, vh, prob: Problem) -> np.ndarray:

@@ -311,10 +311,59 @@ def pin_solver(O):
             and np.max(np.abs(vh)) <= 1e-12 * np.max(np.abs(v0)))
 
 
+def _div_free_problem(O):
+    prob = O.Problem(3, (20, 16, 12), (8, 8, 6), 4, alpha=5e-3, s=1, gamma=1)
+    yy = np.arange(16)[None, :, None] / 16
+    zz = np.arange(12)[:, None, None] / 12
+    xx = np.arange(20)[None, None, :] / 20
+    I0 = np.cos(2 * np.pi * xx) * np.sin(2 * np.pi * (yy + zz)) + 0.3 * np.sin(2 * np.pi * zz)
+    return prob, I0
+
+
+def pin_incompressible_projection(O):
+    """gamma = 1: the projection of an arbitrary band vector is divergence-free to rounding
+    (spectral divergence of the projected vector), idempotent, and leaves a velocity built as
+    a spectral curl unchanged"""
+    prob, _ = _div_free_problem(O)
+    raw = phantoms.random_band_direction(21, 3, prob.k)
+    p = O.project(raw, prob)
+    div = O.div_band(p, prob)
+    ok = np.max(np.abs(div)) <= 1e-12 * np.max(np.abs(p)) * 2 * np.pi * max(prob.k)
+    ok &= np.allclose(O.project(p, prob), p, rtol=0, atol=1e-13 * np.abs(p).max())
+    # curl of a potential: (q2 a3 - q3 a2, ...) is divergence-free by construction
+    q = [2 * np.pi * x for x in O._kl(prob)]
+    a = O.project(phantoms.random_band_direction(22, 3, prob.k), O.Problem(3, prob.n, prob.k, 4))
+    c = np.stack([q[1] * a[2] - q[2] * a[1], q[2] * a[0] - q[0] * a[2], q[0] * a[1] - q[1] * a[0]])
+    c = O.project(c, O.Problem(3, prob.n, prob.k, 4))
+    ok &= np.allclose(O.project(c, prob), c, rtol=0, atol=1e-12 * np.abs(c).max())
+    return ok
+
+
+def pin_incompressible_gradient(O):
+    """gamma = 1: the gradient is divergence-free, the reaction factor of an incompressible
+    flow is 1, and central differences of E along divergence-free directions match <g, w>"""
+    prob, I0 = _div_free_problem(O)
+    vh = O.project(phantoms.raw_band_velocity(23, 3, prob.k), prob)
+    vh *= 1.0 / O.max_displacement_voxels(vh, prob)
+    I1 = np.roll(I0, 1, axis=2)
+    st = O.evaluate(vh, I0, I1, prob)
+    g = O.gradient(st)
+    ok = np.max(np.abs(O.div_band(g, prob))) <= 1e-10 * np.abs(g).max() * 2 * np.pi * max(prob.k)
+    ok &= np.max(np.abs(st.geo["a"] - 1)) < 1e-12
+    for seed in (24, 25):
+        w = O.project(phantoms.raw_band_velocity(seed, 3, prob.k), prob)
+        w /= np.sqrt(np.vdot(w, w).real)
+        eps = 1e-5
+        fd = (O.evaluate(vh + eps * w, I0, I1, prob).E - O.evaluate(vh - eps * w, I0, I1, prob).E) / (2 * eps)
+        ok &= abs(fd - float(np.real(np.vdot(g, w)))) <= 0.1 * abs(fd)   # the optimise-then-discretise gap is ~7% on this coarse grid
+    return ok
+
+
 PINS = [pin_bruteforce_dft, pin_projection, pin_symbol_fd, pin_divergence, pin_roll_and_identity,
         pin_interp_half_voxel, pin_gradient_closed_form, pin_hessvec_closed_form, pin_gradient_fd,
         pin_hessvec_fd_zero_residual, pin_energy_regulariser,
-        pin_incremental_adjoint_is_the_adjoint, pin_symmetry_shift, pin_characteristics, pin_solver]
+        pin_incremental_adjoint_is_the_adjoint, pin_symmetry_shift, pin_characteristics, pin_solver,
+        pin_incompressible_projection, pin_incompressible_gradient]
 
 
 def run_pins(O):
@@ -362,8 +411,14 @@ MUTATIONS = [
      "dlam = interp(dlam, st.geo[\"Y\"], prob)"),
     ("incremental adjoint wrong characteristic", "dlam = st.geo[\"a\"] * interp(dlam, st.geo[\"Y\"], prob)",
      "dlam = st.geo[\"a\"] * interp(dlam, st.geo[\"X\"], prob)"),
-    ("Hessian regulariser missing", "return np.stack([Lh * dvh[j] + pi_(Hb[j], prob) for j in range(d)])",
-     "return np.stack([pi_(Hb[j], prob) for j in range(d)])"),
+    ("Hessian regulariser missing", "np.stack([Lh * dvh[j] + pi_(Hb[j], prob) for j in range(d)])",
+     "np.stack([pi_(Hb[j], prob) for j in range(d)])"),
+    ("incompressible projection sign", "return np.stack([vh[j] - q[j] * s * inv for j in range(prob.dim)])",
+     "return np.stack([vh[j] + q[j] * s * inv for j in range(prob.dim)])"),
+    ("incompressible projection ignores the axis lengths", "q = [2.0 * np.pi * x for x in _kl(prob)]",
+     "q = [2.0 * np.pi * x * (prob.n[j] / prob.nref) for j, x in enumerate(_kl(prob))]"),
+    ("incompressible gradient not projected", "return leray(g, prob) if prob.gamma == 1 else g",
+     "return g"),
     ("update sign", "st_try = evaluate(vh + eps * delta, I0, I1, prob)",
      "st_try = evaluate(vh - eps * delta, I0, I1, prob)"),
     ("trapezoid end weight not halved", "    w[0] *= 0.5\n", "    w[0] *= 1.0\n"),

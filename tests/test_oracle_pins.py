@@ -580,3 +580,22 @@ def test_c1_recovery_of_known_warp():
     assert E[-1] <= O.evaluate(vs, I0, I1, prob).E
     assert stats["status"] == O.CONVERGED
     assert stats["ginf_rel"][-1] < 1e-3
+
+
+def test_incompressible_registration_of_divergence_free_warp():
+    """gamma = 1 with H^1 (s = 1): a target made by a divergence-free velocity is registered
+    with energies decreasing, a divergence-free result, a reaction factor of exactly 1 along
+    the way and an energy at most the generating velocity's"""
+    prob = O.Problem(2, (48, 48), (12, 12), 8, alpha=2e-3, s=1, gamma=1)
+    I0 = phantoms.blobs_2d(4, 48)
+    vs = O.project(phantoms.raw_band_velocity(4, 2, prob.k), prob)
+    vs *= 3.0 / O.max_displacement_voxels(vs, prob)
+    assert np.max(np.abs(O.div_band(vs, prob))) <= 1e-12 * np.abs(vs).max() * 2 * np.pi * 12
+    I1 = O.warp(I0, vs, prob)
+    vh, mT, stats = O.register(I0, I1, np.zeros_like(vs), prob, O.SolverOpts(max_gn=6))
+    E = stats["E"]
+    assert all(E[i + 1] < E[i] for i in range(len(E) - 1))
+    assert stats["mse_rel"][-1] < stats["mse_rel"][0] * 0.2
+    assert np.max(np.abs(O.div_band(vh, prob))) <= 1e-11 * np.abs(vh).max() * 2 * np.pi * 12
+    assert np.max(np.abs(O.setup(vh, prob)["a"] - 1.0)) < 1e-12
+    assert E[-1] <= O.evaluate(vs, I0, I1, prob).E
