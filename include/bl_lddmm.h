@@ -54,7 +54,7 @@ extern "C" {
 /* return codes */
 #define BL_OK             0
 #define BL_E_INVALID     -1   /* bad dim, n, k, nt, alpha, s, sigma, opts or NULL pointer     */
-#define BL_E_UNSUPPORTED -2   /* gamma != 0 (incompressible variant) or unknown precision     */
+#define BL_E_UNSUPPORTED -2   /* unknown precision                                              */
 #define BL_E_NOMEM       -3   /* the working set does not fit in free device memory         */
 #define BL_E_DEVICE      -4   /* a HIP runtime error                                          */
 #define BL_E_NONFINITE   -5   /* NaN/Inf in an input, in E, in the gradient or in H v         */
@@ -81,7 +81,11 @@ typedef struct {
   double  alpha;      /* L = (Id - alpha Lap)^s: alpha >= 0                                 */
   int32_t s;          /*                          0 <= s <= 8                               */
   double  sigma;      /* data weight 1/sigma^2, sigma > 0                                   */
-  int32_t gamma;      /* incompressibility switch of Section 2.2; only 0 is supported      */
+  int32_t gamma;      /* incompressibility switch of Section 2.2 (0 or 1; else INVALID):
+                         1 restricts v~ to divergence-free band vectors; inputs are projected
+                         and gradients and products are their divergence-free parts (the
+                         multiplier term gamma grad~ p~ of Section 3.2), per band index
+                         v~ - q (q . v~) / |q|^2 with q_j = 2 pi k_j / l_j                    */
   int32_t precision;  /* BL_FP32 or BL_MIXED                                                */
   int32_t flags;      /* BL_DEVICE_PTRS or 0                                                */
   void*   stream;     /* hipStream_t used with BL_DEVICE_PTRS (NULL: null stream)           */

@@ -338,6 +338,39 @@ __device__ __forceinline__ int mirror(const Geo& g, int jx, int jy, int jz) {
   return (mz * g.ky + my) * g.kx + mx;
 }
 
+// q_c = 2 pi k_c / l_c (l_c = n_c / N_ref): the spectral divergence is i sum_c q_c v~_c
+template <int DIM>
+__device__ __forceinline__ void div_symbol(const Geo& g, int jx, int jy, int jz, float* q) {
+  const float two_pi = 6.283185307179586f;
+  const int kv[3] = {jx - g.kx / 2, jy - g.ky / 2, jz - g.kz0};
+  const int nn[3] = {g.nx, g.ny, g.nz};
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) q[c] = two_pi * (float)kv[c] * ((float)g.nref / (float)nn[c]);
+}
+
+// Divergence-free part of one band index of a velocity: o - q (q . o) / |q|^2 (identity at
+// k = 0).  Written so that the conjugate-mirror index (q -> -q, o -> conj o) gets exactly the
+// conjugate result, which keeps the output Hermitian.
+template <int DIM>
+__device__ __forceinline__ void leray(const float* q, float2* o) {
+  float qq = 0.f;
+  float2 s = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    qq = fmaf(q[c], q[c], qq);
+    s.x = fmaf(q[c], o[c].x, s.x);
+    s.y = fmaf(q[c], o[c].y, s.y);
+  }
+  if (qq > 0.f) {
+    const float2 t = make_float2(s.x / qq, s.y / qq);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      o[c].x = fmaf(-q[c], t.x, o[c].x);
+      o[c].y = fmaf(-q[c], t.y, o[c].y);
+    }
+  }
+}
+
 template <int DIM>
 __global__ __launch_bounds__(256) void k_band_prep(Geo g, const float2* __restrict__ raw,
                                                    float2* __restrict__ out, int with_div,
@@ -357,12 +390,15 @@ __global__ __launch_bounds__(256) void k_band_prep(Geo g, const float2* __restri
       a[c] = raw[c * B + b];
       m[c] = raw[c * B + mb];
     }
+    float q[DIM];
+    div_symbol<DIM>(g, jx, jy, jz, q);
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) {
+    for (int c = 0; c < DIM; ++c)
       o[c] = up ? make_float2(0.f, 0.f)
                 : make_float2(0.5f * (a[c].x + m[c].x), 0.5f * (a[c].y - m[c].y));
-      out[c * B + b] = o[c];
-    }
+    if (g.gamma) leray<DIM>(q, o);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) out[c * B + b] = o[c];
     if (reg_partial) {
       const double l = Lhat64[b];
 #pragma unroll
@@ -370,15 +406,11 @@ __global__ __launch_bounds__(256) void k_band_prep(Geo g, const float2* __restri
     }
     if (with_div) {
       // r~ = sum_c 2 pi i (k_c / l_c) v~_c with l_c = n_c / N_ref
-      const float two_pi = 6.283185307179586f;
-      const int kv[3] = {jx - g.kx / 2, jy - g.ky / 2, jz - g.kz0};
-      const int nn[3] = {g.nx, g.ny, g.nz};
       float2 d = make_float2(0.f, 0.f);
 #pragma unroll
       for (int c = 0; c < DIM; ++c) {
-        const float qc = two_pi * (float)kv[c] * ((float)g.nref / (float)nn[c]);
-        d.x = fmaf(-qc, o[c].y, d.x);
-        d.y = fmaf(qc, o[c].x, d.y);
+        d.x = fmaf(-q[c], o[c].y, d.x);
+        d.y = fmaf(q[c], o[c].x, d.y);
       }
       out[DIM * B + b] = d;
     }
@@ -394,22 +426,25 @@ __global__ __launch_bounds__(256) void k_band_prep(Geo g, const float2* __restri
   }
 }
 
+// One thread per band index, all C components: Hermitian completion from the kz >= 0 half, the
+// regulariser term, and (leray) the divergence-free part of the C = dim components.
+template <int DIM>
 __global__ __launch_bounds__(256) void k_band_finalize(Geo g, int C,
                                                        const float2* __restrict__ vproj,
                                                        const float* __restrict__ Lhat,
                                                        const float2* __restrict__ P,
                                                        float scale, float2* __restrict__ out,
-                                                       int* __restrict__ nonfinite) {
+                                                       int* __restrict__ nonfinite, int leray_on) {
   const int B = (int)g.B;
-  const int total = C * B;
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < total; i += gridDim.x * 256) {
-    const int c = i / B;
-    const int b = i - c * B;
+  for (int b = blockIdx.x * 256 + threadIdx.x; b < B; b += gridDim.x * 256) {
     int jx, jy, jz;
     band_index(g, b, jx, jy, jz);
-    float2 o = make_float2(0.f, 0.f);
-    if (!unpaired(g, jx, jy, jz)) {
-      const int kzv = jz - g.kz0;
+    const bool up = unpaired(g, jx, jy, jz);
+    const int kzv = jz - g.kz0;
+    float2 o[4];
+    for (int c = 0; c < C; ++c) {
+      o[c] = make_float2(0.f, 0.f);
+      if (up) continue;
       const float2* Pc = P + (size_t)c * g.kzh * g.ky * g.kx;
       float2 pv;
       if (kzv > 0) {
@@ -423,16 +458,23 @@ __global__ __launch_bounds__(256) void k_band_finalize(Geo g, int C,
         const float2 m = Pc[(size_t)(g.ky - jy) * g.kx + (g.kx - jx)];
         pv = make_float2(0.5f * (a.x + m.x), 0.5f * (a.y - m.y));
       }
-      o = make_float2(scale * pv.x, scale * pv.y);
+      o[c] = make_float2(scale * pv.x, scale * pv.y);
       if (vproj) {
         const float l = Lhat[b];
         const float2 v = vproj[c * B + b];
-        o.x = fmaf(l, v.x, o.x);
-        o.y = fmaf(l, v.y, o.y);
+        o[c].x = fmaf(l, v.x, o[c].x);
+        o[c].y = fmaf(l, v.y, o[c].y);
       }
-      if (!isfinite(o.x) || !isfinite(o.y)) *nonfinite = 1;
     }
-    out[i] = o;
+    if (leray_on && !up) {
+      float q[DIM];
+      div_symbol<DIM>(g, jx, jy, jz, q);
+      leray<DIM>(q, o);
+    }
+    for (int c = 0; c < C; ++c) {
+      if (!isfinite(o[c].x) || !isfinite(o[c].y)) *nonfinite = 1;
+      out[c * B + b] = o[c];
+    }
   }
 }
 
@@ -519,11 +561,16 @@ void band_prep(const Geo& g, const float2* raw, float2* out, int with_div, const
 }
 
 void band_finalize(const Geo& g, int C, const float2* vproj, const float* Lhat,
-                   const float2* P, float scale, float2* out, int* nonfinite, hipStream_t s) {
-  const int total = C * (int)g.B;
-  const int blocks = std::min(4096, (total + 255) / 256);
-  hipLaunchKernelGGL(k_band_finalize, dim3(blocks), dim3(256), 0, s, g, C, vproj, Lhat, P,
-                     scale, out, nonfinite);
+                   const float2* P, float scale, float2* out, int* nonfinite, hipStream_t s,
+                   int leray) {
+  const int blocks = std::min(4096, (int)((g.B + 255) / 256));
+  const int on = (leray && g.gamma && C == g.dim) ? 1 : 0;
+  if (g.dim == 3)
+    hipLaunchKernelGGL(k_band_finalize<3>, dim3(blocks), dim3(256), 0, s, g, C, vproj, Lhat, P,
+                       scale, out, nonfinite, on);
+  else
+    hipLaunchKernelGGL(k_band_finalize<2>, dim3(blocks), dim3(256), 0, s, g, C, vproj, Lhat, P,
+                       scale, out, nonfinite, on);
 }
 
 }  // namespace bl

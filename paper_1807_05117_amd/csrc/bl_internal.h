@@ -23,6 +23,7 @@ struct Geo {
   float half_nref;    // nref/2 (central difference scale)
   float lam_scale;    // -2/sigma^2
   float inv_nx, inv_ny, inv_nz;   // 1/n per axis (periodic index wrap)
+  int gamma;          // 1: incompressible flow (velocities projected divergence-free)
   // voxels per thread along z of the transport launches, per kernel class (TR_*): a launch
   // shape only, every choice computes bitwise the same values
   int zv[4];
@@ -73,13 +74,16 @@ void iota_z_mixed(const Geo& g, const DftPlan& p, const float2* F2, int C, float
 void pi_z_mixed(const Geo& g, const DftPlan& p, const float* f, int C, float2* G, hipStream_t s);
 
 // ---- band kernels (bl_dft.hip)
-// out[c] = projection of raw[c] (c < dim); with_div: out[dim] = spectral divergence.
+// out[c] = projection of raw[c] (c < dim): Hermitian, and divergence-free when g.gamma = 1;
+// with_div: out[dim] = spectral divergence.
 // reg_partial (may be null): kRedBlocks partial sums of sum_c Lhat |out_c|^2.
 void band_prep(const Geo& g, const float2* raw, float2* out, int with_div, const double* Lhat64,
                double* reg_partial, hipStream_t s);
-// out[c][k] = Lhat(k) vproj[c][k] + scale * P (Hermitian-completed), zero on unpaired planes.
+// out[c][k] = Lhat(k) vproj[c][k] + scale * P (Hermitian-completed), zero on unpaired planes;
+// leray (C == dim): then projected divergence-free per index k.
 void band_finalize(const Geo& g, int C, const float2* vproj, const float* Lhat,
-                   const float2* P, float scale, float2* out, int* nonfinite, hipStream_t s);
+                   const float2* P, float scale, float2* out, int* nonfinite, hipStream_t s,
+                   int leray = 0);
 
 // ---- transports (bl_transport.hip)
 // X: dim planes of forward offsets; YA = (Y, a) backward offsets and reaction factor

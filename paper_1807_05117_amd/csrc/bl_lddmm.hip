@@ -52,7 +52,7 @@ int validate(const bl_problem* p, bl::Geo* g) {
   if (!std::isfinite(p->alpha) || p->alpha < 0) return fail(BL_E_INVALID, "alpha must be finite and >= 0");
   if (p->s < 0 || p->s > 8) return fail(BL_E_INVALID, "s must be in [0, 8]");
   if (!std::isfinite(p->sigma) || !(p->sigma > 0)) return fail(BL_E_INVALID, "sigma must be finite and > 0");
-  if (p->gamma != 0) return fail(BL_E_UNSUPPORTED, "gamma != 0 (incompressible flow) is not supported");
+  if (p->gamma != 0 && p->gamma != 1) return fail(BL_E_INVALID, "gamma must be 0 or 1");
   if (p->precision != BL_FP32 && p->precision != BL_MIXED)
     return fail(BL_E_UNSUPPORTED, "precision must be BL_FP32 or BL_MIXED");
   if (p->flags & ~BL_DEVICE_PTRS) return fail(BL_E_INVALID, "unknown flag bits");
@@ -72,6 +72,7 @@ int validate(const bl_problem* p, bl::Geo* g) {
     g->inv_nx = 1.0f / (float)n[0];
     g->inv_ny = 1.0f / (float)n[1];
     g->inv_nz = 1.0f / (float)n[2];
+    g->gamma = p->gamma;
     const bool d3 = p->dim == 3;
     g->zv[bl::TR_STATE] = d3 ? 2 : 1;
     g->zv[bl::TR_INC] = d3 ? 2 : 1;
@@ -548,7 +549,8 @@ void op_gradient(bl_ctx* c, float2* gout) {
   bl::terminal(g, c->m + g.nt * M, c->I1, c->L + g.nt * M, s);
   backward_and_body_force(c);
   bl::pi_half(g, c->plan, c->Bf, g.dim, c->P, s);
-  bl::band_finalize(g, g.dim, c->bv, c->Lhat, c->P, (float)(1.0 / (double)g.M), gout, c->flag, s);
+  bl::band_finalize(g, g.dim, c->bv, c->Lhat, c->P, (float)(1.0 / (double)g.M), gout, c->flag, s,
+                    1);
   check_launch("gradient");
 }
 
@@ -571,7 +573,8 @@ void op_hessvec(bl_ctx* c, const float2* draw, float2* hout) {
   bl::inc_last(g, tin, c->X, c->m + g.nt * M, c->DV, c->L + g.nt * M, s);
   backward_and_body_force(c);
   bl::pi_half(g, c->plan, c->Bf, g.dim, c->P, s);
-  bl::band_finalize(g, g.dim, c->bd, c->Lhat, c->P, (float)(1.0 / (double)g.M), hout, c->flag, s);
+  bl::band_finalize(g, g.dim, c->bd, c->Lhat, c->P, (float)(1.0 / (double)g.M), hout, c->flag, s,
+                    1);
   check_launch("hessvec");
 }
 
@@ -1090,6 +1093,7 @@ int bl_band_to_grid(const bl_problem* prob, int32_t ncomp, const float* band, fl
     // project each component separately through the prep kernel (it handles dim components)
     bl::Geo g1 = g;
     g1.dim = 1;
+    g1.gamma = 0;   // single components: Hermitian projection only
     for (int i = 0; i < ncomp; ++i) {
       load_band(c, band + (size_t)2 * g.B * i, c->braw, 1);
       bl::band_prep(g1, c->braw, c->bv + (size_t)g.B * i, 0, nullptr, nullptr, c->stream);

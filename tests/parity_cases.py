@@ -22,13 +22,23 @@ CASES = {
     "c2_full": (3, (128, 128, 128), (32, 32, 32), 10, 6.0, 3),
     # brain-shaped 160x192x160: band 40x48x40, Nt = 10, five classes, 6 voxels
     "c3_full": (3, (160, 192, 160), (40, 48, 40), 10, 6.0, 5),
+    # incompressible H^1 (gamma = 1, s = 1): non-cubic 3D and 2D
+    "h1_incomp_3d": (3, (40, 48, 36), (10, 12, 8), 6, 3.0, 5),
+    "h1_incomp_2d": (2, (64, 64), (16, 16), 10, 4.0, 0),
+}
+# regulariser and flow model per case (default alpha = 1e-3, s = 2, gamma = 0)
+MODEL = {
+    "h1_incomp_3d": dict(alpha=5e-3, s=1, gamma=1),
+    "h1_incomp_2d": dict(alpha=5e-3, s=1, gamma=1),
 }
 
 
 @functools.lru_cache(maxsize=None)
 def case(name, seed=0):
     dim, n, k, nt, disp, ncls = CASES[name]
-    prob = O.Problem(dim, n, k, nt, alpha=1e-3, s=2, sigma=1.0)
+    model = dict(alpha=1e-3, s=2, gamma=0)
+    model.update(MODEL.get(name, {}))
+    prob = O.Problem(dim, n, k, nt, sigma=1.0, **model)
     if dim == 2:
         I0 = phantoms.blobs_2d(seed, n[0])[: n[1], : n[0]]
     else:
@@ -63,7 +73,7 @@ def oracle_hessvec(name, seed=0):
 
 def bl_problem(prob, precision=B.BL_FP32, **kw):
     return B.make_problem(prob.dim, prob.n, prob.k, prob.nt, alpha=prob.alpha, s=prob.s,
-                          sigma=prob.sigma, precision=precision, **kw)
+                          sigma=prob.sigma, gamma=prob.gamma, precision=precision, **kw)
 
 
 def rel2(a, b):

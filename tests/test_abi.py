@@ -51,7 +51,8 @@ BAD = [
     (dict(s=9), B.BL_E_INVALID),
     (dict(sigma=0.0), B.BL_E_INVALID),
     (dict(sigma=float("inf")), B.BL_E_INVALID),
-    (dict(gamma=1), B.BL_E_UNSUPPORTED),
+    (dict(gamma=2), B.BL_E_INVALID),
+    (dict(gamma=-1), B.BL_E_INVALID),
     (dict(precision=7), B.BL_E_UNSUPPORTED),
 ]
 

@@ -1,0 +1,59 @@
+"""GPU parity of the incompressible flow model (gamma = 1, here with the H^1 regulariser
+s = 1): velocities are projected divergence-free, and gradients and Hessian products are the
+divergence-free parts of the gamma = 0 expressions.  Same tolerances as the plain path
+(relative 1e-5); the outputs' spectral divergence and the unit reaction factor are checked
+directly."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1807_05117_amd import binding as B
+
+from parity_cases import (bl_problem, case, grad_error, oracle_gradient, oracle_hessvec,
+                          oracle_state, rel2)
+
+pytestmark = pytest.mark.gpu
+
+CASES = ["h1_incomp_3d", "h1_incomp_2d"]
+
+
+def _div_rel(vh, prob):
+    return float(np.abs(O.div_band(vh.astype(np.complex128), prob)).max()
+                 / (np.abs(vh).max() * 2 * np.pi * max(prob.k)))
+
+
+@pytest.mark.parametrize("precision,tol", [(B.BL_FP32, 1e-5), (B.BL_MIXED, 1e-4)],
+                         ids=["fp32", "mixed"])
+@pytest.mark.parametrize("name", CASES)
+def test_incompressible_gradient_and_hessvec(gpu_lib, name, precision, tol):
+    prob, I0, I1, vs, vh, dv = case(name)
+    ctx = B.Ctx(bl_problem(prob, precision=precision), I0, I1)
+    E, g = ctx.bl_lddmm_ctx_set_velocity(vh.astype(np.complex64))
+    H = ctx.bl_lddmm_ctx_hessvec(dv.astype(np.complex64))
+    a = ctx.bl_lddmm_ctx_get_field("a", 0)
+    ctx.close()
+    eg = grad_error(g, oracle_gradient(name), prob, vh)
+    eh = rel2(H, oracle_hessvec(name))
+    print(f"{name}: gradient rel err {eg:.2e}, hessvec {eh:.2e}, div g {_div_rel(g, prob):.1e}, "
+          f"div Hv {_div_rel(H, prob):.1e}, max|a-1| {np.abs(a - 1).max():.1e}", flush=True)
+    assert eg < tol and eh < tol
+    assert abs(E - oracle_state(name).E) <= tol * oracle_state(name).E
+    assert _div_rel(g, prob) < 1e-6 and _div_rel(H, prob) < 1e-6
+    assert np.abs(a - 1).max() < 1e-5
+
+
+def test_incompressible_register_2d_against_oracle(gpu_lib):
+    prob, I0, I1, vs, vh, dv = case("h1_incomp_2d")
+    v0 = np.zeros_like(vh)
+    opts = O.SolverOpts(max_gn=6)
+    v_ref, m_ref, st_ref = O.register(I0, I1, v0, prob, opts)
+    v_gpu, m_gpu, st = B.bl_lddmm_register(bl_problem(prob), I0, I1, v0.astype(np.complex64),
+                                           B.opts_struct(max_gn=6))
+    print("gpu", st["pcg_iters"], st["mse_rel"][-1], " oracle", st_ref["pcg_iters"],
+          st_ref["mse_rel"][-1], flush=True)
+    assert st["status"] == st_ref["status"]
+    assert st["pcg_iters"] == st_ref["pcg_iters"]
+    assert st["ls_trials"] == st_ref["ls_trials"]
+    assert np.allclose(st["E"], st_ref["E"], rtol=1e-4, atol=0)
+    assert rel2(v_gpu, v_ref) < 1e-3
+    assert _div_rel(v_gpu, prob) < 1e-6
