@@ -62,7 +62,8 @@ import numpy as np
 __all__ = [
     "Problem", "band_freqs", "project", "zero_unpaired", "iota", "pi_", "L_hat",
     "div_band", "leray", "iota_at", "pi_at", "interp", "grad_c", "trapezoid_weights", "setup", "forward_state",
-    "energy", "State", "evaluate", "gradient", "hessvec", "warp", "dot", "norm2",
+    "energy", "State", "evaluate", "gradient", "hessvec", "adjoint", "div_c", "hessvec_newton",
+    "warp", "dot", "norm2",
     "norm_inf", "mse_rel", "register", "SolverOpts", "CONVERGED", "MAXITER", "STALLED",
     "max_displacement_voxels",
 ]
@@ -433,6 +434,80 @@ def hessvec(st: State, dvh: np.ndarray) -> np.ndarray:
         gm = grad_c(st.m[n], prob)
         for j in range(d):
             Hb[j] += w[n] * dlam * gm[j]
+    Lh = L_hat(prob)
+    return _constrained(np.stack([Lh * dvh[j] + pi_(Hb[j], prob) for j in range(d)]), prob)
+
+
+def adjoint(st: State) -> list:
+    """The adjoint at every time step (Section 2.2 adjoint equation and final condition,
+    reading R12): lambda^Nt = -(2/sigma^2)(m^Nt - I1), lambda^n = a Interp(lambda^{n+1}, i + Y).
+    Returns [lambda^0, ..., lambda^Nt]."""
+    prob = st.prob
+    lam = [None] * (prob.nt + 1)
+    lam[-1] = -(2.0 / prob.sigma ** 2) * (st.m[-1] - st.I1)
+    for n in range(prob.nt - 1, -1, -1):
+        lam[n] = st.geo["a"] * interp(lam[n + 1], st.geo["Y"], prob)
+    return lam
+
+
+def div_c(u, prob: Problem) -> np.ndarray:
+    """Central-difference divergence sum_j (u_j(i + e_j) - u_j(i - e_j)) / (2h) of dim fields
+    in spatial order: minus the transpose of grad_c (R10), periodic."""
+    out = np.zeros(prob.shape)
+    for j in range(prob.dim):
+        ax = prob.axis(j)
+        out += (np.roll(u[j], -1, axis=ax) - np.roll(u[j], 1, axis=ax)) * (prob.nref / 2.0)
+    return out
+
+
+def hessvec_newton(st: State, dvh: np.ndarray) -> np.ndarray:
+    """Full Newton Hessian-vector product: the second-order system of Section 2.2 and the
+    Hessian of Section 3.2 equation BLHessianStateEquation with both adjoint terms kept
+    (reading R-N):
+
+      dm^n as in the Gauss-Newton product, every time step kept;
+      s^n = div(lambda^n dv)      (the source -div(lambda dv) of the incremental adjoint);
+      q^Nt = -(2/sigma^2) dm^Nt,
+      q^n = a Interp(q^{n+1} + dt/2 s^{n+1}, i + Y) + dt/2 s^n   (0 < n < Nt),
+      q^0 = a Interp(q^1 + dt/2 s^1, i + Y),
+      dlambda^n = q^n for n < Nt, dlambda^Nt = q^Nt + dt/2 s^Nt;
+      H dv~ = L^ dv~ + pi(sum_n w_n [dlambda^n grad m^n + lambda^n grad dm^n]).
+    The source is integrated by the trapezoid rule along the backward characteristic, with its
+    own-time half weight moved from t = 0 to t = 1: the mirror of dm^n, which has its own-time
+    half weight at every n >= 1 and none at 0.  With the trapezoid weights w_n of the Hessian
+    sum this pairs every term of lambda grad dm with its transpose in dlambda grad m, so the
+    product is exactly symmetric when the transports are permutations (pinned); the moved
+    half weights change the sum by O(dt^2).
+    """
+    prob, d = st.prob, st.prob.dim
+    dvh = project(dvh, prob)
+    dv = [iota(dvh[j], prob) for j in range(d)]
+    dt = prob.dt
+    X, Y, a = st.geo["X"], st.geo["Y"], st.geo["a"]
+
+    def f(n):
+        gm = grad_c(st.m[n], prob)
+        return -sum(gm[j] * dv[j] for j in range(d))
+
+    dm = [np.zeros(prob.shape)]
+    fn = f(0)
+    for n in range(prob.nt):
+        fn1 = f(n + 1)
+        dm.append(interp(dm[-1] + 0.5 * dt * fn, X, prob) + 0.5 * dt * fn1)
+        fn = fn1
+    lam = adjoint(st)
+    src = [div_c([lam[n] * dv[j] for j in range(d)], prob) for n in range(prob.nt + 1)]
+    w = trapezoid_weights(prob.nt)
+    q = -(2.0 / prob.sigma ** 2) * dm[-1]
+    Hb = [np.zeros(prob.shape) for _ in range(d)]
+    for n in range(prob.nt, -1, -1):
+        if n < prob.nt:
+            q = a * interp(q + 0.5 * dt * src[n + 1], Y, prob) + (0.5 * dt * src[n] if n > 0 else 0.0)
+        dlam = q + 0.5 * dt * src[n] if n == prob.nt else q
+        gm = grad_c(st.m[n], prob)
+        gdm = grad_c(dm[n], prob)
+        for j in range(d):
+            Hb[j] += w[n] * (dlam * gm[j] + lam[n] * gdm[j])
     Lh = L_hat(prob)
     return _constrained(np.stack([Lh * dvh[j] + pi_(Hb[j], prob) for j in range(d)]), prob)
 

@@ -359,11 +359,55 @@ def pin_incompressible_gradient(O):
     return ok
 
 
+def pin_newton_symmetric_on_permutations(O):
+    nt = 8
+    prob = O.Problem(2, (32, 32), (8, 8), nt, sigma=0.8)
+    vh = np.zeros((2,) + prob.bshape, complex)
+    vh[(0, 4, 4)] = nt / prob.nref
+    vh[(1, 4, 4)] = -nt / prob.nref
+    I0 = phantoms.blobs_2d(3, 32)
+    st = O.evaluate(vh, I0, np.roll(I0, 2, axis=0) + 0.1, prob)
+    d1, d2 = rand_band(O, prob, 11), rand_band(O, prob, 12)
+    a = np.vdot(O.hessvec_newton(st, d1), d2).real
+    b = np.vdot(d1, O.hessvec_newton(st, d2)).real
+    return abs(a - b) <= 1e-12 * (abs(a) + abs(b))
+
+
+def pin_newton_closed_form(O):
+    """v = 0: H dv = L^ dv + pi((-(2/sigma^2) f + s/2) grad I0 + (lambda/2) grad f)"""
+    prob = O.Problem(3, (12, 10, 8), (4, 4, 4), 5, sigma=0.7, alpha=2e-3, s=1)
+    rng = np.random.default_rng(4)
+    I0, I1 = rng.standard_normal(prob.shape), rng.standard_normal(prob.shape)
+    st = O.evaluate(np.zeros((3,) + prob.bshape, complex), I0, I1, prob)
+    d = rand_band(O, prob, 5)
+    F = np.zeros(prob.shape, complex)
+    idx = np.meshgrid(*[np.mod(np.arange(K) - K // 2, N) for K, N in zip(prob.bshape, prob.shape)],
+                      indexing="ij")
+    dv = []
+    for j in range(3):
+        F[...] = 0
+        F[tuple(idx)] = d[j]
+        dv.append((np.fft.ifftn(F) * prob.M).real)
+    gI = np_grad(I0, prob)
+    c = 2.0 / prob.sigma ** 2
+    lam = -c * (I0 - I1)
+    f = -sum(gI[j] * dv[j] for j in range(3))
+    s_ = sum(np_grad(lam * dv[j], prob)[j] for j in range(3))
+    gf = np_grad(f, prob)
+    ell = [N / prob.nref for N in prob.shape]
+    kk = np.meshgrid(*[(np.arange(K) - K // 2) / l for K, l in zip(prob.bshape, ell)], indexing="ij")
+    Lh = (1 + 4 * np.pi ** 2 * prob.alpha * sum(q ** 2 for q in kk)) ** prob.s
+    ref = np.stack([Lh * d[j] + fft_pi((-c * f + 0.5 * s_) * gI[j] + 0.5 * lam * gf[j], prob)
+                    for j in range(3)])
+    return np.allclose(O.hessvec_newton(st, d), ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+
+
 PINS = [pin_bruteforce_dft, pin_projection, pin_symbol_fd, pin_divergence, pin_roll_and_identity,
         pin_interp_half_voxel, pin_gradient_closed_form, pin_hessvec_closed_form, pin_gradient_fd,
         pin_hessvec_fd_zero_residual, pin_energy_regulariser,
         pin_incremental_adjoint_is_the_adjoint, pin_symmetry_shift, pin_characteristics, pin_solver,
-        pin_incompressible_projection, pin_incompressible_gradient]
+        pin_incompressible_projection, pin_incompressible_gradient, pin_newton_symmetric_on_permutations,
+        pin_newton_closed_form]
 
 
 def run_pins(O):
@@ -426,6 +470,15 @@ MUTATIONS = [
      "m.append(interp(m[-1], [-x for x in X], prob))"),
     ("backward offset predictor at the wrong point", "Y = [0.5 * (u[j] + interp(u[j], u, prob)) for j in range(d)]",
      "Y = [0.5 * (u[j] + interp(u[j], neg_u, prob)) for j in range(d)]"),
+    ("Newton source sign", "src = [div_c([lam[n] * dv[j] for j in range(d)], prob) for n in range(prob.nt + 1)]",
+     "src = [-div_c([lam[n] * dv[j] for j in range(d)], prob) for n in range(prob.nt + 1)]"),
+    ("Newton drops lambda grad dm", "Hb[j] += w[n] * (dlam * gm[j] + lam[n] * gdm[j])",
+     "Hb[j] += w[n] * (dlam * gm[j])"),
+    ("Newton source half weights at both ends",
+     "q = a * interp(q + 0.5 * dt * src[n + 1], Y, prob) + (0.5 * dt * src[n] if n > 0 else 0.0)",
+     "q = a * interp(q + 0.5 * dt * src[n + 1], Y, prob) + 0.5 * dt * src[n]"),
+    ("central divergence sign", "out += (np.roll(u[j], -1, axis=ax) - np.roll(u[j], 1, axis=ax)) * (prob.nref / 2.0)",
+     "out += (np.roll(u[j], 1, axis=ax) - np.roll(u[j], -1, axis=ax)) * (prob.nref / 2.0)"),
     ("preconditioner inverted", "z = r / Lh[None]\n        p = z.copy()", "z = r * Lh[None]\n        p = z.copy()"),
 ]
 
