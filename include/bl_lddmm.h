@@ -67,6 +67,14 @@ extern "C" {
 
 /* flags */
 #define BL_DEVICE_PTRS 1
+/* Hessian products (bl_lddmm_hessvec, contexts, the solver of bl_lddmm_register) are the full
+ * Newton ones of the second-order system of Section 2.2 / the Hessian of Section 3.2 equation
+ * BLHessianStateEquation: the incremental adjoint keeps its source div(lambda dv) and the
+ * product keeps pi(lambda grad dm); without the flag they are Gauss-Newton (Section 3.4). The
+ * Newton product may be indefinite away from a minimum; PCG then stops at the first direction
+ * of non-positive curvature (the preconditioned gradient if it is the first). Needs 2 Nt + 4
+ * more grid planes of device memory (bl_lddmm_footprint includes them). */
+#define BL_NEWTON      2
 
 /* registration status */
 #define BL_CONVERGED 0

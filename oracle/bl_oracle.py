@@ -561,6 +561,7 @@ class SolverOpts:
     gtol: float = 1e-3          # stop when |g|_inf,rel < gtol
     c1: float = 1e-4            # Armijo constant
     max_halvings: int = 10
+    newton: bool = False        # full Newton products (reading R-N) instead of Gauss-Newton
 
 
 def register(I0, I1, vh0, prob: Problem, opts: SolverOpts = SolverOpts()):
@@ -598,7 +599,7 @@ def register(I0, I1, vh0, prob: Problem, opts: SolverOpts = SolverOpts()):
         rz = dot(r, z)
         iters = 0
         for _j in range(opts.max_pcg):
-            Hp = hessvec(st, p)
+            Hp = hessvec_newton(st, p) if opts.newton else hessvec(st, p)
             stats["hessvecs"] += 1
             pHp = dot(p, Hp)
             if pHp <= 0.0:

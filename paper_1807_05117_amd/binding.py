@@ -24,6 +24,7 @@ BL_OK, BL_E_INVALID, BL_E_UNSUPPORTED, BL_E_NOMEM, BL_E_DEVICE, BL_E_NONFINITE =
 BL_PENDING, BL_E_CANCELLED = 1, -6
 BL_FP32, BL_MIXED = 0, 1
 BL_DEVICE_PTRS = 1
+BL_NEWTON = 2
 BL_CONVERGED, BL_MAXITER, BL_STALLED = 0, 1, 2
 BL_MAX_GN = 64
 FIELDS = {"velocity": 0, "div": 1, "X": 2, "Y": 3, "a": 4, "state": 5}
@@ -155,7 +156,7 @@ def _check(rc):
 
 
 def make_problem(dim, n, k, nt, alpha=1e-3, s=2, sigma=1.0, gamma=0, precision=BL_FP32,
-                 device=False, stream=None) -> Problem:
+                 device=False, stream=None, newton=False) -> Problem:
     p = Problem()
     p.dim = dim
     nn = list(n) + [1] * (3 - len(n))
@@ -165,7 +166,7 @@ def make_problem(dim, n, k, nt, alpha=1e-3, s=2, sigma=1.0, gamma=0, precision=B
         p.k[j] = int(kk[j])
     p.nt, p.alpha, p.s, p.sigma = int(nt), float(alpha), int(s), float(sigma)
     p.gamma, p.precision = int(gamma), int(precision)
-    p.flags = BL_DEVICE_PTRS if device else 0
+    p.flags = (BL_DEVICE_PTRS if device else 0) | (BL_NEWTON if newton else 0)
     p.stream = C.c_void_p(stream) if stream else None
     return p
 

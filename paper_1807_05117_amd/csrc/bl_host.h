@@ -67,6 +67,11 @@ struct bl_ctx {
   float* T1 = nullptr;
   float* L = nullptr;      // (nt + 1) planes: adjoint or incremental adjoint
   float* Bf = nullptr;     // dim planes: body force
+  // full Newton products only
+  float* DM = nullptr;     // (nt + 1) planes: dm^n (dm^0 = 0)
+  float* DL = nullptr;     // (nt + 1) planes: dlambda^n
+  float* U0 = nullptr;     // u ping-pong of the incremental adjoint
+  float* U1 = nullptr;
   // band vectors (complex)
   float2* braw = nullptr;  // up to 4 components of staging
   float2* bv = nullptr;    // dim + 1: projected v, divergence
@@ -87,6 +92,7 @@ struct bl_ctx {
   bool tuned = false;
   // state of the last velocity
   bool have_v = false;
+  bool have_lambda = false;   // L holds the adjoint lambda^n of the current velocity
   double E = 0, reg = 0, data_sum = 0;
   // solver vectors (dim * B complex each)
   float2 *sv = nullptr, *sg = nullptr, *sdelta = nullptr, *sr = nullptr, *sz = nullptr,

@@ -24,6 +24,7 @@ struct Geo {
   float lam_scale;    // -2/sigma^2
   float inv_nx, inv_ny, inv_nz;   // 1/n per axis (periodic index wrap)
   int gamma;          // 1: incompressible flow (velocities projected divergence-free)
+  int newton;         // 1: full Newton Hessian products (else Gauss-Newton)
   // voxels per thread along z of the transport launches, per kernel class (TR_*): a launch
   // shape only, every choice computes bitwise the same values
   int zv[4];
@@ -101,6 +102,19 @@ void inc_step(const Geo& g, const float* t_in, const float* X, const float* m_ne
               const float* dv, float* t_out, hipStream_t s);
 void inc_last(const Geo& g, const float* t_in, const float* X, const float* mT,
               const float* dv, float* dlam, hipStream_t s);
+// full Newton product (the incremental adjoint with its source div(lambda dv), lambda grad dm
+// in the body force): incremental state steps that also store dm^{n+1}; the last one also
+// forms dlambda^Nt = -(2/sigma^2) dm^Nt + dt/2 div(lambda^Nt dv)
+void inc_step_n(const Geo& g, const float* t_in, const float* X, const float* m_next,
+                const float* dv, float* t_out, float* dm_out, hipStream_t s);
+void inc_last_n(const Geo& g, const float* t_in, const float* X, const float* mT,
+                const float* dv, const float* lamT, float* dm_out, float* dlam, hipStream_t s);
+// q = a Interp(u_in, i + Y) (+ dt/2 div(lam_n dv) when own); dlam = q; u_out = q + dt/2 div(..)
+void adj_step_n(const Geo& g, const float* u_in, const float4* YA, const float* lam_n,
+                const float* dv, int own, float* dlam, float* u_out, hipStream_t s);
+// b = sum_n w_n (dlam^n grad m^n + lam^n grad dm^n)
+void body_force_n(const Geo& g, const float* dlam, const float* m, const float* lam,
+                  const float* dm, float* b, hipStream_t s);
 // one component of packed float4 voxels into a plane
 void unpack4(const Geo& g, int comp, const float4* in, float* plane, hipStream_t s);
 

@@ -55,7 +55,7 @@ int validate(const bl_problem* p, bl::Geo* g) {
   if (p->gamma != 0 && p->gamma != 1) return fail(BL_E_INVALID, "gamma must be 0 or 1");
   if (p->precision != BL_FP32 && p->precision != BL_MIXED)
     return fail(BL_E_UNSUPPORTED, "precision must be BL_FP32 or BL_MIXED");
-  if (p->flags & ~BL_DEVICE_PTRS) return fail(BL_E_INVALID, "unknown flag bits");
+  if (p->flags & ~(BL_DEVICE_PTRS | BL_NEWTON)) return fail(BL_E_INVALID, "unknown flag bits");
   if (g) {
     g->dim = p->dim;
     g->nx = n[0]; g->ny = n[1]; g->nz = n[2];
@@ -73,6 +73,7 @@ int validate(const bl_problem* p, bl::Geo* g) {
     g->inv_ny = 1.0f / (float)n[1];
     g->inv_nz = 1.0f / (float)n[2];
     g->gamma = p->gamma;
+    g->newton = (p->flags & BL_NEWTON) ? 1 : 0;
     const bool d3 = p->dim == 3;
     g->zv[bl::TR_STATE] = d3 ? 2 : 1;
     g->zv[bl::TR_INC] = d3 ? 2 : 1;
@@ -124,7 +125,7 @@ int nxp_of(const bl::Geo& g) { return round_up(g.nx, 8); }
 int nzp_of(const bl::Geo& g) { return round_up(g.nz, 128); }
 
 struct Offsets {
-  size_t I1, m, X, YA, V, DV, T0, T1, L, Bf, braw, bv, bd, bout, P, Lhat, Lhat64, tw_x, tw_xT,
+  size_t I1, m, X, YA, V, DV, T0, T1, L, Bf, DM, DL, U, braw, bv, bd, bout, P, Lhat, Lhat64, tw_x, tw_xT,
       tw_y, tw_yT, tw_zT, wi, wp, bufA, bufB, red, scal, flag, solver;
   size_t total;
 };
@@ -145,6 +146,11 @@ Offsets plan_layout(const bl::Geo& g, bool transport, bool solver, bool mixed) {
     o.T1 = L.take(pb);
     o.L = L.take(pb * (g.nt + 1));
     o.Bf = L.take(pb * d);
+    if (g.newton) {   // dm^n, dlambda^n (Nt + 1 planes each) and the u ping-pong
+      o.DM = L.take(pb * (g.nt + 1));
+      o.DL = L.take(pb * (g.nt + 1));
+      o.U = L.take(pb * 2);
+    }
   } else {
     o.V = L.take(pb * 4);
   }
@@ -309,6 +315,9 @@ bl_ctx* create_ctx(const bl_problem* prob, const bl::Geo& g, bool transport, boo
       c->YA = reinterpret_cast<float4*>(a + o.YA);
       c->DV = F(o.DV);
       c->T0 = F(o.T0); c->T1 = F(o.T1); c->L = F(o.L); c->Bf = F(o.Bf);
+      if (g.newton) {
+        c->DM = F(o.DM); c->DL = F(o.DL); c->U0 = F(o.U); c->U1 = F(o.U) + g.M;
+      }
     }
     c->V = F(o.V);
     c->braw = C2(o.braw); c->bv = C2(o.bv); c->bd = C2(o.bd); c->bout = C2(o.bout); c->P = C2(o.P);
@@ -386,6 +395,7 @@ bl_ctx* create_ctx(const bl_problem* prob, const bl::Geo& g, bool transport, boo
     HIP_TRY(hipMemcpyAsync(c->Lhat64, L64.data(), L64.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipMemcpyAsync(c->Lhat, L32.data(), L32.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipMemsetAsync(c->flag, 0, 256, c->stream));
+    if (c->DM) HIP_TRY(hipMemsetAsync(c->DM, 0, plane_bytes(g), c->stream));   // dm^0 = 0
     HIP_TRY(hipStreamSynchronize(c->stream));
   } catch (...) {
     destroy_ctx(c);
@@ -527,6 +537,7 @@ void op_set_velocity(bl_ctx* c, const float2* vraw) {
   const double sig = c->prob.sigma;
   c->E = 0.5 * c->reg + c->data_sum / (sig * sig * (double)g.M);
   c->have_v = true;
+  c->have_lambda = false;
   if (!std::isfinite(c->E)) throw NonFinite{"energy"};
 }
 
@@ -548,14 +559,58 @@ void op_gradient(bl_ctx* c, float2* gout) {
   const size_t M = (size_t)g.M;
   bl::terminal(g, c->m + g.nt * M, c->I1, c->L + g.nt * M, s);
   backward_and_body_force(c);
+  c->have_lambda = true;
   bl::pi_half(g, c->plan, c->Bf, g.dim, c->P, s);
   bl::band_finalize(g, g.dim, c->bv, c->Lhat, c->P, (float)(1.0 / (double)g.M), gout, c->flag, s,
                     1);
   check_launch("gradient");
 }
 
+// Full Newton Hessian-vector product: the Gauss-Newton one plus the incremental adjoint's
+// source div(lambda dv) and pi(sum w_n lambda^n grad dm^n); lambda^n (kept in L) comes from the
+// gradient at this velocity, or is computed here if no gradient was taken.
+void op_hessvec_newton(bl_ctx* c, const float2* draw, float2* hout) {
+  const bl::Geo& g = c->g;
+  hipStream_t s = c->stream;
+  const size_t M = (size_t)g.M;
+  if (!c->have_lambda) {
+    bl::terminal(g, c->m + g.nt * M, c->I1, c->L + g.nt * M, s);
+    for (int n = g.nt - 1; n >= 0; --n) bl::adj_step(g, c->L + (n + 1) * M, c->YA, c->L + n * M, s);
+    c->have_lambda = true;
+  }
+  bl::band_prep(g, draw, c->bd, 0, nullptr, nullptr, s);
+  bl::iota(g, c->plan, c->bd, g.dim, c->DV, s);
+  bl::inc_init(g, c->m, c->DV, c->T0, s);
+  float* tin = c->T0;
+  float* tout = c->T1;
+  for (int n = 0; n + 1 < g.nt; ++n) {
+    bl::inc_step_n(g, tin, c->X, c->m + (n + 1) * M, c->DV, tout, c->DM + (n + 1) * M, s);
+    std::swap(tin, tout);
+  }
+  bl::inc_last_n(g, tin, c->X, c->m + g.nt * M, c->DV, c->L + g.nt * M, c->DM + g.nt * M,
+                 c->DL + g.nt * M, s);
+  const float* uin = c->DL + g.nt * M;   // u^Nt = dlambda^Nt
+  float* ua = c->U0;
+  float* ub = c->U1;
+  for (int n = g.nt - 1; n >= 1; --n) {
+    bl::adj_step_n(g, uin, c->YA, c->L + n * M, c->DV, 1, c->DL + n * M, ua, s);
+    uin = ua;
+    std::swap(ua, ub);
+  }
+  bl::adj_step_n(g, uin, c->YA, c->L, c->DV, 0, c->DL, nullptr, s);
+  bl::body_force_n(g, c->DL, c->m, c->L, c->DM, c->Bf, s);
+  bl::pi_half(g, c->plan, c->Bf, g.dim, c->P, s);
+  bl::band_finalize(g, g.dim, c->bd, c->Lhat, c->P, (float)(1.0 / (double)g.M), hout, c->flag, s,
+                    1);
+  check_launch("hessvec (Newton)");
+}
+
 // Gauss-Newton Hessian-vector product of the raw direction draw into hout
 void op_hessvec(bl_ctx* c, const float2* draw, float2* hout) {
+  if (c->g.newton) {
+    op_hessvec_newton(c, draw, hout);
+    return;
+  }
   const bl::Geo& g = c->g;
   hipStream_t s = c->stream;
   const size_t M = (size_t)g.M;

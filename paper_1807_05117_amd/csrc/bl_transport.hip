@@ -365,6 +365,145 @@ __global__ __launch_bounds__(BX* GBY) void k_body_force(Geo g, const float* __re
   }
 }
 
+// ------------------------------------------------------------ full Newton Hessian product
+// The Newton product keeps the adjoint terms the Gauss-Newton one drops: the source
+// s^n = div(lambda^n dv) of the incremental adjoint and lambda^n grad dm^n in the body force.
+// The incremental state steps also store dm^n; the incremental adjoint runs on
+//   q^Nt = -(2/sigma^2) dm^Nt,  dlambda^Nt = u^Nt = q^Nt + dt/2 s^Nt,
+//   q^n = a Interp(u^{n+1}, i + Y) + dt/2 s^n,  dlambda^n = q^n,  u^n = q^n + dt/2 s^n  (0 < n < Nt),
+//   dlambda^0 = a Interp(u^1, i + Y).
+
+// central-difference divergence of lambda dv at voxel p: sum_j (lam dv_j)(i + e_j) - (i - e_j)
+template <int DIM>
+__device__ __forceinline__ float div_lam_dv(const Geo& g, const float* __restrict__ lam,
+                                            const float* __restrict__ dv, int x, int y, int z,
+                                            uint32_t p) {
+  const size_t M = (size_t)g.M;
+  const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x + 1 == g.nx ? 0 : x + 1;
+  const uint32_t row = p - x;
+  float s = lam[row + xp] * dv[row + xp] - lam[row + xm] * dv[row + xm];
+  const uint32_t sy = g.nx;
+  const uint32_t pym = y == 0 ? p + (uint32_t)(g.ny - 1) * sy : p - sy;
+  const uint32_t pyp = y + 1 == g.ny ? p - (uint32_t)(g.ny - 1) * sy : p + sy;
+  s += lam[pyp] * dv[M + pyp] - lam[pym] * dv[M + pym];
+  if (DIM == 3) {
+    const uint32_t sz = (uint32_t)g.nx * g.ny;
+    const uint32_t pzm = z == 0 ? p + (uint32_t)(g.nz - 1) * sz : p - sz;
+    const uint32_t pzp = z + 1 == g.nz ? p - (uint32_t)(g.nz - 1) * sz : p + sz;
+    s += lam[pzp] * dv[2 * M + pzp] - lam[pzm] * dv[2 * M + pzm];
+  }
+  return s * g.half_nref;
+}
+
+// incremental state step that also stores dm^{n+1} = Interp(t^n, i + X) + dt/2 f^{n+1}
+template <int DIM, int ZV>
+__global__ __launch_bounds__(BX* GBY) void k_inc_step_n(Geo g, const float* __restrict__ t_in,
+                                                        const float* __restrict__ X,
+                                                        const float* __restrict__ m_next,
+                                                        const float* __restrict__ dv,
+                                                        float* __restrict__ t_out,
+                                                        float* __restrict__ dm_out) {
+  GATHER_XY
+  const size_t M = (size_t)g.M;
+  float val[ZV], dmv[ZV];
+#pragma unroll
+  for (int zz = 0; zz < ZV; ++zz) {
+    GATHER_Z(zz)
+    (void)live;
+    const float ox = X[p], oy = X[M + p], oz = DIM == 3 ? X[2 * M + p] : 0.f;
+    const float tr = apply<DIM>(field_rsrc(t_in, g), make_tap<DIM>(g, x, y, z, ox, oy, oz));
+    const float f = source_f<DIM>(g, m_next, dv, x, y, z, p);
+    val[zz] = fmaf(g.dt, f, tr);
+    dmv[zz] = fmaf(0.5f * g.dt, f, tr);
+  }
+  STORE_ZV(t_out, val)
+  STORE_ZV(dm_out, dmv)
+}
+
+// last incremental state step: dm^Nt, and dlambda^Nt = u^Nt = -(2/sigma^2) dm^Nt + dt/2 s^Nt
+template <int DIM, int ZV>
+__global__ __launch_bounds__(BX* GBY) void k_inc_last_n(Geo g, const float* __restrict__ t_in,
+                                                        const float* __restrict__ X,
+                                                        const float* __restrict__ mT,
+                                                        const float* __restrict__ dv,
+                                                        const float* __restrict__ lamT,
+                                                        float* __restrict__ dm_out,
+                                                        float* __restrict__ dlam) {
+  GATHER_XY
+  const size_t M = (size_t)g.M;
+  float dmv[ZV], val[ZV];
+#pragma unroll
+  for (int zz = 0; zz < ZV; ++zz) {
+    GATHER_Z(zz)
+    (void)live;
+    const float ox = X[p], oy = X[M + p], oz = DIM == 3 ? X[2 * M + p] : 0.f;
+    const float tr = apply<DIM>(field_rsrc(t_in, g), make_tap<DIM>(g, x, y, z, ox, oy, oz));
+    const float dm = fmaf(0.5f * g.dt, source_f<DIM>(g, mT, dv, x, y, z, p), tr);
+    dmv[zz] = dm;
+    val[zz] = fmaf(0.5f * g.dt, div_lam_dv<DIM>(g, lamT, dv, x, y, z, p), g.lam_scale * dm);
+  }
+  STORE_ZV(dm_out, dmv)
+  STORE_ZV(dlam, val)
+}
+
+// one incremental adjoint step of the Newton product: q = a Interp(u^{n+1}, i + Y) (+ dt/2 s^n
+// when own); dlambda^n = q; with u_out, u^n = q + dt/2 s^n
+template <int DIM, int ZV>
+__global__ __launch_bounds__(BX* GBY) void k_adj_step_n(Geo g, const float* __restrict__ u_in,
+                                                        const float4* __restrict__ YA,
+                                                        const float* __restrict__ lam_n,
+                                                        const float* __restrict__ dv, int own,
+                                                        float* __restrict__ dlam,
+                                                        float* __restrict__ u_out) {
+  GATHER_XY
+  float qv[ZV], uv[ZV];
+#pragma unroll
+  for (int zz = 0; zz < ZV; ++zz) {
+    GATHER_Z(zz)
+    (void)live;
+    const float4 o = YA[p];
+    const float tr = o.w * apply<DIM>(field_rsrc(u_in, g), make_tap<DIM>(g, x, y, z, o.x, o.y, o.z));
+    const float hs = own ? 0.5f * g.dt * div_lam_dv<DIM>(g, lam_n, dv, x, y, z, p) : 0.f;
+    qv[zz] = tr + hs;
+    uv[zz] = qv[zz] + hs;
+  }
+  STORE_ZV(dlam, qv)
+  if (u_out) { STORE_ZV(u_out, uv) }
+}
+
+// Newton body force: sum_n w_n (dlambda^n grad m^n + lambda^n grad dm^n)
+template <int DIM, int ZV>
+__global__ __launch_bounds__(BX* GBY) void k_body_force_n(Geo g, const float* __restrict__ dlam,
+                                                          const float* __restrict__ m,
+                                                          const float* __restrict__ lam,
+                                                          const float* __restrict__ dm,
+                                                          float* __restrict__ b) {
+  GATHER_XY
+  const size_t M = (size_t)g.M;
+  float acc[ZV][3];
+#pragma unroll
+  for (int zz = 0; zz < ZV; ++zz) {
+    GATHER_Z(zz)
+    (void)live;
+    acc[zz][0] = acc[zz][1] = acc[zz][2] = 0.f;
+    for (int n = 0; n <= g.nt; ++n) {
+      const float w = (n == 0 || n == g.nt) ? 0.5f * g.dt : g.dt;
+      float gr[3], gd[3];
+      grad_c<DIM>(g, m + n * M, x, y, z, p, gr);
+      grad_c<DIM>(g, dm + n * M, x, y, z, p, gd);
+      const float wl = w * dlam[n * M + p];
+      const float wa = w * lam[n * M + p];
+      for (int c = 0; c < DIM; ++c) acc[zz][c] = fmaf(wa, gd[c], fmaf(wl, gr[c], acc[zz][c]));
+    }
+  }
+#pragma unroll
+  for (int zz = 0; zz < ZV; ++zz) {
+    GATHER_Z(zz)
+    if (live)
+      for (int c = 0; c < DIM; ++c) b[c * M + p] = acc[zz][c];
+  }
+}
+
 // Deterministic partial sums of (mT - I1)^2: a fixed grid of kRedBlocks blocks, each thread
 // a fixed strided subset, then a fixed tree in LDS.
 __global__ __launch_bounds__(256) void k_energy_partial(int64_t n, const float* __restrict__ a,
@@ -453,6 +592,22 @@ void inc_step(const Geo& g, const float* t_in, const float* X, const float* m_ne
 void inc_last(const Geo& g, const float* t_in, const float* X, const float* mT,
               const float* dv, float* dlam, hipStream_t s) {
   DISPATCH_GATHER(k_inc_last, TR_INC, g, t_in, X, mT, dv, dlam);
+}
+void inc_step_n(const Geo& g, const float* t_in, const float* X, const float* m_next,
+                const float* dv, float* t_out, float* dm_out, hipStream_t s) {
+  DISPATCH_GATHER(k_inc_step_n, TR_INC, g, t_in, X, m_next, dv, t_out, dm_out);
+}
+void inc_last_n(const Geo& g, const float* t_in, const float* X, const float* mT,
+                const float* dv, const float* lamT, float* dm_out, float* dlam, hipStream_t s) {
+  DISPATCH_GATHER(k_inc_last_n, TR_INC, g, t_in, X, mT, dv, lamT, dm_out, dlam);
+}
+void adj_step_n(const Geo& g, const float* u_in, const float4* YA, const float* lam_n,
+                const float* dv, int own, float* dlam, float* u_out, hipStream_t s) {
+  DISPATCH_GATHER(k_adj_step_n, TR_ADJ, g, u_in, YA, lam_n, dv, own, dlam, u_out);
+}
+void body_force_n(const Geo& g, const float* dlam, const float* m, const float* lam,
+                  const float* dm, float* b, hipStream_t s) {
+  DISPATCH_GATHER(k_body_force_n, TR_FORCE, g, dlam, m, lam, dm, b);
 }
 void energy_partial(const Geo& g, const float* mT, const float* I1, double* partial,
                     hipStream_t s) {

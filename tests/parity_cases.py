@@ -71,6 +71,12 @@ def oracle_hessvec(name, seed=0):
     return O.hessvec(oracle_state(name, seed), dv)
 
 
+@functools.lru_cache(maxsize=None)
+def oracle_hessvec_newton(name, seed=0):
+    prob, I0, I1, vs, vh, dv = case(name, seed)
+    return O.hessvec_newton(oracle_state(name, seed), dv)
+
+
 def bl_problem(prob, precision=B.BL_FP32, **kw):
     return B.make_problem(prob.dim, prob.n, prob.k, prob.nt, alpha=prob.alpha, s=prob.s,
                           sigma=prob.sigma, gamma=prob.gamma, precision=precision, **kw)
