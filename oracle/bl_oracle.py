@@ -49,7 +49,11 @@ notes):
   R-gamma gamma = 1 (incompressible flow, Section 2.2 constraint, Section 3.2 band form):
       v~ restricted to divergence-free band vectors; the multiplier terms of the gradient and
       Hessian make them divergence-free, i.e. both are the per-index orthogonal projections
-      I - q q^T / |q|^2 (q_j = 2 pi k_j / l_j) of the gamma = 0 expressions; inputs projected.
+      I - q q^T / |q|^2 (q_j = 2 pi k_j / l_j) of the gamma = 0 expressions; inputs projected;
+  R-N  full Newton: the incremental adjoint's source div(lambda dv) by the trapezoid rule along
+      the backward characteristic with its own-time half weight at t = 1 (see hessvec_newton);
+  R-NS non-stationary velocity: one band field per time node, trapezoid-weighted regulariser
+      and inner product, Heun steps with the velocity at both ends of a step (see ns_setup).
 """
 from __future__ import annotations
 
@@ -65,7 +69,8 @@ __all__ = [
     "energy", "State", "evaluate", "gradient", "hessvec", "adjoint", "div_c", "hessvec_newton",
     "warp", "dot", "norm2",
     "norm_inf", "mse_rel", "register", "SolverOpts", "CONVERGED", "MAXITER", "STALLED",
-    "max_displacement_voxels",
+    "max_displacement_voxels", "ns_project", "ns_dot", "ns_setup", "ns_evaluate", "ns_gradient",
+    "ns_hessvec", "ns_register",
 ]
 
 CONVERGED, MAXITER, STALLED = 0, 1, 2
@@ -639,6 +644,190 @@ def register(I0, I1, vh0, prob: Problem, opts: SolverOpts = SolverOpts()):
         vh = st_try.geo["vh"]
         st = st_try
         g = gradient(st)
+        stats["gradients"] += 1
+        stats["gn_iters"] += 1
+        stats["E"].append(st.E)
+        stats["mse_rel"].append(mse_rel(st.m[-1], I0, I1))
+        stats["ginf_rel"].append(norm_inf(g) / ginf0)
+    else:
+        stats["status"] = MAXITER
+        if norm_inf(g) / ginf0 < opts.gtol:
+            stats["status"] = CONVERGED
+    return vh, st.m[-1], stats
+
+
+# ---------------------------------------------------------- non-stationary velocity (R-NS)
+#
+# The velocity is a band field per time node t_n = n dt, n = 0..Nt: an array of shape
+# (Nt + 1, dim, band...).  Reading R-NS: the regulariser is integrated by the trapezoid rule,
+# E = 1/2 sum_n w_n <L~ v~^n, v~^n> + sigma^-2 |m(1) - I1|^2; the Heun characteristic of the
+# step t_n -> t_{n+1} takes the velocity at its two ends; gradients and Hessian products are
+# the pointwise-in-time expressions of Section 2.2 / 3.2 (FirstOrder4 with v_t), i.e. the
+# representers in the trapezoid-weighted inner product <a, b>_w = sum_n w_n <a^n, b^n>, which
+# the solver uses for every dot product and norm.
+
+def ns_project(vh, prob: Problem) -> np.ndarray:
+    return np.stack([project(vh[n], prob) for n in range(prob.nt + 1)])
+
+
+def ns_dot(a, b, prob: Problem) -> float:
+    """<a, b>_w = sum_n w_n <a^n, b^n>_l2 (trapezoid weights in time, R-NS)."""
+    w = trapezoid_weights(prob.nt)
+    return float(sum(w[n] * dot(a[n], b[n]) for n in range(prob.nt + 1)))
+
+
+def ns_setup(vh, prob: Problem) -> dict:
+    """Per-node velocities and divergences; per step n (t_n -> t_{n+1}) the Heun offsets with
+    the velocity at the step's two ends (R9 with a time-dependent velocity, R-NS):
+      X^n = -(u^{n+1} + Interp(u^n, i - u^{n+1})) / 2     (end point i at t_{n+1}),
+      Y^n = +(u^n + Interp(u^{n+1}, i + u^n)) / 2         (start point i at t_n),
+      a^n = 1 + dt/2 [R + (1 + dt R) r^n],  R = Interp(r^{n+1}, i + Y^n)   (R12)."""
+    vh = ns_project(vh, prob)
+    d, nt = prob.dim, prob.nt
+    v = [[iota(vh[n][j], prob) for j in range(d)] for n in range(nt + 1)]
+    r = [iota(div_band(vh[n], prob), prob) for n in range(nt + 1)]
+    u = [[prob.dt * prob.nref * v[n][j] for j in range(d)] for n in range(nt + 1)]
+    X, Y, a = [], [], []
+    for n in range(nt):
+        back = [-x for x in u[n + 1]]
+        X.append([-0.5 * (u[n + 1][j] + interp(u[n][j], back, prob)) for j in range(d)])
+        Yn = [0.5 * (u[n][j] + interp(u[n + 1][j], u[n], prob)) for j in range(d)]
+        R = interp(r[n + 1], Yn, prob)
+        Y.append(Yn)
+        a.append(1.0 + 0.5 * prob.dt * (R + (1.0 + prob.dt * R) * r[n]))
+    return {"vh": vh, "v": v, "r": r, "X": X, "Y": Y, "a": a}
+
+
+def ns_evaluate(vh, I0, I1, prob: Problem) -> State:
+    I0 = np.asarray(I0, dtype=np.float64)
+    I1 = np.asarray(I1, dtype=np.float64)
+    geo = ns_setup(vh, prob)
+    m = [I0]
+    for n in range(prob.nt):
+        m.append(interp(m[-1], geo["X"][n], prob))
+    Lh = L_hat(prob)
+    w = trapezoid_weights(prob.nt)
+    reg = 0.5 * sum(w[n] * float(np.sum(Lh[None] * np.abs(geo["vh"][n]) ** 2))
+                    for n in range(prob.nt + 1))
+    res = m[-1] - I1
+    return State(prob, I0, I1, geo, m, reg + float(np.mean(res * res)) / prob.sigma ** 2)
+
+
+def ns_gradient(st: State) -> np.ndarray:
+    """g^n = L^ v~^n + pi(lambda^n grad m^n), lambda^Nt = -(2/sigma^2)(m^Nt - I1),
+    lambda^n = a^n Interp(lambda^{n+1}, i + Y^n)."""
+    prob, d = st.prob, st.prob.dim
+    lam = -(2.0 / prob.sigma ** 2) * (st.m[-1] - st.I1)
+    Lh = L_hat(prob)
+    g = [None] * (prob.nt + 1)
+    for n in range(prob.nt, -1, -1):
+        if n < prob.nt:
+            lam = st.geo["a"][n] * interp(lam, st.geo["Y"][n], prob)
+        gm = grad_c(st.m[n], prob)
+        g[n] = _constrained(np.stack([Lh * st.geo["vh"][n][j] + pi_(lam * gm[j], prob)
+                                      for j in range(d)]), prob)
+    return np.stack(g)
+
+
+def ns_hessvec(st: State, dvh) -> np.ndarray:
+    """Gauss-Newton product per node (R-GN, R-NS): dv^n = iota(dv~^n), f^n = -grad m^n . dv^n,
+    dm^{n+1} = Interp(dm^n + dt/2 f^n, i + X^n) + dt/2 f^{n+1}, dlambda^Nt = -(2/sigma^2) dm^Nt,
+    dlambda^n = a^n Interp(dlambda^{n+1}, i + Y^n), (H dv~)^n = L^ dv~^n + pi(dlambda^n grad m^n)."""
+    prob, d, dt = st.prob, st.prob.dim, st.prob.dt
+    dvh = ns_project(dvh, prob)
+
+    def f(n):
+        gm = grad_c(st.m[n], prob)
+        return -sum(gm[j] * iota(dvh[n][j], prob) for j in range(d))
+
+    dm = np.zeros(prob.shape)
+    fn = f(0)
+    for n in range(prob.nt):
+        fn1 = f(n + 1)
+        dm = interp(dm + 0.5 * dt * fn, st.geo["X"][n], prob) + 0.5 * dt * fn1
+        fn = fn1
+    dlam = -(2.0 / prob.sigma ** 2) * dm
+    Lh = L_hat(prob)
+    out = [None] * (prob.nt + 1)
+    for n in range(prob.nt, -1, -1):
+        if n < prob.nt:
+            dlam = st.geo["a"][n] * interp(dlam, st.geo["Y"][n], prob)
+        gm = grad_c(st.m[n], prob)
+        out[n] = _constrained(np.stack([Lh * dvh[n][j] + pi_(dlam * gm[j], prob)
+                                        for j in range(d)]), prob)
+    return np.stack(out)
+
+
+def ns_register(I0, I1, vh0, prob: Problem, opts: SolverOpts = SolverOpts()):
+    """The Gauss-Newton-Krylov solver of `register` on a non-stationary velocity, every dot
+    product and 2-norm in the trapezoid-weighted inner product (R-NS); PCG preconditioner K^
+    per node; the gradient's inf-norm over all nodes."""
+    I0 = np.asarray(I0, dtype=np.float64)
+    I1 = np.asarray(I1, dtype=np.float64)
+    Lh = L_hat(prob)
+    vh = ns_project(vh0, prob)
+    st = ns_evaluate(vh, I0, I1, prob)
+    g = ns_gradient(st)
+    wnorm = lambda x: math.sqrt(max(ns_dot(x, x, prob), 0.0))
+    g0n, ginf0 = wnorm(g), norm_inf(g)
+    stats = {"E": [st.E], "mse_rel": [mse_rel(st.m[-1], I0, I1)], "ginf_rel": [1.0],
+             "pcg_iters": [], "ls_trials": [], "eps": [], "status": MAXITER, "gn_iters": 0,
+             "hessvecs": 0, "gradients": 1, "evaluations": 1}
+    if ginf0 == 0.0:
+        stats["status"] = CONVERGED
+        stats["ginf_rel"][0] = 0.0
+        return vh, st.m[-1], stats
+    for _ in range(opts.max_gn):
+        if norm_inf(g) / ginf0 < opts.gtol:
+            stats["status"] = CONVERGED
+            break
+        gn = wnorm(g)
+        eta = min(0.5, math.sqrt(gn / g0n))
+        delta = np.zeros_like(vh)
+        r = -g
+        z = r / Lh[None, None]
+        p = z.copy()
+        rz = ns_dot(r, z, prob)
+        iters = 0
+        for _j in range(opts.max_pcg):
+            Hp = ns_hessvec(st, p)
+            stats["hessvecs"] += 1
+            pHp = ns_dot(p, Hp, prob)
+            if pHp <= 0.0:
+                if iters == 0:
+                    delta = z.copy()
+                break
+            alpha = rz / pHp
+            delta = delta + alpha * p
+            r = r - alpha * Hp
+            iters += 1
+            if wnorm(r) <= eta * gn:
+                break
+            z = r / Lh[None, None]
+            rz_new = ns_dot(r, z, prob)
+            beta = rz_new / rz
+            rz = rz_new
+            p = z + beta * p
+        stats["pcg_iters"].append(iters)
+        slope = ns_dot(g, delta, prob)
+        eps, accepted, trials = 1.0, False, 0
+        for _t in range(opts.max_halvings + 1):
+            trials += 1
+            st_try = ns_evaluate(vh + eps * delta, I0, I1, prob)
+            stats["evaluations"] += 1
+            if st_try.E <= st.E + opts.c1 * eps * slope:
+                accepted = True
+                break
+            eps *= 0.5
+        stats["ls_trials"].append(trials)
+        if not accepted:
+            stats["status"] = STALLED
+            stats["eps"].append(0.0)
+            break
+        stats["eps"].append(eps)
+        vh = st_try.geo["vh"]
+        st = st_try
+        g = ns_gradient(st)
         stats["gradients"] += 1
         stats["gn_iters"] += 1
         stats["E"].append(st.E)

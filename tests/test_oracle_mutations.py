@@ -402,12 +402,56 @@ def pin_newton_closed_form(O):
     return np.allclose(O.hessvec_newton(st, d), ref, rtol=0, atol=1e-11 * np.abs(ref).max())
 
 
+def pin_ns_characteristics(O):
+    """non-stationary Heun offsets of the first step against the exact flow of
+    v_x(x, t) = (1 + 4t) v(x) of one Fourier mode (fine RK4): X^0 is the displacement from t_1
+    back to 0, Y^0 from 0 to t_1.  Heun's local error is third order (0.1% here); a predictor
+    taken with the wrong node's velocity is off by 0.4%."""
+    prob = O.Problem(2, (64, 64), (8, 8), 16)
+    c = 0.06 * (1.0 - 0.5j)
+    V = np.zeros((prob.nt + 1, 2) + prob.bshape, complex)
+    for n in range(prob.nt + 1):
+        s_ = 1.0 + 4.0 * n * prob.dt
+        V[n, 0, 4, 5] = s_ * c
+        V[n, 0, 4, 3] = s_ * np.conj(c)
+    geo = O.ns_setup(V, prob)
+    v = lambda x, t: (1.0 + 4.0 * t) * 2 * np.real(c * np.exp(2j * np.pi * x))
+    x0 = np.arange(64) / 64.0
+    ok = True
+    for key, t0, t1 in (("Y", 0.0, prob.dt), ("X", prob.dt, 0.0)):
+        x, t, h = x0.copy(), t0, (t1 - t0) / 200
+        for _ in range(200):
+            k1 = v(x, t); k2 = v(x + h / 2 * k1, t + h / 2); k3 = v(x + h / 2 * k2, t + h / 2)
+            k4 = v(x + h * k3, t + h)
+            x, t = x + h / 6 * (k1 + 2 * k2 + 2 * k3 + k4), t + h
+        disp = (x - x0) * prob.nref
+        ok &= np.max(np.abs(geo[key][0][0][0] - disp)) < 2e-3 * np.max(np.abs(disp))
+    return ok
+
+
+def pin_ns_stationary_limit(O):
+    prob = O.Problem(2, (24, 20), (8, 8), 4, sigma=0.8)
+    I0 = phantoms.blobs_2d(7, 24)[:20, :24]
+    vh = O.project(phantoms.raw_band_velocity(1, 2, prob.k), prob)
+    vh *= 1.5 / O.max_displacement_voxels(vh, prob)
+    I1 = np.roll(I0, 1, axis=0)
+    st, sn = O.evaluate(vh, I0, I1, prob), O.ns_evaluate(np.stack([vh] * 5), I0, I1, prob)
+    w = O.trapezoid_weights(prob.nt)
+    g = O.gradient(st)
+    gs = sum(w[n] * O.ns_gradient(sn)[n] for n in range(5))
+    d = rand_band(O, prob, 3)
+    H = O.hessvec(st, d)
+    Hs = sum(w[n] * O.ns_hessvec(sn, np.stack([d] * 5))[n] for n in range(5))
+    return (abs(sn.E - st.E) <= 1e-12 * st.E and np.allclose(gs, g, rtol=0, atol=1e-12 * np.abs(g).max())
+            and np.allclose(Hs, H, rtol=0, atol=1e-12 * np.abs(H).max()))
+
+
 PINS = [pin_bruteforce_dft, pin_projection, pin_symbol_fd, pin_divergence, pin_roll_and_identity,
         pin_interp_half_voxel, pin_gradient_closed_form, pin_hessvec_closed_form, pin_gradient_fd,
         pin_hessvec_fd_zero_residual, pin_energy_regulariser,
         pin_incremental_adjoint_is_the_adjoint, pin_symmetry_shift, pin_characteristics, pin_solver,
         pin_incompressible_projection, pin_incompressible_gradient, pin_newton_symmetric_on_permutations,
-        pin_newton_closed_form]
+        pin_newton_closed_form, pin_ns_characteristics, pin_ns_stationary_limit]
 
 
 def run_pins(O):
@@ -479,6 +523,12 @@ MUTATIONS = [
      "q = a * interp(q + 0.5 * dt * src[n + 1], Y, prob) + 0.5 * dt * src[n]"),
     ("central divergence sign", "out += (np.roll(u[j], -1, axis=ax) - np.roll(u[j], 1, axis=ax)) * (prob.nref / 2.0)",
      "out += (np.roll(u[j], 1, axis=ax) - np.roll(u[j], -1, axis=ax)) * (prob.nref / 2.0)"),
+    ("non-stationary predictor velocity swapped",
+     "X.append([-0.5 * (u[n + 1][j] + interp(u[n][j], back, prob)) for j in range(d)])",
+     "X.append([-0.5 * (u[n][j] + interp(u[n + 1][j], back, prob)) for j in range(d)])"),
+    ("non-stationary regulariser without time weights",
+     "reg = 0.5 * sum(w[n] * float(np.sum(Lh[None] * np.abs(geo[\"vh\"][n]) ** 2))",
+     "reg = 0.5 * sum(float(np.sum(Lh[None] * np.abs(geo[\"vh\"][n]) ** 2))"),
     ("preconditioner inverted", "z = r / Lh[None]\n        p = z.copy()", "z = r * Lh[None]\n        p = z.copy()"),
 ]
 

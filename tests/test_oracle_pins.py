@@ -685,3 +685,102 @@ def test_newton_matches_derivative_of_gradient_away_from_zero_residual():
     gap_n = np.linalg.norm((fd - HN).ravel()) / np.linalg.norm(HN.ravel())
     gap_g = np.linalg.norm((fd - HG).ravel()) / np.linalg.norm(HN.ravel())
     assert gap_n < 0.12 and gap_g > 3 * gap_n
+
+
+# --------------------------------------------------- non-stationary velocity (reading R-NS)
+
+def _ns_case(seed=0, nt=5):
+    prob = O.Problem(3, (20, 16, 12), (8, 6, 4), nt, sigma=0.8)
+    I0 = phantoms.shells_3d(seed, prob.n)
+    I1 = np.roll(I0, 1, axis=2) + 0.05
+    return prob, I0, I1
+
+
+def test_ns_reduces_to_stationary_for_equal_nodes():
+    """all nodes equal: the same transports and energy, and the weighted sums of the per-node
+    gradient and Hessian product are the stationary ones"""
+    prob, I0, I1 = _ns_case()
+    vh = O.project(phantoms.raw_band_velocity(1, 3, prob.k), prob)
+    vh *= 2.0 / O.max_displacement_voxels(vh, prob)
+    V = np.stack([vh] * (prob.nt + 1))
+    st, sn = O.evaluate(vh, I0, I1, prob), O.ns_evaluate(V, I0, I1, prob)
+    assert np.allclose(sn.m[-1], st.m[-1], rtol=0, atol=1e-13) and abs(sn.E - st.E) < 1e-12 * st.E
+    w = O.trapezoid_weights(prob.nt)
+    g = O.gradient(st)
+    gs = sum(w[n] * O.ns_gradient(sn)[n] for n in range(prob.nt + 1))
+    assert np.allclose(gs, g, rtol=0, atol=1e-12 * np.abs(g).max())
+    d = O.project(phantoms.random_band_direction(2, 3, prob.k), prob)
+    H = O.hessvec(st, d)
+    Hs = sum(w[n] * O.ns_hessvec(sn, np.stack([d] * (prob.nt + 1)))[n] for n in range(prob.nt + 1))
+    assert np.allclose(Hs, H, rtol=0, atol=1e-12 * np.abs(H).max())
+
+
+def test_ns_gradient_matches_finite_differences():
+    """central differences of E along time-varying directions (independent per node) against
+    the weighted inner product with the per-node gradient, on a smooth pair: the
+    optimise-then-discretise gap is about 1% here"""
+    prob = O.Problem(2, (48, 48), (8, 8), 6)
+    yy, xx = np.meshgrid(np.arange(48) / 48, np.arange(48) / 48, indexing="ij")
+    I0 = np.cos(2 * np.pi * xx) * np.sin(2 * np.pi * (xx + 2 * yy))
+    I1 = np.cos(2 * np.pi * (xx - 0.03)) * np.sin(2 * np.pi * (xx + 2 * yy + 0.05))
+    base = O.project(phantoms.raw_band_velocity(6, 2, prob.k), prob)
+    V = np.stack([base * (1 + 0.3 * np.sin(n)) for n in range(prob.nt + 1)])
+    V *= 1.0 / max(O.max_displacement_voxels(V[n], prob) for n in range(prob.nt + 1))
+    g = O.ns_gradient(O.ns_evaluate(V, I0, I1, prob))
+    for seed in (7, 8):
+        W = np.stack([O.project(phantoms.raw_band_velocity(seed * 10 + n, 2, prob.k), prob)
+                      for n in range(prob.nt + 1)])
+        W /= np.sqrt(O.ns_dot(W, W, prob))
+        eps = 1e-5
+        fd = (O.ns_evaluate(V + eps * W, I0, I1, prob).E
+              - O.ns_evaluate(V - eps * W, I0, I1, prob).E) / (2 * eps)
+        assert abs(fd - O.ns_dot(g, W, prob)) <= 0.05 * abs(fd)
+
+
+def test_ns_hessian_symmetric_on_permutation_transports():
+    nt = 6
+    prob = O.Problem(2, (32, 32), (8, 8), nt, sigma=0.8)
+    vh = np.zeros((2,) + prob.bshape, complex)
+    vh[(0, 4, 4)] = nt / prob.nref
+    vh[(1, 4, 4)] = -nt / prob.nref
+    V = np.stack([vh] * (nt + 1))
+    I0 = phantoms.blobs_2d(3, 32)
+    sn = O.ns_evaluate(V, I0, np.roll(I0, 2, axis=0), prob)
+    D1 = np.stack([O.project(phantoms.random_band_direction(30 + n, 2, prob.k), prob) for n in range(nt + 1)])
+    D2 = np.stack([O.project(phantoms.random_band_direction(40 + n, 2, prob.k), prob) for n in range(nt + 1)])
+    a = O.ns_dot(O.ns_hessvec(sn, D1), D2, prob)
+    b = O.ns_dot(D1, O.ns_hessvec(sn, D2), prob)
+    assert abs(a - b) <= 1e-12 * (abs(a) + abs(b))
+
+
+def test_ns_hessvec_closed_form_at_zero_velocity():
+    """v = 0: (H dv)^n = L^ dv~^n + (2/sigma^2) pi((sum_k w_k grad I0 . dv^k) grad I0)"""
+    prob = O.Problem(3, (12, 10, 8), (4, 4, 4), 4, sigma=0.7, alpha=2e-3, s=1)
+    rng = np.random.default_rng(6)
+    I0, I1 = rng.standard_normal(prob.shape), rng.standard_normal(prob.shape)
+    sn = O.ns_evaluate(np.zeros((prob.nt + 1, 3) + prob.bshape, complex), I0, I1, prob)
+    D = np.stack([rand_band(prob, 50 + n) for n in range(prob.nt + 1)])
+    w = O.trapezoid_weights(prob.nt)
+    gI = np_grad(I0, prob)
+    S = sum(w[k] * sum(gI[j] * fft_iota(D[k][j], prob).real for j in range(3))
+            for k in range(prob.nt + 1))
+    Lh = O.L_hat(prob)
+    c = 2.0 / prob.sigma ** 2
+    got = O.ns_hessvec(sn, D)
+    for n in range(prob.nt + 1):
+        ref = np.stack([Lh * D[n][j] + c * fft_pi(S * gI[j], prob) for j in range(3)])
+        assert np.allclose(got[n], ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+
+
+def test_ns_registration_of_time_varying_warp():
+    prob = O.Problem(2, (48, 48), (12, 12), 6, alpha=2e-3)
+    I0 = phantoms.blobs_2d(5, 48)
+    V = np.stack([O.project(phantoms.raw_band_velocity(60 + (n > 2), 2, prob.k), prob)
+                  for n in range(prob.nt + 1)])
+    V *= 3.0 / max(O.max_displacement_voxels(V[n], prob) for n in range(prob.nt + 1))
+    sn = O.ns_evaluate(V, I0, np.zeros(prob.shape), prob)
+    I1 = sn.m[-1]
+    vh, mT, stats = O.ns_register(I0, I1, np.zeros_like(V), prob, O.SolverOpts(max_gn=6))
+    E = stats["E"]
+    assert all(E[i + 1] < E[i] for i in range(len(E) - 1))
+    assert stats["mse_rel"][-1] < 0.2 * stats["mse_rel"][0]
