@@ -75,6 +75,15 @@ extern "C" {
  * of non-positive curvature (the preconditioned gradient if it is the first). Needs 2 Nt + 4
  * more grid planes of device memory (bl_lddmm_footprint includes them). */
 #define BL_NEWTON      2
+/* Non-stationary velocity: one band field per time node t_n = n / nt, n = 0..nt, so every
+ * band velocity argument (v_hat, dv_hat, g_hat, hv_hat, the serving v_hat) holds nt + 1
+ * consecutive fields, node-major [n][c][kz][ky][kx].  The regulariser is integrated by the
+ * trapezoid rule in time; each semi-Lagrangian step uses the velocity at both of its ends;
+ * gradients and products are given per node (the pointwise-in-time expressions of Section 2.2,
+ * i.e. representers in the trapezoid-weighted inner product, which the solver uses for its
+ * dot products and norms).  Not combined with BL_NEWTON (BL_E_UNSUPPORTED).  Needs 7 (nt - 1)
+ * more grid planes of offsets (bl_lddmm_footprint includes them). */
+#define BL_NONSTATIONARY 4
 
 /* registration status */
 #define BL_CONVERGED 0

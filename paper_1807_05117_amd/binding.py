@@ -5,7 +5,8 @@ kernels.  Host mode takes NumPy arrays; device mode (`device=True`) takes torch 
 tensors and a torch stream, whose raw pointers are handed to the library.
 
 Arrays: images are float32 of shape ([Nz,] Ny, Nx); band vectors are complex64 of shape
-(dim, [Kz,] Ky, Kx) in centred order (index j stands for frequency j - K/2).  complex64
+(dim, [Kz,] Ky, Kx) in centred order (index j stands for frequency j - K/2), with a leading
+time-node axis (nt + 1, ...) for a non-stationary velocity.  complex64
 memory is the interleaved (re, im) float32 layout of the interface.
 """
 from __future__ import annotations
@@ -25,6 +26,7 @@ BL_PENDING, BL_E_CANCELLED = 1, -6
 BL_FP32, BL_MIXED = 0, 1
 BL_DEVICE_PTRS = 1
 BL_NEWTON = 2
+BL_NONSTATIONARY = 4
 BL_CONVERGED, BL_MAXITER, BL_STALLED = 0, 1, 2
 BL_MAX_GN = 64
 FIELDS = {"velocity": 0, "div": 1, "X": 2, "Y": 3, "a": 4, "state": 5}
@@ -156,7 +158,7 @@ def _check(rc):
 
 
 def make_problem(dim, n, k, nt, alpha=1e-3, s=2, sigma=1.0, gamma=0, precision=BL_FP32,
-                 device=False, stream=None, newton=False) -> Problem:
+                 device=False, stream=None, newton=False, nonstationary=False) -> Problem:
     p = Problem()
     p.dim = dim
     nn = list(n) + [1] * (3 - len(n))
@@ -166,7 +168,8 @@ def make_problem(dim, n, k, nt, alpha=1e-3, s=2, sigma=1.0, gamma=0, precision=B
         p.k[j] = int(kk[j])
     p.nt, p.alpha, p.s, p.sigma = int(nt), float(alpha), int(s), float(sigma)
     p.gamma, p.precision = int(gamma), int(precision)
-    p.flags = (BL_DEVICE_PTRS if device else 0) | (BL_NEWTON if newton else 0)
+    p.flags = ((BL_DEVICE_PTRS if device else 0) | (BL_NEWTON if newton else 0)
+               | (BL_NONSTATIONARY if nonstationary else 0))
     p.stream = C.c_void_p(stream) if stream else None
     return p
 
@@ -176,7 +179,9 @@ def grid_shape(p: Problem):
 
 
 def band_shape(p: Problem):
-    return (p.dim,) + tuple(int(p.k[j]) for j in reversed(range(p.dim)))
+    """(dim, band...) of a velocity; (nt + 1, dim, band...) for a non-stationary one"""
+    shape = (p.dim,) + tuple(int(p.k[j]) for j in reversed(range(p.dim)))
+    return ((int(p.nt) + 1,) + shape) if (p.flags & BL_NONSTATIONARY) else shape
 
 
 def _f32(a, shape):
@@ -275,7 +280,7 @@ def bl_band_to_grid(p, band):
     lib = load()
     band = np.ascontiguousarray(band, dtype=np.complex64)
     nc = band.shape[0]
-    if band.shape[1:] != band_shape(p)[1:]:
+    if band.shape[1:] != band_shape(p)[-p.dim:]:
         raise ValueError("band shape mismatch")
     out = np.empty((nc,) + grid_shape(p), np.float32)
     _check(lib.bl_band_to_grid(C.byref(p), nc, _ptr(band), _ptr(out)))
@@ -288,7 +293,7 @@ def bl_grid_to_band(p, grid):
     nc = grid.shape[0]
     if grid.shape[1:] != grid_shape(p):
         raise ValueError("grid shape mismatch")
-    out = np.empty((nc,) + band_shape(p)[1:], np.complex64)
+    out = np.empty((nc,) + band_shape(p)[-p.dim:], np.complex64)
     _check(lib.bl_grid_to_band(C.byref(p), nc, _ptr(grid), _ptr(out)))
     return out
 

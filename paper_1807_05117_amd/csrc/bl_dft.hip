@@ -375,7 +375,8 @@ template <int DIM>
 __global__ __launch_bounds__(256) void k_band_prep(Geo g, const float2* __restrict__ raw,
                                                    float2* __restrict__ out, int with_div,
                                                    const double* __restrict__ Lhat64,
-                                                   double* __restrict__ reg_partial) {
+                                                   double* __restrict__ reg_partial,
+                                                   double reg_weight, int reg_accumulate) {
   __shared__ double sh[256];
   double acc = 0.0;
   const int B = (int)g.B;
@@ -422,7 +423,10 @@ __global__ __launch_bounds__(256) void k_band_prep(Geo g, const float2* __restri
       if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
       __syncthreads();
     }
-    if (threadIdx.x == 0) reg_partial[blockIdx.x] = sh[0];
+    if (threadIdx.x == 0) {
+      const double v = reg_weight == 1.0 ? sh[0] : reg_weight * sh[0];
+      reg_partial[blockIdx.x] = reg_accumulate ? reg_partial[blockIdx.x] + v : v;
+    }
   }
 }
 
@@ -545,19 +549,19 @@ void pi_half(const Geo& g, const DftPlan& p, const float* grid, int C, float2* P
 }
 
 void band_prep(const Geo& g, const float2* raw, float2* out, int with_div, const double* Lhat64,
-               double* reg_partial, hipStream_t s) {
+               double* reg_partial, hipStream_t s, double reg_weight, int reg_accumulate) {
   // the regulariser sum needs the fixed kRedBlocks grid; the plain projection one thread per
   // band entry
   const int blocks = reg_partial ? kRedBlocks : (int)((g.B + 255) / 256);
   if (g.dim == 3)
     hipLaunchKernelGGL(k_band_prep<3>, dim3(blocks), dim3(256), 0, s, g, raw, out, with_div,
-                       Lhat64, reg_partial);
+                       Lhat64, reg_partial, reg_weight, reg_accumulate);
   else if (g.dim == 2)
     hipLaunchKernelGGL(k_band_prep<2>, dim3(blocks), dim3(256), 0, s, g, raw, out, with_div,
-                       Lhat64, reg_partial);
+                       Lhat64, reg_partial, reg_weight, reg_accumulate);
   else
     hipLaunchKernelGGL(k_band_prep<1>, dim3(blocks), dim3(256), 0, s, g, raw, out, with_div,
-                       Lhat64, reg_partial);
+                       Lhat64, reg_partial, reg_weight, reg_accumulate);
 }
 
 void band_finalize(const Geo& g, int C, const float2* vproj, const float* Lhat,

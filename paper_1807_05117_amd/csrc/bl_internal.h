@@ -25,6 +25,7 @@ struct Geo {
   float inv_nx, inv_ny, inv_nz;   // 1/n per axis (periodic index wrap)
   int gamma;          // 1: incompressible flow (velocities projected divergence-free)
   int newton;         // 1: full Newton Hessian products (else Gauss-Newton)
+  int nodes;          // band velocity fields: 1 (stationary) or nt + 1 (one per time node)
   // voxels per thread along z of the transport launches, per kernel class (TR_*): a launch
   // shape only, every choice computes bitwise the same values
   int zv[4];
@@ -77,9 +78,11 @@ void pi_z_mixed(const Geo& g, const DftPlan& p, const float* f, int C, float2* G
 // ---- band kernels (bl_dft.hip)
 // out[c] = projection of raw[c] (c < dim): Hermitian, and divergence-free when g.gamma = 1;
 // with_div: out[dim] = spectral divergence.
-// reg_partial (may be null): kRedBlocks partial sums of sum_c Lhat |out_c|^2.
+// reg_partial (may be null): kRedBlocks partial sums of reg_weight * sum_c Lhat |out_c|^2,
+// added to the partials already there when reg_accumulate (one velocity per time node).
 void band_prep(const Geo& g, const float2* raw, float2* out, int with_div, const double* Lhat64,
-               double* reg_partial, hipStream_t s);
+               double* reg_partial, hipStream_t s, double reg_weight = 1.0,
+               int reg_accumulate = 0);
 // out[c][k] = Lhat(k) vproj[c][k] + scale * P (Hermitian-completed), zero on unpaired planes;
 // leray (C == dim): then projected divergence-free per index k.
 void band_finalize(const Geo& g, int C, const float2* vproj, const float* Lhat,
@@ -89,6 +92,10 @@ void band_finalize(const Geo& g, int C, const float2* vproj, const float* Lhat,
 // ---- transports (bl_transport.hip)
 // X: dim planes of forward offsets; YA = (Y, a) backward offsets and reaction factor
 void setup(const Geo& g, const float* v, float* X, float4* YA, hipStream_t s);
+// non-stationary step t_n -> t_{n+1}: v0 = (v^n, r^n), v1 = (v^{n+1}, r^{n+1}) (dim + 1 planes)
+void setup_ns(const Geo& g, const float* v0, const float* v1, float* X, float4* YA, hipStream_t s);
+// b = lambda grad m at one time node (dim planes)
+void body_node(const Geo& g, const float* lam, const float* m, float* b, hipStream_t s);
 void state_step(const Geo& g, const float* m_in, const float* X, float* m_out, hipStream_t s);
 void energy_partial(const Geo& g, const float* mT, const float* I1, double* partial,
                     hipStream_t s);
@@ -125,6 +132,8 @@ void reduce_final(const double* partial, int n, double* out, hipStream_t s,
                   double* host = nullptr, const int* flag = nullptr, double* host_flag = nullptr);
 // kRedBlocks partials of Re sum conj(a) b over n complex entries
 void dot_partial(const float2* a, const float2* b, int64_t n, double* partial, hipStream_t s);
+// the same over g.nodes * dim * B entries, node k weighted by the trapezoid weight w_k
+void dot_partial_w(const Geo& g, const float2* a, const float2* b, double* partial, hipStream_t s);
 // kRedBlocks partials of max |a|
 void maxabs_partial(const float2* a, int64_t n, double* partial, hipStream_t s);
 void reduce_max_final(const double* partial, int n, double* out, hipStream_t s,

@@ -55,7 +55,10 @@ int validate(const bl_problem* p, bl::Geo* g) {
   if (p->gamma != 0 && p->gamma != 1) return fail(BL_E_INVALID, "gamma must be 0 or 1");
   if (p->precision != BL_FP32 && p->precision != BL_MIXED)
     return fail(BL_E_UNSUPPORTED, "precision must be BL_FP32 or BL_MIXED");
-  if (p->flags & ~(BL_DEVICE_PTRS | BL_NEWTON)) return fail(BL_E_INVALID, "unknown flag bits");
+  if (p->flags & ~(BL_DEVICE_PTRS | BL_NEWTON | BL_NONSTATIONARY))
+    return fail(BL_E_INVALID, "unknown flag bits");
+  if ((p->flags & BL_NEWTON) && (p->flags & BL_NONSTATIONARY))
+    return fail(BL_E_UNSUPPORTED, "full Newton products of a non-stationary velocity are not supported");
   if (g) {
     g->dim = p->dim;
     g->nx = n[0]; g->ny = n[1]; g->nz = n[2];
@@ -74,6 +77,7 @@ int validate(const bl_problem* p, bl::Geo* g) {
     g->inv_nz = 1.0f / (float)n[2];
     g->gamma = p->gamma;
     g->newton = (p->flags & BL_NEWTON) ? 1 : 0;
+    g->nodes = (p->flags & BL_NONSTATIONARY) ? p->nt + 1 : 1;
     const bool d3 = p->dim == 3;
     g->zv[bl::TR_STATE] = d3 ? 2 : 1;
     g->zv[bl::TR_INC] = d3 ? 2 : 1;
@@ -135,13 +139,15 @@ Offsets plan_layout(const bl::Geo& g, bool transport, bool solver, bool mixed) {
   Offsets o{};
   const size_t pb = plane_bytes(g), bb = band_bytes(g);
   const int d = g.dim;
+  const bool ns = g.nodes > 1;
+  const size_t steps = ns ? (size_t)g.nt : 1;   // offset fields per time step (non-stationary)
   if (transport) {
     o.I1 = L.take(pb);
     o.m = L.take(pb * (g.nt + 1));
-    o.X = L.take(pb * d);
-    o.YA = L.take(pb * 4);
-    o.V = L.take(pb * (d + 1));
-    o.DV = L.take(pb * d);
+    o.X = L.take(pb * d * steps);
+    o.YA = L.take(pb * 4 * steps);
+    o.V = L.take(pb * (d + 1) * (ns ? 2 : 1));   // two time nodes at a time
+    o.DV = L.take(pb * d * (ns ? 2 : 1));
     o.T0 = L.take(pb);
     o.T1 = L.take(pb);
     o.L = L.take(pb * (g.nt + 1));
@@ -154,10 +160,11 @@ Offsets plan_layout(const bl::Geo& g, bool transport, bool solver, bool mixed) {
   } else {
     o.V = L.take(pb * 4);
   }
-  o.braw = L.take(bb * 4);
-  o.bv = L.take(bb * 4);
-  o.bd = L.take(bb * 4);
-  o.bout = L.take(bb * 4);
+  const size_t vb = (size_t)g.nodes * d;   // band components of a velocity
+  o.braw = L.take(bb * std::max<size_t>(4, vb));
+  o.bv = L.take(bb * std::max<size_t>(4, (size_t)g.nodes * (d + 1)));
+  o.bd = L.take(bb * std::max<size_t>(4, vb));
+  o.bout = L.take(bb * std::max<size_t>(4, vb));
   o.P = L.take((size_t)4 * g.kzh * g.ky * g.kx * sizeof(float2));
   o.Lhat = L.take((size_t)g.B * sizeof(float));
   o.Lhat64 = L.take((size_t)g.B * sizeof(double));
@@ -175,7 +182,7 @@ Offsets plan_layout(const bl::Geo& g, bool transport, bool solver, bool mixed) {
   o.red = L.take((size_t)RED_SLOTS * bl::kRedBlocks * sizeof(double));
   o.scal = L.take(64 * sizeof(double));
   o.flag = L.take(256);
-  o.solver = solver ? L.take(bb * d * 8) : 0;
+  o.solver = solver ? L.take(bb * vb * 8) : 0;
   o.total = L.total;
   return o;
 }
@@ -340,7 +347,7 @@ bl_ctx* create_ctx(const bl_problem* prob, const bl::Geo& g, bool transport, boo
     c->flag = reinterpret_cast<int*>(a + o.flag);
     if (solver) {
       float2* s = C2(o.solver);
-      const size_t nb = (size_t)g.dim * g.B;
+      const size_t nb = (size_t)g.nodes * g.dim * g.B;
       c->sv = s; c->sg = s + nb; c->sdelta = s + 2 * nb; c->sr = s + 3 * nb; c->sz = s + 4 * nb;
       c->sp = s + 5 * nb; c->sHp = s + 6 * nb; c->stry = s + 7 * nb;
     }
@@ -513,8 +520,107 @@ void choose_launch_shapes(bl_ctx* c) {
   g_shapes.emplace(key, best);
 }
 
+// ------------------------------------------------ non-stationary velocity (one field per node)
+// Per node: projection (and divergence) of the band fields with the trapezoid-weighted
+// regulariser; per step t_n -> t_{n+1}: iota of the next node's velocity and divergence (two
+// node slots), the step's offsets from both ends, and the state step.
+void op_set_velocity_ns(bl_ctx* c, const float2* vraw) {
+  const bl::Geo& g = c->g;
+  hipStream_t s = c->stream;
+  const size_t M = (size_t)g.M, B = (size_t)g.B;
+  const int d = g.dim;
+  double* red_reg = c->red + RED_REG * bl::kRedBlocks;
+  double* red_data = c->red + RED_DATA * bl::kRedBlocks;
+  for (int n = 0; n <= g.nt; ++n) {
+    const double w = (n == 0 || n == g.nt) ? 0.5 / g.nt : 1.0 / g.nt;
+    bl::band_prep(g, vraw + (size_t)n * d * B, c->bv + (size_t)n * (d + 1) * B, 1, c->Lhat64,
+                  red_reg, s, w, n > 0);
+  }
+  float* slot[2] = {c->V, c->V + (size_t)(d + 1) * M};
+  bl::iota(g, c->plan, c->bv, d + 1, slot[0], s);
+  for (int n = 0; n < g.nt; ++n) {
+    bl::iota(g, c->plan, c->bv + (size_t)(n + 1) * (d + 1) * B, d + 1, slot[(n + 1) & 1], s);
+    bl::setup_ns(g, slot[n & 1], slot[(n + 1) & 1], c->X + (size_t)n * d * M, c->YA + (size_t)n * M, s);
+    if (n == 0 && !c->tuned) choose_launch_shapes(c);
+    bl::state_step(g, c->m + n * M, c->X + (size_t)n * d * M, c->m + (n + 1) * M, s);
+  }
+  bl::energy_partial(g, c->m + g.nt * M, c->I1, red_data, s);
+  bl::reduce_final(red_reg, bl::kRedBlocks, c->scal + S_REG, s, c->hdev + S_REG);
+  bl::reduce_final(red_data, bl::kRedBlocks, c->scal + S_DATA, s, c->hdev + S_DATA);
+  check_launch("set_velocity (non-stationary)");
+  sync(c);
+  c->reg = c->hscal[S_REG];
+  c->data_sum = c->hscal[S_DATA];
+  const double sig = c->prob.sigma;
+  c->E = 0.5 * c->reg + c->data_sum / (sig * sig * (double)g.M);
+  c->have_v = true;
+  c->have_lambda = false;
+  if (!std::isfinite(c->E)) throw NonFinite{"energy"};
+}
+
+// adjoint from L[nt] down to L[0] with the per-step (Y, a)
+void backward_ns(bl_ctx* c) {
+  const bl::Geo& g = c->g;
+  const size_t M = (size_t)g.M;
+  for (int n = g.nt - 1; n >= 0; --n)
+    bl::adj_step(g, c->L + (n + 1) * M, c->YA + (size_t)n * M, c->L + n * M, c->stream);
+}
+
+// per node: b^n = L[n] grad m^n, pi, and the band output L^ vproj^n + pi(b^n)
+void per_node_outputs(bl_ctx* c, const float2* vproj, size_t vstride, float2* out) {
+  const bl::Geo& g = c->g;
+  hipStream_t s = c->stream;
+  const size_t M = (size_t)g.M, B = (size_t)g.B;
+  for (int n = 0; n <= g.nt; ++n) {
+    bl::body_node(g, c->L + n * M, c->m + n * M, c->Bf, s);
+    bl::pi_half(g, c->plan, c->Bf, g.dim, c->P, s);
+    bl::band_finalize(g, g.dim, vproj + n * vstride, c->Lhat, c->P, (float)(1.0 / (double)g.M),
+                      out + (size_t)n * g.dim * B, c->flag, s, 1);
+  }
+}
+
+void op_gradient_ns(bl_ctx* c, float2* gout) {
+  const bl::Geo& g = c->g;
+  const size_t M = (size_t)g.M;
+  bl::terminal(g, c->m + g.nt * M, c->I1, c->L + g.nt * M, c->stream);
+  backward_ns(c);
+  c->have_lambda = true;
+  per_node_outputs(c, c->bv, (size_t)(g.dim + 1) * g.B, gout);
+  check_launch("gradient (non-stationary)");
+}
+
+void op_hessvec_ns(bl_ctx* c, const float2* draw, float2* hout) {
+  const bl::Geo& g = c->g;
+  hipStream_t s = c->stream;
+  const size_t M = (size_t)g.M, B = (size_t)g.B;
+  const int d = g.dim;
+  for (int n = 0; n <= g.nt; ++n)
+    bl::band_prep(g, draw + (size_t)n * d * B, c->bd + (size_t)n * d * B, 0, nullptr, nullptr, s);
+  float* dv[2] = {c->DV, c->DV + (size_t)d * M};
+  bl::iota(g, c->plan, c->bd, d, dv[0], s);
+  bl::inc_init(g, c->m, dv[0], c->T0, s);
+  float* tin = c->T0;
+  float* tout = c->T1;
+  for (int n = 0; n + 1 < g.nt; ++n) {
+    bl::iota(g, c->plan, c->bd + (size_t)(n + 1) * d * B, d, dv[(n + 1) & 1], s);
+    bl::inc_step(g, tin, c->X + (size_t)n * d * M, c->m + (n + 1) * M, dv[(n + 1) & 1], tout, s);
+    std::swap(tin, tout);
+  }
+  bl::iota(g, c->plan, c->bd + (size_t)g.nt * d * B, d, dv[g.nt & 1], s);
+  bl::inc_last(g, tin, c->X + (size_t)(g.nt - 1) * d * M, c->m + g.nt * M, dv[g.nt & 1],
+               c->L + g.nt * M, s);
+  backward_ns(c);
+  c->have_lambda = false;   // L holds the incremental adjoint now
+  per_node_outputs(c, c->bd, (size_t)d * B, hout);
+  check_launch("hessvec (non-stationary)");
+}
+
 // setup + forward state + energy at the raw band vector `vraw` (device, dim components)
 void op_set_velocity(bl_ctx* c, const float2* vraw) {
+  if (c->g.nodes > 1) {
+    op_set_velocity_ns(c, vraw);
+    return;
+  }
   const bl::Geo& g = c->g;
   hipStream_t s = c->stream;
   double* red_reg = c->red + RED_REG * bl::kRedBlocks;
@@ -554,6 +660,10 @@ void backward_and_body_force(bl_ctx* c) {
 
 // gradient at the current velocity into gout (device, dim components)
 void op_gradient(bl_ctx* c, float2* gout) {
+  if (c->g.nodes > 1) {
+    op_gradient_ns(c, gout);
+    return;
+  }
   const bl::Geo& g = c->g;
   hipStream_t s = c->stream;
   const size_t M = (size_t)g.M;
@@ -607,6 +717,10 @@ void op_hessvec_newton(bl_ctx* c, const float2* draw, float2* hout) {
 
 // Gauss-Newton Hessian-vector product of the raw direction draw into hout
 void op_hessvec(bl_ctx* c, const float2* draw, float2* hout) {
+  if (c->g.nodes > 1) {
+    op_hessvec_ns(c, draw, hout);
+    return;
+  }
   if (c->g.newton) {
     op_hessvec_newton(c, draw, hout);
     return;
@@ -645,11 +759,28 @@ void check_flag(bl_ctx* c, const char* what) {
 }
 
 // <g, g>, max |g| and the non-finite flag of the last band kernels, in one synchronisation
+// <a, b> over a velocity-shaped band vector into partials pa: the plain l2 product, or for a
+// non-stationary velocity the trapezoid-weighted one
+void vec_dot_partial(bl_ctx* c, const float2* a, const float2* b, double* pa) {
+  const bl::Geo& g = c->g;
+  if (g.nodes > 1) bl::dot_partial_w(g, a, b, pa, c->stream);
+  else bl::dot_partial(a, b, (int64_t)g.dim * g.B, pa, c->stream);
+}
+
+// the projected velocity (first dim of the dim + 1 components per node in bv) into dst
+void copy_projected_velocity(bl_ctx* c, float2* dst) {
+  const bl::Geo& g = c->g;
+  const size_t B = (size_t)g.B;
+  for (int n = 0; n < g.nodes; ++n)
+    HIP_TRY(hipMemcpyAsync(dst + (size_t)n * g.dim * B, c->bv + (size_t)n * (g.dim + 1) * B,
+                           band_bytes(g) * g.dim, hipMemcpyDeviceToDevice, c->stream));
+}
+
 void grad_stats(bl_ctx* c, const float2* gvec, double* gg, double* ginf) {
-  const int64_t n = (int64_t)c->g.dim * c->g.B;
+  const int64_t n = (int64_t)c->g.nodes * c->g.dim * c->g.B;
   double* pa = c->red + RED_A * bl::kRedBlocks;
   double* pb = c->red + RED_B * bl::kRedBlocks;
-  bl::dot_partial(gvec, gvec, n, pa, c->stream);
+  vec_dot_partial(c, gvec, gvec, pa);
   bl::reduce_final(pa, bl::kRedBlocks, c->scal + S_GG, c->stream, c->hdev + S_GG);
   bl::maxabs_partial(gvec, n, pb, c->stream);
   bl::reduce_max_final(pb, bl::kRedBlocks, c->scal + S_GINF, c->stream, c->hdev + S_GINF, c->flag,
@@ -719,14 +850,14 @@ void solve(bl_ctx* c, const bl_solver_opts& o, bl_stats* st) {
   // line-search trial for E, and once per gradient for its norms and the non-finite flag.
   const bl::Geo& g = c->g;
   hipStream_t s = c->stream;
-  const int64_t nb = (int64_t)g.dim * g.B;
+  const int64_t nb = (int64_t)g.nodes * g.dim * g.B;
   double* pa = c->red + RED_A * bl::kRedBlocks;
   double* pb = c->red + RED_B * bl::kRedBlocks;
   const double den = dev_sqdiff(c, c->m, c->I1);  // |I0 - I1|^2
   auto mse = [&]() { return den > 0 ? 100.0 * c->data_sum / den : 0.0; };
 
   op_set_velocity(c, c->sv);
-  HIP_TRY(hipMemcpyAsync(c->sv, c->bv, band_bytes(g) * g.dim, hipMemcpyDeviceToDevice, s));
+  copy_projected_velocity(c, c->sv);
   op_gradient(c, c->sg);
   double gg, ginf0;
   grad_stats(c, c->sg, &gg, &ginf0);
@@ -762,7 +893,7 @@ void solve(bl_ctx* c, const bl_solver_opts& o, bl_stats* st) {
     for (int j = 0; j < o.max_pcg; ++j) {
       op_hessvec(c, c->sp, c->sHp);
       st->hessvecs += 1;
-      bl::dot_partial(c->sp, c->sHp, nb, pa, s);
+      vec_dot_partial(c, c->sp, c->sHp, pa);
       bl::reduce_final(pa, bl::kRedBlocks, c->scal + S_PHP, s, c->hdev + S_PHP);
       // alpha = <r, z> / <p, Hp>, zero when <p, Hp> <= 0 (then neither vector moves);
       // delta, r, z = K r and the partials of <r, r>, <r, z> in one launch
@@ -787,7 +918,7 @@ void solve(bl_ctx* c, const bl_solver_opts& o, bl_stats* st) {
     st->pcg_iters[it] = iters;
     st->pcg_total += iters;
     // Armijo backtracking on E along delta; the slope <g, delta> arrives with the first trial
-    bl::dot_partial(c->sg, c->sdelta, nb, pa, s);
+    vec_dot_partial(c, c->sg, c->sdelta, pa);
     bl::reduce_final(pa, bl::kRedBlocks, c->scal + S_SLOPE, s, c->hdev + S_SLOPE);
     double eps = 1.0;
     bool accepted = false;
@@ -812,7 +943,7 @@ void solve(bl_ctx* c, const bl_solver_opts& o, bl_stats* st) {
       break;
     }
     st->eps[it] = eps;
-    HIP_TRY(hipMemcpyAsync(c->sv, c->bv, band_bytes(g) * g.dim, hipMemcpyDeviceToDevice, s));
+    copy_projected_velocity(c, c->sv);
     E = c->E;
     op_gradient(c, c->sg);
     grad_stats(c, c->sg, &gg, &ginf);
@@ -987,12 +1118,12 @@ int bl_lddmm_ctx_set_velocity(bl_ctx* c, const float* v_hat, double* energy, flo
   if (!c || !v_hat) return fail(BL_E_INVALID, "NULL pointer argument");
   return guarded([&]() {
     HIP_TRY(hipSetDevice(c->device));
-    load_band(c, v_hat, c->braw, c->g.dim);
+    load_band(c, v_hat, c->braw, c->g.nodes * c->g.dim);
     op_set_velocity(c, c->braw);
     if (energy) *energy = c->E;
     if (g_hat) {
       op_gradient(c, c->bout);
-      store_band(c, c->bout, g_hat, c->g.dim);
+      store_band(c, c->bout, g_hat, c->g.nodes * c->g.dim);
       check_flag(c, "gradient");
     }
     t_collect(c);
@@ -1010,9 +1141,9 @@ int bl_lddmm_ctx_hessvec(bl_ctx* c, const float* dv_hat, float* hv_hat) {
       op_hessvec(c, reinterpret_cast<const float2*>(dv_hat), reinterpret_cast<float2*>(hv_hat));
       return BL_OK;
     }
-    load_band(c, dv_hat, c->braw, c->g.dim);
+    load_band(c, dv_hat, c->braw, c->g.nodes * c->g.dim);
     op_hessvec(c, c->braw, c->bout);
-    store_band(c, c->bout, hv_hat, c->g.dim);
+    store_band(c, c->bout, hv_hat, c->g.nodes * c->g.dim);
     check_flag(c, "Hessian-vector product");
     t_collect(c);
     return BL_OK;
@@ -1060,10 +1191,10 @@ int bl_lddmm_gradient(const bl_problem* prob, const float* I0, const float* I1,
   return guarded([&]() {
     CachedCtx h(prob, g, false);
     load_images(h.c, I0, I1);
-    load_band(h.c, v_hat, h.c->braw, g.dim);
+    load_band(h.c, v_hat, h.c->braw, g.nodes * g.dim);
     op_set_velocity(h.c, h.c->braw);
     op_gradient(h.c, h.c->bout);
-    store_band(h.c, h.c->bout, g_hat, g.dim);
+    store_band(h.c, h.c->bout, g_hat, g.nodes * g.dim);
     check_flag(h.c, "gradient");
     if (energy) *energy = h.c->E;
     h.ok = true;
@@ -1080,11 +1211,11 @@ int bl_lddmm_hessvec(const bl_problem* prob, const float* I0, const float* I1,
   return guarded([&]() {
     CachedCtx h(prob, g, false);
     load_images(h.c, I0, I1);
-    load_band(h.c, v_hat, h.c->braw, g.dim);
+    load_band(h.c, v_hat, h.c->braw, g.nodes * g.dim);
     op_set_velocity(h.c, h.c->braw);
-    load_band(h.c, dv_hat, h.c->braw, g.dim);
+    load_band(h.c, dv_hat, h.c->braw, g.nodes * g.dim);
     op_hessvec(h.c, h.c->braw, h.c->bout);
-    store_band(h.c, h.c->bout, hv_hat, g.dim);
+    store_band(h.c, h.c->bout, hv_hat, g.nodes * g.dim);
     check_flag(h.c, "Hessian-vector product");
     h.ok = true;
     return BL_OK;
@@ -1099,7 +1230,7 @@ int bl_lddmm_warp(const bl_problem* prob, const float* I0, const float* v_hat, f
   return guarded([&]() {
     CachedCtx h(prob, g, false);
     load_images(h.c, I0, nullptr);
-    load_band(h.c, v_hat, h.c->braw, g.dim);
+    load_band(h.c, v_hat, h.c->braw, g.nodes * g.dim);
     op_set_velocity(h.c, h.c->braw);
     store_plane(h.c, h.c->m + (size_t)g.nt * g.M, warped, 1);
     sync(h.c);
@@ -1123,9 +1254,9 @@ int bl_lddmm_register(const bl_problem* prob, const bl_solver_opts* opts, const 
     std::memset(&local, 0, sizeof(local));
     CachedCtx h(prob, g, true);
     load_images(h.c, I0, I1);
-    load_band(h.c, v_hat, h.c->sv, g.dim);
+    load_band(h.c, v_hat, h.c->sv, g.nodes * g.dim);
     solve(h.c, o, &local);
-    store_band(h.c, h.c->sv, v_hat, g.dim);
+    store_band(h.c, h.c->sv, v_hat, g.nodes * g.dim);
     if (warped) store_plane(h.c, h.c->m + (size_t)g.nt * g.M, warped, 1);
     sync(h.c);
     local.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -9,6 +9,15 @@
 namespace bl {
 namespace {
 
+// trapezoid weight of the time node of entry i of a stack of g.nodes velocity fields (1 for
+// a stationary velocity)
+__device__ __forceinline__ double node_weight(const Geo& g, int64_t i) {
+  if (g.nodes <= 1) return 1.0;
+  const int64_t node = i / ((int64_t)g.dim * g.B);
+  const double dt = 1.0 / (double)g.nt;
+  return (node == 0 || node == g.nodes - 1) ? 0.5 * dt : dt;
+}
+
 __device__ __forceinline__ void block_sum_store(double acc, double* __restrict__ partial) {
   __shared__ double sh[256];
   sh[threadIdx.x] = acc;
@@ -74,7 +83,7 @@ __global__ __launch_bounds__(256) void k_pcg_step(Geo g, const float2* __restric
                                                   float2* __restrict__ z,
                                                   double* __restrict__ p0,
                                                   double* __restrict__ p1) {
-  const int64_t n = (int64_t)g.dim * g.B;
+  const int64_t n = (int64_t)g.nodes * g.dim * g.B;
   const double d = pHp[0];
   const double alpha = d > 0.0 ? rz[0] / d : 0.0;
   const double nalpha = d > 0.0 ? -1.0 * (rz[0] / d) : 0.0;
@@ -92,10 +101,18 @@ __global__ __launch_bounds__(256) void k_pcg_step(Geo g, const float2* __restric
     const float inv = 1.0f / Lhat[b];
     const float2 w = make_float2(ri.x * inv, ri.y * inv);
     z[i] = w;
-    rr = fma((double)ri.x, (double)ri.x, rr);
-    rr = fma((double)ri.y, (double)ri.y, rr);
-    rzn = fma((double)ri.x, (double)w.x, rzn);
-    rzn = fma((double)ri.y, (double)w.y, rzn);
+    if (g.nodes > 1) {
+      const double wt = node_weight(g, i);
+      rr = fma(wt * (double)ri.x, (double)ri.x, rr);
+      rr = fma(wt * (double)ri.y, (double)ri.y, rr);
+      rzn = fma(wt * (double)ri.x, (double)w.x, rzn);
+      rzn = fma(wt * (double)ri.y, (double)w.y, rzn);
+    } else {
+      rr = fma((double)ri.x, (double)ri.x, rr);
+      rr = fma((double)ri.y, (double)ri.y, rr);
+      rzn = fma((double)ri.x, (double)w.x, rzn);
+      rzn = fma((double)ri.y, (double)w.y, rzn);
+    }
   }
   block_sum_store(rr, p0);
   __syncthreads();
@@ -124,6 +141,20 @@ __global__ __launch_bounds__(256) void k_dot_partial(const float2* __restrict__ 
     const float2 x = a[i], y = b[i];
     acc = fma((double)x.x, (double)y.x, acc);
     acc = fma((double)x.y, (double)y.y, acc);
+  }
+  block_sum_store(acc, partial);
+}
+
+__global__ __launch_bounds__(256) void k_dot_partial_w(Geo g, const float2* __restrict__ a,
+                                                       const float2* __restrict__ b,
+                                                       double* __restrict__ partial) {
+  const int64_t n = (int64_t)g.nodes * g.dim * g.B;
+  double acc = 0.0;
+  GRID_STRIDE(i, n) {
+    const float2 x = a[i], y = b[i];
+    const double wt = node_weight(g, i);
+    acc = fma(wt * (double)x.x, (double)y.x, acc);
+    acc = fma(wt * (double)x.y, (double)y.y, acc);
   }
   block_sum_store(acc, partial);
 }
@@ -176,7 +207,7 @@ __global__ __launch_bounds__(256) void k_precond_dots(Geo g, const float2* __res
                                                       float2* __restrict__ z,
                                                       double* __restrict__ p0,
                                                       double* __restrict__ p1) {
-  const int64_t n = (int64_t)g.dim * g.B;
+  const int64_t n = (int64_t)g.nodes * g.dim * g.B;
   double rr = 0.0, rz = 0.0;
   GRID_STRIDE(i, n) {
     const int64_t b = i % g.B;
@@ -184,10 +215,18 @@ __global__ __launch_bounds__(256) void k_precond_dots(Geo g, const float2* __res
     const float inv = 1.0f / Lhat[b];
     const float2 w = make_float2(x.x * inv, x.y * inv);
     z[i] = w;
-    rr = fma((double)x.x, (double)x.x, rr);
-    rr = fma((double)x.y, (double)x.y, rr);
-    rz = fma((double)x.x, (double)w.x, rz);
-    rz = fma((double)x.y, (double)w.y, rz);
+    if (g.nodes > 1) {
+      const double wt = node_weight(g, i);
+      rr = fma(wt * (double)x.x, (double)x.x, rr);
+      rr = fma(wt * (double)x.y, (double)x.y, rr);
+      rz = fma(wt * (double)x.x, (double)w.x, rz);
+      rz = fma(wt * (double)x.y, (double)w.y, rz);
+    } else {
+      rr = fma((double)x.x, (double)x.x, rr);
+      rr = fma((double)x.y, (double)x.y, rr);
+      rz = fma((double)x.x, (double)w.x, rz);
+      rz = fma((double)x.y, (double)w.y, rz);
+    }
   }
   block_sum_store(rr, p0);
   __syncthreads();
@@ -231,6 +270,9 @@ void pcg_step(const Geo& g, const float2* p, const float2* Hp, const double* rz,
 void xpby_dev(float2* y, const float2* x, const double* num, const double* den, int64_t n,
               hipStream_t s) {
   hipLaunchKernelGGL(k_xpby_dev, dim3(blocks_for(n)), dim3(256), 0, s, y, x, num, den, n);
+}
+void dot_partial_w(const Geo& g, const float2* a, const float2* b, double* partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_partial_w, dim3(kRedBlocks), dim3(256), 0, s, g, a, b, partial);
 }
 void dot_partial(const float2* a, const float2* b, int64_t n, double* partial, hipStream_t s) {
   hipLaunchKernelGGL(k_dot_partial, dim3(kRedBlocks), dim3(256), 0, s, a, b, n, partial);

@@ -115,11 +115,11 @@ void run_request(bl_server* srv, Slot& slot, int slot_index, Request* r) {
       }
     } guard{slot};
     load_images(c, r->I0.data(), r->I1.data());
-    load_band(c, r->v.data(), c->sv, r->g.dim);
+    load_band(c, r->v.data(), c->sv, r->g.nodes * r->g.dim);
     std::memset(&r->stats, 0, sizeof(r->stats));
     const auto ts = Clock::now();
     solve(c, r->opts, &r->stats);
-    store_band(c, c->sv, r->v.data(), r->g.dim);
+    store_band(c, c->sv, r->v.data(), r->g.nodes * r->g.dim);
     r->warped.resize((size_t)r->g.M);
     store_plane(c, c->m + (size_t)r->g.nt * r->g.M, r->warped.data(), 1);
     sync(c);
@@ -213,7 +213,7 @@ int bl_server_submit(bl_server* srv, const bl_problem* prob, const bl_solver_opt
   if (opts) r->opts = *opts; else fill_default(&r->opts);
   r->g = g;
   r->bytes = ctx_bytes(g, true, true, prob->precision == BL_MIXED);
-  const size_t M = (size_t)g.M, nb = 2 * (size_t)g.dim * (size_t)g.B;
+  const size_t M = (size_t)g.M, nb = 2 * (size_t)g.nodes * (size_t)g.dim * (size_t)g.B;
   r->I0.assign(I0, I0 + M);
   r->I1.assign(I1, I1 + M);
   if (v_hat) r->v.assign(v_hat, v_hat + nb); else r->v.assign(nb, 0.f);

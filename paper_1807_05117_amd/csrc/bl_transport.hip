@@ -207,6 +207,41 @@ __global__ __launch_bounds__(BX* GBY) void k_setup(Geo g, const float* __restric
   YA[p] = make_float4(yo[0], yo[1], yo[2], a);
 }
 
+// Non-stationary step t_n -> t_{n+1}: the Heun characteristics take the velocity at both
+// ends of the step: X = -(u1 + Interp(u0, i - u1)) / 2 (end point i at t_{n+1}),
+// Y = +(u0 + Interp(u1, i + u0)) / 2 (start point i at t_n), R = Interp(r1, i + Y),
+// a = 1 + dt/2 [R + (1 + dt R) r0].  With v0 = v1 these are the stationary formulas.
+template <int DIM>
+__global__ __launch_bounds__(BX* GBY) void k_setup_ns(Geo g, const float* __restrict__ v0,
+                                                      const float* __restrict__ v1,
+                                                      float* __restrict__ X,
+                                                      float4* __restrict__ YA) {
+  constexpr int ZV = 1;
+  GATHER_XY
+  GATHER_Z(0)
+  (void)live;
+  const size_t M = (size_t)g.M;
+  const float s = g.dt * (float)g.nref;
+  float u0[3] = {0.f, 0.f, 0.f}, u1[3] = {0.f, 0.f, 0.f};
+  for (int c = 0; c < DIM; ++c) {
+    u0[c] = s * v0[c * M + p];
+    u1[c] = s * v1[c * M + p];
+  }
+  const Tap<DIM> tf = make_tap<DIM>(g, x, y, z, -u1[0], -u1[1], -u1[2]);
+  const Tap<DIM> tb = make_tap<DIM>(g, x, y, z, u0[0], u0[1], u0[2]);
+  float xo[3] = {0.f, 0.f, 0.f}, yo[3] = {0.f, 0.f, 0.f};
+  for (int c = 0; c < DIM; ++c) {
+    xo[c] = -0.5f * (u1[c] + s * apply<DIM>(field_rsrc(v0 + c * M, g), tf));
+    yo[c] = 0.5f * (u0[c] + s * apply<DIM>(field_rsrc(v1 + c * M, g), tb));
+  }
+  const Tap<DIM> ty = make_tap<DIM>(g, x, y, z, yo[0], yo[1], yo[2]);
+  const float R = apply<DIM>(field_rsrc(v1 + DIM * M, g), ty);
+  const float ri = v0[DIM * M + p];
+  const float a = 1.0f + 0.5f * g.dt * (R + (1.0f + g.dt * R) * ri);
+  for (int c = 0; c < DIM; ++c) X[c * M + p] = xo[c];
+  YA[p] = make_float4(yo[0], yo[1], yo[2], a);
+}
+
 template <int DIM, int ZV>
 __global__ __launch_bounds__(BX* GBY) void k_state_step(Geo g, const float* __restrict__ m_in,
                                                         const float* __restrict__ X,
@@ -504,6 +539,32 @@ __global__ __launch_bounds__(BX* GBY) void k_body_force_n(Geo g, const float* __
   }
 }
 
+// b = lambda grad m at one time node (a non-stationary gradient or product has one body force
+// per node, not a time integral)
+template <int DIM, int ZV>
+__global__ __launch_bounds__(BX* GBY) void k_body_node(Geo g, const float* __restrict__ lam,
+                                                       const float* __restrict__ m,
+                                                       float* __restrict__ b) {
+  GATHER_XY
+  const size_t M = (size_t)g.M;
+  float acc[ZV][3];
+#pragma unroll
+  for (int zz = 0; zz < ZV; ++zz) {
+    GATHER_Z(zz)
+    (void)live;
+    float gr[3];
+    grad_c<DIM>(g, m, x, y, z, p, gr);
+    const float l = lam[p];
+    for (int c = 0; c < DIM; ++c) acc[zz][c] = l * gr[c];
+  }
+#pragma unroll
+  for (int zz = 0; zz < ZV; ++zz) {
+    GATHER_Z(zz)
+    if (live)
+      for (int c = 0; c < DIM; ++c) b[c * M + p] = acc[zz][c];
+  }
+}
+
 // Deterministic partial sums of (mT - I1)^2: a fixed grid of kRedBlocks blocks, each thread
 // a fixed strided subset, then a fixed tree in LDS.
 __global__ __launch_bounds__(256) void k_energy_partial(int64_t n, const float* __restrict__ a,
@@ -568,6 +629,12 @@ inline dim3 gather_grid(const Geo& g, int zv) {
   } while (0)
 void setup(const Geo& g, const float* v, float* X, float4* YA, hipStream_t s) {
   DISPATCH_ONE(k_setup, g, v, X, YA);
+}
+void setup_ns(const Geo& g, const float* v0, const float* v1, float* X, float4* YA, hipStream_t s) {
+  DISPATCH_ONE(k_setup_ns, g, v0, v1, X, YA);
+}
+void body_node(const Geo& g, const float* lam, const float* m, float* b, hipStream_t s) {
+  DISPATCH_GATHER(k_body_node, TR_FORCE, g, lam, m, b);
 }
 void state_step(const Geo& g, const float* m_in, const float* X, float* m_out, hipStream_t s) {
   DISPATCH_GATHER(k_state_step, TR_STATE, g, m_in, X, m_out);
