@@ -84,6 +84,19 @@ extern "C" {
  * dot products and norms).  Not combined with BL_NEWTON (BL_E_UNSUPPORTED).  Needs 7 (nt - 1)
  * more grid planes of offsets (bl_lddmm_footprint includes them). */
 #define BL_NONSTATIONARY 4
+/* Deformation state equation (Section 3.3, with the continuous system of Section 2.3): the
+ * state is the band displacement u~ = phi~ - id of the inverse map phi, stepped in the band by
+ * the classical fourth-order Runge-Kutta method (nt steps) of d_t u~ = -v~ - D~u~ * v~ with
+ * truncated convolutions *; the warped source is m(1) = I0 o phi(1) (d-linear interpolation at
+ * i + N_ref iota(u~(1))).  The gradient L~ v~ + int (I + D~u~)^T * rho~ dt uses the band adjoint
+ * -d_t rho~ - div~(rho~ * v~) = 0 with rho~(1) = pi(lambda(1) (grad I0) o phi(1)), taken as the
+ * exact transpose of the Runge-Kutta step; products are Gauss-Newton (the terms that Section
+ * 3.4 removes for this method are dropped).  Truncated convolutions are formed on a product
+ * grid of 3 K_j / 2 points per axis (rounded up to even).  Stationary velocity; not combined
+ * with BL_NEWTON or BL_NONSTATIONARY (BL_E_UNSUPPORTED).  BL_MIXED applies to the image-grid
+ * transforms only.  bl_lddmm_ctx_get_field gives BL_FIELD_STATE index 0 (I0) and nt (m(1))
+ * only. */
+#define BL_DEFORMATION 8
 
 /* registration status */
 #define BL_CONVERGED 0
@@ -104,7 +117,7 @@ typedef struct {
                          multiplier term gamma grad~ p~ of Section 3.2), per band index
                          v~ - q (q . v~) / |q|^2 with q_j = 2 pi k_j / l_j                    */
   int32_t precision;  /* BL_FP32 or BL_MIXED                                                */
-  int32_t flags;      /* BL_DEVICE_PTRS or 0                                                */
+  int32_t flags;      /* BL_DEVICE_PTRS | BL_NEWTON | BL_NONSTATIONARY | BL_DEFORMATION, or 0 */
   void*   stream;     /* hipStream_t used with BL_DEVICE_PTRS (NULL: null stream)           */
 } bl_problem;
 

@@ -27,6 +27,7 @@ BL_FP32, BL_MIXED = 0, 1
 BL_DEVICE_PTRS = 1
 BL_NEWTON = 2
 BL_NONSTATIONARY = 4
+BL_DEFORMATION = 8
 BL_CONVERGED, BL_MAXITER, BL_STALLED = 0, 1, 2
 BL_MAX_GN = 64
 FIELDS = {"velocity": 0, "div": 1, "X": 2, "Y": 3, "a": 4, "state": 5}
@@ -158,7 +159,8 @@ def _check(rc):
 
 
 def make_problem(dim, n, k, nt, alpha=1e-3, s=2, sigma=1.0, gamma=0, precision=BL_FP32,
-                 device=False, stream=None, newton=False, nonstationary=False) -> Problem:
+                 device=False, stream=None, newton=False, nonstationary=False,
+                 deformation=False) -> Problem:
     p = Problem()
     p.dim = dim
     nn = list(n) + [1] * (3 - len(n))
@@ -169,7 +171,8 @@ def make_problem(dim, n, k, nt, alpha=1e-3, s=2, sigma=1.0, gamma=0, precision=B
     p.nt, p.alpha, p.s, p.sigma = int(nt), float(alpha), int(s), float(sigma)
     p.gamma, p.precision = int(gamma), int(precision)
     p.flags = ((BL_DEVICE_PTRS if device else 0) | (BL_NEWTON if newton else 0)
-               | (BL_NONSTATIONARY if nonstationary else 0))
+               | (BL_NONSTATIONARY if nonstationary else 0)
+               | (BL_DEFORMATION if deformation else 0))
     p.stream = C.c_void_p(stream) if stream else None
     return p
 

@@ -72,6 +72,28 @@ struct bl_ctx {
   float* DL = nullptr;     // (nt + 1) planes: dlambda^n
   float* U0 = nullptr;     // u ping-pong of the incremental adjoint
   float* U1 = nullptr;
+  float* mfinal = nullptr;  // m(1): the warped source
+  // deformation state equation only (image grid)
+  float4* IG = nullptr;    // (I0, central-difference gradient of I0)
+  float4* GP = nullptr;    // (grad I0) o phi(1) (w unused)
+  float* UG = nullptr;     // dim planes: iota(u~(1)), then iota(du~(1)) in products
+  // deformation state equation only (product grid of the truncated convolutions)
+  bl::Geo gP{};            // the product grid as a transform geometry
+  bl::DftPlan planP;
+  float* VP = nullptr;     // dim planes: iota(v~)
+  float* DVP = nullptr;    // dim planes: iota(dv~)
+  float* DUG = nullptr;    // 4 nt stages x dim^2 planes: iota(d~_j U_i) of every stage state
+  float* GW = nullptr;     // dim^2 planes of work
+  float* KG = nullptr;     // dim planes of work
+  float* GACC = nullptr;   // dim planes: deformation part of the gradient integrand
+  float2* DUb = nullptr;   // dim^2 band fields: spectral derivatives of a stage state
+  float2* US = nullptr;    // 2 x dim band fields: u~_n ping-pong
+  float2* ACC = nullptr;   // dim: Runge-Kutta slope sum
+  float2* KAP = nullptr;   // dim: transposed-sweep stage cotangent
+  float2* RHO = nullptr;   // dim: band adjoint
+  float2* ASUM = nullptr;  // dim: running sum of A kap_s within a step
+  float2* KSUM = nullptr;  // dim: identity part of the gradient integrand
+  float2* PH = nullptr;    // dim^2 half spectra of the product grid
   // band vectors (complex)
   float2* braw = nullptr;  // up to 4 components of staging
   float2* bv = nullptr;    // dim + 1: projected v, divergence

@@ -26,6 +26,8 @@ struct Geo {
   int gamma;          // 1: incompressible flow (velocities projected divergence-free)
   int newton;         // 1: full Newton Hessian products (else Gauss-Newton)
   int nodes;          // band velocity fields: 1 (stationary) or nt + 1 (one per time node)
+  int deform;         // 1: deformation state equation (band displacement of the inverse map)
+  int px, py, pz;     // product grid of the truncated convolutions (deformation method)
   // voxels per thread along z of the transport launches, per kernel class (TR_*): a launch
   // shape only, every choice computes bitwise the same values
   int zv[4];
@@ -124,6 +126,45 @@ void body_force_n(const Geo& g, const float* dlam, const float* m, const float* 
                   const float* dm, float* b, hipStream_t s);
 // one component of packed float4 voxels into a plane
 void unpack4(const Geo& g, int comp, const float4* in, float* plane, hipStream_t s);
+
+// ---- deformation state equation (bl_deform.hip)
+// Band fields are full centred bands of g (B entries per component); product-grid planes have
+// MP = px * py * pz points; Ph is a kz >= 0 half spectrum of the product grid (pi_half output,
+// kzh * ky * kx entries per component) and scaleP = 1 / MP.
+// DU[i * dim + j] = d~_j U_i (spectral derivative, lengths of the image grid)
+void def_deriv(const Geo& g, const float2* U, float2* DU, hipStream_t s);
+// one Runge-Kutta stage st = 1..4 of d_t u~ = -src - conv, conv = Herm(Ph) / MP:
+// k = -src - conv; acc = k (st 1), acc + 2k (st 2, 3), acc + k (st 4); the next state
+// un + c h k (st 1, 2, 3; c = 1/2, 1/2, 1) or un + h/6 acc (st 4, also stored to unext);
+// DU (may be null) receives its spectral derivatives
+void def_stage(const Geo& g, float scaleP, const float2* Ph, const float2* src, const float2* un,
+               float2* acc, int st, float2* unext, float2* DU, hipStream_t s);
+// out_i = sum_j DG[i dim + j] V_j (+ DG2[i dim + j] V2_j when DG2 != null), product grid
+void def_prod(const Geo& g, int64_t MP, const float* DG, const float* V, const float* DG2,
+              const float* V2, float* out, hipStream_t s);
+// kap = h/6 rho, Ksum = kap (start of the transposed sweep)
+void def_adj_init(const Geo& g, const float2* rho, float2* kap, float2* Ksum, hipStream_t s);
+// KV[i dim + j] = KG_i V_j; GACC_j (+)= sum_i DUG[i dim + j] KG_i (first: =)
+void def_adj_prod(const Geo& g, int64_t MP, const float* KG, const float* V, const float* DUG,
+                  float* KV, float* GACC, int first, hipStream_t s);
+// A_i = sum_j i q_j Herm(Ph[i dim + j]) / MP; the stage st = 4..1 of the transposed sweep
+// (next kap, the running sum of A, Ksum += kap; st 1: rho += sum A, then kap = h/6 rho when
+// more steps follow)
+void def_adj_combine(const Geo& g, float scaleP, const float2* Ph, float2* rho, float2* Asum,
+                     float2* Ksum, float2* kap, int st, int more, hipStream_t s);
+// out = Lhat vproj (if vproj) + Ksum + Herm(Ph) / MP, divergence-free part when gamma = 1
+void def_out(const Geo& g, float scaleP, const float2* Ph, const float2* Ksum,
+             const float2* vproj, const float* Lhat, float2* out, int* nonfinite, hipStream_t s);
+// image level (image grid): IG = (I0, central-difference gradient of I0)
+void def_ig4(const Geo& g, const float* I0, float4* IG, hipStream_t s);
+// m1 = I0 and GP = grad I0 interpolated at i + N_ref UG (UG: dim planes, domain units)
+void def_warp(const Geo& g, const float* UG, const float4* IG, float* m1, float4* GP,
+              hipStream_t s);
+// Bf_j = -(2/sigma^2)(m1 - I1) GP_j
+void def_rho1(const Geo& g, const float* m1, const float* I1, const float4* GP, float* Bf,
+              hipStream_t s);
+// Bf_j = -(2/sigma^2) (GP . DU) GP_j with DU = dim planes of iota(du~(1))
+void def_drho1(const Geo& g, const float* DU, const float4* GP, float* Bf, hipStream_t s);
 
 // ---- reductions and band vector algebra (bl_reduce.hip)
 // out[0] = sum of n partials in a fixed order (one block); also stored to host[0] (host-mapped

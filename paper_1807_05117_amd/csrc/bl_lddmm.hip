@@ -55,8 +55,11 @@ int validate(const bl_problem* p, bl::Geo* g) {
   if (p->gamma != 0 && p->gamma != 1) return fail(BL_E_INVALID, "gamma must be 0 or 1");
   if (p->precision != BL_FP32 && p->precision != BL_MIXED)
     return fail(BL_E_UNSUPPORTED, "precision must be BL_FP32 or BL_MIXED");
-  if (p->flags & ~(BL_DEVICE_PTRS | BL_NEWTON | BL_NONSTATIONARY))
+  if (p->flags & ~(BL_DEVICE_PTRS | BL_NEWTON | BL_NONSTATIONARY | BL_DEFORMATION))
     return fail(BL_E_INVALID, "unknown flag bits");
+  if ((p->flags & BL_DEFORMATION) && (p->flags & (BL_NEWTON | BL_NONSTATIONARY)))
+    return fail(BL_E_UNSUPPORTED,
+                "the deformation state equation takes Gauss-Newton products of a stationary velocity only");
   if ((p->flags & BL_NEWTON) && (p->flags & BL_NONSTATIONARY))
     return fail(BL_E_UNSUPPORTED, "full Newton products of a non-stationary velocity are not supported");
   if (g) {
@@ -78,6 +81,14 @@ int validate(const bl_problem* p, bl::Geo* g) {
     g->gamma = p->gamma;
     g->newton = (p->flags & BL_NEWTON) ? 1 : 0;
     g->nodes = (p->flags & BL_NONSTATIONARY) ? p->nt + 1 : 1;
+    g->deform = (p->flags & BL_DEFORMATION) ? 1 : 0;
+    // product grid of the truncated convolutions: 3 K / 2 points per axis rounded up to even
+    // (at least 3 K / 2 - 2 keep every product term of two band fields from aliasing into the
+    // band)
+    auto pgrid = [](int kk) { const int v = 3 * kk / 2; return v + (v & 1); };
+    g->px = pgrid(k[0]);
+    g->py = pgrid(k[1]);
+    g->pz = p->dim == 3 ? pgrid(k[2]) : 1;
     const bool d3 = p->dim == 3;
     g->zv[bl::TR_STATE] = d3 ? 2 : 1;
     g->zv[bl::TR_INC] = d3 ? 2 : 1;
@@ -131,8 +142,26 @@ int nzp_of(const bl::Geo& g) { return round_up(g.nz, 128); }
 struct Offsets {
   size_t I1, m, X, YA, V, DV, T0, T1, L, Bf, DM, DL, U, braw, bv, bd, bout, P, Lhat, Lhat64, tw_x, tw_xT,
       tw_y, tw_yT, tw_zT, wi, wp, bufA, bufB, red, scal, flag, solver;
+  // deformation state equation
+  size_t IG, GP, UG, VP, DVP, DUG, GW, KG, GACC, DUb, US, ACC, KAP, RHO, ASUM, KSUM, PH, ptw_x,
+      ptw_xT, ptw_y, ptw_yT, ptw_zT, pbufA, pbufB;
   size_t total;
 };
+
+// the product grid of the deformation method as a transform geometry (same band)
+bl::Geo product_geo(const bl::Geo& g) {
+  bl::Geo p = g;
+  p.nx = g.px;
+  p.ny = g.py;
+  p.nz = g.pz;
+  p.M = (int64_t)g.px * g.py * g.pz;
+  p.nref = std::max(g.px, std::max(g.py, g.pz));
+  p.inv_nx = 1.0f / (float)g.px;
+  p.inv_ny = 1.0f / (float)g.py;
+  p.inv_nz = 1.0f / (float)g.pz;
+  p.half_nref = 0.5f * (float)p.nref;
+  return p;
+}
 
 Offsets plan_layout(const bl::Geo& g, bool transport, bool solver, bool mixed) {
   Layout L;
@@ -141,7 +170,41 @@ Offsets plan_layout(const bl::Geo& g, bool transport, bool solver, bool mixed) {
   const int d = g.dim;
   const bool ns = g.nodes > 1;
   const size_t steps = ns ? (size_t)g.nt : 1;   // offset fields per time step (non-stationary)
-  if (transport) {
+  if (transport && g.deform) {
+    const bl::Geo gp = product_geo(g);
+    const size_t ppb = (size_t)gp.M * sizeof(float);
+    const size_t d2 = (size_t)d * d;
+    o.I1 = L.take(pb);
+    o.m = L.take(pb * 2);          // I0, m(1)
+    o.IG = L.take(pb * 4);
+    o.GP = L.take(pb * 4);
+    o.UG = L.take(pb * d);
+    o.Bf = L.take(pb * d);
+    o.VP = L.take(ppb * d);
+    o.DVP = L.take(ppb * d);
+    o.DUG = L.take(ppb * d2 * 4 * g.nt);
+    o.GW = L.take(ppb * d2);
+    o.KG = L.take(ppb * d);
+    o.GACC = L.take(ppb * d);
+    o.DUb = L.take(bb * d2);
+    o.US = L.take(bb * 2 * d);
+    o.ACC = L.take(bb * d);
+    o.KAP = L.take(bb * d);
+    o.RHO = L.take(bb * d);
+    o.ASUM = L.take(bb * d);
+    o.KSUM = L.take(bb * d);
+    o.PH = L.take(d2 * g.kzh * g.ky * g.kx * sizeof(float2));
+    o.ptw_x = L.take((size_t)kxp_of(gp) * gp.nx * sizeof(float2));
+    o.ptw_xT = L.take((size_t)nxp_of(gp) * gp.kx * sizeof(float2));
+    o.ptw_y = L.take((size_t)kyp_of(gp) * nyp_of(gp) * sizeof(float2));
+    o.ptw_yT = L.take((size_t)nyp_of(gp) * kyp_of(gp) * sizeof(float2));
+    o.ptw_zT = L.take((size_t)bl::kZP * nzp_of(gp) * sizeof(float2));
+    // transform stage buffers for dim^2 components
+    const size_t pst = std::max<size_t>(4, d2) * gp.kzh *
+                       (size_t)std::max<int64_t>((int64_t)gp.ky * gp.nx, (int64_t)gp.ny * gp.nx);
+    o.pbufA = L.take(pst * sizeof(float2));
+    o.pbufB = L.take(pst * sizeof(float2));
+  } else if (transport) {
     o.I1 = L.take(pb);
     o.m = L.take(pb * (g.nt + 1));
     o.X = L.take(pb * d * steps);
@@ -316,8 +379,24 @@ bl_ctx* create_ctx(const bl_problem* prob, const bl::Geo& g, bool transport, boo
     char* a = c->arena;
     auto F = [&](size_t off) { return reinterpret_cast<float*>(a + off); };
     auto C2 = [&](size_t off) { return reinterpret_cast<float2*>(a + off); };
-    if (transport) {
-      c->I1 = F(o.I1); c->m = F(o.m);
+    auto F4 = [&](size_t off) { return reinterpret_cast<float4*>(a + off); };
+    if (transport && g.deform) {
+      c->I1 = F(o.I1); c->m = F(o.m); c->mfinal = c->m + g.M;
+      c->IG = F4(o.IG); c->GP = F4(o.GP); c->UG = F(o.UG); c->Bf = F(o.Bf);
+      c->gP = product_geo(g);
+      c->VP = F(o.VP); c->DVP = F(o.DVP); c->DUG = F(o.DUG); c->GW = F(o.GW); c->KG = F(o.KG);
+      c->GACC = F(o.GACC);
+      c->DUb = C2(o.DUb); c->US = C2(o.US); c->ACC = C2(o.ACC); c->KAP = C2(o.KAP);
+      c->RHO = C2(o.RHO); c->ASUM = C2(o.ASUM); c->KSUM = C2(o.KSUM); c->PH = C2(o.PH);
+      bl::DftPlan& q = c->planP;
+      q.tw_x = C2(o.ptw_x); q.tw_xT = C2(o.ptw_xT); q.tw_y = C2(o.ptw_y); q.tw_yT = C2(o.ptw_yT);
+      q.tw_zT = C2(o.ptw_zT);
+      q.nyp = nyp_of(c->gP); q.kyp = kyp_of(c->gP); q.kxp = kxp_of(c->gP);
+      q.nxp = nxp_of(c->gP); q.nzp = nzp_of(c->gP);
+      q.bufA = C2(o.pbufA); q.bufB = C2(o.pbufB);
+      q.mixed = 0;
+    } else if (transport) {
+      c->I1 = F(o.I1); c->m = F(o.m); c->mfinal = c->m + (size_t)g.nt * g.M;
       c->X = F(o.X);
       c->YA = reinterpret_cast<float4*>(a + o.YA);
       c->DV = F(o.DV);
@@ -326,7 +405,7 @@ bl_ctx* create_ctx(const bl_problem* prob, const bl::Geo& g, bool transport, boo
         c->DM = F(o.DM); c->DL = F(o.DL); c->U0 = F(o.U); c->U1 = F(o.U) + g.M;
       }
     }
-    c->V = F(o.V);
+    if (!g.deform || !transport) c->V = F(o.V);
     c->braw = C2(o.braw); c->bv = C2(o.bv); c->bd = C2(o.bd); c->bout = C2(o.bout); c->P = C2(o.P);
     c->Lhat = F(o.Lhat);
     c->Lhat64 = reinterpret_cast<double*>(a + o.Lhat64);
@@ -364,16 +443,20 @@ bl_ctx* create_ctx(const bl_problem* prob, const bl::Geo& g, bool transport, boo
       HIP_TRY(hipMemcpyAsync(dst, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice, c->stream));
       HIP_TRY(hipStreamSynchronize(c->stream));
     };
-    twiddles(tw, c->plan.kxp, g.nx, g.kx, g.nx, true, false);
-    upload(c->plan.tw_x);
-    twiddles(tw, c->plan.nxp, g.kx, g.kx, g.nx, true, true);
-    upload(c->plan.tw_xT);
-    twiddles(tw, c->plan.kyp, c->plan.nyp, g.ky, g.ny, true, false);
-    upload(c->plan.tw_y);
-    twiddles(tw, c->plan.nyp, c->plan.kyp, g.ky, g.ny, true, true);
-    upload(c->plan.tw_yT);
-    twiddles(tw, c->plan.nzp, bl::kZP, g.kzh, g.nz, false, true);
-    upload(c->plan.tw_zT);
+    auto tables = [&](const bl::Geo& gg, bl::DftPlan& pl) {
+      twiddles(tw, pl.kxp, gg.nx, gg.kx, gg.nx, true, false);
+      upload(pl.tw_x);
+      twiddles(tw, pl.nxp, gg.kx, gg.kx, gg.nx, true, true);
+      upload(pl.tw_xT);
+      twiddles(tw, pl.kyp, pl.nyp, gg.ky, gg.ny, true, false);
+      upload(pl.tw_y);
+      twiddles(tw, pl.nyp, pl.kyp, gg.ky, gg.ny, true, true);
+      upload(pl.tw_yT);
+      twiddles(tw, pl.nzp, bl::kZP, gg.kzh, gg.nz, false, true);
+      upload(pl.tw_zT);
+    };
+    tables(g, c->plan);
+    if (c->DUG) tables(c->gP, c->planP);
     if (mixed) {
       std::vector<unsigned short> wi, wp;
       mixed_tables(g, wi, wp);
@@ -615,8 +698,121 @@ void op_hessvec_ns(bl_ctx* c, const float2* draw, float2* hout) {
   check_launch("hessvec (non-stationary)");
 }
 
+// ------------------------------------------------ deformation state equation (Section 3.3)
+// Every stage of the band Runge-Kutta sweep: iota of the stage state's spectral derivatives
+// onto the product grid, the pointwise products with iota(v~) (and, in products, of the stored
+// stage derivatives with iota(dv~)), pi back to the band, and the band stage update.
+float2* us_slot(bl_ctx* c, int k) { return c->US + (size_t)k * c->g.dim * c->g.B; }
+float* dug_slot(bl_ctx* c, int n, int st) {
+  const size_t d2 = (size_t)c->g.dim * c->g.dim;
+  return c->DUG + (size_t)(n * 4 + (st - 1)) * d2 * (size_t)c->gP.M;
+}
+
+// from u~(0) = 0 (state) or du~(0) = 0 (incremental, source dv~ in bd); returns u~(1) / du~(1)
+const float2* def_sweep_forward(bl_ctx* c, bool incremental) {
+  const bl::Geo& g = c->g;
+  hipStream_t s = c->stream;
+  const int d = g.dim, d2 = d * d;
+  const int64_t MP = c->gP.M;
+  const float scaleP = (float)(1.0 / (double)MP);
+  const float2* src = incremental ? c->bd : c->bv;
+  HIP_TRY(hipMemsetAsync(us_slot(c, 0), 0, band_bytes(g) * d, s));
+  HIP_TRY(hipMemsetAsync(c->DUb, 0, band_bytes(g) * d2, s));
+  int cur = 0;
+  for (int n = 0; n < g.nt; ++n)
+    for (int st = 1; st <= 4; ++st) {
+      float* dg = incremental ? c->GW : dug_slot(c, n, st);
+      bl::iota(c->gP, c->planP, c->DUb, d2, dg, s);
+      if (incremental) bl::def_prod(g, MP, dg, c->VP, dug_slot(c, n, st), c->DVP, c->KG, s);
+      else bl::def_prod(g, MP, dg, c->VP, nullptr, nullptr, c->KG, s);
+      bl::pi_half(c->gP, c->planP, c->KG, d, c->PH, s);
+      const bool last = n + 1 == g.nt && st == 4;
+      bl::def_stage(g, scaleP, c->PH, src, us_slot(c, cur), c->ACC, st, us_slot(c, cur ^ 1),
+                    last ? nullptr : c->DUb, s);
+      if (st == 4) cur ^= 1;
+    }
+  return us_slot(c, cur);
+}
+
+// the transposed sweep from rho~(1) in RHO; out = Lhat vproj + int (I + D~U)^T * rho~ dt
+void def_sweep_backward(bl_ctx* c, const float2* vproj, float2* out) {
+  const bl::Geo& g = c->g;
+  hipStream_t s = c->stream;
+  const int d = g.dim, d2 = d * d;
+  const int64_t MP = c->gP.M;
+  const float scaleP = (float)(1.0 / (double)MP);
+  bl::def_adj_init(g, c->RHO, c->KAP, c->KSUM, s);
+  for (int n = g.nt - 1; n >= 0; --n)
+    for (int st = 4; st >= 1; --st) {
+      bl::iota(c->gP, c->planP, c->KAP, d, c->KG, s);
+      bl::def_adj_prod(g, MP, c->KG, c->VP, dug_slot(c, n, st), c->GW, c->GACC,
+                       n + 1 == g.nt && st == 4, s);
+      bl::pi_half(c->gP, c->planP, c->GW, d2, c->PH, s);
+      bl::def_adj_combine(g, scaleP, c->PH, c->RHO, c->ASUM, c->KSUM, c->KAP, st, n > 0, s);
+    }
+  bl::pi_half(c->gP, c->planP, c->GACC, d, c->PH, s);
+  bl::def_out(g, scaleP, c->PH, c->KSUM, vproj, c->Lhat, out, c->flag, s);
+}
+
+void op_set_velocity_def(bl_ctx* c, const float2* vraw) {
+  const bl::Geo& g = c->g;
+  hipStream_t s = c->stream;
+  double* red_reg = c->red + RED_REG * bl::kRedBlocks;
+  double* red_data = c->red + RED_DATA * bl::kRedBlocks;
+  bl::band_prep(g, vraw, c->bv, 1, c->Lhat64, red_reg, s);
+  bl::iota(c->gP, c->planP, c->bv, g.dim, c->VP, s);
+  const float2* u1 = def_sweep_forward(c, false);
+  bl::iota(g, c->plan, u1, g.dim, c->UG, s);
+  bl::def_warp(g, c->UG, c->IG, c->mfinal, c->GP, s);
+  bl::energy_partial(g, c->mfinal, c->I1, red_data, s);
+  bl::reduce_final(red_reg, bl::kRedBlocks, c->scal + S_REG, s, c->hdev + S_REG);
+  bl::reduce_final(red_data, bl::kRedBlocks, c->scal + S_DATA, s, c->hdev + S_DATA);
+  check_launch("set_velocity (deformation)");
+  sync(c);
+  c->reg = c->hscal[S_REG];
+  c->data_sum = c->hscal[S_DATA];
+  const double sig = c->prob.sigma;
+  c->E = 0.5 * c->reg + c->data_sum / (sig * sig * (double)g.M);
+  c->have_v = true;
+  c->have_lambda = false;
+  if (!std::isfinite(c->E)) throw NonFinite{"energy"};
+}
+
+// rho~(1) = pi(Bf) into RHO (Bf = lambda(1) (grad I0) o phi(1) or its incremental form)
+void def_terminal_band(bl_ctx* c) {
+  const bl::Geo& g = c->g;
+  bl::pi_half(g, c->plan, c->Bf, g.dim, c->P, c->stream);
+  bl::band_finalize(g, g.dim, nullptr, nullptr, c->P, (float)(1.0 / (double)g.M), c->RHO, c->flag,
+                    c->stream, 0);
+}
+
+void op_gradient_def(bl_ctx* c, float2* gout) {
+  const bl::Geo& g = c->g;
+  bl::def_rho1(g, c->mfinal, c->I1, c->GP, c->Bf, c->stream);
+  def_terminal_band(c);
+  def_sweep_backward(c, c->bv, gout);
+  check_launch("gradient (deformation)");
+}
+
+void op_hessvec_def(bl_ctx* c, const float2* draw, float2* hout) {
+  const bl::Geo& g = c->g;
+  hipStream_t s = c->stream;
+  bl::band_prep(g, draw, c->bd, 0, nullptr, nullptr, s);
+  bl::iota(c->gP, c->planP, c->bd, g.dim, c->DVP, s);
+  const float2* du1 = def_sweep_forward(c, true);
+  bl::iota(g, c->plan, du1, g.dim, c->UG, s);
+  bl::def_drho1(g, c->UG, c->GP, c->Bf, s);
+  def_terminal_band(c);
+  def_sweep_backward(c, c->bd, hout);
+  check_launch("hessvec (deformation)");
+}
+
 // setup + forward state + energy at the raw band vector `vraw` (device, dim components)
 void op_set_velocity(bl_ctx* c, const float2* vraw) {
+  if (c->g.deform) {
+    op_set_velocity_def(c, vraw);
+    return;
+  }
   if (c->g.nodes > 1) {
     op_set_velocity_ns(c, vraw);
     return;
@@ -660,6 +856,10 @@ void backward_and_body_force(bl_ctx* c) {
 
 // gradient at the current velocity into gout (device, dim components)
 void op_gradient(bl_ctx* c, float2* gout) {
+  if (c->g.deform) {
+    op_gradient_def(c, gout);
+    return;
+  }
   if (c->g.nodes > 1) {
     op_gradient_ns(c, gout);
     return;
@@ -717,6 +917,10 @@ void op_hessvec_newton(bl_ctx* c, const float2* draw, float2* hout) {
 
 // Gauss-Newton Hessian-vector product of the raw direction draw into hout
 void op_hessvec(bl_ctx* c, const float2* draw, float2* hout) {
+  if (c->g.deform) {
+    op_hessvec_def(c, draw, hout);
+    return;
+  }
   if (c->g.nodes > 1) {
     op_hessvec_ns(c, draw, hout);
     return;
@@ -819,6 +1023,10 @@ void load_images(bl_ctx* c, const float* I0, const float* I1) {
   HIP_TRY(hipMemcpyAsync(c->m, I0, pb, in_kind(c), c->stream));
   if (I1) HIP_TRY(hipMemcpyAsync(c->I1, I1, pb, in_kind(c), c->stream));
   else HIP_TRY(hipMemsetAsync(c->I1, 0, pb, c->stream));
+  if (c->IG) {
+    bl::def_ig4(c->g, c->m, c->IG, c->stream);
+    check_launch("image gradient");
+  }
 }
 
 void load_band(bl_ctx* c, const float* src, float2* dst, int ncomp) {
@@ -1167,6 +1375,12 @@ int bl_lddmm_ctx_get_field(bl_ctx* c, int32_t which, int32_t index, float* out) 
     case BL_FIELD_STATE: if (index >= 0 && index <= g.nt) src = c->m + index * M; break;
     default: break;
   }
+  if (g.deform) {   // only I0 and m(1) are grid fields of the deformation method
+    src = nullptr;
+    packed = nullptr;
+    if (which == BL_FIELD_STATE && index == 0) src = c->m;
+    if (which == BL_FIELD_STATE && index == g.nt) src = c->mfinal;
+  }
   if (!src && !packed) return fail(BL_E_INVALID, "unknown field or index out of range");
   if (!c->have_v && which != BL_FIELD_STATE) return fail(BL_E_INVALID, "no velocity set on this context");
   return guarded([&]() {
@@ -1232,7 +1446,7 @@ int bl_lddmm_warp(const bl_problem* prob, const float* I0, const float* v_hat, f
     load_images(h.c, I0, nullptr);
     load_band(h.c, v_hat, h.c->braw, g.nodes * g.dim);
     op_set_velocity(h.c, h.c->braw);
-    store_plane(h.c, h.c->m + (size_t)g.nt * g.M, warped, 1);
+    store_plane(h.c, h.c->mfinal, warped, 1);
     sync(h.c);
     h.ok = true;
     return BL_OK;
@@ -1257,7 +1471,7 @@ int bl_lddmm_register(const bl_problem* prob, const bl_solver_opts* opts, const 
     load_band(h.c, v_hat, h.c->sv, g.nodes * g.dim);
     solve(h.c, o, &local);
     store_band(h.c, h.c->sv, v_hat, g.nodes * g.dim);
-    if (warped) store_plane(h.c, h.c->m + (size_t)g.nt * g.M, warped, 1);
+    if (warped) store_plane(h.c, h.c->mfinal, warped, 1);
     sync(h.c);
     local.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (stats) *stats = local;

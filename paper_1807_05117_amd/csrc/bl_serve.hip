@@ -121,7 +121,7 @@ void run_request(bl_server* srv, Slot& slot, int slot_index, Request* r) {
     solve(c, r->opts, &r->stats);
     store_band(c, c->sv, r->v.data(), r->g.nodes * r->g.dim);
     r->warped.resize((size_t)r->g.M);
-    store_plane(c, c->m + (size_t)r->g.nt * r->g.M, r->warped.data(), 1);
+    store_plane(c, c->mfinal, r->warped.data(), 1);
     sync(c);
     r->stats.seconds = std::chrono::duration<double>(Clock::now() - ts).count();
     guard.ok = true;

@@ -1,0 +1,113 @@
+"""GPU parity of the deformation state equation (BL_DEFORMATION): the band Runge-Kutta sweep
+with truncated convolutions on the product grid, the image level, the transposed sweep of the
+gradient and the Gauss-Newton product, against the oracle's def_* functions (relative 1e-5
+plain, 1e-4 mixed); the GPU Hessian's symmetry; and a 2D registration with the oracle's solver
+decisions."""
+import functools
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1807_05117_amd import binding as B
+
+from parity_cases import bl_problem, case, grad_error, rel2
+
+pytestmark = pytest.mark.gpu
+
+CASES = ["c1_2d", "ragged_3d", "brainlike_small", "h1_incomp_2d", "h1_incomp_3d"]
+
+
+def _log(*a):
+    print(*a, flush=True)
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_def(name):
+    prob, I0, I1, vs, vh, dv = case(name)
+    st = O.def_evaluate(vh, I0, I1, prob)
+    return st, O.def_gradient(st), O.def_hessvec(st, dv)
+
+
+def _gpu(name, precision=B.BL_FP32):
+    prob, I0, I1, vs, vh, dv = case(name)
+    ctx = B.Ctx(bl_problem(prob, precision=precision, deformation=True), I0, I1)
+    E, g = ctx.bl_lddmm_ctx_set_velocity(vh.astype(np.complex64))
+    H = ctx.bl_lddmm_ctx_hessvec(dv.astype(np.complex64))
+    m1 = ctx.bl_lddmm_ctx_get_field("state", prob.nt)
+    ctx.close()
+    return E, g, H, m1
+
+
+@pytest.mark.parametrize("precision,tol", [(B.BL_FP32, 1e-5), (B.BL_MIXED, 1e-4)],
+                         ids=["fp32", "mixed"])
+@pytest.mark.parametrize("name", CASES)
+def test_deform_parity(gpu_lib, name, precision, tol):
+    prob, I0, I1, vs, vh, dv = case(name)
+    _log(f"deformation {name} precision {precision}: oracle")
+    st, g_ref, H_ref = oracle_def(name)
+    _log("  gpu")
+    E, g, H, m1 = _gpu(name, precision)
+    e_e = abs(E - st.E) / abs(st.E)
+    e_m = np.abs(m1 - st.m1).max() / np.abs(st.m1).max()
+    e_g = grad_error(g, g_ref, prob, vh)
+    e_h = rel2(H, H_ref)
+    _log(f"  E {e_e:.2e}  m(1) {e_m:.2e}  gradient {e_g:.2e}  hessvec {e_h:.2e}")
+    assert e_e < tol and e_m < tol
+    assert e_g < tol and e_h < tol
+
+
+def test_deform_c2_full_size(gpu_lib):
+    """the 128^3 workload (band 32^3, product grid 48^3, Nt = 10) element by element"""
+    name = "c2_full"
+    prob, I0, I1, vs, vh, dv = case(name)
+    _log("deformation c2_full: oracle")
+    st, g_ref, H_ref = oracle_def(name)
+    E, g, H, m1 = _gpu(name)
+    e_g, e_h = grad_error(g, g_ref, prob, vh), rel2(H, H_ref)
+    _log(f"  E {abs(E - st.E) / st.E:.2e}  gradient {e_g:.2e}  hessvec {e_h:.2e}")
+    assert abs(E - st.E) < 1e-5 * st.E
+    assert e_g < 1e-5 and e_h < 1e-5
+
+
+@pytest.mark.parametrize("name", ["c1_2d", "ragged_3d"])
+def test_deform_hessian_symmetric(gpu_lib, name):
+    """the discrete Gauss-Newton Hessian of this method is symmetric at every velocity (the
+    oracle's to 1e-15); on the GPU to FP32 rounding"""
+    prob, I0, I1, vs, vh, dv = case(name)
+    d2 = O.project(np.conj(dv[:, ::-1, ::-1] if prob.dim == 2 else dv[:, ::-1, ::-1, ::-1]), prob)
+    d2 = (d2 / np.abs(d2).max()).astype(np.complex64)
+    ctx = B.Ctx(bl_problem(prob, deformation=True), I0, I1)
+    ctx.bl_lddmm_ctx_set_velocity(vh.astype(np.complex64), want_gradient=False)
+    H1 = ctx.bl_lddmm_ctx_hessvec(dv.astype(np.complex64)).astype(np.complex128)
+    H2 = ctx.bl_lddmm_ctx_hessvec(d2).astype(np.complex128)
+    ctx.close()
+    a, b = O.dot(H1, d2), O.dot(dv, H2)
+    _log(f"  {name} symmetry defect {abs(a - b) / (abs(a) + abs(b)):.2e}")
+    assert abs(a - b) <= 1e-5 * (abs(a) + abs(b))
+
+
+def test_deform_register_c1_against_oracle(gpu_lib):
+    prob, I0, I1, vs, vh, dv = case("c1_2d")
+    opts = O.SolverOpts(max_gn=5, max_pcg=10)
+    _log("deformation c1_2d: oracle register")
+    v_ref, m_ref, s_ref = O.def_register(I0, I1, np.zeros_like(vs), prob, opts)
+    v, m1, s = B.bl_lddmm_register(bl_problem(prob, deformation=True), I0, I1,
+                                   np.zeros_like(vs, dtype=np.complex64),
+                                   B.opts_struct(max_gn=5, max_pcg=10))
+    _log("  gpu", s["pcg_iters"], s["ls_trials"], s["mse_rel"][-1], " oracle", s_ref["pcg_iters"],
+         s_ref["ls_trials"], s_ref["mse_rel"][-1])
+    assert s["status"] == s_ref["status"]
+    assert s["pcg_iters"] == s_ref["pcg_iters"]
+    assert s["ls_trials"] == s_ref["ls_trials"]
+    assert np.allclose(s["E"], s_ref["E"], rtol=1e-4)
+    assert np.abs(m1 - m_ref).max() < 1e-3
+
+
+def test_deform_flag_combinations_rejected(gpu_lib):
+    prob = case("c1_2d")[0]
+    for kw in (dict(newton=True), dict(nonstationary=True)):
+        p = bl_problem(prob, deformation=True, **kw)
+        with pytest.raises(B.BLError) as e:
+            B.Ctx(p, np.zeros(prob.shape, np.float32), np.zeros(prob.shape, np.float32))
+        assert e.value.code == B.BL_E_UNSUPPORTED
