@@ -80,6 +80,7 @@ struct bl_ctx {
   // deformation state equation only (product grid of the truncated convolutions)
   bl::Geo gP{};            // the product grid as a transform geometry
   bl::DftPlan planP;
+  bool fused = false;      // the fused stage kernels run the product-grid sweeps
   float* VP = nullptr;     // dim planes: iota(v~)
   float* DVP = nullptr;    // dim planes: iota(dv~)
   float* DUG = nullptr;    // 4 nt stages x dim^2 planes: iota(d~_j U_i) of every stage state

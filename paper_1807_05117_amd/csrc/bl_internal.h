@@ -166,6 +166,29 @@ void def_rho1(const Geo& g, const float* m1, const float* I1, const float4* GP, 
 // Bf_j = -(2/sigma^2) (GP . DU) GP_j with DU = dim planes of iota(du~(1))
 void def_drho1(const Geo& g, const float* DU, const float4* GP, float* Bf, hipStream_t s);
 
+// fused stage kernels of the deformation method (bl_deform_fused.hip), 3D product grids with
+// pz <= 64 whose tiles fit the LDS budget (fused_ok); F2 and G are work buffers of
+// dim^2 * kzh * py * px complex entries (the product plan's bufA / bufB)
+bool fused_ok(const Geo& g, const Geo& gp);
+// F2[c][h][y][x] from the kz >= 0 half of `in` (dim fields; deriv: the dim^2 fields i q_j in_i)
+void fx_iota_xy(const Geo& g, const Geo& gp, const DftPlan& pl, const float2* in, int deriv,
+                float2* F2, hipStream_t s);
+// columns: iota z, products with VP (+ DUGr . DVP), DUGw <- the derivative fields (if not
+// null), pi z of the dim products into G[i][h][y][x]
+void fx_col_fwd(const Geo& gp, const DftPlan& pl, const float2* F2, const float* VP,
+                float* DUGw, const float* DUGr, const float* DVP, float2* G, hipStream_t s);
+// columns: iota z of the cotangent, GACC (+)= (D~U)^T kap, pi z of the dim^2 products kap_i V_j
+void fx_col_bwd(const Geo& gp, const DftPlan& pl, const float2* F2, const float* VP,
+                const float* DUG, float* GACC, int first, float2* G, hipStream_t s);
+// pi xy of G and the Runge-Kutta stage update (as def_stage; wout receives the next state)
+void fx_pi_yx_stage(const Geo& g, const Geo& gp, const DftPlan& pl, const float2* G, float scaleP,
+                    const float2* src, const float2* un, float2* acc, int st, float2* wout,
+                    hipStream_t s);
+// pi xy of the dim^2 products and the transposed-sweep update (as def_adj_combine)
+void fx_pi_yx_adj(const Geo& g, const Geo& gp, const DftPlan& pl, const float2* G, float scaleP,
+                  float2* rho, float2* Asum, float2* Ksum, float2* kap, int st, int more,
+                  hipStream_t s);
+
 // ---- reductions and band vector algebra (bl_reduce.hip)
 // out[0] = sum of n partials in a fixed order (one block); also stored to host[0] (host-mapped
 // pinned memory) when host != NULL, and *flag published to host_flag[0] when flag != NULL

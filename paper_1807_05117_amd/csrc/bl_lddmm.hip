@@ -395,6 +395,8 @@ bl_ctx* create_ctx(const bl_problem* prob, const bl::Geo& g, bool transport, boo
       q.nxp = nxp_of(c->gP); q.nzp = nzp_of(c->gP);
       q.bufA = C2(o.pbufA); q.bufB = C2(o.pbufB);
       q.mixed = 0;
+      const char* fenv = std::getenv("BL_DEFORM_FUSED");
+      c->fused = bl::fused_ok(g, c->gP) && !(fenv && fenv[0] == '0');
     } else if (transport) {
       c->I1 = F(o.I1); c->m = F(o.m); c->mfinal = c->m + (size_t)g.nt * g.M;
       c->X = F(o.X);
@@ -717,6 +719,24 @@ const float2* def_sweep_forward(bl_ctx* c, bool incremental) {
   const float scaleP = (float)(1.0 / (double)MP);
   const float2* src = incremental ? c->bd : c->bv;
   HIP_TRY(hipMemsetAsync(us_slot(c, 0), 0, band_bytes(g) * d, s));
+  if (c->fused) {
+    // three launches per stage; the stage state U_st is u_n (st = 1) or the state written by
+    // the previous stage into DUb (used as a dim-field buffer here)
+    const bl::DftPlan& pl = c->planP;
+    int cur = 0;
+    for (int n = 0; n < g.nt; ++n)
+      for (int st = 1; st <= 4; ++st) {
+        const float2* state = st == 1 ? us_slot(c, cur) : c->DUb;
+        bl::fx_iota_xy(g, c->gP, pl, state, 1, pl.bufA, s);
+        bl::fx_col_fwd(c->gP, pl, pl.bufA, c->VP, incremental ? nullptr : dug_slot(c, n, st),
+                       incremental ? dug_slot(c, n, st) : nullptr, incremental ? c->DVP : nullptr,
+                       pl.bufB, s);
+        bl::fx_pi_yx_stage(g, c->gP, pl, pl.bufB, scaleP, src, us_slot(c, cur), c->ACC, st,
+                           st == 4 ? us_slot(c, cur ^ 1) : c->DUb, s);
+        if (st == 4) cur ^= 1;
+      }
+    return us_slot(c, cur);
+  }
   HIP_TRY(hipMemsetAsync(c->DUb, 0, band_bytes(g) * d2, s));
   int cur = 0;
   for (int n = 0; n < g.nt; ++n)
@@ -742,6 +762,20 @@ void def_sweep_backward(bl_ctx* c, const float2* vproj, float2* out) {
   const int64_t MP = c->gP.M;
   const float scaleP = (float)(1.0 / (double)MP);
   bl::def_adj_init(g, c->RHO, c->KAP, c->KSUM, s);
+  if (c->fused) {
+    const bl::DftPlan& pl = c->planP;
+    for (int n = g.nt - 1; n >= 0; --n)
+      for (int st = 4; st >= 1; --st) {
+        bl::fx_iota_xy(g, c->gP, pl, c->KAP, 0, pl.bufA, s);
+        bl::fx_col_bwd(c->gP, pl, pl.bufA, c->VP, dug_slot(c, n, st), c->GACC,
+                       n + 1 == g.nt && st == 4, pl.bufB, s);
+        bl::fx_pi_yx_adj(g, c->gP, pl, pl.bufB, scaleP, c->RHO, c->ASUM, c->KSUM, c->KAP, st,
+                         n > 0, s);
+      }
+    bl::pi_half(c->gP, c->planP, c->GACC, d, c->PH, s);
+    bl::def_out(g, scaleP, c->PH, c->KSUM, vproj, c->Lhat, out, c->flag, s);
+    return;
+  }
   for (int n = g.nt - 1; n >= 0; --n)
     for (int st = 4; st >= 1; --st) {
       bl::iota(c->gP, c->planP, c->KAP, d, c->KG, s);

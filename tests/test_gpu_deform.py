@@ -111,3 +111,23 @@ def test_deform_flag_combinations_rejected(gpu_lib):
         with pytest.raises(B.BLError) as e:
             B.Ctx(p, np.zeros(prob.shape, np.float32), np.zeros(prob.shape, np.float32))
         assert e.value.code == B.BL_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("name", ["ragged_3d", "c2_full"])
+def test_fused_stage_kernels_match_unfused(gpu_lib, name, monkeypatch):
+    """the fused product-grid stage kernels (default for 3D) and the unfused kernel chain compute
+    the same E, g and H v up to FP32 rounding order"""
+    prob, I0, I1, vs, vh, dv = case(name)
+    out = {}
+    for flag in ("1", "0"):
+        monkeypatch.setenv("BL_DEFORM_FUSED", flag)
+        ctx = B.Ctx(bl_problem(prob, deformation=True), I0, I1)
+        E, g = ctx.bl_lddmm_ctx_set_velocity(vh.astype(np.complex64))
+        H = ctx.bl_lddmm_ctx_hessvec(dv.astype(np.complex64))
+        ctx.close()
+        out[flag] = (E, g.astype(np.complex128), H.astype(np.complex128))
+    (E1, g1, H1), (E0, g0, H0) = out["1"], out["0"]
+    _log(f"  {name} fused vs unfused: E {abs(E1 - E0) / E0:.2e} g {rel2(g1, g0):.2e} "
+         f"H {rel2(H1, H0):.2e}")
+    assert abs(E1 - E0) <= 1e-6 * E0
+    assert rel2(g1, g0) < 2e-6 and rel2(H1, H0) < 2e-6
