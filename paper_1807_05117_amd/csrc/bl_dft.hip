@@ -431,9 +431,10 @@ __global__ __launch_bounds__(256) void k_band_prep(Geo g, const float2* __restri
 }
 
 // One thread per band index, all C components: Hermitian completion from the kz >= 0 half, the
-// regulariser term, and (leray) the divergence-free part of the C = dim components.
-template <int DIM>
-__global__ __launch_bounds__(256) void k_band_finalize(Geo g, int C,
+// regulariser term, and (leray) the divergence-free part of the C = dim components.  C is a
+// template parameter so that the loads of all components are issued together.
+template <int DIM, int C>
+__global__ __launch_bounds__(256) void k_band_finalize(Geo g,
                                                        const float2* __restrict__ vproj,
                                                        const float* __restrict__ Lhat,
                                                        const float2* __restrict__ P,
@@ -445,7 +446,8 @@ __global__ __launch_bounds__(256) void k_band_finalize(Geo g, int C,
     band_index(g, b, jx, jy, jz);
     const bool up = unpaired(g, jx, jy, jz);
     const int kzv = jz - g.kz0;
-    float2 o[4];
+    float2 o[C];
+#pragma unroll
     for (int c = 0; c < C; ++c) {
       o[c] = make_float2(0.f, 0.f);
       if (up) continue;
@@ -470,15 +472,20 @@ __global__ __launch_bounds__(256) void k_band_finalize(Geo g, int C,
         o[c].y = fmaf(l, v.y, o[c].y);
       }
     }
-    if (leray_on && !up) {
-      float q[DIM];
-      div_symbol<DIM>(g, jx, jy, jz, q);
-      leray<DIM>(q, o);
+    if constexpr (C == DIM) {
+      if (leray_on && !up) {
+        float q[DIM];
+        div_symbol<DIM>(g, jx, jy, jz, q);
+        leray<DIM>(q, o);
+      }
     }
+    bool bad = false;
+#pragma unroll
     for (int c = 0; c < C; ++c) {
-      if (!isfinite(o[c].x) || !isfinite(o[c].y)) *nonfinite = 1;
+      bad = bad || !isfinite(o[c].x) || !isfinite(o[c].y);
       out[c * B + b] = o[c];
     }
+    if (bad) *nonfinite = 1;
   }
 }
 
@@ -569,12 +576,25 @@ void band_finalize(const Geo& g, int C, const float2* vproj, const float* Lhat,
                    int leray) {
   const int blocks = std::min(4096, (int)((g.B + 255) / 256));
   const int on = (leray && g.gamma && C == g.dim) ? 1 : 0;
-  if (g.dim == 3)
-    hipLaunchKernelGGL(k_band_finalize<3>, dim3(blocks), dim3(256), 0, s, g, C, vproj, Lhat, P,
-                       scale, out, nonfinite, on);
-  else
-    hipLaunchKernelGGL(k_band_finalize<2>, dim3(blocks), dim3(256), 0, s, g, C, vproj, Lhat, P,
-                       scale, out, nonfinite, on);
+#define BF_LAUNCH(D, CC)                                                                        \
+  hipLaunchKernelGGL((k_band_finalize<D, CC>), dim3(blocks), dim3(256), 0, s, g, vproj, Lhat, P, \
+                     scale, out, nonfinite, on)
+  if (g.dim == 3) {
+    switch (C) {
+      case 1: BF_LAUNCH(3, 1); break;
+      case 2: BF_LAUNCH(3, 2); break;
+      case 3: BF_LAUNCH(3, 3); break;
+      default: BF_LAUNCH(3, 4); break;
+    }
+  } else {
+    switch (C) {
+      case 1: BF_LAUNCH(2, 1); break;
+      case 2: BF_LAUNCH(2, 2); break;
+      case 3: BF_LAUNCH(2, 3); break;
+      default: BF_LAUNCH(2, 4); break;
+    }
+  }
+#undef BF_LAUNCH
 }
 
 }  // namespace bl
