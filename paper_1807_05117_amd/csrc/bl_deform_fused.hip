@@ -8,8 +8,7 @@
 //           formed on the fly from the state U.
 //   2. col: per (y, x) column of the product grid: the z contraction of iota, the pointwise
 //           products (and their side outputs), and the z contraction of pi, the column's z
-//           values exchanged through LDS.  Wave w handles the z planes w, w + 8, ...; twiddles
-//           are wave-uniform (scalar loads).
+//           values exchanged through LDS; two lanes per column split the kz spectrum.
 //   3. yx:  G[c][h][y][x] -> the band: the x and y contractions of pi for one (component, h)
 //           plane and a chunk of kx, the G plane staged in LDS, followed by the band-side update
 //           of the stage (forward) or of the transposed sweep (backward) at kz = h and at the
@@ -22,10 +21,10 @@
 namespace bl {
 namespace {
 
-constexpr int kColW = 64;     // columns per column-kernel block (one per lane)
+constexpr int kColW = 32;     // columns per column-kernel block (two lanes each)
 constexpr int kColWaves = 8;  // waves per column-kernel block
 constexpr int kXC = 16;       // x outputs per iota xy block
-constexpr int kKC = 8;        // kx outputs per pi yx block
+constexpr int kKC = 4;        // kx outputs per pi yx block
 
 __device__ __forceinline__ void cmac(float2& acc, float2 a, float2 b) {
   acc.x = fmaf(a.x, b.x, acc.x);
@@ -123,17 +122,23 @@ __global__ __launch_bounds__(256) void k_fx_iota_xy(Geo g, Geo gp, const float2*
 }
 
 // ---------------------------------------------------------------------------- 2. columns
-// Block (64 columns, component): wave w handles the z planes w, w + 8, ... of its 64 columns.
-// The block's z twiddles exp(+2 pi i h z / pz) are staged in LDS (tz[z][h], KZH per row) and
-// read as broadcasts, each shared by the three fields a block contracts.
+// Block (32 columns, component), eight waves: lane l of a wave serves column l mod 32 and the
+// half l / 32 of the kz spectrum (h in [half KZH / 2, (half + 1) KZH / 2)), so each lane holds
+// half of a column's coefficients and the two halves' partial sums meet in one lane swap.  Wave
+// w handles the z planes w, w + 8, ... of the block's columns.  The block's z twiddles
+// exp(+2 pi i h z / pz) are staged in LDS (tz[z][h], KZH per row) and read as broadcasts, each
+// shared by the three fields a block contracts.
 
-// the half-spectrum column of one field (h < kzh; zero past kzh), all loads issued together
+// this lane's half of the column of one field (h < kzh; zero past kzh), loads issued together
 template <int KZH>
-__device__ __forceinline__ void load_col(const float2* __restrict__ Fc, size_t hstride, int kzh,
-                                         float2* F) {
+__device__ __forceinline__ void load_half(const float2* __restrict__ Fc, size_t hstride, int kzh,
+                                          int half, float2* F) {
+  constexpr int NHH = KZH / 2;
 #pragma unroll
-  for (int h = 0; h < KZH; ++h)
-    F[h] = h < kzh ? Fc[(size_t)h * hstride] : make_float2(0.f, 0.f);
+  for (int u = 0; u < NHH; ++u) {
+    const int h = half * NHH + u;
+    F[u] = h < kzh ? Fc[(size_t)h * hstride] : make_float2(0.f, 0.f);
+  }
 }
 
 template <int KZH>
@@ -145,26 +150,33 @@ __device__ __forceinline__ void stage_tz(const float2* __restrict__ tw_zT, int p
   }
 }
 
-// f_j(z) = Re F_j[0] + 2 sum_{h >= 1} Re(F_j[h] tz[z][h]) for three fields at one plane z
+// f_j(z) = Re F_j[0] + 2 sum_{h >= 1} Re(F_j[h] tz[z][h]) for three fields at one plane z: each
+// half sums its h range, then the halves exchange partial sums (lane l <-> l ^ 32)
 template <int KZH>
-__device__ __forceinline__ void iota_z3(const float2 (*F)[KZH], const float2* tz, int z, float* f) {
+__device__ __forceinline__ void iota_z3(const float2 (*F)[KZH / 2], const float2* tz, int z,
+                                        int half, float* f) {
+  constexpr int NHH = KZH / 2;
 #pragma unroll
-  for (int j = 0; j < 3; ++j) f[j] = F[j][0].x;
+  for (int j = 0; j < 3; ++j) f[j] = 0.f;
 #pragma unroll
-  for (int h = 1; h < KZH; ++h) {
+  for (int u = 0; u < NHH; ++u) {
+    const int h = half * NHH + u;
     const float2 t = tz[z * KZH + h];
+    const float sc = h == 0 ? 1.f : 2.f;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      f[j] = fmaf(2.f * F[j][h].x, t.x, f[j]);
-      f[j] = fmaf(-2.f * F[j][h].y, t.y, f[j]);
+      f[j] = fmaf(sc * F[j][u].x, t.x, f[j]);
+      f[j] = fmaf(-sc * F[j][u].y, t.y, f[j]);
     }
   }
+#pragma unroll
+  for (int j = 0; j < 3; ++j) f[j] += __shfl_xor(f[j], 32);
 }
 
 // Forward stage, block (column chunk, component i): f_(i,j)(z) = iota_z(F2[i dim + j]);
 // out(z) = sum_j f_(i,j)(z) V_j(z) (+ sum_j DUGr_(i,j)(z) DVP_j(z) for products); the state
-// pass stores DUGw_(i,j)(z) = f_(i,j)(z); G[i][h] = sum_z out(z) conj tz[z][h], the eight waves
-// taking h = w, w + 8, ...
+// pass stores DUGw_(i,j)(z) = f_(i,j)(z); G[i][h] = sum_z out(z) conj tz[z][h], wave w taking
+// h = half KZH / 2 + w.
 template <int NZS, int KZH, bool INC>
 __global__ __launch_bounds__(64 * kColWaves) void k_fx_col_fwd(Geo gp, const float2* __restrict__ F2,
                                                     const float* __restrict__ VP,
@@ -176,17 +188,19 @@ __global__ __launch_bounds__(64 * kColWaves) void k_fx_col_fwd(Geo gp, const flo
   __shared__ float2 tz[kColWaves * NZS * KZH];
   __shared__ float buf[kColWaves * NZS][kColW];
   const int lane = threadIdx.x & 63;
+  const int col = lane & (kColW - 1), half = lane >> 5;
   const int w = wave_uniform(threadIdx.x >> 6);
   const int i = blockIdx.y;
   const int nq = gp.nx * gp.ny;
-  const int q = blockIdx.x * kColW + lane;
+  const int q = blockIdx.x * kColW + col;
   const int qc = q < nq ? q : nq - 1;
   const bool live = q < nq;
   const int pz = gp.nz, kzh = gp.kzh;
   const int64_t MP = gp.M;
-  float2 F[3][KZH];
+  float2 F[3][KZH / 2];
 #pragma unroll
-  for (int j = 0; j < 3; ++j) load_col<KZH>(F2 + (size_t)(3 * i + j) * kzh * nq + qc, (size_t)nq, kzh, F[j]);
+  for (int j = 0; j < 3; ++j)
+    load_half<KZH>(F2 + (size_t)(3 * i + j) * kzh * nq + qc, (size_t)nq, kzh, half, F[j]);
   stage_tz<KZH>(tw_zT, pz, kzh, tz);
   // planes past pz are computed at the clamped plane pz - 1 and not stored: no branch keeps the
   // loads of later planes from being issued early
@@ -204,44 +218,44 @@ __global__ __launch_bounds__(64 * kColWaves) void k_fx_col_fwd(Geo gp, const flo
     const int zc = min(z, pz - 1);
     const int64_t at = (int64_t)zc * nq + qc;
     float f[3];
-    iota_z3<KZH>(F, tz, zc, f);
+    iota_z3<KZH>(F, tz, zc, half, f);
     float o = 0.f;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       o = fmaf(f[j], vp[j][s], o);
       const int64_t ac = (int64_t)(3 * i + j) * MP + at;
       if (INC) o = fmaf(DUGr[ac], DVP[j * MP + at], o);
-      else if (live && z < pz) DUGw[ac] = f[j];
+      else if (live && half == 0 && z < pz) DUGw[ac] = f[j];
     }
-    buf[z][lane] = o;
+    if (half == 0) buf[z][col] = o;
   }
   __syncthreads();
   if (!live) return;
-  // h = w + 8 u: every z value read once for the wave's KZH / 8 outputs
-  constexpr int NH = KZH / kColWaves;
-  float2 a[NH];
-#pragma unroll
-  for (int u = 0; u < NH; ++u) a[u] = make_float2(0.f, 0.f);
+  const int h = half * (KZH / 2) + w;
+  if (w >= KZH / 2 || h >= kzh) return;
+  float2 a = make_float2(0.f, 0.f), b = a;
+  int z = 0;
 #pragma unroll 4
-  for (int z = 0; z < pz; ++z) {
-    const float v = buf[z][lane];
-#pragma unroll
-    for (int u = 0; u < NH; ++u) {
-      const float2 t = tz[z * KZH + w + kColWaves * u];
-      a[u].x = fmaf(v, t.x, a[u].x);
-      a[u].y = fmaf(-v, t.y, a[u].y);
-    }
+  for (; z + 1 < pz; z += 2) {
+    const float v0 = buf[z][col], v1 = buf[z + 1][col];
+    const float2 t0 = tz[z * KZH + h], t1 = tz[(z + 1) * KZH + h];
+    a.x = fmaf(v0, t0.x, a.x);
+    a.y = fmaf(-v0, t0.y, a.y);
+    b.x = fmaf(v1, t1.x, b.x);
+    b.y = fmaf(-v1, t1.y, b.y);
   }
-#pragma unroll
-  for (int u = 0; u < NH; ++u) {
-    const int h = w + kColWaves * u;
-    if (h < kzh) G[((size_t)i * kzh + h) * nq + q] = a[u];
+  if (z < pz) {
+    const float v0 = buf[z][col];
+    const float2 t0 = tz[z * KZH + h];
+    a.x = fmaf(v0, t0.x, a.x);
+    a.y = fmaf(-v0, t0.y, a.y);
   }
+  G[((size_t)i * kzh + h) * nq + q] = make_float2(a.x + b.x, a.y + b.y);
 }
 
 // Backward stage, block (column chunk, component j): kg_i(z) = iota_z(F2[i]) of the cotangent;
 // GACC_j (+)= sum_i DUG_(i,j)(z) kg_i(z); G[i dim + j][h] = sum_z kg_i(z) V_j(z) conj tz[z][h]
-// for i < 3, the (i, h) outputs spread over the eight waves.
+// for i < 3, wave w taking h = half KZH / 2 + w.
 template <int NZS, int KZH, bool UNUSED>
 __global__ __launch_bounds__(64 * kColWaves) void k_fx_col_bwd(Geo gp, const float2* __restrict__ F2,
                                                     const float* __restrict__ VP,
@@ -252,17 +266,19 @@ __global__ __launch_bounds__(64 * kColWaves) void k_fx_col_bwd(Geo gp, const flo
   __shared__ float2 tz[kColWaves * NZS * KZH];
   __shared__ float bk[3][kColWaves * NZS][kColW];   // kg_i(z) V_j(z)
   const int lane = threadIdx.x & 63;
+  const int col = lane & (kColW - 1), half = lane >> 5;
   const int w = wave_uniform(threadIdx.x >> 6);
   const int j = blockIdx.y;
   const int nq = gp.nx * gp.ny;
-  const int q = blockIdx.x * kColW + lane;
+  const int q = blockIdx.x * kColW + col;
   const int qc = q < nq ? q : nq - 1;
   const bool live = q < nq;
   const int pz = gp.nz, kzh = gp.kzh;
   const int64_t MP = gp.M;
-  float2 F[3][KZH];
+  float2 F[3][KZH / 2];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) load_col<KZH>(F2 + (size_t)c * kzh * nq + qc, (size_t)nq, kzh, F[c]);
+  for (int c = 0; c < 3; ++c)
+    load_half<KZH>(F2 + (size_t)c * kzh * nq + qc, (size_t)nq, kzh, half, F[c]);
   stage_tz<KZH>(tw_zT, pz, kzh, tz);
   __syncthreads();
 #pragma unroll
@@ -270,47 +286,37 @@ __global__ __launch_bounds__(64 * kColWaves) void k_fx_col_bwd(Geo gp, const flo
     const int z = w + kColWaves * s;
     const int64_t at = (int64_t)min(z, pz - 1) * nq + qc;
     float kg[3];
-    iota_z3<KZH>(F, tz, min(z, pz - 1), kg);
+    iota_z3<KZH>(F, tz, min(z, pz - 1), half, kg);
     const float g0 = GACC[j * MP + at];
     float a = first ? 0.f : g0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) a = fmaf(DUG[(int64_t)(3 * c + j) * MP + at], kg[c], a);
-    if (live && z < pz) GACC[j * MP + at] = a;
+    if (live && half == 0 && z < pz) GACC[j * MP + at] = a;
     const float vj = VP[j * MP + at];
+    if (half == 0) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) bk[c][z][lane] = kg[c] * vj;
+      for (int c = 0; c < 3; ++c) bk[c][z][col] = kg[c] * vj;
+    }
   }
   __syncthreads();
   if (!live) return;
-  // h = w + 8 u for all three c: every z value and twiddle read once per wave
-  constexpr int NH = KZH / kColWaves;
-  float2 a[3][NH];
+  const int h = half * (KZH / 2) + w;
+  if (w >= KZH / 2 || h >= kzh) return;
+  float2 a[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int u = 0; u < NH; ++u) a[c][u] = make_float2(0.f, 0.f);
-#pragma unroll 2
+  for (int c = 0; c < 3; ++c) a[c] = make_float2(0.f, 0.f);
+#pragma unroll 4
   for (int z = 0; z < pz; ++z) {
-    float v[3];
+    const float2 t = tz[z * KZH + h];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) v[c] = bk[c][z][lane];
-#pragma unroll
-    for (int u = 0; u < NH; ++u) {
-      const float2 t = tz[z * KZH + w + kColWaves * u];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        a[c][u].x = fmaf(v[c], t.x, a[c][u].x);
-        a[c][u].y = fmaf(-v[c], t.y, a[c][u].y);
-      }
+    for (int c = 0; c < 3; ++c) {
+      const float v = bk[c][z][col];
+      a[c].x = fmaf(v, t.x, a[c].x);
+      a[c].y = fmaf(-v, t.y, a[c].y);
     }
   }
 #pragma unroll
-  for (int u = 0; u < NH; ++u) {
-    const int h = w + kColWaves * u;
-    if (h >= kzh) continue;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) G[((size_t)(3 * c + j) * kzh + h) * nq + q] = a[c][u];
-  }
+  for (int c = 0; c < 3; ++c) G[((size_t)(3 * c + j) * kzh + h) * nq + q] = a[c];
 }
 
 // ------------------------------------------------------------------------------ 3. pi yx
@@ -597,7 +603,7 @@ size_t lds_yx(const Geo& g, const Geo& gp) {
 }  // namespace
 
 bool fused_ok(const Geo& g, const Geo& gp) {
-  return g.dim == 3 && gp.nz <= 48 && g.kzh <= 16 && g.ky * kKC <= 4 * 256 &&
+  return g.dim == 3 && gp.nz <= 48 && g.kzh <= 16 && g.kzh >= 2 && g.ky * kKC <= 4 * 256 &&
          lds_xy(g, gp) <= 64 * 1024 && lds_yx(g, gp) <= 64 * 1024;
 }
 
