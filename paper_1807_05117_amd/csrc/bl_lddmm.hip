@@ -128,8 +128,13 @@ namespace host {
 
 size_t plane_bytes(const bl::Geo& g) { return (size_t)g.M * sizeof(float); }
 size_t band_bytes(const bl::Geo& g) { return (size_t)g.B * sizeof(float2); }
+// components of the widest transform: 4, or every node's velocity and divergence at once for a
+// non-stationary velocity
+size_t max_components(const bl::Geo& g) {
+  return std::max<size_t>(4, g.nodes > 1 ? (size_t)g.nodes * (g.dim + 1) : 4);
+}
 size_t stage_elems(const bl::Geo& g) {
-  return (size_t)4 * g.kzh * (size_t)std::max<int64_t>((int64_t)g.ky * g.nx, (int64_t)g.ny * g.nx);
+  return max_components(g) * g.kzh * (size_t)std::max<int64_t>((int64_t)g.ky * g.nx, (int64_t)g.ny * g.nx);
 }
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
@@ -209,12 +214,13 @@ Offsets plan_layout(const bl::Geo& g, bool transport, bool solver, bool mixed) {
     o.m = L.take(pb * (g.nt + 1));
     o.X = L.take(pb * d * steps);
     o.YA = L.take(pb * 4 * steps);
-    o.V = L.take(pb * (d + 1) * (ns ? 2 : 1));   // two time nodes at a time
-    o.DV = L.take(pb * d * (ns ? 2 : 1));
+    // non-stationary: every node's fields at once, so that each transform is one launch
+    o.V = L.take(pb * (d + 1) * g.nodes);
+    o.DV = L.take(pb * d * g.nodes);
     o.T0 = L.take(pb);
     o.T1 = L.take(pb);
     o.L = L.take(pb * (g.nt + 1));
-    o.Bf = L.take(pb * d);
+    o.Bf = L.take(pb * d * g.nodes);
     if (g.newton) {   // dm^n, dlambda^n (Nt + 1 planes each) and the u ping-pong
       o.DM = L.take(pb * (g.nt + 1));
       o.DL = L.take(pb * (g.nt + 1));
@@ -228,7 +234,7 @@ Offsets plan_layout(const bl::Geo& g, bool transport, bool solver, bool mixed) {
   o.bv = L.take(bb * std::max<size_t>(4, (size_t)g.nodes * (d + 1)));
   o.bd = L.take(bb * std::max<size_t>(4, vb));
   o.bout = L.take(bb * std::max<size_t>(4, vb));
-  o.P = L.take((size_t)4 * g.kzh * g.ky * g.kx * sizeof(float2));
+  o.P = L.take(max_components(g) * g.kzh * g.ky * g.kx * sizeof(float2));
   o.Lhat = L.take((size_t)g.B * sizeof(float));
   o.Lhat64 = L.take((size_t)g.B * sizeof(double));
   o.tw_x = L.take((size_t)kxp_of(g) * g.nx * sizeof(float2));
@@ -607,8 +613,8 @@ void choose_launch_shapes(bl_ctx* c) {
 
 // ------------------------------------------------ non-stationary velocity (one field per node)
 // Per node: projection (and divergence) of the band fields with the trapezoid-weighted
-// regulariser; per step t_n -> t_{n+1}: iota of the next node's velocity and divergence (two
-// node slots), the step's offsets from both ends, and the state step.
+// regulariser; iota of every node's velocity and divergence in one launch sequence; per step
+// t_n -> t_{n+1}: the step's offsets from both ends, and the state step.
 void op_set_velocity_ns(bl_ctx* c, const float2* vraw) {
   const bl::Geo& g = c->g;
   hipStream_t s = c->stream;
@@ -621,11 +627,11 @@ void op_set_velocity_ns(bl_ctx* c, const float2* vraw) {
     bl::band_prep(g, vraw + (size_t)n * d * B, c->bv + (size_t)n * (d + 1) * B, 1, c->Lhat64,
                   red_reg, s, w, n > 0);
   }
-  float* slot[2] = {c->V, c->V + (size_t)(d + 1) * M};
-  bl::iota(g, c->plan, c->bv, d + 1, slot[0], s);
+  // (v^n, r^n) of every node in one transform: V[n][c]
+  bl::iota(g, c->plan, c->bv, (g.nt + 1) * (d + 1), c->V, s);
   for (int n = 0; n < g.nt; ++n) {
-    bl::iota(g, c->plan, c->bv + (size_t)(n + 1) * (d + 1) * B, d + 1, slot[(n + 1) & 1], s);
-    bl::setup_ns(g, slot[n & 1], slot[(n + 1) & 1], c->X + (size_t)n * d * M, c->YA + (size_t)n * M, s);
+    bl::setup_ns(g, c->V + (size_t)n * (d + 1) * M, c->V + (size_t)(n + 1) * (d + 1) * M,
+                 c->X + (size_t)n * d * M, c->YA + (size_t)n * M, s);
     if (n == 0 && !c->tuned) choose_launch_shapes(c);
     bl::state_step(g, c->m + n * M, c->X + (size_t)n * d * M, c->m + (n + 1) * M, s);
   }
@@ -651,17 +657,20 @@ void backward_ns(bl_ctx* c) {
     bl::adj_step(g, c->L + (n + 1) * M, c->YA + (size_t)n * M, c->L + n * M, c->stream);
 }
 
-// per node: b^n = L[n] grad m^n, pi, and the band output L^ vproj^n + pi(b^n)
+// per node: b^n = L[n] grad m^n (every node's planes, then one pi), and the band output
+// L^ vproj^n + pi(b^n)
 void per_node_outputs(bl_ctx* c, const float2* vproj, size_t vstride, float2* out) {
   const bl::Geo& g = c->g;
   hipStream_t s = c->stream;
   const size_t M = (size_t)g.M, B = (size_t)g.B;
-  for (int n = 0; n <= g.nt; ++n) {
-    bl::body_node(g, c->L + n * M, c->m + n * M, c->Bf, s);
-    bl::pi_half(g, c->plan, c->Bf, g.dim, c->P, s);
-    bl::band_finalize(g, g.dim, vproj + n * vstride, c->Lhat, c->P, (float)(1.0 / (double)g.M),
-                      out + (size_t)n * g.dim * B, c->flag, s, 1);
-  }
+  const int d = g.dim;
+  for (int n = 0; n <= g.nt; ++n)
+    bl::body_node(g, c->L + n * M, c->m + n * M, c->Bf + (size_t)n * d * M, s);
+  bl::pi_half(g, c->plan, c->Bf, (g.nt + 1) * d, c->P, s);
+  const size_t ph = (size_t)g.kzh * g.ky * g.kx;
+  for (int n = 0; n <= g.nt; ++n)
+    bl::band_finalize(g, d, vproj + n * vstride, c->Lhat, c->P + (size_t)n * d * ph,
+                      (float)(1.0 / (double)g.M), out + (size_t)n * d * B, c->flag, s, 1);
 }
 
 void op_gradient_ns(bl_ctx* c, float2* gout) {
@@ -681,19 +690,18 @@ void op_hessvec_ns(bl_ctx* c, const float2* draw, float2* hout) {
   const int d = g.dim;
   for (int n = 0; n <= g.nt; ++n)
     bl::band_prep(g, draw + (size_t)n * d * B, c->bd + (size_t)n * d * B, 0, nullptr, nullptr, s);
-  float* dv[2] = {c->DV, c->DV + (size_t)d * M};
-  bl::iota(g, c->plan, c->bd, d, dv[0], s);
-  bl::inc_init(g, c->m, dv[0], c->T0, s);
+  // every node's dv^n in one transform: DV[n][c]
+  bl::iota(g, c->plan, c->bd, (g.nt + 1) * d, c->DV, s);
+  bl::inc_init(g, c->m, c->DV, c->T0, s);
   float* tin = c->T0;
   float* tout = c->T1;
   for (int n = 0; n + 1 < g.nt; ++n) {
-    bl::iota(g, c->plan, c->bd + (size_t)(n + 1) * d * B, d, dv[(n + 1) & 1], s);
-    bl::inc_step(g, tin, c->X + (size_t)n * d * M, c->m + (n + 1) * M, dv[(n + 1) & 1], tout, s);
+    bl::inc_step(g, tin, c->X + (size_t)n * d * M, c->m + (n + 1) * M,
+                 c->DV + (size_t)(n + 1) * d * M, tout, s);
     std::swap(tin, tout);
   }
-  bl::iota(g, c->plan, c->bd + (size_t)g.nt * d * B, d, dv[g.nt & 1], s);
-  bl::inc_last(g, tin, c->X + (size_t)(g.nt - 1) * d * M, c->m + g.nt * M, dv[g.nt & 1],
-               c->L + g.nt * M, s);
+  bl::inc_last(g, tin, c->X + (size_t)(g.nt - 1) * d * M, c->m + g.nt * M,
+               c->DV + (size_t)g.nt * d * M, c->L + g.nt * M, s);
   backward_ns(c);
   c->have_lambda = false;   // L holds the incremental adjoint now
   per_node_outputs(c, c->bd, (size_t)d * B, hout);
