@@ -61,12 +61,12 @@ struct bl_ctx {
   float* m = nullptr;      // (nt + 1) planes, m[0] = I0
   float* X = nullptr;      // dim planes: forward departure offsets
   float4* YA = nullptr;    // (Y, a): backward offsets and adjoint reaction factor
-  float* V = nullptr;      // dim + 1 planes: v, r
-  float* DV = nullptr;     // dim planes: dv
+  float* V = nullptr;      // dim + 1 planes: v, r (per time node when non-stationary)
+  float* DV = nullptr;     // dim planes: dv (per time node when non-stationary)
   float* T0 = nullptr;
   float* T1 = nullptr;
   float* L = nullptr;      // (nt + 1) planes: adjoint or incremental adjoint
-  float* Bf = nullptr;     // dim planes: body force
+  float* Bf = nullptr;     // dim planes: body force (per time node when non-stationary)
   // full Newton products only
   float* DM = nullptr;     // (nt + 1) planes: dm^n (dm^0 = 0)
   float* DL = nullptr;     // (nt + 1) planes: dlambda^n
@@ -100,7 +100,7 @@ struct bl_ctx {
   float2* bv = nullptr;    // dim + 1: projected v, divergence
   float2* bd = nullptr;    // dim: projected dv
   float2* bout = nullptr;  // dim
-  float2* P = nullptr;     // up to 4 * kzh * ky * kx
+  float2* P = nullptr;     // C_max * kzh * ky * kx half spectra
   float* Lhat = nullptr;
   double* Lhat64 = nullptr;
   bl::DftPlan plan;

@@ -52,7 +52,8 @@ struct DftPlan {
   float2* tw_yT = nullptr;  // [nyp][kyp]  the same, transposed
   float2* tw_zT = nullptr;  // [nzp][kZP]  exp(+2 pi i h z / nz), h = 0..kzh-1; zero outside
   int kxp = 0, nxp = 0, kyp = 0, nyp = 0, nzp = 0;
-  float2* bufA = nullptr;   // stage buffers, each 4 * kzh * max(ky*nx, ny*nx) complex
+  float2* bufA = nullptr;   // stage buffers, each C_max * kzh * max(ky*nx, ny*nx) complex, C_max
+                            // the widest transform (4, or every node of a non-stationary field)
   float2* bufB = nullptr;
   // split hi/lo BF16 twiddle matrices of the mixed-precision z stages (FP32 mode: unused)
   unsigned short* wi_bf16 = nullptr;   // [2][nzp32][mixed_kp]    iota: (hi, lo)

@@ -63,6 +63,40 @@ def test_results_identical_alone_and_in_mix(gpu_lib, pairs):
     srv.close()
 
 
+# every model variant of the library in one serving mix: (grid, band, nt, make_problem options)
+VARIANTS = [((32, 32, 32), (8, 8, 8), 5, dict(deformation=True)),
+            ((40, 48, 40), (10, 12, 10), 4, dict(nonstationary=True)),
+            ((32, 32, 32), (8, 8, 8), 5, dict(newton=True)),
+            ((40, 48, 40), (10, 12, 10), 4, dict(gamma=1, s=1, alpha=5e-3)),
+            ((32, 32, 32), (8, 8, 8), 5, dict(deformation=True, precision=B.BL_MIXED)),
+            ((24, 24, 24), (8, 8, 8), 6, dict())]
+
+
+def test_model_variants_identical_alone_and_in_mix(gpu_lib):
+    """deformation, non-stationary, Newton, incompressible and plain problems served together:
+    each result is bitwise the one bl_lddmm_register gives alone"""
+    opts = B.opts_struct(max_gn=3, max_pcg=4)
+    probs, data, alone = [], [], []
+    for i, (g, k, nt, kw) in enumerate(VARIANTS):
+        p = B.make_problem(3, g, k, nt, **kw)
+        I0, I1 = make_pair(g, k, nt, 10 + i)
+        v0 = np.zeros(B.band_shape(p), np.complex64)
+        probs.append(p)
+        data.append((I0, I1))
+        alone.append(B.bl_lddmm_register(p, I0, I1, v0, opts))
+    srv = B.Server(max_slots=3)
+    tickets = [srv.submit(p, I0, I1, opts=opts) for p, (I0, I1) in zip(probs, data)]
+    for i, t in enumerate(tickets):
+        rc, v, w, st, times = srv.wait(t)
+        assert rc == B.BL_OK, i
+        va, wa, sa = alone[i]
+        assert np.array_equal(v, va), VARIANTS[i]
+        assert np.array_equal(w, wa), VARIANTS[i]
+        assert st["pcg_iters"] == sa["pcg_iters"] and st["E"] == sa["E"], VARIANTS[i]
+    assert srv.info()["completed"] == len(VARIANTS)
+    srv.close()
+
+
 def test_budget_limits_resident_pairs(gpu_lib, pairs):
     p0 = _problem(0)
     fp = B.bl_lddmm_footprint(p0)
