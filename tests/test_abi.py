@@ -54,6 +54,9 @@ BAD = [
     (dict(gamma=2), B.BL_E_INVALID),
     (dict(gamma=-1), B.BL_E_INVALID),
     (dict(precision=7), B.BL_E_UNSUPPORTED),
+    (dict(deformation=True, newton=True), B.BL_E_UNSUPPORTED),
+    (dict(deformation=True, nonstationary=True), B.BL_E_UNSUPPORTED),
+    (dict(newton=True, nonstationary=True), B.BL_E_UNSUPPORTED),
 ]
 
 
@@ -116,6 +119,24 @@ def test_footprint_scales_with_problem(lib):
     # (nt + 1) state and adjoint planes, offsets, reaction, velocity, ping-pong, body force
     M = 128 ** 3
     assert c2 >= (11 + 11 + 3 + 4 + 4 + 3 + 2 + 3 + 1) * 4 * M
+
+
+def test_unknown_flag_bits_rejected(lib):
+    p = _p()
+    p.flags = 16
+    assert lib.bl_lddmm_footprint(C.byref(p)) == 0
+    assert "flag" in lib.bl_lddmm_last_error().decode()
+
+
+def test_deformation_footprint(lib):
+    """the deformation state equation keeps two image planes of m, the interpolation table and
+    (grad I0) o phi(1), and per Runge-Kutta stage nine product-grid planes of derivatives"""
+    state = lib.bl_lddmm_footprint(C.byref(B.make_problem(3, (128,) * 3, (32,) * 3, 10)))
+    deform = lib.bl_lddmm_footprint(C.byref(B.make_problem(3, (128,) * 3, (32,) * 3, 10,
+                                                           deformation=True)))
+    M, MP = 128 ** 3, 48 ** 3
+    assert deform >= (2 + 1 + 4 + 4 + 3 + 3) * 4 * M + 9 * 4 * 10 * 4 * MP
+    assert 0 < deform < state
 
 
 def test_default_opts(lib):
