@@ -352,13 +352,41 @@ __device__ __forceinline__ void yx_twiddles(const Geo& g, const Geo& gp,
 // R[jy][kl] = sum_y sum_x G[y][x] conj Tx[jx][x] conj Ty[jy][y] for the block's kx chunk, the
 // G plane (c, h) staged in LDS; R for (jy, jx = k0 + kl) lands in L.Rs.  Starts and ends with a
 // block barrier.
+__device__ __forceinline__ void pi_yx_passes(const Geo& g, const Geo& gp, const YxLds& L);
+
 __device__ __forceinline__ void pi_yx_plane(const Geo& g, const Geo& gp,
                                             const float2* __restrict__ Gp, const YxLds& L) {
-  const int KY = g.ky, PX = gp.nx, PY = gp.ny, SP = PX + 1;
+  const int PX = gp.nx, PY = gp.ny, SP = PX + 1;
   for (int o = threadIdx.x; o < PY * PX; o += 256) {
     const int y = o / PX;
     L.Pl[y * SP + (o - y * PX)] = Gp[o];
   }
+  pi_yx_passes(g, gp, L);
+}
+
+// a G plane held in registers, kPlaneRegs entries per thread (entry o = threadIdx.x + 256 u)
+constexpr int kPlaneRegs = 24;
+__device__ __forceinline__ void plane_to_regs(const float2* __restrict__ Gp, int n, float2* R) {
+#pragma unroll
+  for (int u = 0; u < kPlaneRegs; ++u) {
+    const int o = threadIdx.x + 256 * u;
+    R[u] = o < n ? Gp[o] : make_float2(0.f, 0.f);
+  }
+}
+__device__ __forceinline__ void regs_to_lds(const float2* R, int PX, int n, float2* Pl) {
+#pragma unroll
+  for (int u = 0; u < kPlaneRegs; ++u) {
+    const int o = threadIdx.x + 256 * u;
+    if (o < n) {
+      const int y = o / PX;
+      Pl[y * (PX + 1) + (o - y * PX)] = R[u];
+    }
+  }
+}
+
+// the x and y contractions of the plane staged in L.Pl (a block barrier first and last)
+__device__ __forceinline__ void pi_yx_passes(const Geo& g, const Geo& gp, const YxLds& L) {
+  const int KY = g.ky, PX = gp.nx, PY = gp.ny, SP = PX + 1;
   __syncthreads();
   for (int o = threadIdx.x; o < PY * kKC; o += 256) {
     const int y = o / kKC, kl = o - y * kKC;
@@ -547,12 +575,18 @@ __global__ __launch_bounds__(256) void k_fx_pi_yx_adj(Geo g, Geo gp, const float
   const int k0 = blockIdx.y * kKC;
   const int jz = g.kz0 + h;
   yx_twiddles(g, gp, tw_xT, tw_yT, kyp, k0, L);
-  // A for the thread's outputs, accumulated over j (at most 256 * 4 outputs per thread pass)
+  // A for the thread's outputs, accumulated over j (at most 256 * 4 outputs per thread pass);
+  // the next plane's loads are in flight while the current plane is contracted
   float2 A[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) A[u] = make_float2(0.f, 0.f);
+  const int np = PY * PX;
+  float2 R[kPlaneRegs];
+  plane_to_regs(G + ((size_t)(3 * i) * g.kzh + h) * np, np, R);
   for (int j = 0; j < 3; ++j) {
-    pi_yx_plane(g, gp, G + ((size_t)(3 * i + j) * g.kzh + h) * PY * PX, L);
+    regs_to_lds(R, PX, np, L.Pl);
+    if (j < 2) plane_to_regs(G + ((size_t)(3 * i + j + 1) * g.kzh + h) * np, np, R);
+    pi_yx_passes(g, gp, L);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int o = threadIdx.x + 256 * u;
@@ -604,6 +638,7 @@ size_t lds_yx(const Geo& g, const Geo& gp) {
 
 bool fused_ok(const Geo& g, const Geo& gp) {
   return g.dim == 3 && gp.nz <= 48 && g.kzh <= 16 && g.kzh >= 2 && g.ky * kKC <= 4 * 256 &&
+         gp.nx * gp.ny <= 256 * kPlaneRegs &&
          lds_xy(g, gp) <= 64 * 1024 && lds_yx(g, gp) <= 64 * 1024;
 }
 
