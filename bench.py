@@ -51,29 +51,37 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else None
 
 
-def make_inputs(seed=0, **model):
-    I0 = phantoms.shells_3d(seed, GRID, n_classes=3).astype(np.float32)
-    raw = phantoms.raw_band_velocity(seed, 3, BAND).astype(np.complex64)
-    p = B.make_problem(3, GRID, BAND, NT, **model)
+# the large single instance: 256^3, six tissue classes, 8 voxels, band 64^3, Nt = 20
+LARGE = dict(grid=(256, 256, 256), band=(64, 64, 64), nt=20, disp=8.0, ncls=6)
+
+
+def make_inputs(seed=0, grid=None, band=None, nt=None, disp=None, ncls=3, **model):
+    grid, band = grid or GRID, band or BAND
+    nt, disp = nt or NT, disp or DISP
+    I0 = phantoms.shells_3d(seed, grid, n_classes=ncls).astype(np.float32)
+    raw = phantoms.raw_band_velocity(seed, 3, band).astype(np.complex64)
+    p = B.make_problem(3, grid, band, nt, **model)
     v = B.bl_band_to_grid(p, raw)                       # projected inside the library
-    vmax = float(np.sqrt((v.astype(np.float64) ** 2).sum(axis=0)).max()) * max(GRID)
-    vs = (raw * (DISP / vmax)).astype(np.complex64)
+    vmax = float(np.sqrt((v.astype(np.float64) ** 2).sum(axis=0)).max()) * max(grid)
+    vs = (raw * (disp / vmax)).astype(np.complex64)
     I1 = B.bl_lddmm_warp(p, I0, vs)
     return I0, I1, vs
 
 
 def gpu_leg(steps, warmup, n_hv=200, n_lat=50, n_grad=20, precision=B.BL_FP32, inputs=None,
-            model=None):
+            model=None, size=None):
     import torch
 
     model = model or {}
-    p = B.make_problem(3, GRID, BAND, NT, precision=precision, **model)
-    I0, I1, vs = inputs if inputs is not None else make_inputs(0, **model)
+    size = size or {}
+    grid, band, nt = size.get("grid", GRID), size.get("band", BAND), size.get("nt", NT)
+    p = B.make_problem(3, grid, band, nt, precision=precision, **model)
+    I0, I1, vs = inputs if inputs is not None else make_inputs(0, **size, **model)
     v0 = np.zeros_like(vs)
     # registrations on resident device inputs, the library's calls ordered on torch's stream;
     # every registration starts from its own zero initial guess allocated beforehand
     stream = torch.cuda.current_stream()
-    pr = B.make_problem(3, GRID, BAND, NT, device=True, stream=stream.cuda_stream,
+    pr = B.make_problem(3, grid, band, nt, device=True, stream=stream.cuda_stream,
                         precision=precision, **model)
     rI0 = torch.from_numpy(I0).cuda()
     rI1 = torch.from_numpy(I1).cuda()
@@ -106,7 +114,7 @@ def gpu_leg(steps, warmup, n_hv=200, n_lat=50, n_grad=20, precision=B.BL_FP32, i
     # Hessian-vector products at a cached mid-optimisation state, device pointers on the
     # library's own context stream = torch's current stream
     stream = torch.cuda.current_stream()
-    pd = B.make_problem(3, GRID, BAND, NT, device=True, stream=stream.cuda_stream,
+    pd = B.make_problem(3, grid, band, nt, device=True, stream=stream.cuda_stream,
                         precision=precision, **model)
     dI0 = torch.from_numpy(I0).cuda()
     dI1 = torch.from_numpy(I1).cuda()
@@ -154,7 +162,7 @@ def gpu_leg(steps, warmup, n_hv=200, n_lat=50, n_grad=20, precision=B.BL_FP32, i
         kern[k] = (n, ms)
     ctx.bl_kernel_timing_enable(False)
     ctx.close()
-    if precision != B.BL_FP32 or model:
+    if precision != B.BL_FP32 or model or size:
         return dict(elapsed=elapsed, lat=lat, stats=stats, hv_s=hv_s, hv_lat=hv_lat,
                     grad_s=grad_s, kern=kern, E=E, inputs=(I0, I1, vs), warped=warped,
                     t_host=t_host)
@@ -316,6 +324,38 @@ def traffic_record(kernel):
     return rec["kernels"][kernel]["bytes_per_launch"]
 
 
+def large_main(steps, warmup, reps):
+    """256^3 single instance (band 64^3, Nt = 20): plain FP32 and the mixed form on the same
+    pair, registrations/min, Hv/s, final mismatch, and the transports' HBM GB/s from HIP-event
+    timing.  Printed as one JSON line; not the default benchmark."""
+    size = dict(LARGE)
+    ncls = size.pop("ncls")
+    progress("large instance: inputs")
+    inputs = make_inputs(0, ncls=ncls, **size)
+    M = int(np.prod(size["grid"]))
+    out = {"metric": "registrations/min and GN Hv/s at 256^3, plain FP32 vs mixed form",
+           "workload": "256^3 6-class shell phantom, 8 vox, band 64^3, Nt = 20, 10 GN x <= 10 PCG",
+           "data": "synthetic", "n_gpus": 1}
+    for name, prec in (("fp32", B.BL_FP32), ("mixed", B.BL_MIXED)):
+        progress(f"large instance: {name}")
+        r = gpu_leg(steps, warmup, *reps, precision=prec, inputs=inputs, size=size)
+        kern = {}
+        for k, (n, ms) in r["kern"].items():
+            cname, bpv = KCLASS[k]
+            avg = ms / 1000.0 / max(n, 1)
+            kern[cname] = {"avg_us": avg * 1e6, "gbs_algorithmic": bpv * M / avg / 1e9 if n else None,
+                           "frac_of_peak": bpv * M / avg / 1e9 / HBM_PEAK_GBS if n else None}
+        out[name] = {"registrations_per_min": 60000.0 / (1000.0 * r["elapsed"] / steps),
+                     "hv_per_s": r["hv_s"], "hv_p50_ms": percentile(r["hv_lat"], 50),
+                     "gradients_per_s": r["grad_s"], "gn_iters": r["stats"]["gn_iters"],
+                     "hessvecs": r["stats"]["hessvecs"],
+                     "final_mse_rel": r["stats"]["mse_rel"][-1], "kernels": kern,
+                     "warped": r["warped"]}
+    wf, wm = out["fp32"].pop("warped"), out["mixed"].pop("warped")
+    out["warped_max_abs_diff_mixed_vs_fp32"] = float(np.abs(wf - wm).max())
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -325,6 +365,8 @@ def main():
     ap.add_argument("--quick", action="store_true",
                     help="fewer Hessian-vector repetitions (for profiler passes)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--large", action="store_true",
+                    help="the 256^3 single instance instead (plain FP32 vs mixed form)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the registration path has no multi-GPU mode "
@@ -335,6 +377,9 @@ def main():
     if not B.device_available():
         raise RuntimeError("no HIP device visible")
     reps = (20, 5, 2) if args.quick else (200, 50, 20)
+    if args.large:
+        large_main(args.steps, args.warmup, (20, 5, 3) if args.quick else (50, 20, 5))
+        return
     r = gpu_leg(args.steps, args.warmup, *reps)
     progress("mixed-precision form")
     rm = gpu_leg(max(1, args.steps // 2), 1, *reps, precision=B.BL_MIXED, inputs=r["inputs"])
