@@ -182,6 +182,9 @@ def gpu_leg(steps, warmup, n_hv=200, n_lat=50, n_grad=20, precision=B.BL_FP32, i
     e1.synchronize()
     copy_gbs = 10 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) / 1000.0) / 1e9
     # an in-place read-modify-write of the same 1 GiB reaches more than a copy on this chip
+    for _ in range(3):
+        dst.add_(1.0)
+    torch.cuda.synchronize()
     e0.record()
     for _ in range(10):
         dst.add_(1.0)
