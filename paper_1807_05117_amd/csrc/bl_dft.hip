@@ -376,10 +376,13 @@ __global__ __launch_bounds__(256) void k_band_prep(Geo g, const float2* __restri
                                                    float2* __restrict__ out, int with_div,
                                                    const double* __restrict__ Lhat64,
                                                    double* __restrict__ reg_partial,
-                                                   double reg_weight, int reg_accumulate) {
+                                                   double reg_weight, int reg_accumulate,
+                                                   size_t nstride) {
   __shared__ double sh[256];
   double acc = 0.0;
   const int B = (int)g.B;
+  raw += blockIdx.y * nstride;   // node blockIdx.y (nodes > 1 only without the regulariser sum)
+  out += blockIdx.y * nstride;
   for (int b = blockIdx.x * 256 + threadIdx.x; b < B; b += gridDim.x * 256) {
     int jx, jy, jz;
     band_index(g, b, jx, jy, jz);
@@ -439,8 +442,13 @@ __global__ __launch_bounds__(256) void k_band_finalize(Geo g,
                                                        const float* __restrict__ Lhat,
                                                        const float2* __restrict__ P,
                                                        float scale, float2* __restrict__ out,
-                                                       int* __restrict__ nonfinite, int leray_on) {
+                                                       int* __restrict__ nonfinite, int leray_on,
+                                                       size_t vstride, size_t pstride,
+                                                       size_t ostride) {
   const int B = (int)g.B;
+  if (vproj) vproj += blockIdx.y * vstride;   // node blockIdx.y
+  P += blockIdx.y * pstride;
+  out += blockIdx.y * ostride;
   for (int b = blockIdx.x * 256 + threadIdx.x; b < B; b += gridDim.x * 256) {
     int jx, jy, jz;
     band_index(g, b, jx, jy, jz);
@@ -562,23 +570,41 @@ void band_prep(const Geo& g, const float2* raw, float2* out, int with_div, const
   const int blocks = reg_partial ? kRedBlocks : (int)((g.B + 255) / 256);
   if (g.dim == 3)
     hipLaunchKernelGGL(k_band_prep<3>, dim3(blocks), dim3(256), 0, s, g, raw, out, with_div,
-                       Lhat64, reg_partial, reg_weight, reg_accumulate);
+                       Lhat64, reg_partial, reg_weight, reg_accumulate, (size_t)0);
   else if (g.dim == 2)
     hipLaunchKernelGGL(k_band_prep<2>, dim3(blocks), dim3(256), 0, s, g, raw, out, with_div,
-                       Lhat64, reg_partial, reg_weight, reg_accumulate);
+                       Lhat64, reg_partial, reg_weight, reg_accumulate, (size_t)0);
   else
     hipLaunchKernelGGL(k_band_prep<1>, dim3(blocks), dim3(256), 0, s, g, raw, out, with_div,
-                       Lhat64, reg_partial, reg_weight, reg_accumulate);
+                       Lhat64, reg_partial, reg_weight, reg_accumulate, (size_t)0);
+}
+
+void band_prep_nodes(const Geo& g, const float2* raw, float2* out, int nodes, size_t stride,
+                     hipStream_t s) {
+  const dim3 grid((unsigned)((g.B + 255) / 256), (unsigned)nodes);
+  if (g.dim == 3)
+    hipLaunchKernelGGL(k_band_prep<3>, grid, dim3(256), 0, s, g, raw, out, 0, nullptr, nullptr,
+                       1.0, 0, stride);
+  else
+    hipLaunchKernelGGL(k_band_prep<2>, grid, dim3(256), 0, s, g, raw, out, 0, nullptr, nullptr,
+                       1.0, 0, stride);
 }
 
 void band_finalize(const Geo& g, int C, const float2* vproj, const float* Lhat,
                    const float2* P, float scale, float2* out, int* nonfinite, hipStream_t s,
                    int leray) {
-  const int blocks = std::min(4096, (int)((g.B + 255) / 256));
+  band_finalize_nodes(g, C, vproj, 0, Lhat, P, 0, scale, out, 0, 1, nonfinite, s, leray);
+}
+
+void band_finalize_nodes(const Geo& g, int C, const float2* vproj, size_t vstride,
+                         const float* Lhat, const float2* P, size_t pstride, float scale,
+                         float2* out, size_t ostride, int nodes, int* nonfinite, hipStream_t s,
+                         int leray) {
+  const dim3 blocks((unsigned)std::min(4096, (int)((g.B + 255) / 256)), (unsigned)nodes);
   const int on = (leray && g.gamma && C == g.dim) ? 1 : 0;
 #define BF_LAUNCH(D, CC)                                                                        \
-  hipLaunchKernelGGL((k_band_finalize<D, CC>), dim3(blocks), dim3(256), 0, s, g, vproj, Lhat, P, \
-                     scale, out, nonfinite, on)
+  hipLaunchKernelGGL((k_band_finalize<D, CC>), blocks, dim3(256), 0, s, g, vproj, Lhat, P,      \
+                     scale, out, nonfinite, on, vstride, pstride, ostride)
   if (g.dim == 3) {
     switch (C) {
       case 1: BF_LAUNCH(3, 1); break;

@@ -86,19 +86,31 @@ void pi_z_mixed(const Geo& g, const DftPlan& p, const float* f, int C, float2* G
 void band_prep(const Geo& g, const float2* raw, float2* out, int with_div, const double* Lhat64,
                double* reg_partial, hipStream_t s, double reg_weight = 1.0,
                int reg_accumulate = 0);
+// the plain projection (no divergence, no regulariser sum) of `nodes` band vectors spaced
+// `stride` complex entries apart, in one launch
+void band_prep_nodes(const Geo& g, const float2* raw, float2* out, int nodes, size_t stride,
+                     hipStream_t s);
 // out[c][k] = Lhat(k) vproj[c][k] + scale * P (Hermitian-completed), zero on unpaired planes;
 // leray (C == dim): then projected divergence-free per index k.
 void band_finalize(const Geo& g, int C, const float2* vproj, const float* Lhat,
                    const float2* P, float scale, float2* out, int* nonfinite, hipStream_t s,
                    int leray = 0);
+// band_finalize of `nodes` vectors in one launch: node n reads vproj + n vstride and
+// P + n pstride and writes out + n ostride
+void band_finalize_nodes(const Geo& g, int C, const float2* vproj, size_t vstride,
+                         const float* Lhat, const float2* P, size_t pstride, float scale,
+                         float2* out, size_t ostride, int nodes, int* nonfinite, hipStream_t s,
+                         int leray = 0);
 
 // ---- transports (bl_transport.hip)
 // X: dim planes of forward offsets; YA = (Y, a) backward offsets and reaction factor
 void setup(const Geo& g, const float* v, float* X, float4* YA, hipStream_t s);
 // non-stationary step t_n -> t_{n+1}: v0 = (v^n, r^n), v1 = (v^{n+1}, r^{n+1}) (dim + 1 planes)
 void setup_ns(const Geo& g, const float* v0, const float* v1, float* X, float4* YA, hipStream_t s);
-// b = lambda grad m at one time node (dim planes)
-void body_node(const Geo& g, const float* lam, const float* m, float* b, hipStream_t s);
+// b^n = lambda^n grad m^n for the time nodes n < nodes (lam, m: one plane per node; b: dim
+// planes per node), one launch
+void body_nodes(const Geo& g, const float* lam, const float* m, float* b, int nodes,
+                hipStream_t s);
 void state_step(const Geo& g, const float* m_in, const float* X, float* m_out, hipStream_t s);
 void energy_partial(const Geo& g, const float* mT, const float* I1, double* partial,
                     hipStream_t s);

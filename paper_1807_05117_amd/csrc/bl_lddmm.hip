@@ -664,13 +664,11 @@ void per_node_outputs(bl_ctx* c, const float2* vproj, size_t vstride, float2* ou
   hipStream_t s = c->stream;
   const size_t M = (size_t)g.M, B = (size_t)g.B;
   const int d = g.dim;
-  for (int n = 0; n <= g.nt; ++n)
-    bl::body_node(g, c->L + n * M, c->m + n * M, c->Bf + (size_t)n * d * M, s);
+  bl::body_nodes(g, c->L, c->m, c->Bf, g.nt + 1, s);
   bl::pi_half(g, c->plan, c->Bf, (g.nt + 1) * d, c->P, s);
   const size_t ph = (size_t)g.kzh * g.ky * g.kx;
-  for (int n = 0; n <= g.nt; ++n)
-    bl::band_finalize(g, d, vproj + n * vstride, c->Lhat, c->P + (size_t)n * d * ph,
-                      (float)(1.0 / (double)g.M), out + (size_t)n * d * B, c->flag, s, 1);
+  bl::band_finalize_nodes(g, d, vproj, vstride, c->Lhat, c->P, (size_t)d * ph,
+                          (float)(1.0 / (double)g.M), out, (size_t)d * B, g.nt + 1, c->flag, s, 1);
 }
 
 void op_gradient_ns(bl_ctx* c, float2* gout) {
@@ -688,8 +686,7 @@ void op_hessvec_ns(bl_ctx* c, const float2* draw, float2* hout) {
   hipStream_t s = c->stream;
   const size_t M = (size_t)g.M, B = (size_t)g.B;
   const int d = g.dim;
-  for (int n = 0; n <= g.nt; ++n)
-    bl::band_prep(g, draw + (size_t)n * d * B, c->bd + (size_t)n * d * B, 0, nullptr, nullptr, s);
+  bl::band_prep_nodes(g, draw, c->bd, g.nt + 1, (size_t)d * B, s);
   // every node's dv^n in one transform: DV[n][c]
   bl::iota(g, c->plan, c->bd, (g.nt + 1) * d, c->DV, s);
   bl::inc_init(g, c->m, c->DV, c->T0, s);

@@ -539,14 +539,17 @@ __global__ __launch_bounds__(BX* GBY) void k_body_force_n(Geo g, const float* __
   }
 }
 
-// b = lambda grad m at one time node (a non-stationary gradient or product has one body force
-// per node, not a time integral)
+// b^n = lambda^n grad m^n at the time node n = blockIdx.y (a non-stationary gradient or
+// product has one body force per node, not a time integral); all nodes in one launch
 template <int DIM, int ZV>
 __global__ __launch_bounds__(BX* GBY) void k_body_node(Geo g, const float* __restrict__ lam,
                                                        const float* __restrict__ m,
                                                        float* __restrict__ b) {
   GATHER_XY
   const size_t M = (size_t)g.M;
+  lam += blockIdx.y * M;
+  m += blockIdx.y * M;
+  b += blockIdx.y * (size_t)DIM * M;
   float acc[ZV][3];
 #pragma unroll
   for (int zz = 0; zz < ZV; ++zz) {
@@ -603,23 +606,26 @@ inline dim3 gather_grid(const Geo& g, int zv) {
 }
 }  // namespace
 
-// 3D launches take the class's voxels per thread along z (1, 2, 4 or 8); 2D runs one per thread
-#define DISPATCH_GATHER(KERNEL, CLS, ...)                                                       \
+// 3D launches take the class's voxels per thread along z (1, 2, 4 or 8); 2D runs one per thread.
+// NY > 1 repeats the grid over blockIdx.y (one copy per time node).
+#define GRID_N(ZV_, NY) dim3(gather_grid(g, ZV_).x, (NY))
+#define DISPATCH_GATHER_N(KERNEL, CLS, NY, ...)                                                 \
   do {                                                                                          \
     if (g.dim == 3) {                                                                           \
       const int zv_ = g.zv[CLS];                                                                \
       if (zv_ == 8)                                                                             \
-        hipLaunchKernelGGL((KERNEL<3, 8>), gather_grid(g, 8), dim3(BX, GBY), 0, s, __VA_ARGS__); \
+        hipLaunchKernelGGL((KERNEL<3, 8>), GRID_N(8, NY), dim3(BX, GBY), 0, s, __VA_ARGS__);    \
       else if (zv_ == 4)                                                                        \
-        hipLaunchKernelGGL((KERNEL<3, 4>), gather_grid(g, 4), dim3(BX, GBY), 0, s, __VA_ARGS__); \
+        hipLaunchKernelGGL((KERNEL<3, 4>), GRID_N(4, NY), dim3(BX, GBY), 0, s, __VA_ARGS__);    \
       else if (zv_ == 2)                                                                        \
-        hipLaunchKernelGGL((KERNEL<3, 2>), gather_grid(g, 2), dim3(BX, GBY), 0, s, __VA_ARGS__); \
+        hipLaunchKernelGGL((KERNEL<3, 2>), GRID_N(2, NY), dim3(BX, GBY), 0, s, __VA_ARGS__);    \
       else                                                                                      \
-        hipLaunchKernelGGL((KERNEL<3, 1>), gather_grid(g, 1), dim3(BX, GBY), 0, s, __VA_ARGS__); \
+        hipLaunchKernelGGL((KERNEL<3, 1>), GRID_N(1, NY), dim3(BX, GBY), 0, s, __VA_ARGS__);    \
     } else {                                                                                    \
-      hipLaunchKernelGGL((KERNEL<2, 1>), gather_grid(g, 1), dim3(BX, GBY), 0, s, __VA_ARGS__);  \
+      hipLaunchKernelGGL((KERNEL<2, 1>), GRID_N(1, NY), dim3(BX, GBY), 0, s, __VA_ARGS__);     \
     }                                                                                           \
   } while (0)
+#define DISPATCH_GATHER(KERNEL, CLS, ...) DISPATCH_GATHER_N(KERNEL, CLS, 1, __VA_ARGS__)
 #define DISPATCH_ONE(KERNEL, ...)                                                          \
   do {                                                                                     \
     if (g.dim == 3)                                                                        \
@@ -633,8 +639,9 @@ void setup(const Geo& g, const float* v, float* X, float4* YA, hipStream_t s) {
 void setup_ns(const Geo& g, const float* v0, const float* v1, float* X, float4* YA, hipStream_t s) {
   DISPATCH_ONE(k_setup_ns, g, v0, v1, X, YA);
 }
-void body_node(const Geo& g, const float* lam, const float* m, float* b, hipStream_t s) {
-  DISPATCH_GATHER(k_body_node, TR_FORCE, g, lam, m, b);
+void body_nodes(const Geo& g, const float* lam, const float* m, float* b, int nodes,
+                hipStream_t s) {
+  DISPATCH_GATHER_N(k_body_node, TR_FORCE, nodes, g, lam, m, b);
 }
 void state_step(const Geo& g, const float* m_in, const float* X, float* m_out, hipStream_t s) {
   DISPATCH_GATHER(k_state_step, TR_STATE, g, m_in, X, m_out);
