@@ -49,6 +49,28 @@ __device__ __forceinline__ float qaxis(const Geo& g, int a, int j) {
   return two_pi * (float)kv * ((float)g.nref / (float)n);
 }
 
+// Staging of tables into LDS with a thread's loads in flight together.  A runtime loop of
+// load-then-store waits for one memory round trip per iteration; here a thread first loads R
+// entries of a table into registers (entries past the end read the clamped last entry), and
+// only then stores them.  Loads of several tables are issued before any of their stores.
+template <int NT, int R>
+struct Stager {
+  float2 v[R];
+  template <class Ld>
+  __device__ __forceinline__ void load(int n, int base, Ld ld) {
+#pragma unroll
+    for (int u = 0; u < R; ++u) v[u] = ld(min(base + (int)threadIdx.x + NT * u, n - 1));
+  }
+  template <class St>
+  __device__ __forceinline__ void store(int n, int base, St st) const {
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int o = base + (int)threadIdx.x + NT * u;
+      if (o < n) st(o, v[u]);
+    }
+  }
+};
+
 // ---------------------------------------------------------------------------- 1. iota xy
 // block (c * kzh + h, x chunk); F2[c][h][y][x] = sum_ky sum_kx S[ky][kx] Tx[kx][x] Ty[ky][y]
 // with S the band plane kz = h of component c (deriv: i q_j U_i for c = i dim + j).  The band
@@ -72,22 +94,33 @@ __global__ __launch_bounds__(256) void k_fx_iota_xy(Geo g, Geo gp, const float2*
   const int ci = deriv ? c / d : c;
   const int cj = deriv ? c - ci * d : 0;
   const float2* plane = in + ((size_t)ci * g.kz + jz) * KY * KX;
-  for (int o = threadIdx.x; o < KY * KX; o += 256) {
-    const int jy = o / KX, jx = o - jy * KX;
-    float2 v = plane[o];
-    if (deriv) {
-      const float q = cj == 0 ? qaxis(g, 0, jx) : (cj == 1 ? qaxis(g, 1, jy) : qaxis(g, 2, jz));
-      v = make_float2(-q * v.y, q * v.x);
-    }
-    S[jy * SX + jx] = v;
-  }
-  for (int o = threadIdx.x; o < KX * kXC; o += 256) {
-    const int jx = o / kXC, xl = o - jx * kXC;
-    Txc[o] = tw_x[(size_t)jx * PX + min(x0 + xl, PX - 1)];
-  }
-  for (int o = threadIdx.x; o < KY * PY; o += 256) {
-    const int jy = o / PY, y = o - jy * PY;
-    Ty[o] = tw_y[(size_t)jy * nyp + y];
+  // the band plane and both twiddle tables, all loads of a round in flight together (one round
+  // up to a 32 x 32 band and 48 y values)
+  const int nS = KY * KX, nX = KX * kXC, nY = KY * PY;
+  const int rounds = max(max((nS + 1023) / 1024, (nX + 511) / 512), (nY + 1535) / 1536);
+  for (int r = 0; r < rounds; ++r) {
+    Stager<256, 4> sS;
+    Stager<256, 2> sX;
+    Stager<256, 6> sY;
+    sS.load(nS, r * 1024, [&](int o) { return plane[o]; });
+    sX.load(nX, r * 512, [&](int o) {
+      const int jx = o / kXC, xl = o - jx * kXC;
+      return tw_x[(size_t)jx * PX + min(x0 + xl, PX - 1)];
+    });
+    sY.load(nY, r * 1536, [&](int o) {
+      const int jy = o / PY, y = o - jy * PY;
+      return tw_y[(size_t)jy * nyp + y];
+    });
+    sS.store(nS, r * 1024, [&](int o, float2 v) {
+      const int jy = o / KX, jx = o - jy * KX;
+      if (deriv) {
+        const float q = cj == 0 ? qaxis(g, 0, jx) : (cj == 1 ? qaxis(g, 1, jy) : qaxis(g, 2, jz));
+        v = make_float2(-q * v.y, q * v.x);
+      }
+      S[jy * SX + jx] = v;
+    });
+    sX.store(nX, r * 512, [&](int o, float2 v) { Txc[o] = v; });
+    sY.store(nY, r * 1536, [&](int o, float2 v) { Ty[o] = v; });
   }
   __syncthreads();
   // x: T[jy][xl] = sum_jx S[jy][jx] Tx[jx][x0 + xl]
@@ -141,14 +174,25 @@ __device__ __forceinline__ void load_half(const float2* __restrict__ Fc, size_t 
   }
 }
 
+// the block's z twiddles tz[z][h] (zero past kzh): pz * KZH <= 48 * 16 entries, two per thread;
+// the loads are issued here and the LDS stores made later by tz_store, so that the caller's
+// other loads are in flight at the same time
 template <int KZH>
-__device__ __forceinline__ void stage_tz(const float2* __restrict__ tw_zT, int pz, int kzh,
-                                         float2* tz) {
-  for (int o = threadIdx.x; o < pz * KZH; o += 64 * kColWaves) {
-    const int z = o / KZH, h = o - z * KZH;
-    tz[o] = h < kzh ? tw_zT[(size_t)z * kZP + h] : make_float2(0.f, 0.f);
+struct TzStage {
+  Stager<64 * kColWaves, 2> st;
+  __device__ __forceinline__ void load(const float2* __restrict__ tw_zT, int pz, int kzh) {
+    st.load(pz * KZH, 0, [&](int o) {
+      const int z = o / KZH, h = o - z * KZH;
+      return tw_zT[(size_t)z * kZP + min(h, kzh - 1)];
+    });
   }
-}
+  __device__ __forceinline__ void store(int pz, int kzh, float2* tz) const {
+    st.store(pz * KZH, 0, [&](int o, float2 v) {
+      const int h = o % KZH;
+      tz[o] = h < kzh ? v : make_float2(0.f, 0.f);
+    });
+  }
+};
 
 // f_j(z) = Re F_j[0] + 2 sum_{h >= 1} Re(F_j[h] tz[z][h]) for three fields at one plane z: each
 // half sums its h range, then the halves exchange partial sums (lane l <-> l ^ 32)
@@ -201,16 +245,25 @@ __global__ __launch_bounds__(64 * kColWaves) void k_fx_col_fwd(Geo gp, const flo
 #pragma unroll
   for (int j = 0; j < 3; ++j)
     load_half<KZH>(F2 + (size_t)(3 * i + j) * kzh * nq + qc, (size_t)nq, kzh, half, F[j]);
-  stage_tz<KZH>(tw_zT, pz, kzh, tz);
+  TzStage<KZH> tzs;
+  tzs.load(tw_zT, pz, kzh);
   // planes past pz are computed at the clamped plane pz - 1 and not stored: no branch keeps the
-  // loads of later planes from being issued early
-  float vp[3][NZS];
+  // loads of later planes from being issued early.  Every load of the block's inputs is issued
+  // before the first LDS store and barrier.
+  float vp[3][NZS], dg[3][NZS], dw[3][NZS];
 #pragma unroll
   for (int s = 0; s < NZS; ++s) {
     const int64_t at = (int64_t)min(w + kColWaves * s, pz - 1) * nq + qc;
 #pragma unroll
-    for (int j = 0; j < 3; ++j) vp[j][s] = VP[j * MP + at];
+    for (int j = 0; j < 3; ++j) {
+      vp[j][s] = VP[j * MP + at];
+      if (INC) {
+        dg[j][s] = DUGr[(int64_t)(3 * i + j) * MP + at];
+        dw[j][s] = DVP[j * MP + at];
+      }
+    }
   }
+  tzs.store(pz, kzh, tz);
   __syncthreads();
 #pragma unroll
   for (int s = 0; s < NZS; ++s) {
@@ -224,7 +277,7 @@ __global__ __launch_bounds__(64 * kColWaves) void k_fx_col_fwd(Geo gp, const flo
     for (int j = 0; j < 3; ++j) {
       o = fmaf(f[j], vp[j][s], o);
       const int64_t ac = (int64_t)(3 * i + j) * MP + at;
-      if (INC) o = fmaf(DUGr[ac], DVP[j * MP + at], o);
+      if (INC) o = fmaf(dg[j][s], dw[j][s], o);
       else if (live && half == 0 && z < pz) DUGw[ac] = f[j];
     }
     if (half == 0) buf[z][col] = o;
@@ -279,7 +332,19 @@ __global__ __launch_bounds__(64 * kColWaves) void k_fx_col_bwd(Geo gp, const flo
 #pragma unroll
   for (int c = 0; c < 3; ++c)
     load_half<KZH>(F2 + (size_t)c * kzh * nq + qc, (size_t)nq, kzh, half, F[c]);
-  stage_tz<KZH>(tw_zT, pz, kzh, tz);
+  TzStage<KZH> tzs;
+  tzs.load(tw_zT, pz, kzh);
+  // the planes' accumulator, state derivatives and velocity, loaded before the barrier
+  float ga[NZS], du[3][NZS], vv[NZS];
+#pragma unroll
+  for (int s = 0; s < NZS; ++s) {
+    const int64_t at = (int64_t)min(w + kColWaves * s, pz - 1) * nq + qc;
+    ga[s] = GACC[j * MP + at];
+    vv[s] = VP[j * MP + at];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) du[c][s] = DUG[(int64_t)(3 * c + j) * MP + at];
+  }
+  tzs.store(pz, kzh, tz);
   __syncthreads();
 #pragma unroll
   for (int s = 0; s < NZS; ++s) {
@@ -287,12 +352,11 @@ __global__ __launch_bounds__(64 * kColWaves) void k_fx_col_bwd(Geo gp, const flo
     const int64_t at = (int64_t)min(z, pz - 1) * nq + qc;
     float kg[3];
     iota_z3<KZH>(F, tz, min(z, pz - 1), half, kg);
-    const float g0 = GACC[j * MP + at];
-    float a = first ? 0.f : g0;
+    float a = first ? 0.f : ga[s];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) a = fmaf(DUG[(int64_t)(3 * c + j) * MP + at], kg[c], a);
+    for (int c = 0; c < 3; ++c) a = fmaf(du[c][s], kg[c], a);
     if (live && half == 0 && z < pz) GACC[j * MP + at] = a;
-    const float vj = VP[j * MP + at];
+    const float vj = vv[s];
     if (half == 0) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) bk[c][z][col] = kg[c] * vj;
@@ -333,19 +397,28 @@ __device__ __forceinline__ YxLds yx_lds(const Geo& g, const Geo& gp, float2* bas
   L.Ty = L.Tx + (size_t)gp.nx * kKC;          // [PY][KY]
   return L;
 }
-// the block's twiddles into LDS (once per block)
+// the block's twiddles into LDS (once per block); one round of loads in flight together up to
+// 64 x values and 48 x 32 (y, ky) pairs
 __device__ __forceinline__ void yx_twiddles(const Geo& g, const Geo& gp,
                                             const float2* __restrict__ tw_xT,
                                             const float2* __restrict__ tw_yT, int kyp, int k0,
                                             const YxLds& L) {
   const int KX = g.kx, KY = g.ky, PX = gp.nx, PY = gp.ny;
-  for (int o = threadIdx.x; o < PX * kKC; o += 256) {
-    const int x = o / kKC, kl = o - x * kKC;
-    L.Tx[o] = tw_xT[(size_t)x * KX + min(k0 + kl, KX - 1)];
-  }
-  for (int o = threadIdx.x; o < PY * KY; o += 256) {
-    const int y = o / KY, jy = o - y * KY;
-    L.Ty[o] = tw_yT[(size_t)y * kyp + jy];
+  const int nX = PX * kKC, nY = PY * KY;
+  const int rounds = max((nX + 255) / 256, (nY + 1535) / 1536);
+  for (int r = 0; r < rounds; ++r) {
+    Stager<256, 1> sx;
+    Stager<256, 6> sy;
+    sx.load(nX, r * 256, [&](int o) {
+      const int x = o / kKC, kl = o - x * kKC;
+      return tw_xT[(size_t)x * KX + min(k0 + kl, KX - 1)];
+    });
+    sy.load(nY, r * 1536, [&](int o) {
+      const int y = o / KY, jy = o - y * KY;
+      return tw_yT[(size_t)y * kyp + jy];
+    });
+    sx.store(nX, r * 256, [&](int o, float2 v) { L.Tx[o] = v; });
+    sy.store(nY, r * 1536, [&](int o, float2 v) { L.Ty[o] = v; });
   }
 }
 
@@ -353,16 +426,6 @@ __device__ __forceinline__ void yx_twiddles(const Geo& g, const Geo& gp,
 // G plane (c, h) staged in LDS; R for (jy, jx = k0 + kl) lands in L.Rs.  Starts and ends with a
 // block barrier.
 __device__ __forceinline__ void pi_yx_passes(const Geo& g, const Geo& gp, const YxLds& L);
-
-__device__ __forceinline__ void pi_yx_plane(const Geo& g, const Geo& gp,
-                                            const float2* __restrict__ Gp, const YxLds& L) {
-  const int PX = gp.nx, PY = gp.ny, SP = PX + 1;
-  for (int o = threadIdx.x; o < PY * PX; o += 256) {
-    const int y = o / PX;
-    L.Pl[y * SP + (o - y * PX)] = Gp[o];
-  }
-  pi_yx_passes(g, gp, L);
-}
 
 // a G plane held in registers, kPlaneRegs entries per thread (entry o = threadIdx.x + 256 u)
 constexpr int kPlaneRegs = 24;
@@ -455,22 +518,33 @@ __device__ __forceinline__ Target target(const Geo& g, int h, int jx, int jy) {
   return t;
 }
 
+// the band values a forward stage update of component i at band index b reads (b < 0: a
+// harmless in-bounds load of entry 0, not used)
+struct StageIn {
+  float2 s, u, p;
+};
+__device__ __forceinline__ StageIn stage_load(const Geo& g, int i, int b,
+                                              const float2* __restrict__ src,
+                                              const float2* __restrict__ un,
+                                              const float2* __restrict__ acc) {
+  const size_t o = (size_t)i * g.B + max(b, 0);
+  return StageIn{src[o], un[o], acc[o]};
+}
+
 // Forward stage update of component i at band index b with conv (unscaled)
 __device__ __forceinline__ void stage_entry(const Geo& g, int i, int b, float2 cv, float scaleP,
-                                            const float2* __restrict__ src,
-                                            const float2* __restrict__ un,
-                                            float2* __restrict__ acc, int st,
+                                            const StageIn& in, float2* __restrict__ acc, int st,
                                             float2* __restrict__ wout) {
   const size_t o = (size_t)i * g.B + b;
   const float h = g.dt;
-  const float2 sv = src[o];
+  const float2 sv = in.s;
   const float2 k = make_float2(-sv.x - scaleP * cv.x, -sv.y - scaleP * cv.y);
-  const float2 u = un[o];
+  const float2 u = in.u;
   float2 a;
   if (st == 1) {
     a = k;
   } else {
-    const float2 p = acc[o];
+    const float2 p = in.p;
     const float f = st == 4 ? 1.f : 2.f;
     a = make_float2(fmaf(f, k.x, p.x), fmaf(f, k.y, p.y));
   }
@@ -491,7 +565,9 @@ __device__ __forceinline__ void stage_zero(const Geo& g, int i, int b, float2* _
   wout[o] = make_float2(0.f, 0.f);
 }
 
-// block (i * kzh + h, kx chunk)
+// block (i * kzh + h, kx chunk); NO = output entries (jy, kl) per thread.  The G plane, the
+// twiddles and the band values of the thread's entries are all loaded before the first barrier.
+template <int NO>
 __global__ __launch_bounds__(256) void k_fx_pi_yx_stage(Geo g, Geo gp, const float2* __restrict__ G,
                                                         const float2* __restrict__ tw_xT,
                                                         const float2* __restrict__ tw_yT, int kyp,
@@ -507,41 +583,70 @@ __global__ __launch_bounds__(256) void k_fx_pi_yx_stage(Geo g, Geo gp, const flo
   const int ih = blockIdx.x;
   const int i = ih / g.kzh, h = ih - i * g.kzh;
   const int k0 = blockIdx.y * kKC;
-  yx_twiddles(g, gp, tw_xT, tw_yT, kyp, k0, L);
-  pi_yx_plane(g, gp, G + (size_t)ih * PY * PX, L);
-  for (int o = threadIdx.x; o < KY * kKC; o += 256) {
+  const int np = PY * PX;
+  float2 R[kPlaneRegs];
+  plane_to_regs(G + (size_t)ih * np, np, R);
+  Target t[NO];
+  StageIn in[NO][2];
+#pragma unroll
+  for (int u = 0; u < NO; ++u) {
+    const int o = threadIdx.x + 256 * u;
     const int jy = o / kKC, kl = o - jy * kKC;
     const int jx = k0 + kl;
-    if (jx >= g.kx) continue;
-    const Target t = target(g, h, jx, jy);
-    if (t.b < 0) continue;
-    if (t.zero) {
-      stage_zero(g, i, t.b, acc, st, wout);
-      if (t.bz >= 0) stage_zero(g, i, t.bz, acc, st, wout);
+    t[u] = target(g, h, min(jx, g.kx - 1), min(jy, KY - 1));
+    if (o >= KY * kKC || jx >= g.kx) t[u].b = -1;   // no entry for this slot
+    in[u][0] = stage_load(g, i, t[u].zero ? -1 : t[u].b, src, un, acc);
+    in[u][1] = stage_load(g, i, t[u].bm, src, un, acc);
+  }
+  yx_twiddles(g, gp, tw_xT, tw_yT, kyp, k0, L);
+  regs_to_lds(R, PX, np, L.Pl);
+  pi_yx_passes(g, gp, L);
+#pragma unroll
+  for (int u = 0; u < NO; ++u) {
+    const int o = threadIdx.x + 256 * u;
+    const Target& tu = t[u];
+    if (tu.b < 0) continue;
+    if (tu.zero) {
+      stage_zero(g, i, tu.b, acc, st, wout);
+      if (tu.bz >= 0) stage_zero(g, i, tu.bz, acc, st, wout);
       continue;
     }
     float2 r = Rs[o];
-    if (t.real) r.y = 0.f;
-    stage_entry(g, i, t.b, r, scaleP, src, un, acc, st, wout);
-    if (t.bm >= 0) stage_entry(g, i, t.bm, make_float2(r.x, -r.y), scaleP, src, un, acc, st, wout);
+    if (tu.real) r.y = 0.f;
+    stage_entry(g, i, tu.b, r, scaleP, in[u][0], acc, st, wout);
+    if (tu.bm >= 0) stage_entry(g, i, tu.bm, make_float2(r.x, -r.y), scaleP, in[u][1], acc, st, wout);
   }
   if (h == 0 && blockIdx.y == 0) {   // the unpaired plane kz = -K/2
     for (int o = threadIdx.x; o < g.ky * g.kx; o += 256) stage_zero(g, i, o, acc, st, wout);
   }
 }
 
+// the band values a transposed-sweep update of component i at band index b reads (b < 0: a
+// harmless in-bounds load of entry 0, not used)
+struct AdjIn {
+  float2 r, p, ks;
+};
+__device__ __forceinline__ AdjIn adj_load(const Geo& g, int i, int b,
+                                          const float2* __restrict__ rho,
+                                          const float2* __restrict__ Asum,
+                                          const float2* __restrict__ Ksum) {
+  const size_t o = (size_t)i * g.B + max(b, 0);
+  return AdjIn{rho[o], Asum[o], Ksum[o]};
+}
+
 // Transposed-sweep update of component i at band index b with A = sum_j i q_j R_j / MP
 __device__ __forceinline__ void adj_entry(const Geo& g, int i, int b, float2 A, int st, int more,
-                                          float2* __restrict__ rho, float2* __restrict__ Asum,
-                                          float2* __restrict__ Ksum, float2* __restrict__ kap) {
+                                          const AdjIn& in, float2* __restrict__ rho,
+                                          float2* __restrict__ Asum, float2* __restrict__ Ksum,
+                                          float2* __restrict__ kap) {
   const size_t o = (size_t)i * g.B + b;
   const float h = g.dt;
   const float cr = st == 2 ? h / 6.f : h / 3.f;
   const float ca = st == 4 ? h : 0.5f * h;
-  const float2 r = rho[o];
+  const float2 r = in.r;
   float2 as = A;
   if (st != 4) {
-    const float2 p = Asum[o];
+    const float2 p = in.p;
     as = make_float2(p.x + A.x, p.y + A.y);
   }
   float2 kp;
@@ -555,10 +660,13 @@ __device__ __forceinline__ void adj_entry(const Geo& g, int i, int b, float2 A, 
     kp = make_float2(h / 6.f * rn.x, h / 6.f * rn.y);
   }
   kap[o] = kp;
-  const float2 ks = Ksum[o];
+  const float2 ks = in.ks;
   Ksum[o] = make_float2(ks.x + kp.x, ks.y + kp.y);
 }
 
+// block (i * kzh + h, kx chunk); NO = output entries (jy, kl) per thread.  The first G plane,
+// the twiddles and the band values of the thread's entries are loaded before the first barrier.
+template <int NO>
 __global__ __launch_bounds__(256) void k_fx_pi_yx_adj(Geo g, Geo gp, const float2* __restrict__ G,
                                                       const float2* __restrict__ tw_xT,
                                                       const float2* __restrict__ tw_yT, int kyp,
@@ -574,21 +682,34 @@ __global__ __launch_bounds__(256) void k_fx_pi_yx_adj(Geo g, Geo gp, const float
   const int i = ih / g.kzh, h = ih - i * g.kzh;
   const int k0 = blockIdx.y * kKC;
   const int jz = g.kz0 + h;
-  yx_twiddles(g, gp, tw_xT, tw_yT, kyp, k0, L);
-  // A for the thread's outputs, accumulated over j (at most 256 * 4 outputs per thread pass);
-  // the next plane's loads are in flight while the current plane is contracted
-  float2 A[4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) A[u] = make_float2(0.f, 0.f);
   const int np = PY * PX;
   float2 R[kPlaneRegs];
   plane_to_regs(G + ((size_t)(3 * i) * g.kzh + h) * np, np, R);
+  Target t[NO];
+  AdjIn in[NO][3];
+#pragma unroll
+  for (int u = 0; u < NO; ++u) {
+    const int o = threadIdx.x + 256 * u;
+    const int jy = o / kKC, kl = o - jy * kKC;
+    const int jx = k0 + kl;
+    t[u] = target(g, h, min(jx, g.kx - 1), min(jy, KY - 1));
+    if (o >= KY * kKC || jx >= g.kx) t[u].b = -1;   // no entry for this slot
+    in[u][0] = adj_load(g, i, t[u].b, rho, Asum, Ksum);
+    in[u][1] = adj_load(g, i, t[u].bm, rho, Asum, Ksum);
+    in[u][2] = adj_load(g, i, t[u].bz, rho, Asum, Ksum);
+  }
+  yx_twiddles(g, gp, tw_xT, tw_yT, kyp, k0, L);
+  // A for the thread's outputs, accumulated over j; the next plane's loads are in flight while
+  // the current plane is contracted
+  float2 A[NO];
+#pragma unroll
+  for (int u = 0; u < NO; ++u) A[u] = make_float2(0.f, 0.f);
   for (int j = 0; j < 3; ++j) {
     regs_to_lds(R, PX, np, L.Pl);
     if (j < 2) plane_to_regs(G + ((size_t)(3 * i + j + 1) * g.kzh + h) * np, np, R);
     pi_yx_passes(g, gp, L);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < NO; ++u) {
       const int o = threadIdx.x + 256 * u;
       if (o >= KY * kKC) break;
       const int jy = o / kKC, kl = o - jy * kKC;
@@ -601,23 +722,30 @@ __global__ __launch_bounds__(256) void k_fx_pi_yx_adj(Geo g, Geo gp, const float
     __syncthreads();   // Rs and Pl are rewritten by the next plane
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int o = threadIdx.x + 256 * u;
-    if (o >= KY * kKC) break;
-    const int jy = o / kKC, kl = o - jy * kKC;
-    const int jx = k0 + kl;
-    if (jx >= g.kx) continue;
-    const Target t = target(g, h, jx, jy);
-    if (t.b < 0) continue;
-    float2 a = t.zero ? make_float2(0.f, 0.f) : A[u];
-    if (t.real) a.y = 0.f;
-    adj_entry(g, i, t.b, a, st, more, rho, Asum, Ksum, kap);
-    if (t.bm >= 0) adj_entry(g, i, t.bm, make_float2(a.x, -a.y), st, more, rho, Asum, Ksum, kap);
-    if (t.bz >= 0) adj_entry(g, i, t.bz, make_float2(0.f, 0.f), st, more, rho, Asum, Ksum, kap);
+  for (int u = 0; u < NO; ++u) {
+    const Target& tu = t[u];
+    if (tu.b < 0) continue;
+    float2 a = tu.zero ? make_float2(0.f, 0.f) : A[u];
+    if (tu.real) a.y = 0.f;
+    adj_entry(g, i, tu.b, a, st, more, in[u][0], rho, Asum, Ksum, kap);
+    if (tu.bm >= 0)
+      adj_entry(g, i, tu.bm, make_float2(a.x, -a.y), st, more, in[u][1], rho, Asum, Ksum, kap);
+    if (tu.bz >= 0)
+      adj_entry(g, i, tu.bz, make_float2(0.f, 0.f), st, more, in[u][2], rho, Asum, Ksum, kap);
   }
   if (h == 0 && blockIdx.y == 0) {   // the unpaired plane kz = -K/2: A = 0 there
-    for (int o = threadIdx.x; o < g.ky * g.kx; o += 256)
-      adj_entry(g, i, o, make_float2(0.f, 0.f), st, more, rho, Asum, Ksum, kap);
+    const int n = g.ky * g.kx;
+    for (int base = 0; base < n; base += 1024) {
+      AdjIn zin[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        zin[u] = adj_load(g, i, min(base + (int)threadIdx.x + 256 * u, n - 1), rho, Asum, Ksum);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int o = base + (int)threadIdx.x + 256 * u;
+        if (o < n) adj_entry(g, i, o, make_float2(0.f, 0.f), st, more, zin[u], rho, Asum, Ksum, kap);
+      }
+    }
   }
 }
 
@@ -687,20 +815,30 @@ void fx_col_bwd(const Geo& gp, const DftPlan& pl, const float2* F2, const float*
   NZS_DISPATCH(k_fx_col_bwd, gp, F2, VP, DUG, GACC, first, pl.tw_zT, G);
 }
 
+// output entries per thread of a yx block: ky * kKC <= 4 * 256 (fused_ok)
+#define NO_DISPATCH(KERNEL, ...)                                                                  \
+  do {                                                                                            \
+    const dim3 grid_(g.dim * g.kzh, (g.kx + kKC - 1) / kKC);                                      \
+    switch ((g.ky * kKC + 255) / 256) {                                                           \
+      case 1: hipLaunchKernelGGL(KERNEL<1>, grid_, dim3(256), lds_yx(g, gp), s, __VA_ARGS__); break; \
+      case 2: hipLaunchKernelGGL(KERNEL<2>, grid_, dim3(256), lds_yx(g, gp), s, __VA_ARGS__); break; \
+      case 3: hipLaunchKernelGGL(KERNEL<3>, grid_, dim3(256), lds_yx(g, gp), s, __VA_ARGS__); break; \
+      default: hipLaunchKernelGGL(KERNEL<4>, grid_, dim3(256), lds_yx(g, gp), s, __VA_ARGS__); break; \
+    }                                                                                             \
+  } while (0)
+
 void fx_pi_yx_stage(const Geo& g, const Geo& gp, const DftPlan& pl, const float2* G, float scaleP,
                     const float2* src, const float2* un, float2* acc, int st, float2* wout,
                     hipStream_t s) {
-  hipLaunchKernelGGL(k_fx_pi_yx_stage, dim3(g.dim * g.kzh, (g.kx + kKC - 1) / kKC), dim3(256),
-                     lds_yx(g, gp), s, g, gp, G, pl.tw_xT, pl.tw_yT, pl.kyp, scaleP, src, un, acc,
-                     st, wout);
+  NO_DISPATCH(k_fx_pi_yx_stage, g, gp, G, pl.tw_xT, pl.tw_yT, pl.kyp, scaleP, src, un, acc, st,
+              wout);
 }
 
 void fx_pi_yx_adj(const Geo& g, const Geo& gp, const DftPlan& pl, const float2* G, float scaleP,
                   float2* rho, float2* Asum, float2* Ksum, float2* kap, int st, int more,
                   hipStream_t s) {
-  hipLaunchKernelGGL(k_fx_pi_yx_adj, dim3(g.dim * g.kzh, (g.kx + kKC - 1) / kKC), dim3(256),
-                     lds_yx(g, gp), s, g, gp, G, pl.tw_xT, pl.tw_yT, pl.kyp, scaleP, rho, Asum,
-                     Ksum, kap, st, more);
+  NO_DISPATCH(k_fx_pi_yx_adj, g, gp, G, pl.tw_xT, pl.tw_yT, pl.kyp, scaleP, rho, Asum, Ksum, kap,
+              st, more);
 }
 
 }  // namespace bl
