@@ -377,26 +377,62 @@ __global__ __launch_bounds__(BX* GBY) void k_inc_last(Geo g, const float* __rest
 }
 
 // b = sum_n w_n lambda^n grad m^n over the stored adjoint and state planes (trapezoid in
-// time), one pass after the backward transport.
+// time), one pass after the backward transport.  A thread takes its ZV voxels of a z run for
+// every time node in turn (node loop outside, voxel loop inside), so its z differences come
+// from a sliding window of three planes held in registers: each m^n plane of the run is read
+// once, plus one plane above and below, and the ZV voxels' loads of a node are in flight
+// together.
 template <int DIM, int ZV>
 __global__ __launch_bounds__(BX* GBY) void k_body_force(Geo g, const float* __restrict__ lam,
                                                         const float* __restrict__ m,
                                                         float* __restrict__ b) {
   GATHER_XY
   const size_t M = (size_t)g.M;
+  const uint32_t sz = (uint32_t)g.nx * g.ny;
+  const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x + 1 == g.nx ? 0 : x + 1;
+  const uint32_t sy = g.nx;
+  float acc[ZV][3];
+#pragma unroll
+  for (int zz = 0; zz < ZV; ++zz) acc[zz][0] = acc[zz][1] = acc[zz][2] = 0.f;
+  // the run's first voxel and its lower z neighbour (periodic); the run starts below nz
+  const int z0 = tile.bz * ZV;
+  const uint32_t p0 = ((uint32_t)z0 * g.ny + y) * g.nx + x;
+  const uint32_t p0m = z0 == 0 ? p0 + (uint32_t)(g.nz - 1) * sz : p0 - sz;
+  for (int n = 0; n <= g.nt; ++n) {
+    const float w = (n == 0 || n == g.nt) ? 0.5f * g.dt : g.dt;
+    const float* __restrict__ mn = m + n * M;
+    const float* __restrict__ ln = lam + n * M;
+    float prev = DIM == 3 ? mn[p0m] : 0.f;   // m at z - 1
+    float cur = DIM == 3 ? mn[p0] : 0.f;     // m at z
+#pragma unroll
+    for (int zz = 0; zz < ZV; ++zz) {
+      GATHER_Z(zz)
+      (void)live;
+      const uint32_t row = p - x;
+      const float gx = (mn[row + xp] - mn[row + xm]) * g.half_nref;
+      const uint32_t pym = y == 0 ? p + (uint32_t)(g.ny - 1) * sy : p - sy;
+      const uint32_t pyp = y + 1 == g.ny ? p - (uint32_t)(g.ny - 1) * sy : p + sy;
+      const float gy = (mn[pyp] - mn[pym]) * g.half_nref;
+      float gz = 0.f;
+      if (DIM == 3) {
+        // voxels past nz repeat the clamped last plane and are not stored
+        const uint32_t pzp = z + 1 == g.nz ? p - (uint32_t)(g.nz - 1) * sz : p + sz;
+        const float next = mn[pzp];
+        gz = (next - prev) * g.half_nref;
+        prev = cur;
+        cur = next;
+      }
+      const float wl = w * ln[p];
+      acc[zz][0] = fmaf(wl, gx, acc[zz][0]);
+      acc[zz][1] = fmaf(wl, gy, acc[zz][1]);
+      if (DIM == 3) acc[zz][2] = fmaf(wl, gz, acc[zz][2]);
+    }
+  }
 #pragma unroll
   for (int zz = 0; zz < ZV; ++zz) {
     GATHER_Z(zz)
-    float acc[3] = {0.f, 0.f, 0.f};
-    for (int n = 0; n <= g.nt; ++n) {
-      const float w = (n == 0 || n == g.nt) ? 0.5f * g.dt : g.dt;
-      float gr[3];
-      grad_c<DIM>(g, m + n * M, x, y, z, p, gr);
-      const float wl = w * lam[n * M + p];
-      for (int c = 0; c < DIM; ++c) acc[c] = fmaf(wl, gr[c], acc[c]);
-    }
     if (live)
-      for (int c = 0; c < DIM; ++c) b[c * M + p] = acc[c];
+      for (int c = 0; c < DIM; ++c) b[c * M + p] = acc[zz][c];
   }
 }
 
