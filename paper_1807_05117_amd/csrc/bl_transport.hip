@@ -542,7 +542,9 @@ __global__ __launch_bounds__(BX* GBY) void k_adj_step_n(Geo g, const float* __re
   if (u_out) { STORE_ZV(u_out, uv) }
 }
 
-// Newton body force: sum_n w_n (dlambda^n grad m^n + lambda^n grad dm^n)
+// Newton body force: sum_n w_n (dlambda^n grad m^n + lambda^n grad dm^n); the node loop is
+// outside the thread's z run and the z differences of m^n and dm^n come from sliding windows,
+// as in k_body_force
 template <int DIM, int ZV>
 __global__ __launch_bounds__(BX* GBY) void k_body_force_n(Geo g, const float* __restrict__ dlam,
                                                           const float* __restrict__ m,
@@ -551,19 +553,47 @@ __global__ __launch_bounds__(BX* GBY) void k_body_force_n(Geo g, const float* __
                                                           float* __restrict__ b) {
   GATHER_XY
   const size_t M = (size_t)g.M;
+  const uint32_t sz = (uint32_t)g.nx * g.ny;
+  const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x + 1 == g.nx ? 0 : x + 1;
+  const uint32_t sy = g.nx;
   float acc[ZV][3];
 #pragma unroll
-  for (int zz = 0; zz < ZV; ++zz) {
-    GATHER_Z(zz)
-    (void)live;
-    acc[zz][0] = acc[zz][1] = acc[zz][2] = 0.f;
-    for (int n = 0; n <= g.nt; ++n) {
-      const float w = (n == 0 || n == g.nt) ? 0.5f * g.dt : g.dt;
+  for (int zz = 0; zz < ZV; ++zz) acc[zz][0] = acc[zz][1] = acc[zz][2] = 0.f;
+  const int z0 = tile.bz * ZV;
+  const uint32_t p0 = ((uint32_t)z0 * g.ny + y) * g.nx + x;
+  const uint32_t p0m = z0 == 0 ? p0 + (uint32_t)(g.nz - 1) * sz : p0 - sz;
+  for (int n = 0; n <= g.nt; ++n) {
+    const float w = (n == 0 || n == g.nt) ? 0.5f * g.dt : g.dt;
+    const float* __restrict__ mn = m + n * M;
+    const float* __restrict__ dn = dm + n * M;
+    float mprev = DIM == 3 ? mn[p0m] : 0.f, mcur = DIM == 3 ? mn[p0] : 0.f;
+    float dprev = DIM == 3 ? dn[p0m] : 0.f, dcur = DIM == 3 ? dn[p0] : 0.f;
+#pragma unroll
+    for (int zz = 0; zz < ZV; ++zz) {
+      GATHER_Z(zz)
+      (void)live;
+      const uint32_t row = p - x;
+      const uint32_t pym = y == 0 ? p + (uint32_t)(g.ny - 1) * sy : p - sy;
+      const uint32_t pyp = y + 1 == g.ny ? p - (uint32_t)(g.ny - 1) * sy : p + sy;
       float gr[3], gd[3];
-      grad_c<DIM>(g, m + n * M, x, y, z, p, gr);
-      grad_c<DIM>(g, dm + n * M, x, y, z, p, gd);
+      gr[0] = (mn[row + xp] - mn[row + xm]) * g.half_nref;
+      gr[1] = (mn[pyp] - mn[pym]) * g.half_nref;
+      gd[0] = (dn[row + xp] - dn[row + xm]) * g.half_nref;
+      gd[1] = (dn[pyp] - dn[pym]) * g.half_nref;
+      gr[2] = gd[2] = 0.f;
+      if (DIM == 3) {
+        const uint32_t pzp = z + 1 == g.nz ? p - (uint32_t)(g.nz - 1) * sz : p + sz;
+        const float mnext = mn[pzp], dnext = dn[pzp];
+        gr[2] = (mnext - mprev) * g.half_nref;
+        gd[2] = (dnext - dprev) * g.half_nref;
+        mprev = mcur;
+        mcur = mnext;
+        dprev = dcur;
+        dcur = dnext;
+      }
       const float wl = w * dlam[n * M + p];
       const float wa = w * lam[n * M + p];
+#pragma unroll
       for (int c = 0; c < DIM; ++c) acc[zz][c] = fmaf(wa, gd[c], fmaf(wl, gr[c], acc[zz][c]));
     }
   }
