@@ -28,6 +28,10 @@ struct Geo {
   int nodes;          // band velocity fields: 1 (stationary) or nt + 1 (one per time node)
   int deform;         // 1: deformation state equation (band displacement of the inverse map)
   int px, py, pz;     // product grid of the truncated convolutions (deformation method)
+  // 1: the transports store their outputs with the streaming (non-temporal) hint.  Set when the
+  // nine grid fields an incremental step touches exceed the 256 MiB last-level cache: there
+  // the hint speeds the steps up, below it the next step's reads of the output would miss.
+  int stream_out;
   // voxels per thread along z of the transport launches, per kernel class (TR_*): a launch
   // shape only, every choice computes bitwise the same values
   int zv[4];

@@ -94,6 +94,7 @@ int validate(const bl_problem* p, bl::Geo* g) {
     g->zv[bl::TR_INC] = d3 ? 2 : 1;
     g->zv[bl::TR_ADJ] = d3 ? 2 : 1;
     g->zv[bl::TR_FORCE] = 1;
+    g->stream_out = 9 * 4 * g->M > (int64_t(256) << 20) ? 1 : 0;
   }
   return BL_OK;
 }
@@ -165,6 +166,7 @@ bl::Geo product_geo(const bl::Geo& g) {
   p.inv_ny = 1.0f / (float)g.py;
   p.inv_nz = 1.0f / (float)g.pz;
   p.half_nref = 0.5f * (float)p.nref;
+  p.stream_out = 0;   // no transport runs on the product grid
   return p;
 }
 

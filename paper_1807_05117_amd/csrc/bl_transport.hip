@@ -168,11 +168,20 @@ __device__ __forceinline__ TileIdx xcd_tile(int gx, int gy, int gz) {
   const bool live = zr < g.nz;                           \
   const uint32_t p = ((uint32_t)z * g.ny + y) * g.nx + x;
 // The values of a thread's ZV voxels are computed first and stored afterwards, so no store
-// sits between the voxels' loads.
+// sits between the voxels' loads.  Large grids store with the streaming hint (Geo::stream_out).
+// Both forms are raw buffer stores that differ in their cache-policy immediate (bit 1: nt), so
+// the compiler cannot merge the two branches into one plain store.
+__device__ __forceinline__ void store_out(const Geo& g, float* out, uint32_t p, float v) {
+  const __amdgpu_buffer_rsrc_t rs = field_rsrc(out, g);
+  if (g.stream_out)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rs, (int)(p * 4u), 0, 2);
+  else
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rs, (int)(p * 4u), 0, 0);
+}
 #define STORE_ZV(out, val)                                 \
   _Pragma("unroll") for (int zz = 0; zz < ZV; ++zz) {      \
     GATHER_Z(zz)                                           \
-    if (live) (out)[p] = (val)[zz];                        \
+    if (live) store_out(g, (out), p, (val)[zz]);           \
   }
 
 template <int DIM>
