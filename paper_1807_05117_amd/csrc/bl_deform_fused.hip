@@ -18,6 +18,8 @@
 // Twiddle tables are those of the product grid's transform plan (bl_dft.hip layout).
 #include "bl_internal.h"
 
+#include <mutex>
+
 namespace bl {
 namespace {
 
@@ -664,8 +666,19 @@ __device__ __forceinline__ void adj_entry(const Geo& g, int i, int b, float2 A, 
   Ksum[o] = make_float2(ks.x + kp.x, ks.y + kp.y);
 }
 
-// block (i * kzh + h, kx chunk); NO = output entries (jy, kl) per thread.  The first G plane,
-// the twiddles and the band values of the thread's entries are loaded before the first barrier.
+// Transposed-sweep yx block (i * kzh + h, kx chunk); NO = output entries (jy, kl) per thread.
+// A = i scaleP sum_j q_j R_j with R_j = Y(X(G_j)) and q_j the derivative symbol of axis j.  q_x
+// depends on kx only and q_z is constant in the block, so both commute with the y contraction:
+//   A = i scaleP [Y(q_x X(G_0) + q_z X(G_2)) + q_y Y(X(G_1))].
+// The three G planes are staged in LDS together; one x pass forms T02 = q_x X(G_0) + q_z X(G_2)
+// and T1 = X(G_1), one y pass both y sums.  All global loads (planes, twiddles, the band entries
+// the thread updates) are issued before the first barrier.
+constexpr int kAdjRegs = 9;   // plane entries per thread and round (one round for 48 x 48)
+
+__host__ __device__ __forceinline__ size_t adj_plane_stride(const Geo& gp) {
+  return (size_t)gp.ny * (gp.nx + 1);
+}
+
 template <int NO>
 __global__ __launch_bounds__(256) void k_fx_pi_yx_adj(Geo g, Geo gp, const float2* __restrict__ G,
                                                       const float2* __restrict__ tw_xT,
@@ -675,16 +688,22 @@ __global__ __launch_bounds__(256) void k_fx_pi_yx_adj(Geo g, Geo gp, const float
                                                       float2* __restrict__ Ksum,
                                                       float2* __restrict__ kap, int st, int more) {
   extern __shared__ float2 lds[];
-  const int KY = g.ky, PX = gp.nx, PY = gp.ny;
-  const YxLds L = yx_lds(g, gp, lds);
-  const float2* Rs = L.Rs;
+  const int KX = g.kx, KY = g.ky, PX = gp.nx, PY = gp.ny, SP = PX + 1;
+  const size_t PS = adj_plane_stride(gp);
+  float2* Pl = lds;                      // [3][PY][SP]
+  float2* T02 = Pl + 3 * PS;             // [PY][kKC]
+  float2* T1 = T02 + (size_t)PY * kKC;   // [PY][kKC]
+  float2* Tx = T1 + (size_t)PY * kKC;    // [PX][kKC]
+  float2* Ty = Tx + (size_t)PX * kKC;    // [PY][KY]
   const int ih = blockIdx.x;
   const int i = ih / g.kzh, h = ih - i * g.kzh;
   const int k0 = blockIdx.y * kKC;
   const int jz = g.kz0 + h;
   const int np = PY * PX;
-  float2 R[kPlaneRegs];
-  plane_to_regs(G + ((size_t)(3 * i) * g.kzh + h) * np, np, R);
+  const float2* Gp[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) Gp[j] = G + ((size_t)(3 * i + j) * g.kzh + h) * np;
+  // the band entries this thread updates, loaded first
   Target t[NO];
   AdjIn in[NO][3];
 #pragma unroll
@@ -692,34 +711,66 @@ __global__ __launch_bounds__(256) void k_fx_pi_yx_adj(Geo g, Geo gp, const float
     const int o = threadIdx.x + 256 * u;
     const int jy = o / kKC, kl = o - jy * kKC;
     const int jx = k0 + kl;
-    t[u] = target(g, h, min(jx, g.kx - 1), min(jy, KY - 1));
-    if (o >= KY * kKC || jx >= g.kx) t[u].b = -1;   // no entry for this slot
+    t[u] = target(g, h, min(jx, KX - 1), min(jy, KY - 1));
+    if (o >= KY * kKC || jx >= KX) t[u].b = -1;   // no entry for this slot
     in[u][0] = adj_load(g, i, t[u].b, rho, Asum, Ksum);
     in[u][1] = adj_load(g, i, t[u].bm, rho, Asum, Ksum);
     in[u][2] = adj_load(g, i, t[u].bz, rho, Asum, Ksum);
   }
-  yx_twiddles(g, gp, tw_xT, tw_yT, kyp, k0, L);
-  // A for the thread's outputs, accumulated over j; the next plane's loads are in flight while
-  // the current plane is contracted
+  // the three planes, kAdjRegs entries of each per thread and round, then the twiddles
+  const int rounds = (np + 256 * kAdjRegs - 1) / (256 * kAdjRegs);
+  for (int r = 0; r < rounds; ++r) {
+    const int base = r * 256 * kAdjRegs;
+    Stager<256, kAdjRegs> sp[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) sp[j].load(np, base, [&](int o) { return Gp[j][o]; });
+    if (r == 0) yx_twiddles(g, gp, tw_xT, tw_yT, kyp, k0, YxLds{nullptr, nullptr, nullptr, Tx, Ty});
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      sp[j].store(np, base, [&](int o, float2 v) {
+        const int y = o / PX;
+        Pl[j * PS + y * SP + (o - y * PX)] = v;
+      });
+  }
+  __syncthreads();
+  // x pass: (y, kl) outputs, the three planes' sums together
+  const float qz = qaxis(g, 2, jz);
+  for (int o = threadIdx.x; o < PY * kKC; o += 256) {
+    const int y = o / kKC, kl = o - y * kKC;
+    const float qx = qaxis(g, 0, min(k0 + kl, KX - 1));
+    float2 a0 = make_float2(0.f, 0.f), a1 = a0, a2 = a0;
+    const float2* r0 = Pl + y * SP;
+    const float2* r1 = r0 + PS;
+    const float2* r2 = r1 + PS;
+#pragma unroll 4
+    for (int x = 0; x < PX; ++x) {
+      const float2 tw = Tx[x * kKC + kl];
+      cmac_conj(a0, r0[x], tw);
+      cmac_conj(a1, r1[x], tw);
+      cmac_conj(a2, r2[x], tw);
+    }
+    T02[o] = make_float2(fmaf(qx, a0.x, qz * a2.x), fmaf(qx, a0.y, qz * a2.y));
+    T1[o] = a1;
+  }
+  __syncthreads();
+  // y pass: A for the thread's outputs
   float2 A[NO];
 #pragma unroll
-  for (int u = 0; u < NO; ++u) A[u] = make_float2(0.f, 0.f);
-  for (int j = 0; j < 3; ++j) {
-    regs_to_lds(R, PX, np, L.Pl);
-    if (j < 2) plane_to_regs(G + ((size_t)(3 * i + j + 1) * g.kzh + h) * np, np, R);
-    pi_yx_passes(g, gp, L);
-#pragma unroll
-    for (int u = 0; u < NO; ++u) {
-      const int o = threadIdx.x + 256 * u;
-      if (o >= KY * kKC) break;
-      const int jy = o / kKC, kl = o - jy * kKC;
-      const int jx = min(k0 + kl, g.kx - 1);
-      const float q = j == 0 ? qaxis(g, 0, jx) : (j == 1 ? qaxis(g, 1, jy) : qaxis(g, 2, jz));
-      const float2 r = Rs[o];
-      A[u].x = fmaf(-q * scaleP, r.y, A[u].x);
-      A[u].y = fmaf(q * scaleP, r.x, A[u].y);
+  for (int u = 0; u < NO; ++u) {
+    A[u] = make_float2(0.f, 0.f);
+    const int o = threadIdx.x + 256 * u;
+    if (o >= KY * kKC) continue;
+    const int jy = o / kKC, kl = o - jy * kKC;
+    float2 s02 = make_float2(0.f, 0.f), s1 = s02;
+#pragma unroll 4
+    for (int y = 0; y < PY; ++y) {
+      const float2 tw = Ty[y * KY + jy];
+      cmac_conj(s02, T02[y * kKC + kl], tw);
+      cmac_conj(s1, T1[y * kKC + kl], tw);
     }
-    __syncthreads();   // Rs and Pl are rewritten by the next plane
+    const float qy = qaxis(g, 1, jy);
+    const float2 R = make_float2(fmaf(qy, s1.x, s02.x), fmaf(qy, s1.y, s02.y));
+    A[u] = make_float2(-scaleP * R.y, scaleP * R.x);
   }
 #pragma unroll
   for (int u = 0; u < NO; ++u) {
@@ -734,7 +785,7 @@ __global__ __launch_bounds__(256) void k_fx_pi_yx_adj(Geo g, Geo gp, const float
       adj_entry(g, i, tu.bz, make_float2(0.f, 0.f), st, more, in[u][2], rho, Asum, Ksum, kap);
   }
   if (h == 0 && blockIdx.y == 0) {   // the unpaired plane kz = -K/2: A = 0 there
-    const int n = g.ky * g.kx;
+    const int n = KY * KX;
     for (int base = 0; base < n; base += 1024) {
       AdjIn zin[4];
 #pragma unroll
@@ -756,6 +807,11 @@ size_t lds_xy(const Geo& g, const Geo& gp) {
   return ((size_t)g.ky * (g.kx + 1) + (size_t)g.ky * kXC + (size_t)g.kx * kXC + (size_t)g.ky * gp.ny) *
          sizeof(float2);
 }
+size_t lds_yx_adj(const Geo& g, const Geo& gp) {
+  return (3 * adj_plane_stride(gp) + 2 * (size_t)gp.ny * kKC + (size_t)gp.nx * kKC +
+          (size_t)gp.ny * g.ky) *
+         sizeof(float2);
+}
 size_t lds_yx(const Geo& g, const Geo& gp) {
   return ((size_t)gp.ny * (gp.nx + 1) + (size_t)gp.ny * kKC + (size_t)g.ky * kKC + (size_t)gp.nx * kKC +
           (size_t)gp.ny * g.ky) *
@@ -767,7 +823,8 @@ size_t lds_yx(const Geo& g, const Geo& gp) {
 bool fused_ok(const Geo& g, const Geo& gp) {
   return g.dim == 3 && gp.nz <= 48 && g.kzh <= 16 && g.kzh >= 2 && g.ky * kKC <= 4 * 256 &&
          gp.nx * gp.ny <= 256 * kPlaneRegs &&
-         lds_xy(g, gp) <= 64 * 1024 && lds_yx(g, gp) <= 64 * 1024;
+         lds_xy(g, gp) <= 64 * 1024 && lds_yx(g, gp) <= 64 * 1024 &&
+         lds_yx_adj(g, gp) <= 160 * 1024;
 }
 
 void fx_iota_xy(const Geo& g, const Geo& gp, const DftPlan& pl, const float2* in, int deriv,
@@ -816,29 +873,40 @@ void fx_col_bwd(const Geo& gp, const DftPlan& pl, const float2* F2, const float*
 }
 
 // output entries per thread of a yx block: ky * kKC <= 4 * 256 (fused_ok)
-#define NO_DISPATCH(KERNEL, ...)                                                                  \
-  do {                                                                                            \
-    const dim3 grid_(g.dim * g.kzh, (g.kx + kKC - 1) / kKC);                                      \
-    switch ((g.ky * kKC + 255) / 256) {                                                           \
-      case 1: hipLaunchKernelGGL(KERNEL<1>, grid_, dim3(256), lds_yx(g, gp), s, __VA_ARGS__); break; \
-      case 2: hipLaunchKernelGGL(KERNEL<2>, grid_, dim3(256), lds_yx(g, gp), s, __VA_ARGS__); break; \
-      case 3: hipLaunchKernelGGL(KERNEL<3>, grid_, dim3(256), lds_yx(g, gp), s, __VA_ARGS__); break; \
-      default: hipLaunchKernelGGL(KERNEL<4>, grid_, dim3(256), lds_yx(g, gp), s, __VA_ARGS__); break; \
-    }                                                                                             \
+#define NO_DISPATCH(KERNEL, LDS, ...)                                                       \
+  do {                                                                                      \
+    const dim3 grid_(g.dim * g.kzh, (g.kx + kKC - 1) / kKC);                                \
+    const size_t lds_ = (LDS);                                                              \
+    switch ((g.ky * kKC + 255) / 256) {                                                     \
+      case 1: hipLaunchKernelGGL(KERNEL<1>, grid_, dim3(256), lds_, s, __VA_ARGS__); break; \
+      case 2: hipLaunchKernelGGL(KERNEL<2>, grid_, dim3(256), lds_, s, __VA_ARGS__); break; \
+      case 3: hipLaunchKernelGGL(KERNEL<3>, grid_, dim3(256), lds_, s, __VA_ARGS__); break; \
+      default: hipLaunchKernelGGL(KERNEL<4>, grid_, dim3(256), lds_, s, __VA_ARGS__); break; \
+    }                                                                                       \
   } while (0)
 
 void fx_pi_yx_stage(const Geo& g, const Geo& gp, const DftPlan& pl, const float2* G, float scaleP,
                     const float2* src, const float2* un, float2* acc, int st, float2* wout,
                     hipStream_t s) {
-  NO_DISPATCH(k_fx_pi_yx_stage, g, gp, G, pl.tw_xT, pl.tw_yT, pl.kyp, scaleP, src, un, acc, st,
-              wout);
+  NO_DISPATCH(k_fx_pi_yx_stage, lds_yx(g, gp), g, gp, G, pl.tw_xT, pl.tw_yT, pl.kyp, scaleP,
+              src, un, acc, st, wout);
 }
 
 void fx_pi_yx_adj(const Geo& g, const Geo& gp, const DftPlan& pl, const float2* G, float scaleP,
                   float2* rho, float2* Asum, float2* Ksum, float2* kap, int st, int more,
                   hipStream_t s) {
-  NO_DISPATCH(k_fx_pi_yx_adj, g, gp, G, pl.tw_xT, pl.tw_yT, pl.kyp, scaleP, rho, Asum, Ksum, kap,
-              st, more);
+  // the three staged planes take up to 160 KiB of LDS (fused_ok): allow the launches that size
+  static std::once_flag once;
+  std::call_once(once, [] {
+    const int cap = 160 * 1024;
+    (void)hipFuncSetAttribute((const void*)k_fx_pi_yx_adj<1>, hipFuncAttributeMaxDynamicSharedMemorySize, cap);
+    (void)hipFuncSetAttribute((const void*)k_fx_pi_yx_adj<2>, hipFuncAttributeMaxDynamicSharedMemorySize, cap);
+    (void)hipFuncSetAttribute((const void*)k_fx_pi_yx_adj<3>, hipFuncAttributeMaxDynamicSharedMemorySize, cap);
+    (void)hipFuncSetAttribute((const void*)k_fx_pi_yx_adj<4>, hipFuncAttributeMaxDynamicSharedMemorySize, cap);
+    (void)hipGetLastError();   // an attribute the runtime does not need leaves no error behind
+  });
+  NO_DISPATCH(k_fx_pi_yx_adj, lds_yx_adj(g, gp), g, gp, G, pl.tw_xT, pl.tw_yT, pl.kyp, scaleP,
+              rho, Asum, Ksum, kap, st, more);
 }
 
 }  // namespace bl
