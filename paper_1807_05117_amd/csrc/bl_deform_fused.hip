@@ -164,16 +164,18 @@ __global__ __launch_bounds__(256) void k_fx_iota_xy(Geo g, Geo gp, const float2*
 // exp(+2 pi i h z / pz) are staged in LDS (tz[z][h], KZH per row) and read as broadcasts, each
 // shared by the three fields a block contracts.
 
-// this lane's half of the column of one field (h < kzh; zero past kzh), loads issued together
+// this lane's half of the column of one field (h < kzh; zero past kzh).  Every load is made,
+// at the clamped plane past kzh, and zeroed afterwards: a guarded load compiles to a branch and
+// a wait per load, an unguarded one lets all of them be in flight together.
 template <int KZH>
 __device__ __forceinline__ void load_half(const float2* __restrict__ Fc, size_t hstride, int kzh,
                                           int half, float2* F) {
   constexpr int NHH = KZH / 2;
+  float2 v[NHH];
 #pragma unroll
-  for (int u = 0; u < NHH; ++u) {
-    const int h = half * NHH + u;
-    F[u] = h < kzh ? Fc[(size_t)h * hstride] : make_float2(0.f, 0.f);
-  }
+  for (int u = 0; u < NHH; ++u) v[u] = Fc[(size_t)min(half * NHH + u, kzh - 1) * hstride];
+#pragma unroll
+  for (int u = 0; u < NHH; ++u) F[u] = half * NHH + u < kzh ? v[u] : make_float2(0.f, 0.f);
 }
 
 // the block's z twiddles tz[z][h] (zero past kzh): pz * KZH <= 48 * 16 entries, two per thread;
