@@ -454,30 +454,39 @@ __global__ __launch_bounds__(256) void k_band_finalize(Geo g,
     band_index(g, b, jx, jy, jz);
     const bool up = unpaired(g, jx, jy, jz);
     const int kzv = jz - g.kz0;
+    // Both half-spectrum entries a component may need, at indices valid for every band index
+    // (unpaired ones read entry 0 and are zeroed): the direct entry for kz >= 0, the conjugate
+    // mirror for kz <= 0.  All loads are unconditional so that they are in flight together; a
+    // load inside a branch waits before the next one.
+    const size_t ia = up || kzv < 0 ? 0 : ((size_t)kzv * g.ky + jy) * g.kx + jx;
+    const size_t im = up || kzv > 0 ? 0 : ((size_t)(-kzv) * g.ky + (g.ky - jy)) * g.kx + (g.kx - jx);
+    const size_t ph = (size_t)g.kzh * g.ky * g.kx;
+    float2 va[C], vm[C], vp[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      va[c] = P[c * ph + ia];
+      vm[c] = P[c * ph + im];
+      vp[c] = vproj ? vproj[c * B + b] : make_float2(0.f, 0.f);
+    }
+    const float l = vproj ? Lhat[b] : 0.f;
     float2 o[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       o[c] = make_float2(0.f, 0.f);
       if (up) continue;
-      const float2* Pc = P + (size_t)c * g.kzh * g.ky * g.kx;
       float2 pv;
       if (kzv > 0) {
-        pv = Pc[((size_t)kzv * g.ky + jy) * g.kx + jx];
+        pv = va[c];
       } else if (kzv < 0) {
-        const float2 m = Pc[((size_t)(-kzv) * g.ky + (g.ky - jy)) * g.kx + (g.kx - jx)];
-        pv = make_float2(m.x, -m.y);
+        pv = make_float2(vm[c].x, -vm[c].y);
       } else {
         // kz = 0 plane: average with the conjugate mirror so the output is exactly Hermitian
-        const float2 a = Pc[(size_t)jy * g.kx + jx];
-        const float2 m = Pc[(size_t)(g.ky - jy) * g.kx + (g.kx - jx)];
-        pv = make_float2(0.5f * (a.x + m.x), 0.5f * (a.y - m.y));
+        pv = make_float2(0.5f * (va[c].x + vm[c].x), 0.5f * (va[c].y - vm[c].y));
       }
       o[c] = make_float2(scale * pv.x, scale * pv.y);
       if (vproj) {
-        const float l = Lhat[b];
-        const float2 v = vproj[c * B + b];
-        o[c].x = fmaf(l, v.x, o[c].x);
-        o[c].y = fmaf(l, v.y, o[c].y);
+        o[c].x = fmaf(l, vp[c].x, o[c].x);
+        o[c].y = fmaf(l, vp[c].y, o[c].y);
       }
     }
     if constexpr (C == DIM) {
