@@ -125,34 +125,67 @@ __global__ __launch_bounds__(256) void k_fx_iota_xy(Geo g, Geo gp, const float2*
     sY.store(nY, r * 1536, [&](int o, float2 v) { Ty[o] = v; });
   }
   __syncthreads();
-  // x: T[jy][xl] = sum_jx S[jy][jx] Tx[jx][x0 + xl]
-  for (int o = threadIdx.x; o < KY * kXC; o += 256) {
-    const int jy = o / kXC, xl = o - jy * kXC;
-    float2 a = make_float2(0.f, 0.f), b = a;
+  // Both passes give a thread several outputs of one column xl (256 is a multiple of kXC) and
+  // compute them together: the operand they share is read once per term, and their chains of
+  // dependent LDS reads run side by side.  Each output keeps its own two alternating partial
+  // sums, as a single-output loop would.
+  const int xl = threadIdx.x % kXC;
+  // x: T[jy][xl] = sum_jx S[jy][jx] Tx[jx][x0 + xl], two rows per thread and round
+  const int nT = KY * kXC;
+  for (int ob = 0; ob < nT; ob += 512) {
+    const int o0 = ob + threadIdx.x, o1 = o0 + 256;
+    const int jy0 = min(o0, nT - 1) / kXC, jy1 = min(o1, nT - 1) / kXC;
+    float2 a0 = make_float2(0.f, 0.f), b0 = a0, a1 = a0, b1 = a0;
     int jx = 0;
 #pragma unroll 4
     for (; jx + 1 < KX; jx += 2) {
-      cmac(a, S[jy * SX + jx], Txc[jx * kXC + xl]);
-      cmac(b, S[jy * SX + jx + 1], Txc[(jx + 1) * kXC + xl]);
+      const float2 t0 = Txc[jx * kXC + xl], t1 = Txc[(jx + 1) * kXC + xl];
+      cmac(a0, S[jy0 * SX + jx], t0);
+      cmac(b0, S[jy0 * SX + jx + 1], t1);
+      cmac(a1, S[jy1 * SX + jx], t0);
+      cmac(b1, S[jy1 * SX + jx + 1], t1);
     }
-    if (jx < KX) cmac(a, S[jy * SX + jx], Txc[jx * kXC + xl]);
-    T[o] = make_float2(a.x + b.x, a.y + b.y);
+    if (jx < KX) {
+      const float2 t0 = Txc[jx * kXC + xl];
+      cmac(a0, S[jy0 * SX + jx], t0);
+      cmac(a1, S[jy1 * SX + jx], t0);
+    }
+    if (o0 < nT) T[o0] = make_float2(a0.x + b0.x, a0.y + b0.y);
+    if (o1 < nT) T[o1] = make_float2(a1.x + b1.x, a1.y + b1.y);
   }
   __syncthreads();
-  // y: F2[y][x0 + xl] = sum_jy T[jy][xl] Ty[jy][y]
+  // y: F2[y][x0 + xl] = sum_jy T[jy][xl] Ty[jy][y], three rows per thread and round
   float2* dst = F2 + (size_t)ch * PY * PX;
-  for (int o = threadIdx.x; o < PY * kXC; o += 256) {
-    const int y = o / kXC, xl = o - y * kXC;
-    if (x0 + xl >= PX) continue;
-    float2 a = make_float2(0.f, 0.f), b = a;
+  const int nF = PY * kXC;
+  const bool xin = x0 + xl < PX;
+  for (int ob = 0; ob < nF; ob += 768) {
+    int yr[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) yr[u] = min(ob + (int)threadIdx.x + 256 * u, nF - 1) / kXC;
+    float2 a[3], b[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) a[u] = b[u] = make_float2(0.f, 0.f);
     int jy = 0;
-#pragma unroll 4
+#pragma unroll 2
     for (; jy + 1 < KY; jy += 2) {
-      cmac(a, T[jy * kXC + xl], Ty[jy * PY + y]);
-      cmac(b, T[(jy + 1) * kXC + xl], Ty[(jy + 1) * PY + y]);
+      const float2 t0 = T[jy * kXC + xl], t1 = T[(jy + 1) * kXC + xl];
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        cmac(a[u], t0, Ty[jy * PY + yr[u]]);
+        cmac(b[u], t1, Ty[(jy + 1) * PY + yr[u]]);
+      }
     }
-    if (jy < KY) cmac(a, T[jy * kXC + xl], Ty[jy * PY + y]);
-    dst[(size_t)y * PX + x0 + xl] = make_float2(a.x + b.x, a.y + b.y);
+    if (jy < KY) {
+      const float2 t0 = T[jy * kXC + xl];
+#pragma unroll
+      for (int u = 0; u < 3; ++u) cmac(a[u], t0, Ty[jy * PY + yr[u]]);
+    }
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int o = ob + (int)threadIdx.x + 256 * u;
+      if (xin && o < nF)
+        dst[(size_t)yr[u] * PX + x0 + xl] = make_float2(a[u].x + b[u].x, a[u].y + b[u].y);
+    }
   }
 }
 
