@@ -109,8 +109,9 @@ void band_finalize_nodes(const Geo& g, int C, const float2* vproj, size_t vstrid
 // ---- transports (bl_transport.hip)
 // X: dim planes of forward offsets; YA = (Y, a) backward offsets and reaction factor
 void setup(const Geo& g, const float* v, float* X, float4* YA, hipStream_t s);
-// non-stationary step t_n -> t_{n+1}: v0 = (v^n, r^n), v1 = (v^{n+1}, r^{n+1}) (dim + 1 planes)
-void setup_ns(const Geo& g, const float* v0, const float* v1, float* X, float4* YA, hipStream_t s);
+// non-stationary steps t_n -> t_{n+1} for n < steps, one launch: V holds (v^n, r^n) of every
+// node (dim + 1 planes each); step n writes X + n dim M and YA + n M
+void setup_ns(const Geo& g, const float* V, float* X, float4* YA, int steps, hipStream_t s);
 // b^n = lambda^n grad m^n for the time nodes n < nodes (lam, m: one plane per node; b: dim
 // planes per node), one launch
 void body_nodes(const Geo& g, const float* lam, const float* m, float* b, int nodes,

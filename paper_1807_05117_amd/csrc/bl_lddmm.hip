@@ -631,12 +631,11 @@ void op_set_velocity_ns(bl_ctx* c, const float2* vraw) {
   }
   // (v^n, r^n) of every node in one transform: V[n][c]
   bl::iota(g, c->plan, c->bv, (g.nt + 1) * (d + 1), c->V, s);
-  for (int n = 0; n < g.nt; ++n) {
-    bl::setup_ns(g, c->V + (size_t)n * (d + 1) * M, c->V + (size_t)(n + 1) * (d + 1) * M,
-                 c->X + (size_t)n * d * M, c->YA + (size_t)n * M, s);
-    if (n == 0 && !c->tuned) choose_launch_shapes(c);
+  // every step's offsets in one launch, then the state steps
+  bl::setup_ns(g, c->V, c->X, c->YA, g.nt, s);
+  if (!c->tuned) choose_launch_shapes(c);
+  for (int n = 0; n < g.nt; ++n)
     bl::state_step(g, c->m + n * M, c->X + (size_t)n * d * M, c->m + (n + 1) * M, s);
-  }
   bl::energy_partial(g, c->m + g.nt * M, c->I1, red_data, s);
   bl::reduce_final(red_reg, bl::kRedBlocks, c->scal + S_REG, s, c->hdev + S_REG);
   bl::reduce_final(red_data, bl::kRedBlocks, c->scal + S_DATA, s, c->hdev + S_DATA);

@@ -220,16 +220,22 @@ __global__ __launch_bounds__(BX* GBY) void k_setup(Geo g, const float* __restric
 // ends of the step: X = -(u1 + Interp(u0, i - u1)) / 2 (end point i at t_{n+1}),
 // Y = +(u0 + Interp(u1, i + u0)) / 2 (start point i at t_n), R = Interp(r1, i + Y),
 // a = 1 + dt/2 [R + (1 + dt R) r0].  With v0 = v1 these are the stationary formulas.
+// (every step n of the time grid in one launch: n = blockIdx.y, v0 = V[n], v1 = V[n + 1] with
+// dim + 1 planes per node, X[n], YA[n])
 template <int DIM>
-__global__ __launch_bounds__(BX* GBY) void k_setup_ns(Geo g, const float* __restrict__ v0,
-                                                      const float* __restrict__ v1,
-                                                      float* __restrict__ X,
-                                                      float4* __restrict__ YA) {
+__global__ __launch_bounds__(BX* GBY) void k_setup_ns(Geo g, const float* __restrict__ V,
+                                                      float* __restrict__ Xall,
+                                                      float4* __restrict__ YAall) {
   constexpr int ZV = 1;
   GATHER_XY
   GATHER_Z(0)
   (void)live;
   const size_t M = (size_t)g.M;
+  const size_t n = blockIdx.y;
+  const float* __restrict__ v0 = V + n * (DIM + 1) * M;
+  const float* __restrict__ v1 = v0 + (DIM + 1) * M;
+  float* __restrict__ X = Xall + n * DIM * M;
+  float4* __restrict__ YA = YAall + n * M;
   const float s = g.dt * (float)g.nref;
   float u0[3] = {0.f, 0.f, 0.f}, u1[3] = {0.f, 0.f, 0.f};
   for (int c = 0; c < DIM; ++c) {
@@ -711,8 +717,12 @@ inline dim3 gather_grid(const Geo& g, int zv) {
 void setup(const Geo& g, const float* v, float* X, float4* YA, hipStream_t s) {
   DISPATCH_ONE(k_setup, g, v, X, YA);
 }
-void setup_ns(const Geo& g, const float* v0, const float* v1, float* X, float4* YA, hipStream_t s) {
-  DISPATCH_ONE(k_setup_ns, g, v0, v1, X, YA);
+void setup_ns(const Geo& g, const float* V, float* X, float4* YA, int steps, hipStream_t s) {
+  const dim3 grid(gather_grid(g, 1).x, (unsigned)steps);
+  if (g.dim == 3)
+    hipLaunchKernelGGL(k_setup_ns<3>, grid, dim3(BX, GBY), 0, s, g, V, X, YA);
+  else
+    hipLaunchKernelGGL(k_setup_ns<2>, grid, dim3(BX, GBY), 0, s, g, V, X, YA);
 }
 void body_nodes(const Geo& g, const float* lam, const float* m, float* b, int nodes,
                 hipStream_t s) {
