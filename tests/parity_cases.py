@@ -25,6 +25,9 @@ CASES = {
     # incompressible H^1 (gamma = 1, s = 1): non-cubic 3D and 2D
     "h1_incomp_3d": (3, (40, 48, 36), (10, 12, 8), 6, 3.0, 5),
     "h1_incomp_2d": (2, (64, 64), (16, 16), 10, 4.0, 0),
+    # a strongly anisotropic band (2 x 66 x 4): the deformation method's fused yx kernels then
+    # give each thread two band entries (ky * 4 > 256), within their LDS limits
+    "aniso_band_3d": (3, (8, 72, 12), (2, 66, 4), 4, 1.0, 3),
 }
 # regulariser and flow model per case (default alpha = 1e-3, s = 2, gamma = 0)
 MODEL = {

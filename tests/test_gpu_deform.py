@@ -15,7 +15,7 @@ from parity_cases import bl_problem, case, grad_error, rel2
 
 pytestmark = pytest.mark.gpu
 
-CASES = ["c1_2d", "ragged_3d", "brainlike_small", "h1_incomp_2d", "h1_incomp_3d"]
+CASES = ["c1_2d", "ragged_3d", "brainlike_small", "h1_incomp_2d", "h1_incomp_3d", "aniso_band_3d"]
 
 
 def _log(*a):
@@ -113,7 +113,7 @@ def test_deform_flag_combinations_rejected(gpu_lib):
         assert e.value.code == B.BL_E_UNSUPPORTED
 
 
-@pytest.mark.parametrize("name", ["ragged_3d", "c2_full"])
+@pytest.mark.parametrize("name", ["ragged_3d", "aniso_band_3d", "c2_full"])
 def test_fused_stage_kernels_match_unfused(gpu_lib, name, monkeypatch):
     """the fused product-grid stage kernels (default for 3D) and the unfused kernel chain compute
     the same E, g and H v up to FP32 rounding order"""
