@@ -10,12 +10,16 @@
 //           products (and their side outputs), and the z contraction of pi, the column's z
 //           values exchanged through LDS; two lanes per column split the kz spectrum.
 //   3. yx:  G[c][h][y][x] -> the band: the x and y contractions of pi for one (component, h)
-//           plane and a chunk of kx, the G plane staged in LDS, followed by the band-side update
-//           of the stage (forward) or of the transposed sweep (backward) at kz = h and at the
+//           plane and a chunk of kx, the G plane staged in LDS (the transposed sweep stages
+//           its three derivative planes together), followed by the band-side update of the
+//           stage (forward) or of the transposed sweep (backward) at kz = h and at the
 //           conjugate-mirror index -k.  On the kz = 0 plane the entry k is owned by the half
 //           ky > 0 or (ky = 0, kx >= 0); its owner writes k and -k, so the result is exactly
 //           Hermitian, and k = 0 takes the real part.
 // Twiddle tables are those of the product grid's transform plan (bl_dft.hip layout).
+// These kernels are bound by memory latency at ~1.5 waves per SIMD, so every global load a
+// phase needs is issued before its first wait: no load sits behind a condition (a guarded load
+// compiles to a branch and a wait) and no runtime loop alternates loads and LDS stores.
 #include "bl_internal.h"
 
 #include <mutex>
