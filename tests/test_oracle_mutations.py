@@ -446,12 +446,27 @@ def pin_ns_stationary_limit(O):
             and np.allclose(Hs, H, rtol=0, atol=1e-12 * np.abs(H).max()))
 
 
+def pin_mse_rel(O):
+    """MSE_rel (reading R-MSE) on the hand-worked 2 x 2 example (100 / 13) and exactly 100 %
+    at the zero initial guess of a registration"""
+    I0 = np.array([[0.5, 0.0], [1.0, 1.0]])
+    I1 = np.array([[2.0, 0.0], [1.0, 0.0]])
+    mT = np.array([[2.0, 0.5], [1.0, 0.0]])
+    if abs(O.mse_rel(mT, I0, I1) - 100.0 / 13.0) > 1e-13:
+        return False
+    prob = O.Problem(2, (16, 12), (8, 4), 4)
+    J0 = phantoms.blobs_2d(3, 16)[:12, :16]
+    _, _, stats = O.register(J0, np.roll(J0, 1, axis=1), np.zeros((2,) + prob.bshape, complex),
+                             prob, O.SolverOpts(max_gn=1, max_pcg=2))
+    return abs(stats["mse_rel"][0] - 100.0) <= 4e-14
+
+
 PINS = [pin_bruteforce_dft, pin_projection, pin_symbol_fd, pin_divergence, pin_roll_and_identity,
         pin_interp_half_voxel, pin_gradient_closed_form, pin_hessvec_closed_form, pin_gradient_fd,
         pin_hessvec_fd_zero_residual, pin_energy_regulariser,
         pin_incremental_adjoint_is_the_adjoint, pin_symmetry_shift, pin_characteristics, pin_solver,
         pin_incompressible_projection, pin_incompressible_gradient, pin_newton_symmetric_on_permutations,
-        pin_newton_closed_form, pin_ns_characteristics, pin_ns_stationary_limit]
+        pin_newton_closed_form, pin_ns_characteristics, pin_ns_stationary_limit, pin_mse_rel]
 
 
 def run_pins(O):
@@ -530,6 +545,14 @@ MUTATIONS = [
      "reg = 0.5 * sum(w[n] * float(np.sum(Lh[None] * np.abs(geo[\"vh\"][n]) ** 2))",
      "reg = 0.5 * sum(float(np.sum(Lh[None] * np.abs(geo[\"vh\"][n]) ** 2))"),
     ("preconditioner inverted", "z = r / Lh[None]\n        p = z.copy()", "z = r * Lh[None]\n        p = z.copy()"),
+    ("MSE_rel over |I1|^2", "den = float(np.sum((np.asarray(I0, np.float64) - I1) ** 2))",
+     "den = float(np.sum(np.asarray(I1, np.float64) ** 2))"),
+    ("MSE_rel over |I0|^2", "den = float(np.sum((np.asarray(I0, np.float64) - I1) ** 2))",
+     "den = float(np.sum(np.asarray(I0, np.float64) ** 2))"),
+    ("MSE_rel without the percent factor", "return 100.0 * num / den if den > 0 else 0.0",
+     "return num / den if den > 0 else 0.0"),
+    ("MSE_rel residual against the source", "num = float(np.sum((np.asarray(mT, np.float64) - I1) ** 2))",
+     "num = float(np.sum((np.asarray(mT, np.float64) - I0) ** 2))"),
 ]
 
 

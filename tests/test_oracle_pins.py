@@ -569,6 +569,33 @@ def c1_problem(seed=0):
     return prob, I0, I1, vs
 
 
+def test_mse_rel_hand_computed_value():
+    """MSE_rel of Section 4.1 (reading R-MSE: 100 |m(1) - I1|^2 / |I0 - I1|^2 in percent) on a
+    2 x 2 example worked by hand: |m(1) - I1|^2 = 0.5^2 = 0.25, |I0 - I1|^2 = 1.5^2 + 1 = 3.25,
+    so the value is 100 / 13.  The alternatives a plausible mistake would give all differ:
+    |I1|^2 = 5 or |I0|^2 = 2.25 as the denominator (5, 11.1), a dropped factor 100 (0.077), or
+    m(1) compared with I0 instead of I1 (107.7)."""
+    I0 = np.array([[0.5, 0.0], [1.0, 1.0]])
+    I1 = np.array([[2.0, 0.0], [1.0, 0.0]])
+    mT = np.array([[2.0, 0.5], [1.0, 0.0]])
+    assert O.mse_rel(mT, I0, I1) == pytest.approx(7.6923076923076923, rel=1e-15, abs=0)
+    # no mismatch left and no motion at all are the two ends of the scale
+    assert O.mse_rel(I1, I0, I1) == 0.0
+    assert O.mse_rel(I0, I0, I1) == 100.0
+
+
+def test_mse_rel_starts_at_100_from_zero_velocity():
+    """at the zero initial guess every transport is the identity, so m(1) = I0 exactly and the
+    first MSE_rel of a registration is 100 % up to the rounding of 100 x / x"""
+    prob = O.Problem(2, (16, 12), (8, 4), 4)
+    I0 = phantoms.blobs_2d(3, 16)[:12, :16]
+    I1 = np.roll(I0, 1, axis=1)
+    _, _, stats = O.register(I0, I1, np.zeros((2,) + prob.bshape, complex), prob,
+                             O.SolverOpts(max_gn=1, max_pcg=2))
+    assert stats["mse_rel"][0] == pytest.approx(100.0, rel=4e-16, abs=0)
+    assert 0.0 < stats["mse_rel"][1] < 100.0
+
+
 def test_c1_recovery_of_known_warp():
     prob, I0, I1, vs = c1_problem(0)
     vh, mT, stats = O.register(I0, I1, np.zeros_like(vs), prob, O.SolverOpts())
