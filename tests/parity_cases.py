@@ -97,3 +97,56 @@ def grad_error(g_gpu, g_ref, prob, vh):
     pb = g_ref - Lv
     den = np.linalg.norm(Lv.ravel()) + np.linalg.norm(pb.ravel())
     return float(np.linalg.norm((np.asarray(g_gpu) - g_ref).ravel()) / den)
+
+
+def _components(a, lead):
+    """view with the first `lead` axes (component, or node and component) flattened into rows"""
+    a = np.asarray(a)
+    rows = int(np.prod(a.shape[:lead]))
+    return a.reshape(rows, -1)
+
+
+def elem_error(a, ref, lead=1):
+    """worst component of max_i |a_i - ref_i| / max_i |ref_i| (per velocity component, or per
+    node and component for non-stationary fields)"""
+    A, R = _components(a, lead), _components(ref, lead)
+    return float(max(np.abs(A[c] - R[c]).max() / np.abs(R[c]).max() for c in range(R.shape[0])))
+
+
+def grad_elem_error(g_gpu, g_ref, prob, vh):
+    """worst component of max |g - g_ref| / (max |L v| + max |pi(b)|): the element-wise form of
+    grad_error, with the regulariser and the data part normalised separately"""
+    Lv = O.L_hat(prob)[None] * O.project(vh, prob)
+    pb = g_ref - Lv
+    G, R = np.asarray(g_gpu), np.asarray(g_ref)
+    return float(max(np.abs(G[c] - R[c]).max() / (np.abs(Lv[c]).max() + np.abs(pb[c]).max())
+                     for c in range(R.shape[0])))
+
+
+def check_gradient(g_gpu, g_ref, prob, vh, tol, label=""):
+    """gradient parity in the 2-norm and element by element (both within tol); returns both"""
+    e2 = grad_error(g_gpu, g_ref, prob, vh)
+    ee = grad_elem_error(g_gpu, g_ref, prob, vh)
+    print(f"  {label} gradient rel err 2-norm {e2:.2e}, element-wise {ee:.2e}", flush=True)
+    assert e2 < tol and ee < tol, (label, e2, ee)
+    return e2, ee
+
+
+def check_hessvec(h_gpu, h_ref, tol, label="", lead=1):
+    """Hessian-vector parity in the 2-norm and element by element (both within tol)"""
+    e2 = rel2(h_gpu, h_ref)
+    ee = elem_error(h_gpu, h_ref, lead)
+    print(f"  {label} hessvec rel err 2-norm {e2:.2e}, element-wise {ee:.2e}", flush=True)
+    assert e2 < tol and ee < tol, (label, e2, ee)
+    return e2, ee
+
+
+def check_mse_rel(st_gpu, st_ref, rtol, label=""):
+    """the library's per-iteration MSE_rel statistic against the oracle's (same solver
+    decisions assumed: equal lengths)"""
+    a = np.asarray(st_gpu["mse_rel"], dtype=np.float64)
+    b = np.asarray(st_ref["mse_rel"], dtype=np.float64)
+    print(f"  {label} mse_rel gpu {a[-1]:.6f} oracle {b[-1]:.6f}, max rel diff "
+          f"{np.max(np.abs(a - b) / np.abs(b)):.2e}", flush=True)
+    assert a.shape == b.shape, (label, a.shape, b.shape)
+    assert np.all(np.abs(a - b) <= rtol * np.abs(b)), (label, a, b)

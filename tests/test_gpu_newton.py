@@ -10,7 +10,7 @@ import oracle as O
 from paper_1807_05117_amd import binding as B
 from paper_1807_05117_amd import phantoms
 
-from parity_cases import bl_problem, case, oracle_hessvec_newton, rel2
+from parity_cases import bl_problem, case, check_hessvec, check_mse_rel, oracle_hessvec_newton, rel2
 
 pytestmark = pytest.mark.gpu
 
@@ -28,9 +28,7 @@ def test_newton_hessvec_parity(gpu_lib, name, precision, tol):
     ctx.bl_lddmm_ctx_set_velocity(vh.astype(np.complex64))
     H2 = ctx.bl_lddmm_ctx_hessvec(dv.astype(np.complex64))
     ctx.close()
-    err = rel2(H1, oracle_hessvec_newton(name))
-    print(f"newton {name}: hessvec rel err {err:.2e}", flush=True)
-    assert err < tol
+    check_hessvec(H1, oracle_hessvec_newton(name), tol, f"newton {name}")
     assert np.array_equal(H1, H2)
 
 
@@ -78,3 +76,4 @@ def test_newton_register_c1_against_oracle(gpu_lib):
     assert st["pcg_iters"] == st_ref["pcg_iters"]
     assert st["ls_trials"] == st_ref["ls_trials"]
     assert np.allclose(st["E"], st_ref["E"], rtol=1e-4, atol=0)
+    check_mse_rel(st, st_ref, 1e-5, "newton c1_2d")

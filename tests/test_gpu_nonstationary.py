@@ -1,6 +1,7 @@
 """GPU parity of the non-stationary velocity (BL_NONSTATIONARY): one band field per time node,
 per-step offsets from both ends of a step, gradients and Gauss-Newton products per node,
-against the oracle's ns_* functions (relative 1e-5 plain, 1e-4 mixed), the stationary limit,
+against the oracle's ns_* functions (relative 1e-5 plain, 1e-4 mixed, in the 2-norm and per
+node and component element by element), the stationary limit,
 and a 2D registration with the oracle's solver decisions."""
 import functools
 
@@ -11,7 +12,7 @@ import oracle as O
 from paper_1807_05117_amd import binding as B
 from paper_1807_05117_amd import phantoms
 
-from parity_cases import bl_problem, case, rel2
+from parity_cases import bl_problem, case, check_hessvec, check_mse_rel, rel2
 
 pytestmark = pytest.mark.gpu
 
@@ -38,6 +39,14 @@ def _grad_err(g, gref, prob, V):
     return float(np.linalg.norm((np.asarray(g) - gref).ravel()) / den)
 
 
+def _grad_elem_err(g, gref, prob, V):
+    """worst (node, component) of max |dg| / (max |L v| + max |pi(b)|)"""
+    Lv = O.L_hat(prob)[None, None] * O.ns_project(V, prob)
+    G, R, L = (np.asarray(a).reshape(a.shape[0] * a.shape[1], -1) for a in (g, gref, Lv))
+    return float(max(np.abs(G[i] - R[i]).max() / (np.abs(L[i]).max() + np.abs(R[i] - L[i]).max())
+                     for i in range(R.shape[0])))
+
+
 @pytest.mark.parametrize("precision,tol", [(B.BL_FP32, 1e-5), (B.BL_MIXED, 1e-4)],
                          ids=["fp32", "mixed"])
 @pytest.mark.parametrize("name", CASES)
@@ -47,9 +56,11 @@ def test_ns_gradient_and_hessvec(gpu_lib, name, precision, tol):
     E, g = ctx.bl_lddmm_ctx_set_velocity(V.astype(np.complex64))
     H = ctx.bl_lddmm_ctx_hessvec(D.astype(np.complex64))
     ctx.close()
-    eg, eh = _grad_err(g, gref, prob, V), rel2(H, href)
-    print(f"non-stationary {name}: gradient rel err {eg:.2e}, hessvec {eh:.2e}", flush=True)
-    assert eg < tol and eh < tol
+    eg, ee = _grad_err(g, gref, prob, V), _grad_elem_err(g, gref, prob, V)
+    print(f"non-stationary {name}: gradient rel err 2-norm {eg:.2e}, element-wise {ee:.2e}",
+          flush=True)
+    assert eg < tol and ee < tol
+    check_hessvec(H, href, tol, f"non-stationary {name}", lead=2)
     assert abs(E - st.E) <= tol * st.E
 
 
@@ -84,4 +95,5 @@ def test_ns_register_2d_against_oracle(gpu_lib):
     assert st["pcg_iters"] == st_ref["pcg_iters"]
     assert st["ls_trials"] == st_ref["ls_trials"]
     assert np.allclose(st["E"], st_ref["E"], rtol=1e-4, atol=0)
+    check_mse_rel(st, st_ref, 1e-5, "non-stationary c1_2d")
     assert rel2(v_gpu, v_ref) < 1e-3

@@ -97,6 +97,33 @@ def test_model_variants_identical_alone_and_in_mix(gpu_lib):
     srv.close()
 
 
+def test_served_pair_matches_oracle(gpu_lib, pairs):
+    """a 3D pair registered by the serving loop (in a mix with the other pairs) against the
+    FP64 oracle's registration: solver decisions, energies, MSE_rel, final v~ and m(1)"""
+    g, k, nt, prec, _ = MIX[0]
+    prob = O.Problem(3, g, k, nt)
+    I0, I1 = pairs[0]
+    opts = B.opts_struct(max_gn=4, max_pcg=5)
+    srv = B.Server(max_slots=3)
+    tickets = [srv.submit(_problem(i), *pairs[i], opts=opts) for i in range(3)]
+    res = [srv.wait(t) for t in tickets]
+    srv.close()
+    rc, v, w, st, _ = res[0]
+    assert rc == B.BL_OK
+    v_ref, m_ref, st_ref = O.register(I0.astype(np.float64), I1.astype(np.float64),
+                                      np.zeros((3,) + prob.bshape, complex), prob,
+                                      O.SolverOpts(max_gn=4, max_pcg=5))
+    print("served", st["pcg_iters"], st["ls_trials"], " oracle", st_ref["pcg_iters"],
+          st_ref["ls_trials"], flush=True)
+    assert st["status"] == st_ref["status"]
+    assert st["pcg_iters"] == st_ref["pcg_iters"]
+    assert st["ls_trials"] == st_ref["ls_trials"]
+    assert np.allclose(st["E"], st_ref["E"], rtol=1e-5, atol=0)
+    assert np.allclose(st["mse_rel"], st_ref["mse_rel"], rtol=1e-5, atol=0)
+    assert np.linalg.norm((v - v_ref).ravel()) < 1e-3 * np.linalg.norm(v_ref.ravel())
+    assert np.abs(w - m_ref).max() < 1e-4 * np.abs(m_ref).max()
+
+
 def test_budget_limits_resident_pairs(gpu_lib, pairs):
     p0 = _problem(0)
     fp = B.bl_lddmm_footprint(p0)
