@@ -235,27 +235,35 @@ def cpu_leg(stats):
 SERVE_SIZES = [(96, 96, 96), (128, 128, 128), (160, 192, 160)]
 
 
+def _serve_phantom(args):
+    seed, shp = args
+    return phantoms.shells_3d(seed, shp, n_classes=3 if shp[0] < 160 else 5).astype(np.float32)
+
+
 def serve_leg(n_pairs=64, rate=4.0, slots=8, seed=1000):
     """Continuous-batching request loop on a stream of registration pairs of mixed sizes:
     grids uniform over 96^3, 128^3 and 160x192x160, band = grid/4 per axis, Nt in {5, 10},
-    per-pair velocity seeds (6 voxels).  Three runs over the same pairs: sequential plain FP32
-    (one bl_lddmm_register after the other), saturated mixed-precision serving (all pairs
-    queued at t = 0) and open-loop mixed-precision serving with Poisson arrivals."""
+    per-pair phantom and velocity seeds (6 voxels).  Runs over the same pairs: sequential plain
+    FP32 (one bl_lddmm_register after the other), saturated serving (all pairs queued at
+    t = 0) by the slot-thread server and by the cohort server, and open-loop serving with
+    Poisson arrivals by the cohort server."""
+    from concurrent.futures import ThreadPoolExecutor
+
     rng = np.random.default_rng(seed)
-    base = {}
-    for i, shp in enumerate(SERVE_SIZES):
-        base[shp] = phantoms.shells_3d(seed + i, shp, n_classes=3 if i < 2 else 5).astype(np.float32)
+    shapes = [SERVE_SIZES[int(rng.integers(len(SERVE_SIZES)))] for _ in range(n_pairs)]
+    nts = [int(rng.choice([5, 10])) for _ in range(n_pairs)]
+    with ThreadPoolExecutor(max_workers=8) as ex:   # NumPy releases the GIL in the bulk work
+        sources = list(ex.map(_serve_phantom, [(seed + 100 + i, shapes[i]) for i in range(n_pairs)]))
     pairs = []
     for i in range(n_pairs):
-        shp = SERVE_SIZES[int(rng.integers(len(SERVE_SIZES)))]
-        nt = int(rng.choice([5, 10]))
+        shp, nt = shapes[i], nts[i]
         band = tuple(n // 4 for n in shp)
         raw = phantoms.raw_band_velocity(seed + 10 + i, 3, band).astype(np.complex64)
         p = B.make_problem(3, shp, band, nt)
         v = B.bl_band_to_grid(p, raw)
         vmax = float(np.sqrt((v.astype(np.float64) ** 2).sum(axis=0)).max()) * max(shp)
-        I1 = B.bl_lddmm_warp(p, base[shp], (raw * (DISP / vmax)).astype(np.complex64))
-        pairs.append((shp, band, nt, base[shp], I1))
+        I1 = B.bl_lddmm_warp(p, sources[i], (raw * (DISP / vmax)).astype(np.complex64))
+        pairs.append((shp, band, nt, sources[i], I1))
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_pairs))
     progress(f"serving: {n_pairs} pairs ready; sequential FP32")
 
@@ -263,16 +271,21 @@ def serve_leg(n_pairs=64, rate=4.0, slots=8, seed=1000):
         shp, band, nt, _, _ = pairs[i]
         return B.make_problem(3, shp, band, nt, precision=precision)
 
-    seq_mse = []
-    t0 = time.perf_counter()
-    for i, (shp, band, nt, I0, I1) in enumerate(pairs):
-        v0 = np.zeros(B.band_shape(prob(i, B.BL_FP32)), np.complex64)
-        _, _, st = B.bl_lddmm_register(prob(i, B.BL_FP32), I0, I1, v0)
-        seq_mse.append(st["mse_rel"][-1])
-    t_seq = time.perf_counter() - t0
+    def sequential(precision):
+        mse, vs = [], []
+        t0 = time.perf_counter()
+        for i, (shp, band, nt, I0, I1) in enumerate(pairs):
+            v0 = np.zeros(B.band_shape(prob(i, precision)), np.complex64)
+            v, _, st = B.bl_lddmm_register(prob(i, precision), I0, I1, v0)
+            mse.append(st["mse_rel"][-1])
+            vs.append(v)
+        return time.perf_counter() - t0, mse, vs
 
-    def serve(arrive):
-        srv = B.Server(max_slots=slots)
+    t_seq, seq_mse, _ = sequential(B.BL_FP32)
+    B.bl_lddmm_release_cached()
+
+    def serve(arrive, batched, precision):
+        srv = B.Server(max_slots=slots, batched=batched)
         t_start = time.perf_counter()
         tickets = []
         for i, (shp, band, nt, I0, I1) in enumerate(pairs):
@@ -280,40 +293,52 @@ def serve_leg(n_pairs=64, rate=4.0, slots=8, seed=1000):
                 delay = arrive[i] - (time.perf_counter() - t_start)
                 if delay > 0:
                     time.sleep(delay)
-            tickets.append(srv.submit(prob(i, B.BL_MIXED), I0, I1))
-        lat, mse = [], []
+            tickets.append(srv.submit(prob(i, precision), I0, I1))
+        lat, mse, vs = [], [], []
         for t in tickets:
-            rc, _, _, st, tm = srv.wait(t)
+            rc, v, _, st, tm = srv.wait(t)
             if rc != B.BL_OK:
                 raise RuntimeError(f"serving request failed: {rc}")
             lat.append(tm["finished"] - tm["submitted"])
             mse.append(st["mse_rel"][-1])
+            vs.append(v)
         wall = time.perf_counter() - t_start
         info = srv.info()
         srv.close()
-        return wall, lat, mse, info
+        return dict(wall=wall, lat=lat, mse=mse, info=info, v=vs)
 
-    progress("serving: saturated")
-    w_sat, lat_sat, mse_sat, info_sat = serve(None)
-    progress("serving: Poisson arrivals")
-    w_poi, lat_poi, mse_poi, info_poi = serve(arrivals)
-    dm = [abs(a - b) / max(abs(b), 1e-12) for a, b in zip(mse_sat, seq_mse)]
+    def record(r):
+        return {"registrations_per_min": 60.0 * n_pairs / r["wall"], "seconds": r["wall"],
+                "p50_ms": 1000 * percentile(r["lat"], 50), "p99_ms": 1000 * percentile(r["lat"], 99),
+                "peak_resident": r["info"]["peak_resident"],
+                "peak_gb": r["info"]["peak_bytes"] / 1e9,
+                "final_mse_rel_max_rel_diff_vs_fp32": max(
+                    abs(a - b) / max(abs(b), 1e-12) for a, b in zip(r["mse"], seq_mse))}
+
+    progress("serving: saturated, slot threads (mixed)")
+    thr = serve(None, False, B.BL_MIXED)
+    progress("serving: saturated, cohorts (mixed)")
+    coh = serve(None, True, B.BL_MIXED)
+    progress("serving: saturated, cohorts (fp32)")
+    coh32 = serve(None, True, B.BL_FP32)
+    progress("serving: Poisson arrivals, cohorts (mixed)")
+    poi = serve(arrivals, True, B.BL_MIXED)
+    # the cohort server's results are bitwise those of one-pair registrations
+    t_seqm, _, seqm_v = sequential(B.BL_MIXED)
+    identical = all(np.array_equal(a, b) for a, b in zip(coh["v"], seqm_v))
     return {
         "pairs": n_pairs, "slots": slots,
         "grids": [list(g) for g in SERVE_SIZES], "band": "grid/4", "nt": [5, 10],
+        "phantoms": "per-pair seeds",
         "sequential_fp32": {"registrations_per_min": 60.0 * n_pairs / t_seq, "seconds": t_seq},
-        "saturated_mixed": {"registrations_per_min": 60.0 * n_pairs / w_sat, "seconds": w_sat,
-                            "p50_ms": 1000 * percentile(lat_sat, 50),
-                            "p99_ms": 1000 * percentile(lat_sat, 99),
-                            "peak_resident": info_sat["peak_resident"],
-                            "peak_gb": info_sat["peak_bytes"] / 1e9},
-        "poisson_mixed": {"rate_per_s": rate, "seconds": w_poi,
-                          "registrations_per_min": 60.0 * n_pairs / w_poi,
-                          "p50_ms": 1000 * percentile(lat_poi, 50),
-                          "p99_ms": 1000 * percentile(lat_poi, 99),
-                          "peak_resident": info_poi["peak_resident"]},
-        "speedup_saturated_vs_sequential_fp32": t_seq / w_sat,
-        "final_mse_rel_max_rel_diff_vs_fp32": max(dm),
+        "sequential_mixed": {"registrations_per_min": 60.0 * n_pairs / t_seqm, "seconds": t_seqm},
+        "saturated_mixed_slot_threads": record(thr),
+        "saturated_mixed_cohorts": record(coh),
+        "saturated_fp32_cohorts": record(coh32),
+        "poisson_mixed_cohorts": dict(record(poi), rate_per_s=rate),
+        "speedup_saturated_vs_sequential_fp32": t_seq / coh["wall"],
+        "speedup_slot_threads_vs_sequential_fp32": t_seq / thr["wall"],
+        "cohort_results_bitwise_equal_to_one_pair_mixed": identical,
     }
 
 
@@ -494,6 +519,7 @@ def main():
         "cpu_baseline": None,
     }
     if not args.no_serve:
+        B.bl_lddmm_release_cached()
         line["serving"] = serve_leg()
     if not args.no_cpu:
         progress("oracle baseline on the host")

@@ -318,6 +318,26 @@ typedef struct {
 } bl_server_info;
 
 int bl_server_create(uint64_t budget_bytes, int32_t max_slots, bl_server** server);
+/*
+ * Cohort server: the same queue, budget, submit / wait / cancel / info / destroy calls, a
+ * different engine.  Requests of equal problems (grid, band, Nt, alpha, s, sigma, gamma,
+ * precision) share a cohort of up to max_pairs (1..64) resident pairs; every kernel of the
+ * Gauss-Newton-Krylov path is one launch for all pairs of a cohort (each pair's buffers at a
+ * fixed stride of one arena, a per-pair gate in device memory), and each Newton step -- up to
+ * 10 PCG iterations with their stopping tests evaluated on the device, the line-search slope,
+ * one Armijo trial, and the gradient at an accepted trial -- is one replay of a HIP graph
+ * captured when the cohort is created.  The host reads one control block per pair after a
+ * step, records the statistics, retires finished pairs and fills free slots with queued
+ * requests of the same problem.  The budget is charged with each cohort's whole arena while
+ * the cohort exists (capacity = min(max_pairs, free budget / footprint)); an empty cohort is
+ * freed when a request of another problem needs the memory.  The queue is strictly FIFO.
+ * Every result is bitwise the one bl_lddmm_register gives alone (same per-element arithmetic,
+ * same reduction order, the same FP64 decisions).  Only the stationary Gauss-Newton
+ * state-equation model is served (gamma 0 or 1, BL_FP32 or BL_MIXED): a request with
+ * BL_NEWTON, BL_NONSTATIONARY or BL_DEFORMATION completes at once with BL_E_UNSUPPORTED.
+ * bl_request_times.slot is the pair's slot within its cohort.
+ */
+int bl_server_create_batched(uint64_t budget_bytes, int32_t max_pairs, bl_server** server);
 int bl_server_submit(bl_server* server, const bl_problem* prob, const bl_solver_opts* opts,
                      const float* I0, const float* I1, const float* v_hat, uint64_t* ticket);
 int bl_server_wait(bl_server* server, uint64_t ticket, double timeout_s, float* v_hat,

@@ -126,6 +126,7 @@ def load():
         "bl_kernel_timing_read": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
         "bl_lddmm_ctx_launch_shapes": (C.c_int, [_P, C.POINTER(C.c_int32)]),
         "bl_server_create": (C.c_int, [C.c_uint64, C.c_int32, C.POINTER(C.c_void_p)]),
+        "bl_server_create_batched": (C.c_int, [C.c_uint64, C.c_int32, C.POINTER(C.c_void_p)]),
         "bl_server_submit": (C.c_int, [_P, PP, C.POINTER(SolverOpts), _P, _P, _P,
                                        C.POINTER(C.c_uint64)]),
         "bl_server_wait": (C.c_int, [_P, C.c_uint64, C.c_double, _P, _P, C.POINTER(Stats),
@@ -391,12 +392,14 @@ class Ctx:
 # ----------------------------------------------------------------------------- serving
 class Server:
     """The registration request loop (bl_server_*): submit returns a ticket immediately;
-    wait returns (rc, v_hat, warped, stats, times)."""
+    wait returns (rc, v_hat, warped, stats, times).  batched=True: the cohort engine
+    (bl_server_create_batched, max_slots = pairs per cohort)."""
 
-    def __init__(self, budget_bytes=0, max_slots=4):
+    def __init__(self, budget_bytes=0, max_slots=4, batched=False):
         self.lib = load()
         h = C.c_void_p()
-        _check(self.lib.bl_server_create(int(budget_bytes), int(max_slots), C.byref(h)))
+        create = self.lib.bl_server_create_batched if batched else self.lib.bl_server_create
+        _check(create(int(budget_bytes), int(max_slots), C.byref(h)))
         self.h = h
         self._shapes = {}
 

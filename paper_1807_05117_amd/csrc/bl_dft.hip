@@ -50,9 +50,12 @@ __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_rea
 __global__ __launch_bounds__(64) void k_iota_x(Geo g, const float2* __restrict__ band,
                                                const float2* __restrict__ tw_x,
                                                float2* __restrict__ F1) {
+  BL_BATCH(g.bat)
+  BL_AT(band, g.bat);
+  BL_AT(F1, g.bat);
   const int x = blockIdx.x * 64 + threadIdx.x;
   const int jy = blockIdx.y;
-  const int ch = blockIdx.z;
+  const int ch = batch_bz(g.bat, bpair_);
   if (x >= g.nx) return;
   const int c = ch / g.kzh, h = ch - c * g.kzh;
   const float2* row = band + ((size_t)(c * g.kz + g.kz0 + h) * g.ky + jy) * g.kx;
@@ -78,9 +81,12 @@ __global__ __launch_bounds__(64) void k_iota_x(Geo g, const float2* __restrict__
 __global__ __launch_bounds__(64) void k_iota_y(Geo g, const float2* __restrict__ F1,
                                                const float2* __restrict__ tw_y, int nyp,
                                                float2* __restrict__ F2) {
+  BL_BATCH(g.bat)
+  BL_AT(F1, g.bat);
+  BL_AT(F2, g.bat);
   const int x = blockIdx.x * 64 + threadIdx.x;
   const int y0 = blockIdx.y * kYG;
-  const int ch = blockIdx.z;
+  const int ch = batch_bz(g.bat, bpair_);
   if (x >= g.nx) return;
   const float2* col = F1 + (size_t)ch * g.ky * g.nx + x;
   float2 acc[kYG];
@@ -112,12 +118,15 @@ template <int KZH>
 __global__ __launch_bounds__(256) void k_iota_z(Geo g, const float2* __restrict__ F2,
                                                 const float2* __restrict__ tw_zT,
                                                 float* __restrict__ out, int zchunk) {
+  BL_BATCH(g.bat)
+  BL_AT(F2, g.bat);
+  BL_AT(out, g.bat);
   extern __shared__ float4 tws4[];   // zchunk rows of KZH (even) or 2 (KZH == 1) float2
   constexpr int RW = KZH == 1 ? 2 : KZH;   // row width in float2
   float2* tws = reinterpret_cast<float2*>(tws4);
   const int nq = g.nx * g.ny;
   const int q = blockIdx.x * 256 + threadIdx.x;
-  const int c = blockIdx.z;
+  const int c = batch_bz(g.bat, bpair_);
   const int zmax = g.nz / 2;
   const int z0 = blockIdx.y * zchunk;
   for (int i = threadIdx.x; i < zchunk * RW; i += 256) {
@@ -165,6 +174,9 @@ template <int KZH>
 __global__ __launch_bounds__(64 * kNW) void k_pi_z(Geo g, const float* __restrict__ f,
                                                    const float2* __restrict__ tw_zT,
                                                    float2* __restrict__ G) {
+  BL_BATCH(g.bat)
+  BL_AT(f, g.bat);
+  BL_AT(G, g.bat);
   constexpr int CH = (KZH % 8 == 0) ? 8 : ((KZH % 4 == 0) ? 4 : 1);
   __shared__ float2 sh[kNW - 1][CH][64];
   const int nq = g.nx * g.ny;
@@ -228,12 +240,15 @@ constexpr int kYS = 8;
 __global__ __launch_bounds__(64 * kYS) void k_pi_y(Geo g, const float2* __restrict__ G,
                                                    const float2* __restrict__ tw_yT, int kyp,
                                                    int yseg, float2* __restrict__ H) {
+  BL_BATCH(g.bat)
+  BL_AT(G, g.bat);
+  BL_AT(H, g.bat);
   __shared__ float2 sh[kYS - 1][kJG][64];
   const int tx = threadIdx.x;
   const int sgm = wave_uniform(threadIdx.y);
   const int x = blockIdx.x * 64 + tx;
   const int j0 = blockIdx.y * kJG;
-  const int ch = blockIdx.z;
+  const int ch = batch_bz(g.bat, bpair_);
   const int xc = x < g.nx ? x : g.nx - 1;
   const float2* col = G + (size_t)ch * g.ny * g.nx + xc;
   float2 acc[kJG];
@@ -284,6 +299,9 @@ __global__ __launch_bounds__(64 * kXS) void k_pi_x(Geo g, int rows, int xseg,
                                                    const float2* __restrict__ H,
                                                    const float2* __restrict__ tw_xT,
                                                    float2* __restrict__ P) {
+  BL_BATCH(g.bat)
+  BL_AT(H, g.bat);
+  BL_AT(P, g.bat);
   __shared__ float2 sh[kXS - 1][64];
   const int tx = threadIdx.x;
   const int sgm = wave_uniform(threadIdx.y);
@@ -378,6 +396,11 @@ __global__ __launch_bounds__(256) void k_band_prep(Geo g, const float2* __restri
                                                    double* __restrict__ reg_partial,
                                                    double reg_weight, int reg_accumulate,
                                                    size_t nstride) {
+  BL_BATCH(g.bat)
+  BL_AT(raw, g.bat);
+  BL_AT(out, g.bat);
+  BL_AT(Lhat64, g.bat);
+  BL_AT(reg_partial, g.bat);
   __shared__ double sh[256];
   double acc = 0.0;
   const int B = (int)g.B;
@@ -445,6 +468,12 @@ __global__ __launch_bounds__(256) void k_band_finalize(Geo g,
                                                        int* __restrict__ nonfinite, int leray_on,
                                                        size_t vstride, size_t pstride,
                                                        size_t ostride) {
+  BL_BATCH(g.bat)
+  BL_AT(vproj, g.bat);
+  BL_AT(Lhat, g.bat);
+  BL_AT(P, g.bat);
+  BL_AT(out, g.bat);
+  BL_AT(nonfinite, g.bat);
   const int B = (int)g.B;
   if (vproj) vproj += blockIdx.y * vstride;   // node blockIdx.y
   P += blockIdx.y * pstride;
@@ -521,11 +550,11 @@ void launch_z_pair(const Geo& g, const DftPlan& p, const float2* F2, float* out,
     const int zchunk = (npair + nchunk - 1) / nchunk;
     nchunk = (npair + zchunk - 1) / zchunk;
     const size_t lds = (size_t)zchunk * (KZH == 1 ? 2 : KZH) * sizeof(float2);
-    hipLaunchKernelGGL(k_iota_z<KZH>, dim3(qblocks, nchunk, C), dim3(256), lds, s, g, F2,
-                       p.tw_zT, out, zchunk);
+    hipLaunchKernelGGL(k_iota_z<KZH>, batch_grid(dim3(qblocks, nchunk, C), g.bat), dim3(256), lds,
+                       s, g, F2, p.tw_zT, out, zchunk);
   } else {
-    hipLaunchKernelGGL(k_pi_z<KZH>, dim3((nq + 63) / 64, C), dim3(64, kNW), 0, s, g, f,
-                       p.tw_zT, G);
+    hipLaunchKernelGGL(k_pi_z<KZH>, batch_grid(dim3((nq + 63) / 64, C), g.bat), dim3(64, kNW), 0,
+                       s, g, f, p.tw_zT, G);
   }
 }
 
@@ -548,9 +577,10 @@ void z_stage(const Geo& g, const DftPlan& p, const float2* F2, float* out, int C
 
 void iota(const Geo& g, const DftPlan& p, const float2* band, int C, float* out, hipStream_t s) {
   const int xb = (g.nx + 63) / 64;
-  hipLaunchKernelGGL(k_iota_x, dim3(xb, g.ky, C * g.kzh), dim3(64), 0, s, g, band, p.tw_x, p.bufA);
-  hipLaunchKernelGGL(k_iota_y, dim3(xb, p.nyp / kYG, C * g.kzh), dim3(64), 0, s, g, p.bufA, p.tw_y,
-                     p.nyp, p.bufB);
+  hipLaunchKernelGGL(k_iota_x, batch_grid(dim3(xb, g.ky, C * g.kzh), g.bat), dim3(64), 0, s, g,
+                     band, p.tw_x, p.bufA);
+  hipLaunchKernelGGL(k_iota_y, batch_grid(dim3(xb, p.nyp / kYG, C * g.kzh), g.bat), dim3(64), 0,
+                     s, g, p.bufA, p.tw_y, p.nyp, p.bufB);
   if (p.mixed)
     iota_z_mixed(g, p, p.bufB, C, out, s);
   else
@@ -564,12 +594,12 @@ void pi_half(const Geo& g, const DftPlan& p, const float* grid, int C, float2* P
   else
     z_stage(g, p, nullptr, nullptr, C, grid, p.bufA, s, false);
   const int yseg = ((g.ny + kYS - 1) / kYS + kUY - 1) / kUY * kUY;
-  hipLaunchKernelGGL(k_pi_y, dim3(xb, p.kyp / kJG, C * g.kzh), dim3(64, kYS), 0, s, g, p.bufA,
-                     p.tw_yT, p.kyp, yseg, p.bufB);
+  hipLaunchKernelGGL(k_pi_y, batch_grid(dim3(xb, p.kyp / kJG, C * g.kzh), g.bat), dim3(64, kYS),
+                     0, s, g, p.bufA, p.tw_yT, p.kyp, yseg, p.bufB);
   const int rows = C * g.kzh * g.ky;
   const int xseg = ((g.nx + kXS - 1) / kXS + kU - 1) / kU * kU;
-  hipLaunchKernelGGL(k_pi_x, dim3((rows * g.kx + 63) / 64), dim3(64, kXS), 0, s, g, rows, xseg,
-                     p.bufB, p.tw_xT, P);
+  hipLaunchKernelGGL(k_pi_x, batch_grid(dim3((rows * g.kx + 63) / 64), g.bat), dim3(64, kXS), 0,
+                     s, g, rows, xseg, p.bufB, p.tw_xT, P);
 }
 
 void band_prep(const Geo& g, const float2* raw, float2* out, int with_div, const double* Lhat64,
@@ -578,13 +608,13 @@ void band_prep(const Geo& g, const float2* raw, float2* out, int with_div, const
   // band entry
   const int blocks = reg_partial ? kRedBlocks : (int)((g.B + 255) / 256);
   if (g.dim == 3)
-    hipLaunchKernelGGL(k_band_prep<3>, dim3(blocks), dim3(256), 0, s, g, raw, out, with_div,
+    hipLaunchKernelGGL(k_band_prep<3>, batch_grid(dim3(blocks), g.bat), dim3(256), 0, s, g, raw, out, with_div,
                        Lhat64, reg_partial, reg_weight, reg_accumulate, (size_t)0);
   else if (g.dim == 2)
-    hipLaunchKernelGGL(k_band_prep<2>, dim3(blocks), dim3(256), 0, s, g, raw, out, with_div,
+    hipLaunchKernelGGL(k_band_prep<2>, batch_grid(dim3(blocks), g.bat), dim3(256), 0, s, g, raw, out, with_div,
                        Lhat64, reg_partial, reg_weight, reg_accumulate, (size_t)0);
   else
-    hipLaunchKernelGGL(k_band_prep<1>, dim3(blocks), dim3(256), 0, s, g, raw, out, with_div,
+    hipLaunchKernelGGL(k_band_prep<1>, batch_grid(dim3(blocks), g.bat), dim3(256), 0, s, g, raw, out, with_div,
                        Lhat64, reg_partial, reg_weight, reg_accumulate, (size_t)0);
 }
 
@@ -612,7 +642,8 @@ void band_finalize_nodes(const Geo& g, int C, const float2* vproj, size_t vstrid
   const dim3 blocks((unsigned)std::min(4096, (int)((g.B + 255) / 256)), (unsigned)nodes);
   const int on = (leray && g.gamma && C == g.dim) ? 1 : 0;
 #define BF_LAUNCH(D, CC)                                                                        \
-  hipLaunchKernelGGL((k_band_finalize<D, CC>), blocks, dim3(256), 0, s, g, vproj, Lhat, P,      \
+  hipLaunchKernelGGL((k_band_finalize<D, CC>), batch_grid(blocks, g.bat), dim3(256), 0, s, g,     \
+                     vproj, Lhat, P,                                                            \
                      scale, out, nonfinite, on, vstride, pstride, ostride)
   if (g.dim == 3) {
     switch (C) {

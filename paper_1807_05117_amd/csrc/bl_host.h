@@ -151,6 +151,13 @@ void load_band(bl_ctx* c, const float* src, float2* dst, int ncomp);
 void store_band(bl_ctx* c, const float2* src, float* dst, int ncomp);
 void store_plane(bl_ctx* c, const float* src, float* dst, size_t nplanes);
 void solve(bl_ctx* c, const bl_solver_opts& o, bl_stats* st);
+// operator sequences on a context (enqueued on c->stream; launches follow c->g.bat)
+void enqueue_set_velocity(bl_ctx* c, const float2* vraw);   // stationary state equation only
+void op_set_velocity(bl_ctx* c, const float2* vraw);        // enqueue, synchronise, read E
+void op_gradient(bl_ctx* c, float2* gout);
+void op_hessvec(bl_ctx* c, const float2* draw, float2* hout);
+void vec_dot_partial(bl_ctx* c, const float2* a, const float2* b, double* pa);
+void choose_launch_shapes(bl_ctx* c);
 
 template <class F>
 int guarded(F&& f) {

@@ -8,6 +8,47 @@
 
 namespace bl {
 
+// Several problems of one shape in one launch (the batched serving engine).  Problem p's
+// device buffers lie p * stride bytes after problem 0's (one arena per problem, equal
+// layouts), the launch's gridDim.z is `count` times the single-problem launch's, and the
+// blocks of problem p return at once when gate[p * gate_stride] reads 0.  The default (one
+// problem, no gate) is the plain launch.  Twiddle tables are read from problem 0 (they depend
+// on the grid and band only, which every problem of a batch shares).
+struct Batch {
+  int64_t stride = 0;
+  const int* gate = nullptr;
+  int64_t gate_stride = 0;   // ints between consecutive problems' gates
+  int count = 1;
+};
+
+// problem index of this block, and blockIdx.z within the problem's own launch
+__device__ __forceinline__ int batch_pair(const Batch& b) {
+  const int zper = b.count > 1 ? (int)gridDim.z / b.count : 0;
+  return zper > 0 ? (int)blockIdx.z / zper : 0;
+}
+__device__ __forceinline__ int batch_bz(const Batch& b, int pair) {
+  return (int)blockIdx.z - pair * ((int)gridDim.z / b.count);
+}
+__device__ __forceinline__ bool batch_gated_off(const Batch& b, int pair) {
+  return b.gate != nullptr && b.gate[(size_t)pair * b.gate_stride] == 0;
+}
+// problem pair's copy of a buffer of problem 0 (null stays null)
+template <class T>
+__device__ __forceinline__ T* batch_ptr(T* p, const Batch& b, int pair) {
+  if (p == nullptr || pair == 0) return p;
+  return reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) +
+                              (uintptr_t)((int64_t)pair * b.stride));
+}
+inline dim3 batch_grid(dim3 d, const Batch& b) {
+  d.z *= (unsigned)b.count;
+  return d;
+}
+// kernel prologue: the block's problem, gated-off problems return; BL_AT shifts a buffer
+#define BL_BATCH(bt)                                  \
+  const int bpair_ = ::bl::batch_pair(bt);            \
+  if (::bl::batch_gated_off(bt, bpair_)) return;
+#define BL_AT(p, bt) p = ::bl::batch_ptr(p, bt, bpair_)
+
 // Geometry and weights of one problem, passed by value to every kernel.
 struct Geo {
   int dim;            // 2 or 3
@@ -35,6 +76,8 @@ struct Geo {
   // voxels per thread along z of the transport launches, per kernel class (TR_*): a launch
   // shape only, every choice computes bitwise the same values
   int zv[4];
+  // several problems of this shape in one launch (default: one)
+  Batch bat;
 };
 
 // kernel classes of the transport launch shapes (Geo::zv)
@@ -211,18 +254,28 @@ void fx_pi_yx_adj(const Geo& g, const Geo& gp, const DftPlan& pl, const float2* 
 // out[0] = sum of n partials in a fixed order (one block); also stored to host[0] (host-mapped
 // pinned memory) when host != NULL, and *flag published to host_flag[0] when flag != NULL
 void reduce_final(const double* partial, int n, double* out, hipStream_t s,
-                  double* host = nullptr, const int* flag = nullptr, double* host_flag = nullptr);
+                  double* host = nullptr, const int* flag = nullptr, double* host_flag = nullptr,
+                  const Batch& bt = Batch{});
 // kRedBlocks partials of Re sum conj(a) b over n complex entries
-void dot_partial(const float2* a, const float2* b, int64_t n, double* partial, hipStream_t s);
+void dot_partial(const float2* a, const float2* b, int64_t n, double* partial, hipStream_t s,
+                 const Batch& bt = Batch{});
 // the same over g.nodes * dim * B entries, node k weighted by the trapezoid weight w_k
 void dot_partial_w(const Geo& g, const float2* a, const float2* b, double* partial, hipStream_t s);
 // kRedBlocks partials of max |a|
-void maxabs_partial(const float2* a, int64_t n, double* partial, hipStream_t s);
+void maxabs_partial(const float2* a, int64_t n, double* partial, hipStream_t s,
+                    const Batch& bt = Batch{});
 void reduce_max_final(const double* partial, int n, double* out, hipStream_t s,
                       double* host = nullptr, const int* flag = nullptr,
-                      double* host_flag = nullptr);
+                      double* host_flag = nullptr, const Batch& bt = Batch{});
 // y = alpha x + y
-void axpy(float2* y, const float2* x, double alpha, int64_t n, hipStream_t s);
+void axpy(float2* y, const float2* x, double alpha, int64_t n, hipStream_t s,
+          const Batch& bt = Batch{});
+// y = 0; y = x (kernels, so that a captured graph holds no memset or copy node)
+void zero_band(float2* y, int64_t n, hipStream_t s, const Batch& bt = Batch{});
+void copy_band(float2* y, const float2* x, int64_t n, hipStream_t s, const Batch& bt = Batch{});
+// y = x + eps[0] d (step length in device memory)
+void add_scaled_dev(float2* y, const float2* x, const float2* d, const double* eps, int64_t n,
+                    hipStream_t s, const Batch& bt = Batch{});
 // y = x + beta y
 void xpby(float2* y, const float2* x, double beta, int64_t n, hipStream_t s);
 // one PCG step: alpha = rz / pHp (0 unless pHp > 0), delta += alpha p, r -= alpha Hp,
@@ -232,7 +285,7 @@ void pcg_step(const Geo& g, const float2* p, const float2* Hp, const double* rz,
               double* p0, double* p1, hipStream_t s);
 // y = x + (num[0] / den[0]) y with device scalars
 void xpby_dev(float2* y, const float2* x, const double* num, const double* den, int64_t n,
-              hipStream_t s);
+              hipStream_t s, const Batch& bt = Batch{});
 // z = r / Lhat (per component); also kRedBlocks partials of <r, r> (p0) and <r, z> (p1)
 void precond_dots(const Geo& g, const float2* r, const float* Lhat, float2* z, double* p0,
                   double* p1, hipStream_t s);
@@ -240,6 +293,7 @@ void precond_dots(const Geo& g, const float2* r, const float* Lhat, float2* z, d
 void add_scaled(float2* y, const float2* x, const float2* d, double eps, int64_t n,
                 hipStream_t s);
 // partials of sum (a - b)^2 over n reals
-void sqdiff_partial(const float* a, const float* b, int64_t n, double* partial, hipStream_t s);
+void sqdiff_partial(const float* a, const float* b, int64_t n, double* partial, hipStream_t s,
+                    const Batch& bt = Batch{});
 
 }  // namespace bl

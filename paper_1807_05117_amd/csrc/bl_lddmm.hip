@@ -847,16 +847,13 @@ void op_hessvec_def(bl_ctx* c, const float2* draw, float2* hout) {
   check_launch("hessvec (deformation)");
 }
 
-// setup + forward state + energy at the raw band vector `vraw` (device, dim components)
-void op_set_velocity(bl_ctx* c, const float2* vraw) {
-  if (c->g.deform) {
-    op_set_velocity_def(c, vraw);
-    return;
-  }
-  if (c->g.nodes > 1) {
-    op_set_velocity_ns(c, vraw);
-    return;
-  }
+// host-mapped mirror of a device scalar slot, for single-problem launches (a batched launch
+// publishes nothing to host memory: its scalars are read by the device control kernels)
+double* publish(bl_ctx* c, int slot) { return c->g.bat.count > 1 ? nullptr : c->hdev + slot; }
+
+// setup + forward state + energy sums at the raw band vector `vraw` (stationary state
+// equation), enqueued only: the regulariser and data sums land in scal[S_REG], scal[S_DATA]
+void enqueue_set_velocity(bl_ctx* c, const float2* vraw) {
   const bl::Geo& g = c->g;
   hipStream_t s = c->stream;
   double* red_reg = c->red + RED_REG * bl::kRedBlocks;
@@ -870,9 +867,25 @@ void op_set_velocity(bl_ctx* c, const float2* vraw) {
   for (int n = 0; n < g.nt; ++n) bl::state_step(g, c->m + n * M, c->X, c->m + (n + 1) * M, s);
   if (c->timing) t_end(c, 0, g.nt);
   bl::energy_partial(g, c->m + g.nt * M, c->I1, red_data, s);
-  bl::reduce_final(red_reg, bl::kRedBlocks, c->scal + S_REG, s, c->hdev + S_REG);
-  bl::reduce_final(red_data, bl::kRedBlocks, c->scal + S_DATA, s, c->hdev + S_DATA);
+  bl::reduce_final(red_reg, bl::kRedBlocks, c->scal + S_REG, s, publish(c, S_REG), nullptr,
+                   nullptr, g.bat);
+  bl::reduce_final(red_data, bl::kRedBlocks, c->scal + S_DATA, s, publish(c, S_DATA), nullptr,
+                   nullptr, g.bat);
   check_launch("set_velocity");
+}
+
+// setup + forward state + energy at the raw band vector `vraw` (device, dim components)
+void op_set_velocity(bl_ctx* c, const float2* vraw) {
+  if (c->g.deform) {
+    op_set_velocity_def(c, vraw);
+    return;
+  }
+  if (c->g.nodes > 1) {
+    op_set_velocity_ns(c, vraw);
+    return;
+  }
+  const bl::Geo& g = c->g;
+  enqueue_set_velocity(c, vraw);
   sync(c);
   c->reg = c->hscal[S_REG];
   c->data_sum = c->hscal[S_DATA];
@@ -1008,7 +1021,7 @@ void check_flag(bl_ctx* c, const char* what) {
 void vec_dot_partial(bl_ctx* c, const float2* a, const float2* b, double* pa) {
   const bl::Geo& g = c->g;
   if (g.nodes > 1) bl::dot_partial_w(g, a, b, pa, c->stream);
-  else bl::dot_partial(a, b, (int64_t)g.dim * g.B, pa, c->stream);
+  else bl::dot_partial(a, b, (int64_t)g.dim * g.B, pa, c->stream, g.bat);
 }
 
 // the projected velocity (first dim of the dim + 1 components per node in bv) into dst
@@ -1130,6 +1143,8 @@ void solve(bl_ctx* c, const bl_solver_opts& o, bl_stats* st) {
     }
     const double gn = std::sqrt(std::max(gg, 0.0));
     const double eta = std::min(0.5, std::sqrt(gn / g0n));
+    const double thr = eta * gn;
+    const double thr2 = thr * thr;
     // PCG on H delta = -g with preconditioner K = 1/Lhat, delta_0 = 0
     HIP_TRY(hipMemsetAsync(c->sdelta, 0, nb * sizeof(float2), s));
     HIP_TRY(hipMemsetAsync(c->sr, 0, nb * sizeof(float2), s));
@@ -1158,7 +1173,9 @@ void solve(bl_ctx* c, const bl_solver_opts& o, bl_stats* st) {
         break;
       }
       iters += 1;
-      if (std::sqrt(std::max(c->hscal[S_RR], 0.0)) <= eta * gn) break;
+      // |r| <= eta |g|, compared as squares (the same FP64 operations as the batched engine's
+      // device-side test, so both take the same decisions)
+      if (std::max(c->hscal[S_RR], 0.0) <= thr2) break;
       bl::xpby_dev(c->sp, c->sz, c->scal + rz_next, c->scal + rz_cur, nb, s);  // p = z + beta p
       std::swap(rz_cur, rz_next);
     }

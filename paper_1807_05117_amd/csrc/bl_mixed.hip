@@ -53,6 +53,9 @@ __global__ __launch_bounds__(256) void k_iota_z_mfma(Geo g, const float2* __rest
                                                      const unsigned short* __restrict__ Wi,
                                                      int nzp32, float* __restrict__ out,
                                                      int nqt) {
+  BL_BATCH(g.bat)
+  BL_AT(F2, g.bat);
+  BL_AT(out, g.bat);
   constexpr int KP = 16 * KS;
   const int lane = threadIdx.x & 63;
   const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -129,6 +132,9 @@ template <int JT>
 __global__ __launch_bounds__(256) void k_pi_z_mfma(Geo g, const float* __restrict__ f,
                                                    const unsigned short* __restrict__ Wp,
                                                    int nzp16, float2* __restrict__ G) {
+  BL_BATCH(g.bat)
+  BL_AT(f, g.bat);
+  BL_AT(G, g.bat);
   __shared__ float red[3][JT][16][64];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -214,7 +220,7 @@ void iota_z_mixed(const Geo& g, const DftPlan& p, const float2* F2, int C, float
                   hipStream_t s) {
   const int nq = g.nx * g.ny;
   const int nqt = (nq + 31) / 32;
-  const dim3 grid((nqt + 3) / 4, C);
+  const dim3 grid = batch_grid(dim3((nqt + 3) / 4, C), g.bat);
   const int ks = mixed_kp(g) / 16;
 #define L_IOTA(K)                                                                             \
   hipLaunchKernelGGL(k_iota_z_mfma<K>, grid, dim3(256), 0, s, g, F2, p.wi_bf16, p.nzp32, out, \
@@ -234,7 +240,7 @@ void iota_z_mixed(const Geo& g, const DftPlan& p, const float2* F2, int C, float
 
 void pi_z_mixed(const Geo& g, const DftPlan& p, const float* f, int C, float2* G, hipStream_t s) {
   const int nq = g.nx * g.ny;
-  const dim3 grid((nq + 31) / 32, C);
+  const dim3 grid = batch_grid(dim3((nq + 31) / 32, C), g.bat);
   switch (mixed_jt(g)) {
     case 1:
       hipLaunchKernelGGL(k_pi_z_mfma<1>, grid, dim3(256), 0, s, g, f, p.wp_bf16, p.nzp16, G);

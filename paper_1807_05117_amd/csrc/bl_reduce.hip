@@ -52,7 +52,13 @@ __global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__
                                                       double* __restrict__ out,
                                                       double* __restrict__ host,
                                                       const int* __restrict__ flag,
-                                                      double* __restrict__ host_flag) {
+                                                      double* __restrict__ host_flag,
+                                                      Batch bt) {
+  // host-mapped outputs (host, host_flag) belong to single-problem launches only
+  BL_BATCH(bt)
+  BL_AT(partial, bt);
+  BL_AT(out, bt);
+  BL_AT(flag, bt);
   __shared__ double sh[256];
   double acc = 0.0;
   for (int i = threadIdx.x; i < n; i += 256) acc = MAX ? fmax(acc, partial[i]) : acc + partial[i];
@@ -83,6 +89,17 @@ __global__ __launch_bounds__(256) void k_pcg_step(Geo g, const float2* __restric
                                                   float2* __restrict__ z,
                                                   double* __restrict__ p0,
                                                   double* __restrict__ p1) {
+  BL_BATCH(g.bat)
+  BL_AT(p, g.bat);
+  BL_AT(Hp, g.bat);
+  BL_AT(rz, g.bat);
+  BL_AT(pHp, g.bat);
+  BL_AT(delta, g.bat);
+  BL_AT(r, g.bat);
+  BL_AT(Lhat, g.bat);
+  BL_AT(z, g.bat);
+  BL_AT(p0, g.bat);
+  BL_AT(p1, g.bat);
   const int64_t n = (int64_t)g.nodes * g.dim * g.B;
   const double d = pHp[0];
   const double alpha = d > 0.0 ? rz[0] / d : 0.0;
@@ -122,7 +139,13 @@ __global__ __launch_bounds__(256) void k_pcg_step(Geo g, const float2* __restric
 // y = x + (num / den) y: the PCG direction update with beta = <r', z'> / <r, z> on the device
 __global__ __launch_bounds__(256) void k_xpby_dev(float2* __restrict__ y, const float2* __restrict__ x,
                                                   const double* __restrict__ num,
-                                                  const double* __restrict__ den, int64_t n) {
+                                                  const double* __restrict__ den, int64_t n,
+                                                  Batch bt) {
+  BL_BATCH(bt)
+  BL_AT(y, bt);
+  BL_AT(x, bt);
+  BL_AT(num, bt);
+  BL_AT(den, bt);
   const double beta = num[0] / den[0];
   GRID_STRIDE(i, n) {
     const float2 a = x[i];
@@ -135,7 +158,11 @@ __global__ __launch_bounds__(256) void k_xpby_dev(float2* __restrict__ y, const 
 
 __global__ __launch_bounds__(256) void k_dot_partial(const float2* __restrict__ a,
                                                      const float2* __restrict__ b, int64_t n,
-                                                     double* __restrict__ partial) {
+                                                     double* __restrict__ partial, Batch bt) {
+  BL_BATCH(bt)
+  BL_AT(a, bt);
+  BL_AT(b, bt);
+  BL_AT(partial, bt);
   double acc = 0.0;
   GRID_STRIDE(i, n) {
     const float2 x = a[i], y = b[i];
@@ -160,7 +187,10 @@ __global__ __launch_bounds__(256) void k_dot_partial_w(Geo g, const float2* __re
 }
 
 __global__ __launch_bounds__(256) void k_maxabs_partial(const float2* __restrict__ a, int64_t n,
-                                                        double* __restrict__ partial) {
+                                                        double* __restrict__ partial, Batch bt) {
+  BL_BATCH(bt)
+  BL_AT(a, bt);
+  BL_AT(partial, bt);
   double acc = 0.0;
   GRID_STRIDE(i, n) {
     const float2 x = a[i];
@@ -170,7 +200,10 @@ __global__ __launch_bounds__(256) void k_maxabs_partial(const float2* __restrict
 }
 
 __global__ __launch_bounds__(256) void k_axpy(float2* __restrict__ y, const float2* __restrict__ x,
-                                              double alpha, int64_t n) {
+                                              double alpha, int64_t n, Batch bt) {
+  BL_BATCH(bt)
+  BL_AT(y, bt);
+  BL_AT(x, bt);
   GRID_STRIDE(i, n) {
     const float2 a = x[i];
     float2 b = y[i];
@@ -194,7 +227,11 @@ __global__ __launch_bounds__(256) void k_xpby(float2* __restrict__ y, const floa
 __global__ __launch_bounds__(256) void k_add_scaled(float2* __restrict__ y,
                                                     const float2* __restrict__ x,
                                                     const float2* __restrict__ d, double eps,
-                                                    int64_t n) {
+                                                    int64_t n, Batch bt) {
+  BL_BATCH(bt)
+  BL_AT(y, bt);
+  BL_AT(x, bt);
+  BL_AT(d, bt);
   GRID_STRIDE(i, n) {
     const float2 a = x[i], b = d[i];
     y[i] = make_float2((float)fma(eps, (double)b.x, (double)a.x),
@@ -207,6 +244,12 @@ __global__ __launch_bounds__(256) void k_precond_dots(Geo g, const float2* __res
                                                       float2* __restrict__ z,
                                                       double* __restrict__ p0,
                                                       double* __restrict__ p1) {
+  BL_BATCH(g.bat)
+  BL_AT(r, g.bat);
+  BL_AT(Lhat, g.bat);
+  BL_AT(z, g.bat);
+  BL_AT(p0, g.bat);
+  BL_AT(p1, g.bat);
   const int64_t n = (int64_t)g.nodes * g.dim * g.B;
   double rr = 0.0, rz = 0.0;
   GRID_STRIDE(i, n) {
@@ -235,13 +278,51 @@ __global__ __launch_bounds__(256) void k_precond_dots(Geo g, const float2* __res
 
 __global__ __launch_bounds__(256) void k_sqdiff_partial(const float* __restrict__ a,
                                                         const float* __restrict__ b, int64_t n,
-                                                        double* __restrict__ partial) {
+                                                        double* __restrict__ partial, Batch bt) {
+  BL_BATCH(bt)
+  BL_AT(a, bt);
+  BL_AT(b, bt);
+  BL_AT(partial, bt);
   double acc = 0.0;
   GRID_STRIDE(i, n) {
     const double d = (double)a[i] - (double)b[i];
     acc = fma(d, d, acc);
   }
   block_sum_store(acc, partial);
+}
+
+// y = 0 (a kernel rather than a memset, so that a captured graph holds no memset node)
+__global__ __launch_bounds__(256) void k_zero(float2* __restrict__ y, int64_t n, Batch bt) {
+  BL_BATCH(bt)
+  BL_AT(y, bt);
+  GRID_STRIDE(i, n) y[i] = make_float2(0.f, 0.f);
+}
+
+__global__ __launch_bounds__(256) void k_copy(float2* __restrict__ y, const float2* __restrict__ x,
+                                              int64_t n, Batch bt) {
+  BL_BATCH(bt)
+  BL_AT(y, bt);
+  BL_AT(x, bt);
+  GRID_STRIDE(i, n) y[i] = x[i];
+}
+
+// y = x + eps d with the step length eps read from device memory
+__global__ __launch_bounds__(256) void k_add_scaled_dev(float2* __restrict__ y,
+                                                        const float2* __restrict__ x,
+                                                        const float2* __restrict__ d,
+                                                        const double* __restrict__ epsp,
+                                                        int64_t n, Batch bt) {
+  BL_BATCH(bt)
+  BL_AT(y, bt);
+  BL_AT(x, bt);
+  BL_AT(d, bt);
+  BL_AT(epsp, bt);
+  const double eps = epsp[0];
+  GRID_STRIDE(i, n) {
+    const float2 a = x[i], b = d[i];
+    y[i] = make_float2((float)fma(eps, (double)b.x, (double)a.x),
+                       (float)fma(eps, (double)b.y, (double)a.y));
+  }
 }
 
 inline int blocks_for(int64_t n) {
@@ -252,50 +333,69 @@ inline int blocks_for(int64_t n) {
 }  // namespace
 
 void reduce_final(const double* partial, int n, double* out, hipStream_t s, double* host,
-                  const int* flag, double* host_flag) {
-  hipLaunchKernelGGL(k_reduce_final<false>, dim3(1), dim3(256), 0, s, partial, n, out, host, flag,
-                     host_flag);
+                  const int* flag, double* host_flag, const Batch& bt) {
+  hipLaunchKernelGGL(k_reduce_final<false>, batch_grid(dim3(1), bt), dim3(256), 0, s, partial, n,
+                     out, host, flag, host_flag, bt);
 }
 void reduce_max_final(const double* partial, int n, double* out, hipStream_t s, double* host,
-                      const int* flag, double* host_flag) {
-  hipLaunchKernelGGL(k_reduce_final<true>, dim3(1), dim3(256), 0, s, partial, n, out, host, flag,
-                     host_flag);
+                      const int* flag, double* host_flag, const Batch& bt) {
+  hipLaunchKernelGGL(k_reduce_final<true>, batch_grid(dim3(1), bt), dim3(256), 0, s, partial, n,
+                     out, host, flag, host_flag, bt);
 }
 void pcg_step(const Geo& g, const float2* p, const float2* Hp, const double* rz,
               const double* pHp, float2* delta, float2* r, const float* Lhat, float2* z,
               double* p0, double* p1, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_step, dim3(kRedBlocks), dim3(256), 0, s, g, p, Hp, rz, pHp, delta, r,
-                     Lhat, z, p0, p1);
+  hipLaunchKernelGGL(k_pcg_step, batch_grid(dim3(kRedBlocks), g.bat), dim3(256), 0, s, g, p, Hp,
+                     rz, pHp, delta, r, Lhat, z, p0, p1);
 }
 void xpby_dev(float2* y, const float2* x, const double* num, const double* den, int64_t n,
-              hipStream_t s) {
-  hipLaunchKernelGGL(k_xpby_dev, dim3(blocks_for(n)), dim3(256), 0, s, y, x, num, den, n);
+              hipStream_t s, const Batch& bt) {
+  hipLaunchKernelGGL(k_xpby_dev, batch_grid(dim3(blocks_for(n)), bt), dim3(256), 0, s, y, x, num,
+                     den, n, bt);
 }
 void dot_partial_w(const Geo& g, const float2* a, const float2* b, double* partial, hipStream_t s) {
   hipLaunchKernelGGL(k_dot_partial_w, dim3(kRedBlocks), dim3(256), 0, s, g, a, b, partial);
 }
-void dot_partial(const float2* a, const float2* b, int64_t n, double* partial, hipStream_t s) {
-  hipLaunchKernelGGL(k_dot_partial, dim3(kRedBlocks), dim3(256), 0, s, a, b, n, partial);
+void dot_partial(const float2* a, const float2* b, int64_t n, double* partial, hipStream_t s,
+                 const Batch& bt) {
+  hipLaunchKernelGGL(k_dot_partial, batch_grid(dim3(kRedBlocks), bt), dim3(256), 0, s, a, b, n,
+                     partial, bt);
 }
-void maxabs_partial(const float2* a, int64_t n, double* partial, hipStream_t s) {
-  hipLaunchKernelGGL(k_maxabs_partial, dim3(kRedBlocks), dim3(256), 0, s, a, n, partial);
+void maxabs_partial(const float2* a, int64_t n, double* partial, hipStream_t s, const Batch& bt) {
+  hipLaunchKernelGGL(k_maxabs_partial, batch_grid(dim3(kRedBlocks), bt), dim3(256), 0, s, a, n,
+                     partial, bt);
 }
-void axpy(float2* y, const float2* x, double alpha, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_axpy, dim3(blocks_for(n)), dim3(256), 0, s, y, x, alpha, n);
+void axpy(float2* y, const float2* x, double alpha, int64_t n, hipStream_t s, const Batch& bt) {
+  hipLaunchKernelGGL(k_axpy, batch_grid(dim3(blocks_for(n)), bt), dim3(256), 0, s, y, x, alpha, n,
+                     bt);
+}
+void zero_band(float2* y, int64_t n, hipStream_t s, const Batch& bt) {
+  hipLaunchKernelGGL(k_zero, batch_grid(dim3(blocks_for(n)), bt), dim3(256), 0, s, y, n, bt);
+}
+void copy_band(float2* y, const float2* x, int64_t n, hipStream_t s, const Batch& bt) {
+  hipLaunchKernelGGL(k_copy, batch_grid(dim3(blocks_for(n)), bt), dim3(256), 0, s, y, x, n, bt);
+}
+void add_scaled_dev(float2* y, const float2* x, const float2* d, const double* eps, int64_t n,
+                    hipStream_t s, const Batch& bt) {
+  hipLaunchKernelGGL(k_add_scaled_dev, batch_grid(dim3(blocks_for(n)), bt), dim3(256), 0, s, y, x,
+                     d, eps, n, bt);
 }
 void xpby(float2* y, const float2* x, double beta, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_xpby, dim3(blocks_for(n)), dim3(256), 0, s, y, x, beta, n);
 }
 void add_scaled(float2* y, const float2* x, const float2* d, double eps, int64_t n,
                 hipStream_t s) {
-  hipLaunchKernelGGL(k_add_scaled, dim3(blocks_for(n)), dim3(256), 0, s, y, x, d, eps, n);
+  hipLaunchKernelGGL(k_add_scaled, dim3(blocks_for(n)), dim3(256), 0, s, y, x, d, eps, n, Batch{});
 }
 void precond_dots(const Geo& g, const float2* r, const float* Lhat, float2* z, double* p0,
                   double* p1, hipStream_t s) {
-  hipLaunchKernelGGL(k_precond_dots, dim3(kRedBlocks), dim3(256), 0, s, g, r, Lhat, z, p0, p1);
+  hipLaunchKernelGGL(k_precond_dots, batch_grid(dim3(kRedBlocks), g.bat), dim3(256), 0, s, g, r,
+                     Lhat, z, p0, p1);
 }
-void sqdiff_partial(const float* a, const float* b, int64_t n, double* partial, hipStream_t s) {
-  hipLaunchKernelGGL(k_sqdiff_partial, dim3(kRedBlocks), dim3(256), 0, s, a, b, n, partial);
+void sqdiff_partial(const float* a, const float* b, int64_t n, double* partial, hipStream_t s,
+                    const Batch& bt) {
+  hipLaunchKernelGGL(k_sqdiff_partial, batch_grid(dim3(kRedBlocks), bt), dim3(256), 0, s, a, b, n,
+                     partial, bt);
 }
 
 }  // namespace bl

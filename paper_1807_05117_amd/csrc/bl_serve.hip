@@ -1,15 +1,25 @@
 // Serving: many registrations resident on one GPU at once (continuous batching).
 //
-// A FIFO queue of requests, a device-memory budget and `max_slots` worker threads.  A slot
-// takes the queue head as soon as the head's footprint fits in the unused budget, registers
-// the pair (the same Gauss-Newton-Krylov driver as bl_lddmm_register) on the slot's own HIP
-// stream in a device arena the slot keeps and reuses, and frees the budget when done, so the
-// pairs' kernels overlap on the device and finished pairs are replaced without waiting for
-// the others.  Arenas grow to the largest footprint a slot has seen and are otherwise never
-// reallocated, so the steady state performs no device allocation.
+// Two engines behind one request queue and one device-memory budget:
+//
+// Slot threads (bl_server_create): `max_slots` worker threads.  A free slot takes the queue
+// head as soon as the memory it needs fits in the budget, registers the pair (the same
+// Gauss-Newton-Krylov driver as bl_lddmm_register) on the slot's own HIP stream in a device
+// arena the slot keeps, and takes the next request when done, so the pairs' kernels overlap
+// on the device.  The budget is charged with every slot's arena as long as the slot holds it;
+// an idle slot frees its arena when the head of the queue needs the memory.
+//
+// Cohorts (bl_server_create_batched): one scheduler thread.  Requests of equal problems
+// (grid, band, Nt, model, precision) share a cohort: up to `max_pairs` resident pairs whose
+// device state lies in one arena at a fixed stride, advanced together one Newton step at a
+// time by one replay of the cohort's captured step graph (every kernel one launch for all its
+// pairs; see bl_batch.h).  New requests join free slots of a cohort between steps; a cohort's
+// whole arena is charged to the budget while it exists, and an empty cohort is freed when a
+// request of another shape needs the memory.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -19,6 +29,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "bl_batch.h"
 #include "bl_host.h"
 
 namespace {
@@ -49,6 +60,23 @@ struct Slot {
   size_t arena_bytes = 0;
   double* hscal = nullptr;
   bl_ctx* ctx = nullptr;   // the last request's context (tables built), reused for the same problem
+  bool busy = false;
+};
+
+// a request resident in a cohort slot, with the host side of its Gauss-Newton loop
+struct Resident {
+  Request* r = nullptr;
+  int phase = 0;         // 0 free, 1 initial evaluation pending, 2 Gauss-Newton iterations
+  int it = 0;            // current Gauss-Newton iteration
+  bool pcg_open = false; // PCG of iteration `it` runs
+  double ginf0 = 0, g0n = 0, gg = 0, ginf = 0;
+};
+
+struct CohortEntry {
+  std::unique_ptr<bl::batch::Cohort> co;
+  std::vector<Resident> res;
+  int active = 0;
+  bool launched = false;
 };
 
 }  // namespace
@@ -62,7 +90,10 @@ struct bl_server {
   int resident = 0, peak_resident = 0;
   int64_t submitted = 0, completed = 0, failed = 0, cancelled = 0;
   int max_slots = 0;
+  bool batched = false;
   bool stopping = false;
+  std::thread sched;
+  std::vector<std::unique_ptr<CohortEntry>> cohorts;   // owned by the scheduler thread
   uint64_t next_id = 1;
   int device = 0;
   Clock::time_point t0;
@@ -86,22 +117,15 @@ bool same_request_problem(const bl_problem& a, const bl_problem& b) {
 void run_request(bl_server* srv, Slot& slot, int slot_index, Request* r) {
   r->rc = guarded([&]() {
     // a context of the same problem as the slot's last one is reused as it is (its tables
-    // and launch shapes); any other problem gets a new context in the slot's arena
+    // and launch shapes); any other problem gets a new context in the slot's arena (the
+    // worker has sized the arena and charged it to the budget)
     if (slot.ctx && !same_request_problem(slot.ctx->prob, r->prob)) {
       destroy_ctx(slot.ctx);
       slot.ctx = nullptr;
     }
-    if (!slot.ctx) {
-      if (slot.arena_bytes < r->bytes) {
-        if (slot.arena) HIP_TRY(hipFree(slot.arena));
-        slot.arena = nullptr;
-        slot.arena_bytes = 0;
-        HIP_TRY(hipMalloc(&slot.arena, r->bytes));
-        slot.arena_bytes = r->bytes;
-      }
+    if (!slot.ctx)
       slot.ctx = create_ctx(&r->prob, r->g, true, true, slot.arena, slot.arena_bytes, slot.stream,
                             slot.hscal);
-    }
     bl_ctx* c = slot.ctx;
     c->have_v = false;
     struct Guard {   // a failed request leaves no context behind
@@ -132,39 +156,433 @@ void run_request(bl_server* srv, Slot& slot, int slot_index, Request* r) {
   (void)slot_index;
 }
 
+// the slot's context and arena are given back to the device (their bytes leave the budget)
+void release_slot_memory(bl_server* srv, Slot& slot) {
+  destroy_ctx(slot.ctx);
+  slot.ctx = nullptr;
+  if (slot.arena) hipFree(slot.arena);
+  slot.arena = nullptr;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  srv->in_use -= slot.arena_bytes;
+  slot.arena_bytes = 0;
+}
+
+void finish_request(bl_server* srv, Request* r) {
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->resident -= 1;
+    r->times.finished = srv->now();
+    r->state = DONE;
+    if (r->rc == BL_OK) srv->completed += 1; else srv->failed += 1;
+  }
+  srv->cv_done.notify_all();
+  srv->cv_work.notify_all();
+}
+
+void admit_locked(bl_server* srv, Request* r, int slot_index) {
+  r->state = RUNNING;
+  r->times.admitted = srv->now();
+  r->times.slot = slot_index;
+  srv->resident += 1;
+  srv->peak_resident = std::max(srv->peak_resident, srv->resident);
+}
+
+// Slot thread.  The budget is charged with the slot's arena while the slot holds it: taking
+// the head of the queue needs max(arena, footprint) to fit beside every other slot's arena; a
+// slot that cannot take the head gives its own arena back, so the head is admitted once
+// enough idle memory is returned.
 void worker(bl_server* srv, int index) {
   Slot& slot = srv->slots[index];
   hipSetDevice(srv->device);
   for (;;) {
     Request* r = nullptr;
+    size_t need = 0;
+    bool give_back = false;
     {
       std::unique_lock<std::mutex> lk(srv->mu);
-      srv->cv_work.wait(lk, [&]() {
-        if (srv->stopping) return true;
-        return !srv->queue.empty() && srv->in_use + srv->queue.front()->bytes <= srv->budget;
-      });
-      if (srv->stopping) return;
-      r = srv->queue.front();
-      srv->queue.pop_front();
-      r->state = RUNNING;
-      r->times.admitted = srv->now();
-      r->times.slot = index;
-      srv->in_use += r->bytes;
-      srv->peak = std::max(srv->peak, srv->in_use);
-      srv->resident += 1;
-      srv->peak_resident = std::max(srv->peak_resident, srv->resident);
+      for (;;) {
+        if (srv->stopping) return;
+        if (!srv->queue.empty()) {
+          Request* h = srv->queue.front();
+          need = std::max(slot.arena_bytes, h->bytes);
+          if (srv->in_use - slot.arena_bytes + need <= srv->budget) {
+            r = h;
+            srv->queue.pop_front();
+            srv->in_use += need - slot.arena_bytes;   // reserved before the allocation
+            srv->peak = std::max(srv->peak, srv->in_use);
+            admit_locked(srv, r, index);
+            break;
+          }
+          if (slot.arena_bytes > 0) {
+            give_back = true;
+            break;
+          }
+        }
+        srv->cv_work.wait(lk);
+      }
+    }
+    if (give_back) {
+      release_slot_memory(srv, slot);
+      srv->cv_work.notify_all();
+      continue;
+    }
+    if (need > slot.arena_bytes) {
+      // a larger arena: the old one (and its context) first, then exactly the footprint
+      destroy_ctx(slot.ctx);
+      slot.ctx = nullptr;
+      if (slot.arena) hipFree(slot.arena);
+      slot.arena = nullptr;
+      if (hipMalloc(&slot.arena, need) != hipSuccess) {
+        slot.arena = nullptr;
+        {
+          std::lock_guard<std::mutex> lk(srv->mu);
+          srv->in_use -= need;
+          slot.arena_bytes = 0;
+        }
+        r->rc = BL_E_NOMEM;
+        r->err = "device memory for the slot arena is not available";
+        finish_request(srv, r);
+        continue;
+      }
+      slot.arena_bytes = need;
     }
     run_request(srv, slot, index, r);
-    {
-      std::lock_guard<std::mutex> lk(srv->mu);
-      srv->in_use -= r->bytes;
-      srv->resident -= 1;
-      r->times.finished = srv->now();
-      r->state = DONE;
-      if (r->rc == BL_OK) srv->completed += 1; else srv->failed += 1;
+    finish_request(srv, r);
+  }
+}
+
+// ------------------------------------------------------------------------- cohort scheduler
+using bl::batch::Cohort;
+using bl::batch::Ctl;
+
+void fail_resident(bl_server* srv, CohortEntry& ce, int s, int rc, const std::string& msg) {
+  Resident& R = ce.res[s];
+  R.r->rc = rc;
+  R.r->err = msg;
+  finish_request(srv, R.r);
+  R = Resident{};
+  ce.co->ctl_in(s) = Ctl{};
+  ce.active -= 1;
+}
+
+void complete_resident(bl_server* srv, CohortEntry& ce, int s) {
+  Resident& R = ce.res[s];
+  Request* r = R.r;
+  r->rc = guarded([&]() {
+    r->warped.resize((size_t)r->g.M);
+    ce.co->store(s, r->v.data(), r->warped.data());
+    return BL_OK;
+  });
+  if (r->rc != BL_OK) r->err = bl_lddmm_last_error();
+  r->stats.seconds = srv->now() - r->times.admitted;
+  finish_request(srv, r);
+  R = Resident{};
+  ce.co->ctl_in(s) = Ctl{};
+  ce.active -= 1;
+}
+
+// Begin Gauss-Newton iteration R.it, or end the registration (same tests and order as the
+// single-registration driver).  Returns false when the request is complete.
+bool begin_iteration(Resident& R, Ctl& in) {
+  const bl_solver_opts& o = R.r->opts;
+  if (R.it >= o.max_gn) return false;
+  if (R.ginf / R.ginf0 < o.gtol) {
+    R.r->stats.status = BL_CONVERGED;
+    return false;
+  }
+  const double gn = std::sqrt(std::max(R.gg, 0.0));
+  const double eta = std::min(0.5, std::sqrt(gn / R.g0n));
+  const double thr = eta * gn;
+  in.thr2 = thr * thr;
+  in.iters = 0;
+  in.g_pstart = 1;
+  in.g_pcg = 1;   // max_pcg >= 1
+  R.pcg_open = true;
+  return true;
+}
+
+// Read slot s's control block after a step and prepare its next step.
+void advance(bl_server* srv, CohortEntry& ce, int s) {
+  Resident& R = ce.res[s];
+  Request* r = R.r;
+  const Ctl out = ce.co->ctl_out(s);
+  Ctl& in = ce.co->ctl_in(s);
+  in = out;   // the device's state carries over to the next step
+  in.hv = in.evals = in.grads = 0;
+  in.accepted = 0;
+  in.g_pstart = 0;
+  bl_stats& st = r->stats;
+  st.hessvecs += out.hv;
+  st.evaluations += out.evals;
+  if (out.nonfinite) {
+    fail_resident(srv, ce, s, BL_E_NONFINITE,
+                  out.grads || R.phase == 2 ? "non-finite value in gradient"
+                                            : "non-finite value in energy");
+    return;
+  }
+  const bl_solver_opts& o = r->opts;
+  auto mse = [&](double data) { return out.den > 0 ? 100.0 * data / out.den : 0.0; };
+  if (R.phase == 1) {   // initial velocity evaluated: energy and gradient
+    st.E[0] = out.E;
+    st.mse_rel[0] = mse(out.data);
+    st.ginf_rel[0] = 1.0;
+    st.gradients = out.grads;
+    st.status = BL_MAXITER;
+    if (out.ginf == 0.0) {
+      st.status = BL_CONVERGED;
+      st.ginf_rel[0] = 0.0;
+      complete_resident(srv, ce, s);
+      return;
     }
-    srv->cv_done.notify_all();
-    srv->cv_work.notify_all();
+    R.phase = 2;
+    R.ginf0 = out.ginf;
+    R.g0n = std::sqrt(std::max(out.gg, 0.0));
+    R.gg = out.gg;
+    R.ginf = out.ginf;
+    R.it = 0;
+    if (!begin_iteration(R, in)) complete_resident(srv, ce, s);
+    return;
+  }
+  if (R.pcg_open && !out.g_pcg) {
+    st.pcg_iters[R.it] = out.iters;
+    st.pcg_total += out.iters;
+    R.pcg_open = false;
+  }
+  if (out.accepted) {
+    st.ls_trials[R.it] = out.trials;
+    st.eps[R.it] = out.eps;
+    st.gradients += out.grads;
+    st.gn_iters += 1;
+    R.gg = out.gg;
+    R.ginf = out.ginf;
+    st.E[st.gn_iters] = out.E;
+    st.mse_rel[st.gn_iters] = mse(out.data);
+    st.ginf_rel[st.gn_iters] = R.ginf / R.ginf0;
+    if (R.it + 1 == o.max_gn && R.ginf / R.ginf0 < o.gtol) st.status = BL_CONVERGED;
+    R.it += 1;
+    if (!begin_iteration(R, in)) complete_resident(srv, ce, s);
+    return;
+  }
+  if (out.stalled) {
+    st.ls_trials[R.it] = out.trials;
+    st.status = BL_STALLED;
+    st.eps[R.it] = 0.0;
+    const int rc = guarded([&]() {
+      ce.co->restore_state(s);   // the state of the returned velocity
+      return BL_OK;
+    });
+    if (rc != BL_OK) fail_resident(srv, ce, s, rc, bl_lddmm_last_error());
+    else complete_resident(srv, ce, s);
+  }
+  // otherwise PCG continues or the line search retries with half the step in the next step
+}
+
+// Admit queued requests into cohort slots (FIFO; a request joins a free slot of a cohort of
+// its problem or a new cohort; empty cohorts of other problems are freed when the memory is
+// needed).  Cohorts are created and loaded outside the lock.
+void admit_batched(bl_server* srv, int max_pairs) {
+  struct Plan {
+    Request* r;
+    CohortEntry* ce;   // null: the new cohort `fresh`
+    int fresh;
+  };
+  struct Fresh {
+    bl_problem prob;
+    bl::Geo g;
+    int cap;
+    std::unique_ptr<CohortEntry> ce;
+  };
+  std::vector<Plan> plan;
+  std::vector<Fresh> fresh;
+  std::vector<std::unique_ptr<CohortEntry>> drop;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->stopping) return;
+    std::vector<int> used(srv->cohorts.size(), 0);
+    std::vector<int> fresh_used;
+    for (auto it = srv->queue.begin(); it != srv->queue.end();) {
+      Request* r = *it;
+      bool placed = false, defer = false;
+      if (bl::batch::batchable(r->prob)) {
+        for (size_t i = 0; i < srv->cohorts.size() && !placed; ++i) {
+          CohortEntry& ce = *srv->cohorts[i];
+          if (!ce.co || !same_request_problem(ce.co->problem(), r->prob)) continue;
+          if (ce.active + used[i] < ce.co->capacity()) {
+            // a cohort in flight reads its control blocks: it takes requests after its step
+            if (ce.launched) {
+              defer = true;
+              continue;
+            }
+            plan.push_back({r, &ce, -1});
+            used[i] += 1;
+            placed = true;
+          }
+        }
+        if (!placed && defer) {
+          if (it == srv->queue.begin()) break;
+          ++it;
+          continue;
+        }
+        for (size_t f = 0; f < fresh.size() && !placed; ++f) {
+          if (same_request_problem(fresh[f].prob, r->prob) && fresh_used[f] < fresh[f].cap) {
+            plan.push_back({r, nullptr, (int)f});
+            fresh_used[f] += 1;
+            placed = true;
+          }
+        }
+        if (!placed) {
+          // a new cohort: free empty cohorts of other problems while the memory is short
+          for (size_t i = 0; i < srv->cohorts.size() && srv->in_use + r->bytes > srv->budget;
+               ++i) {
+            CohortEntry& ce = *srv->cohorts[i];
+            if (ce.co && ce.active == 0 && used[i] == 0 && !ce.launched) {
+              srv->in_use -= ce.co->bytes();
+              drop.push_back(std::move(srv->cohorts[i]));
+              srv->cohorts[i].reset(new CohortEntry());   // placeholder, removed below
+            }
+          }
+          const uint64_t room = srv->budget - std::min(srv->budget, srv->in_use);
+          const int cap = (int)std::min<uint64_t>((uint64_t)max_pairs, room / r->bytes);
+          if (cap >= 1) {
+            Fresh f{r->prob, r->g, cap, nullptr};
+            fresh.push_back(std::move(f));
+            fresh_used.push_back(1);
+            srv->in_use += (uint64_t)cap * r->bytes;
+            srv->peak = std::max(srv->peak, srv->in_use);
+            plan.push_back({r, nullptr, (int)fresh.size() - 1});
+            placed = true;
+          }
+        }
+      } else {
+        // other models are not batched: the request fails at once
+        r->rc = BL_E_UNSUPPORTED;
+        r->err = "the cohort server registers the stationary Gauss-Newton state-equation model "
+                 "(BL_NEWTON, BL_NONSTATIONARY and BL_DEFORMATION need bl_server_create)";
+        r->state = DONE;
+        r->times.admitted = r->times.finished = srv->now();
+        srv->failed += 1;
+        it = srv->queue.erase(it);
+        srv->cv_done.notify_all();
+        continue;
+      }
+      if (!placed) {
+        if (it == srv->queue.begin()) break;   // the head waits for memory; FIFO order kept
+        ++it;
+        continue;
+      }
+      admit_locked(srv, r, -1);
+      it = srv->queue.erase(it);
+    }
+    // remove the placeholders of freed cohorts
+    srv->cohorts.erase(std::remove_if(srv->cohorts.begin(), srv->cohorts.end(),
+                                      [](const std::unique_ptr<CohortEntry>& e) { return !e->co; }),
+                       srv->cohorts.end());
+  }
+  drop.clear();   // frees the empty cohorts' memory (outside the lock)
+  // create the new cohorts
+  for (Fresh& f : fresh) {
+    f.ce.reset(new CohortEntry());
+    const int rc = guarded([&]() {
+      f.ce->co.reset(new Cohort(f.prob, f.g, f.cap));
+      return BL_OK;
+    });
+    if (rc != BL_OK) f.ce.reset();
+    f.ce ? (void)f.ce->res.resize(f.cap) : (void)0;
+  }
+  // load the admitted requests
+  std::vector<CohortEntry*> fresh_ptrs(fresh.size(), nullptr);
+  for (size_t f = 0; f < fresh.size(); ++f) {
+    if (!fresh[f].ce) {
+      std::lock_guard<std::mutex> lk(srv->mu);
+      srv->in_use -= (uint64_t)fresh[f].cap * Cohort::problem_bytes(fresh[f].prob, fresh[f].g);
+      continue;
+    }
+    fresh_ptrs[f] = fresh[f].ce.get();
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->cohorts.push_back(std::move(fresh[f].ce));
+  }
+  for (const Plan& pl : plan) {
+    CohortEntry* ce = pl.ce ? pl.ce : fresh_ptrs[pl.fresh];
+    Request* r = pl.r;
+    if (!ce) {
+      r->rc = BL_E_NOMEM;
+      r->err = "device memory for a new cohort is not available";
+      finish_request(srv, r);
+      continue;
+    }
+    int s = 0;
+    while (ce->res[s].r) ++s;
+    Resident& R = ce->res[s];
+    R = Resident{};
+    R.r = r;
+    R.phase = 1;
+    std::memset(&r->stats, 0, sizeof(r->stats));
+    r->times.slot = s;
+    const int rc = guarded([&]() {
+      ce->co->load(s, r->I0.data(), r->I1.data(), r->v.data());
+      ce->co->prepare(s);
+      return BL_OK;
+    });
+    ce->active += 1;
+    Ctl& in = ce->co->ctl_in(s);
+    in = Ctl{};
+    if (rc != BL_OK) {
+      fail_resident(srv, *ce, s, rc, bl_lddmm_last_error());
+      continue;
+    }
+    const double sig = r->prob.sigma;
+    in.g_init = 1;
+    in.c1 = r->opts.c1;
+    in.sig2M = sig * sig * (double)r->g.M;
+    in.max_pcg = r->opts.max_pcg;
+    in.max_halvings = r->opts.max_halvings;
+  }
+}
+
+void scheduler(bl_server* srv, int max_pairs) {
+  hipSetDevice(srv->device);
+  std::deque<CohortEntry*> order;   // cohorts in flight, in launch order
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(srv->mu);
+      bool any = false;
+      for (auto& ce : srv->cohorts) any = any || ce->active > 0;
+      if (srv->stopping && !any) return;
+      if (!any && srv->queue.empty()) {
+        srv->cv_work.wait(lk, [&]() { return srv->stopping || !srv->queue.empty(); });
+        continue;
+      }
+    }
+    admit_batched(srv, max_pairs);
+    for (auto& up : srv->cohorts) {
+      CohortEntry& ce = *up;
+      if (ce.active == 0 || ce.launched) continue;
+      const int rc = guarded([&]() {
+        ce.co->launch();
+        return BL_OK;
+      });
+      if (rc != BL_OK) {
+        const std::string msg = bl_lddmm_last_error();
+        for (int s = 0; s < (int)ce.res.size(); ++s)
+          if (ce.res[s].r) fail_resident(srv, ce, s, rc, msg);
+        continue;
+      }
+      ce.launched = true;
+      order.push_back(&ce);
+    }
+    if (order.empty()) continue;
+    CohortEntry& ce = *order.front();
+    order.pop_front();
+    ce.launched = false;
+    const int rc = guarded([&]() {
+      ce.co->wait();
+      return BL_OK;
+    });
+    for (int s = 0; s < (int)ce.res.size(); ++s) {
+      if (!ce.res[s].r) continue;
+      if (rc != BL_OK) fail_resident(srv, ce, s, rc, bl_lddmm_last_error());
+      else advance(srv, ce, s);
+    }
   }
 }
 
@@ -194,6 +612,29 @@ int bl_server_create(uint64_t budget_bytes, int32_t max_slots, bl_server** out) 
     }
     bl_server* raw = s.get();
     for (int i = 0; i < max_slots; ++i) raw->slots[i].th = std::thread(worker, raw, i);
+    *out = s.release();
+    return BL_OK;
+  });
+}
+
+int bl_server_create_batched(uint64_t budget_bytes, int32_t max_pairs, bl_server** out) {
+  if (out) *out = nullptr;
+  if (!out) return fail(BL_E_INVALID, "NULL pointer argument");
+  if (max_pairs < 1 || max_pairs > 64) return fail(BL_E_INVALID, "max_pairs must be in [1, 64]");
+  return guarded([&]() {
+    std::unique_ptr<bl_server> s(new bl_server());
+    HIP_TRY(hipGetDevice(&s->device));
+    if (budget_bytes == 0) {
+      size_t free_b = 0, total_b = 0;
+      HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+      budget_bytes = (uint64_t)(0.8 * (double)free_b);
+    }
+    s->budget = budget_bytes;
+    s->max_slots = max_pairs;
+    s->batched = true;
+    s->t0 = Clock::now();
+    bl_server* raw = s.get();
+    raw->sched = std::thread(scheduler, raw, max_pairs);
     *out = s.release();
     return BL_OK;
   });
@@ -304,7 +745,9 @@ void bl_server_destroy(bl_server* srv) {
   srv->cv_done.notify_all();
   for (auto& sl : srv->slots)
     if (sl.th.joinable()) sl.th.join();
+  if (srv->sched.joinable()) srv->sched.join();
   hipSetDevice(srv->device);
+  srv->cohorts.clear();
   for (auto& sl : srv->slots) {
     if (sl.stream) hipStreamSynchronize(sl.stream);
     destroy_ctx(sl.ctx);   // does not own the arena, stream or host scalars

@@ -188,6 +188,10 @@ template <int DIM>
 __global__ __launch_bounds__(BX* GBY) void k_setup(Geo g, const float* __restrict__ v,
                                                    float* __restrict__ X,
                                                    float4* __restrict__ YA) {
+  BL_BATCH(g.bat)
+  BL_AT(v, g.bat);
+  BL_AT(X, g.bat);
+  BL_AT(YA, g.bat);
   constexpr int ZV = 1;
   GATHER_XY
   GATHER_Z(0)
@@ -226,6 +230,10 @@ template <int DIM>
 __global__ __launch_bounds__(BX* GBY) void k_setup_ns(Geo g, const float* __restrict__ V,
                                                       float* __restrict__ Xall,
                                                       float4* __restrict__ YAall) {
+  BL_BATCH(g.bat)
+  BL_AT(V, g.bat);
+  BL_AT(Xall, g.bat);
+  BL_AT(YAall, g.bat);
   constexpr int ZV = 1;
   GATHER_XY
   GATHER_Z(0)
@@ -261,6 +269,10 @@ template <int DIM, int ZV>
 __global__ __launch_bounds__(BX* GBY) void k_state_step(Geo g, const float* __restrict__ m_in,
                                                         const float* __restrict__ X,
                                                         float* __restrict__ m_out) {
+  BL_BATCH(g.bat)
+  BL_AT(m_in, g.bat);
+  BL_AT(X, g.bat);
+  BL_AT(m_out, g.bat);
   GATHER_XY
   const size_t M = (size_t)g.M;
   float val[ZV];
@@ -278,6 +290,10 @@ template <int DIM, int ZV>
 __global__ __launch_bounds__(BX* GBY) void k_adj_step(Geo g, const float* __restrict__ lam_in,
                                                       const float4* __restrict__ YA,
                                                       float* __restrict__ lam_out) {
+  BL_BATCH(g.bat)
+  BL_AT(lam_in, g.bat);
+  BL_AT(YA, g.bat);
+  BL_AT(lam_out, g.bat);
   GATHER_XY
   float val[ZV];
 #pragma unroll
@@ -294,6 +310,10 @@ template <int DIM>
 __global__ __launch_bounds__(BX* GBY) void k_terminal(Geo g, const float* __restrict__ mT,
                                                       const float* __restrict__ I1,
                                                       float* __restrict__ lam) {
+  BL_BATCH(g.bat)
+  BL_AT(mT, g.bat);
+  BL_AT(I1, g.bat);
+  BL_AT(lam, g.bat);
   constexpr int ZV = 1;
   GATHER_XY
   GATHER_Z(0)
@@ -339,6 +359,10 @@ template <int DIM, int ZV>
 __global__ __launch_bounds__(BX* GBY) void k_inc_init(Geo g, const float* __restrict__ m0,
                                                       const float* __restrict__ dv,
                                                       float* __restrict__ t0) {
+  BL_BATCH(g.bat)
+  BL_AT(m0, g.bat);
+  BL_AT(dv, g.bat);
+  BL_AT(t0, g.bat);
   GATHER_XY
   float val[ZV];
 #pragma unroll
@@ -356,6 +380,12 @@ __global__ __launch_bounds__(BX* GBY) void k_inc_step(Geo g, const float* __rest
                                                       const float* __restrict__ m_next,
                                                       const float* __restrict__ dv,
                                                       float* __restrict__ t_out) {
+  BL_BATCH(g.bat)
+  BL_AT(t_in, g.bat);
+  BL_AT(X, g.bat);
+  BL_AT(m_next, g.bat);
+  BL_AT(dv, g.bat);
+  BL_AT(t_out, g.bat);
   GATHER_XY
   const size_t M = (size_t)g.M;
   float val[ZV];
@@ -376,6 +406,12 @@ __global__ __launch_bounds__(BX* GBY) void k_inc_last(Geo g, const float* __rest
                                                       const float* __restrict__ mT,
                                                       const float* __restrict__ dv,
                                                       float* __restrict__ dlam) {
+  BL_BATCH(g.bat)
+  BL_AT(t_in, g.bat);
+  BL_AT(X, g.bat);
+  BL_AT(mT, g.bat);
+  BL_AT(dv, g.bat);
+  BL_AT(dlam, g.bat);
   GATHER_XY
   const size_t M = (size_t)g.M;
   float val[ZV];
@@ -401,6 +437,10 @@ template <int DIM, int ZV>
 __global__ __launch_bounds__(BX* GBY) void k_body_force(Geo g, const float* __restrict__ lam,
                                                         const float* __restrict__ m,
                                                         float* __restrict__ b) {
+  BL_BATCH(g.bat)
+  BL_AT(lam, g.bat);
+  BL_AT(m, g.bat);
+  BL_AT(b, g.bat);
   GATHER_XY
   const size_t M = (size_t)g.M;
   const uint32_t sz = (uint32_t)g.nx * g.ny;
@@ -489,6 +529,13 @@ __global__ __launch_bounds__(BX* GBY) void k_inc_step_n(Geo g, const float* __re
                                                         const float* __restrict__ dv,
                                                         float* __restrict__ t_out,
                                                         float* __restrict__ dm_out) {
+  BL_BATCH(g.bat)
+  BL_AT(t_in, g.bat);
+  BL_AT(X, g.bat);
+  BL_AT(m_next, g.bat);
+  BL_AT(dv, g.bat);
+  BL_AT(t_out, g.bat);
+  BL_AT(dm_out, g.bat);
   GATHER_XY
   const size_t M = (size_t)g.M;
   float val[ZV], dmv[ZV];
@@ -515,6 +562,14 @@ __global__ __launch_bounds__(BX* GBY) void k_inc_last_n(Geo g, const float* __re
                                                         const float* __restrict__ lamT,
                                                         float* __restrict__ dm_out,
                                                         float* __restrict__ dlam) {
+  BL_BATCH(g.bat)
+  BL_AT(t_in, g.bat);
+  BL_AT(X, g.bat);
+  BL_AT(mT, g.bat);
+  BL_AT(dv, g.bat);
+  BL_AT(lamT, g.bat);
+  BL_AT(dm_out, g.bat);
+  BL_AT(dlam, g.bat);
   GATHER_XY
   const size_t M = (size_t)g.M;
   float dmv[ZV], val[ZV];
@@ -541,6 +596,13 @@ __global__ __launch_bounds__(BX* GBY) void k_adj_step_n(Geo g, const float* __re
                                                         const float* __restrict__ dv, int own,
                                                         float* __restrict__ dlam,
                                                         float* __restrict__ u_out) {
+  BL_BATCH(g.bat)
+  BL_AT(u_in, g.bat);
+  BL_AT(YA, g.bat);
+  BL_AT(lam_n, g.bat);
+  BL_AT(dv, g.bat);
+  BL_AT(dlam, g.bat);
+  BL_AT(u_out, g.bat);
   GATHER_XY
   float qv[ZV], uv[ZV];
 #pragma unroll
@@ -566,6 +628,12 @@ __global__ __launch_bounds__(BX* GBY) void k_body_force_n(Geo g, const float* __
                                                           const float* __restrict__ lam,
                                                           const float* __restrict__ dm,
                                                           float* __restrict__ b) {
+  BL_BATCH(g.bat)
+  BL_AT(dlam, g.bat);
+  BL_AT(m, g.bat);
+  BL_AT(lam, g.bat);
+  BL_AT(dm, g.bat);
+  BL_AT(b, g.bat);
   GATHER_XY
   const size_t M = (size_t)g.M;
   const uint32_t sz = (uint32_t)g.nx * g.ny;
@@ -626,6 +694,10 @@ template <int DIM, int ZV>
 __global__ __launch_bounds__(BX* GBY) void k_body_node(Geo g, const float* __restrict__ lam,
                                                        const float* __restrict__ m,
                                                        float* __restrict__ b) {
+  BL_BATCH(g.bat)
+  BL_AT(lam, g.bat);
+  BL_AT(m, g.bat);
+  BL_AT(b, g.bat);
   GATHER_XY
   const size_t M = (size_t)g.M;
   lam += blockIdx.y * M;
@@ -653,7 +725,11 @@ __global__ __launch_bounds__(BX* GBY) void k_body_node(Geo g, const float* __res
 // a fixed strided subset, then a fixed tree in LDS.
 __global__ __launch_bounds__(256) void k_energy_partial(int64_t n, const float* __restrict__ a,
                                                         const float* __restrict__ b,
-                                                        double* __restrict__ partial) {
+                                                        double* __restrict__ partial, Batch bt) {
+  BL_BATCH(bt)
+  BL_AT(a, bt);
+  BL_AT(b, bt);
+  BL_AT(partial, bt);
   __shared__ double sh[256];
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
@@ -689,7 +765,7 @@ inline dim3 gather_grid(const Geo& g, int zv) {
 
 // 3D launches take the class's voxels per thread along z (1, 2, 4 or 8); 2D runs one per thread.
 // NY > 1 repeats the grid over blockIdx.y (one copy per time node).
-#define GRID_N(ZV_, NY) dim3(gather_grid(g, ZV_).x, (NY))
+#define GRID_N(ZV_, NY) batch_grid(dim3(gather_grid(g, ZV_).x, (NY)), g.bat)
 #define DISPATCH_GATHER_N(KERNEL, CLS, NY, ...)                                                 \
   do {                                                                                          \
     if (g.dim == 3) {                                                                           \
@@ -710,15 +786,17 @@ inline dim3 gather_grid(const Geo& g, int zv) {
 #define DISPATCH_ONE(KERNEL, ...)                                                          \
   do {                                                                                     \
     if (g.dim == 3)                                                                        \
-      hipLaunchKernelGGL(KERNEL<3>, gather_grid(g, 1), dim3(BX, GBY), 0, s, __VA_ARGS__);  \
+      hipLaunchKernelGGL(KERNEL<3>, batch_grid(gather_grid(g, 1), g.bat), dim3(BX, GBY), 0, s, \
+                         __VA_ARGS__);                                                     \
     else                                                                                   \
-      hipLaunchKernelGGL(KERNEL<2>, gather_grid(g, 1), dim3(BX, GBY), 0, s, __VA_ARGS__);  \
+      hipLaunchKernelGGL(KERNEL<2>, batch_grid(gather_grid(g, 1), g.bat), dim3(BX, GBY), 0, s, \
+                         __VA_ARGS__);                                                     \
   } while (0)
 void setup(const Geo& g, const float* v, float* X, float4* YA, hipStream_t s) {
   DISPATCH_ONE(k_setup, g, v, X, YA);
 }
 void setup_ns(const Geo& g, const float* V, float* X, float4* YA, int steps, hipStream_t s) {
-  const dim3 grid(gather_grid(g, 1).x, (unsigned)steps);
+  const dim3 grid = batch_grid(dim3(gather_grid(g, 1).x, (unsigned)steps), g.bat);
   if (g.dim == 3)
     hipLaunchKernelGGL(k_setup_ns<3>, grid, dim3(BX, GBY), 0, s, g, V, X, YA);
   else
@@ -770,7 +848,8 @@ void body_force_n(const Geo& g, const float* dlam, const float* m, const float* 
 }
 void energy_partial(const Geo& g, const float* mT, const float* I1, double* partial,
                     hipStream_t s) {
-  hipLaunchKernelGGL(k_energy_partial, dim3(kRedBlocks), dim3(256), 0, s, g.M, mT, I1, partial);
+  hipLaunchKernelGGL(k_energy_partial, batch_grid(dim3(kRedBlocks), g.bat), dim3(256), 0, s, g.M,
+                     mT, I1, partial, g.bat);
 }
 void unpack4(const Geo& g, int comp, const float4* in, float* plane, hipStream_t s) {
   hipLaunchKernelGGL(k_unpack4, dim3((unsigned)((g.M + 255) / 256)), dim3(256), 0, s, g.M, comp,
