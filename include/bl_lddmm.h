@@ -255,8 +255,12 @@ int bl_lddmm_device_count(void);
  * Per-kernel timing with HIP events on the library's stream, for benchmarks: while enabled,
  * each run of consecutive launches of a transport step kernel is bracketed by one event
  * pair (no per-launch event overhead); bl_kernel_timing_read
- * returns the number of launches and the summed milliseconds per kernel class
- * (0 = forward state step, 1 = incremental forward step, 2 = adjoint step) and resets.
+ * returns the number of launches (runs for classes 3 and 4) and the summed milliseconds per
+ * class and resets: 0 = forward state step, 1 = incremental forward step, 2 = adjoint step,
+ * 3 = iota of the direction in a Gauss-Newton product (its three stages), 4 = pi of the
+ * product's body force (its three stages), 5 = body-force pass, 6 = departure-point setup.
+ * Classes 3-5 are timed in Gauss-Newton products and gradients of the stationary state
+ * equation only.  Errors: BL_E_INVALID for a NULL argument or a class outside [0, 6].
  */
 int bl_kernel_timing_enable(bl_ctx* ctx, int32_t on);
 int bl_kernel_timing_read(bl_ctx* ctx, int32_t kclass, int64_t* launches, double* ms);
@@ -320,8 +324,9 @@ typedef struct {
 int bl_server_create(uint64_t budget_bytes, int32_t max_slots, bl_server** server);
 /*
  * Cohort server: the same queue, budget, submit / wait / cancel / info / destroy calls, a
- * different engine.  Requests of equal problems (grid, band, Nt, alpha, s, sigma, gamma,
- * precision) share a cohort of up to max_pairs (1..64) resident pairs; every kernel of the
+ * different engine.  At most max_pairs (1..64) pairs are resident at once.  Requests of equal
+ * problems (grid, band, Nt, alpha, s, sigma, gamma, precision) share a cohort of resident
+ * pairs, as many as fit the last-level cache with their time-step working sets; every kernel of the
  * Gauss-Newton-Krylov path is one launch for all pairs of a cohort (each pair's buffers at a
  * fixed stride of one arena, a per-pair gate in device memory), and each Newton step -- up to
  * 10 PCG iterations with their stopping tests evaluated on the device, the line-search slope,
@@ -329,7 +334,7 @@ int bl_server_create(uint64_t budget_bytes, int32_t max_slots, bl_server** serve
  * captured when the cohort is created.  The host reads one control block per pair after a
  * step, records the statistics, retires finished pairs and fills free slots with queued
  * requests of the same problem.  The budget is charged with each cohort's whole arena while
- * the cohort exists (capacity = min(max_pairs, free budget / footprint)); an empty cohort is
+ * the cohort exists (capacity = min(max_pairs, cache-sized count, free budget / footprint)); an empty cohort is
  * freed when a request of another problem needs the memory.  The queue is strictly FIFO.
  * Every result is bitwise the one bl_lddmm_register gives alone (same per-element arithmetic,
  * same reduction order, the same FP64 decisions).  Only the stationary Gauss-Newton

@@ -56,6 +56,12 @@ struct Ctl {
   double den;         // |I0 - I1|^2
 };
 
+constexpr int kMaxPcgPerStep = 10;   // PCG iterations of the largest step graph
+// Device bytes the time steps of a cohort's pairs may touch together and still be served by
+// the last-level cache between steps (the 256 MiB MALL, minus room for the rest): the offset
+// and velocity fields are re-read by every time step, so a cohort larger than this turns
+// those cache hits into HBM reads.
+constexpr double kLlcBytes = 192.0 * 1024 * 1024;
 constexpr int kCtlSlot = 16;   // doubles into bl_ctx::scal (64 doubles, S_SLOTS used before)
 static_assert(sizeof(Ctl) <= (64 - kCtlSlot) * sizeof(double), "control block too large");
 
@@ -79,14 +85,18 @@ class Cohort {
 
   // copy a problem's images and initial guess into slot s (stream-ordered, host pointers)
   void load(int s, const float* I0, const float* I1, const float* v);
-  // choose launch shapes on slot s's data and capture the step graph (once, after the first
-  // load); later calls do nothing
+  // choose launch shapes on slot s's data (once, after the first load); the step graphs are
+  // captured at their first launch
   void prepare(int s);
+  // pairs whose time-step working set fits the last-level cache together
+  static int llc_capacity(const Geo& g);
   Ctl& ctl_in(int s) { return hin_[s]; }
   const Ctl& ctl_out(int s) const { return hout_[s]; }
-  // enqueue one step of every problem whose gates are set in ctl_in; then wait for it
-  void launch();
+  // enqueue one step (k_pcg PCG iterations, 0..kMaxPcgPerStep, then the line-search trial and
+  // gradient) of every problem whose gates are set in ctl_in; wait or poll for its end
+  void launch(int k_pcg);
   void wait();
+  bool poll();
   bool in_flight() const { return in_flight_; }
   // results of slot s: velocity (nb floats) and the warped source m(1) (M floats)
   void store(int s, float* v, float* warped);
@@ -95,7 +105,8 @@ class Cohort {
   hipStream_t stream() const { return stream_; }
 
  private:
-  void enqueue_step();
+  void enqueue_step(int k_pcg);
+  hipGraphExec_t graph(int k_pcg);
   void release();
   Batch gated(const int* gate) const;
 
@@ -111,10 +122,10 @@ class Cohort {
   Ctl* hout_ = nullptr;  // pinned host control blocks (step outputs)
   Ctl* din_ = nullptr;   // their device addresses
   Ctl* dout_ = nullptr;
-  hipGraphExec_t exec_ = nullptr;
+  std::vector<hipGraphExec_t> exec_;   // step graphs by PCG iterations per step
+  bool prepared_ = false;
   hipEvent_t done_ = nullptr;
   bool in_flight_ = false;
-  int k_pcg_ = 0;        // PCG iterations per captured step
 };
 
 }  // namespace batch

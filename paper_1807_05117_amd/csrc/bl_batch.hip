@@ -15,6 +15,7 @@
 // The control kernels evaluate these tests with floating-point contraction disabled, so each
 // FP64 operation rounds exactly as the host's does.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 
 #include "bl_batch.h"
@@ -209,8 +210,9 @@ Cohort::~Cohort() { release(); }
 
 void Cohort::release() {
   if (stream_) hipStreamSynchronize(stream_);
-  if (exec_) hipGraphExecDestroy(exec_);
-  exec_ = nullptr;
+  for (hipGraphExec_t& e : exec_)
+    if (e) hipGraphExecDestroy(e);
+  exec_.clear();
   for (bl_ctx* c : ctx_) destroy_ctx(c);   // does not own the arena, stream or host scalars
   ctx_.clear();
   for (double* h : hscal_) hipHostFree(h);
@@ -234,7 +236,7 @@ void Cohort::load(int s, const float* I0, const float* I1, const float* v) {
 }
 
 void Cohort::prepare(int s) {
-  if (exec_) return;
+  if (prepared_) return;
   // launch shapes from a real state evaluation of the first problem (the tuner times the
   // transports on its offsets; the step graph re-evaluates this problem from scratch)
   bl_ctx* c0 = ctx_[s];
@@ -244,23 +246,29 @@ void Cohort::prepare(int s) {
     c->tuned = true;
   }
   for (int k = 0; k < 4; ++k) g_.zv[k] = c0->g.zv[k];
-  k_pcg_ = 10;
+  exec_.assign(kMaxPcgPerStep + 1, nullptr);
+  prepared_ = true;
+}
+
+// the step graph with k PCG iterations, captured at its first use
+hipGraphExec_t Cohort::graph(int k) {
+  if (exec_[k]) return exec_[k];
   hipGraph_t graph = nullptr;
   HIP_TRY(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
   try {
-    enqueue_step();
+    enqueue_step(k);
   } catch (...) {
     hipStreamEndCapture(stream_, &graph);
     if (graph) hipGraphDestroy(graph);
     throw;
   }
   HIP_TRY(hipStreamEndCapture(stream_, &graph));
-  const hipError_t e = hipGraphInstantiate(&exec_, graph, nullptr, nullptr, 0);
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
   hipGraphDestroy(graph);
-  if (e != hipSuccess) {
-    exec_ = nullptr;
-    throw DeviceError{e, "hipGraphInstantiate (cohort step)"};
-  }
+  if (e != hipSuccess) throw DeviceError{e, "hipGraphInstantiate (cohort step)"};
+  exec_[k] = ex;
+  return ex;
 }
 
 Batch Cohort::gated(const int* gate) const {
@@ -274,7 +282,7 @@ Batch Cohort::gated(const int* gate) const {
 
 // The launch sequence of one step on problem 0's buffers; every launch is batched over the
 // cohort and gated per problem.  Only kernels (no memset or copy nodes) are captured.
-void Cohort::enqueue_step() {
+void Cohort::enqueue_step(int k_pcg) {
   bl_ctx* c = ctx_[0];
   hipStream_t s = stream_;
   const Geo g0 = c->g;
@@ -310,7 +318,7 @@ void Cohort::enqueue_step() {
   bl::copy_band(c->sp, c->sz, nb, s, b);
 
   // PCG iterations
-  for (int j = 0; j < k_pcg_; ++j) {
+  for (int j = 0; j < k_pcg; ++j) {
     b = use(&ctl0->g_pcg);
     op_hessvec(c, c->sp, c->sHp);
     vec_dot_partial(c, c->sp, c->sHp, pa);
@@ -356,8 +364,9 @@ void Cohort::enqueue_step() {
   check_launch("cohort step");
 }
 
-void Cohort::launch() {
-  HIP_TRY(hipGraphLaunch(exec_, stream_));
+void Cohort::launch(int k_pcg) {
+  k_pcg = std::max(0, std::min(k_pcg, kMaxPcgPerStep));
+  HIP_TRY(hipGraphLaunch(graph(k_pcg), stream_));
   HIP_TRY(hipEventRecord(done_, stream_));
   in_flight_ = true;
 }
@@ -366,6 +375,24 @@ void Cohort::wait() {
   if (!in_flight_) return;
   HIP_TRY(hipEventSynchronize(done_));
   in_flight_ = false;
+}
+
+bool Cohort::poll() {
+  if (!in_flight_) return true;
+  const hipError_t e = hipEventQuery(done_);
+  if (e == hipErrorNotReady) return false;
+  if (e != hipSuccess) throw DeviceError{e, "hipEventQuery (cohort step)"};
+  in_flight_ = false;
+  return true;
+}
+
+int Cohort::llc_capacity(const Geo& g) {
+  // grid bytes one incremental-state step of a pair touches: X (dim planes), dv (dim),
+  // m^{n+1}, t^n and t^{n+1}
+  const double step = (double)g.M * 4.0 * (2.0 * g.dim + 3.0);
+  double llc = kLlcBytes;
+  if (const char* e = std::getenv("BL_COHORT_LLC_BYTES")) llc = std::atof(e);
+  return std::max(1, (int)(llc / step));
 }
 
 void Cohort::store(int s, float* v, float* warped) {

@@ -127,8 +127,8 @@ struct bl_ctx {
   std::vector<Run> ev_used;  // timed runs: class, pool index of the start event, launches
   size_t ev_next = 0;
   int ev_open = -1;
-  int64_t t_launch[3] = {0, 0, 0};
-  double t_ms[3] = {0, 0, 0};
+  int64_t t_launch[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double t_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 namespace bl {
@@ -154,6 +154,7 @@ void solve(bl_ctx* c, const bl_solver_opts& o, bl_stats* st);
 // operator sequences on a context (enqueued on c->stream; launches follow c->g.bat)
 void enqueue_set_velocity(bl_ctx* c, const float2* vraw);   // stationary state equation only
 void op_set_velocity(bl_ctx* c, const float2* vraw);        // enqueue, synchronise, read E
+void finish_set_velocity(bl_ctx* c);   // E from the published sums (after a sync)
 void op_gradient(bl_ctx* c, float2* gout);
 void op_hessvec(bl_ctx* c, const float2* draw, float2* hout);
 void vec_dot_partial(bl_ctx* c, const float2* a, const float2* b, double* pa);

@@ -270,6 +270,8 @@ void reduce_max_final(const double* partial, int n, double* out, hipStream_t s,
 // y = alpha x + y
 void axpy(float2* y, const float2* x, double alpha, int64_t n, hipStream_t s,
           const Batch& bt = Batch{});
+// host_flag[0] = flag[0] (host-mapped destination)
+void publish_flag(const int* flag, double* host_flag, hipStream_t s);
 // y = 0; y = x (kernels, so that a captured graph holds no memset or copy node)
 void zero_band(float2* y, int64_t n, hipStream_t s, const Batch& bt = Batch{});
 void copy_band(float2* y, const float2* x, int64_t n, hipStream_t s, const Batch& bt = Batch{});

@@ -860,7 +860,9 @@ void enqueue_set_velocity(bl_ctx* c, const float2* vraw) {
   double* red_data = c->red + RED_DATA * bl::kRedBlocks;
   bl::band_prep(g, vraw, c->bv, 1, c->Lhat64, red_reg, s);
   bl::iota(g, c->plan, c->bv, g.dim + 1, c->V, s);
+  if (c->timing) t_begin(c);
   bl::setup(g, c->V, c->X, c->YA, s);
+  if (c->timing) t_end(c, 6, 1);
   if (!c->tuned) choose_launch_shapes(c);
   const size_t M = (size_t)g.M;
   if (c->timing) t_begin(c);
@@ -884,9 +886,14 @@ void op_set_velocity(bl_ctx* c, const float2* vraw) {
     op_set_velocity_ns(c, vraw);
     return;
   }
-  const bl::Geo& g = c->g;
   enqueue_set_velocity(c, vraw);
   sync(c);
+  finish_set_velocity(c);
+}
+
+// E and the state flags from the published sums of enqueue_set_velocity (after a sync)
+void finish_set_velocity(bl_ctx* c) {
+  const bl::Geo& g = c->g;
   c->reg = c->hscal[S_REG];
   c->data_sum = c->hscal[S_DATA];
   const double sig = c->prob.sigma;
@@ -894,6 +901,27 @@ void op_set_velocity(bl_ctx* c, const float2* vraw) {
   c->have_v = true;
   c->have_lambda = false;
   if (!std::isfinite(c->E)) throw NonFinite{"energy"};
+}
+
+// Energy and gradient at the raw band vector `vraw` into gout with one host synchronisation
+// (stationary state equation): the energy sums and the non-finite flag of the band outputs
+// are published to host-mapped memory and read together; `after` enqueues the caller's
+// copies of the results before that synchronisation.
+template <class After>
+void op_energy_gradient(bl_ctx* c, const float2* vraw, float2* gout, After&& after) {
+  enqueue_set_velocity(c, vraw);
+  op_gradient(c, gout);
+  bl::publish_flag(c->flag, c->hdev + S_FLAG, c->stream);
+  after();
+  check_launch("energy and gradient");
+  sync(c);
+  finish_set_velocity(c);
+  c->have_lambda = true;   // L holds this velocity's adjoint (the full Newton product reuses it)
+  if (c->hscal[S_FLAG] != 0.0) {
+    HIP_TRY(hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
+    sync(c);
+    throw NonFinite{"gradient"};
+  }
 }
 
 // backward transport of L[nt] down to L[0], then the body force b = sum_n w_n L[n] grad m^n
@@ -904,7 +932,9 @@ void backward_and_body_force(bl_ctx* c) {
   if (c->timing) t_begin(c);
   for (int n = g.nt - 1; n >= 0; --n) bl::adj_step(g, c->L + (n + 1) * M, c->YA, c->L + n * M, s);
   if (c->timing) t_end(c, 2, g.nt);
+  if (c->timing) t_begin(c);
   bl::body_force(g, c->L, c->m, c->Bf, s);
+  if (c->timing) t_end(c, 5, 1);
 }
 
 // gradient at the current velocity into gout (device, dim components)
@@ -986,7 +1016,9 @@ void op_hessvec(bl_ctx* c, const float2* draw, float2* hout) {
   hipStream_t s = c->stream;
   const size_t M = (size_t)g.M;
   bl::band_prep(g, draw, c->bd, 0, nullptr, nullptr, s);
+  if (c->timing) t_begin(c);
   bl::iota(g, c->plan, c->bd, g.dim, c->DV, s);
+  if (c->timing) t_end(c, 3, 1);
   bl::inc_init(g, c->m, c->DV, c->T0, s);
   float* tin = c->T0;
   float* tout = c->T1;
@@ -998,7 +1030,9 @@ void op_hessvec(bl_ctx* c, const float2* draw, float2* hout) {
   if (c->timing && g.nt > 1) t_end(c, 1, g.nt - 1);
   bl::inc_last(g, tin, c->X, c->m + g.nt * M, c->DV, c->L + g.nt * M, s);
   backward_and_body_force(c);
+  if (c->timing) t_begin(c);
   bl::pi_half(g, c->plan, c->Bf, g.dim, c->P, s);
+  if (c->timing) t_end(c, 4, 1);
   bl::band_finalize(g, g.dim, c->bd, c->Lhat, c->P, (float)(1.0 / (double)g.M), hout, c->flag, s,
                     1);
   check_launch("hessvec");
@@ -1384,6 +1418,13 @@ int bl_lddmm_ctx_set_velocity(bl_ctx* c, const float* v_hat, double* energy, flo
   return guarded([&]() {
     HIP_TRY(hipSetDevice(c->device));
     load_band(c, v_hat, c->braw, c->g.nodes * c->g.dim);
+    if (g_hat && !c->g.deform && c->g.nodes == 1) {
+      op_energy_gradient(c, c->braw, c->bout,
+                         [&]() { store_band(c, c->bout, g_hat, c->g.dim); });
+      if (energy) *energy = c->E;
+      t_collect(c);
+      return BL_OK;
+    }
     op_set_velocity(c, c->braw);
     if (energy) *energy = c->E;
     if (g_hat) {
@@ -1463,10 +1504,15 @@ int bl_lddmm_gradient(const bl_problem* prob, const float* I0, const float* I1,
     CachedCtx h(prob, g, false);
     load_images(h.c, I0, I1);
     load_band(h.c, v_hat, h.c->braw, g.nodes * g.dim);
-    op_set_velocity(h.c, h.c->braw);
-    op_gradient(h.c, h.c->bout);
-    store_band(h.c, h.c->bout, g_hat, g.nodes * g.dim);
-    check_flag(h.c, "gradient");
+    if (!g.deform && g.nodes == 1) {
+      op_energy_gradient(h.c, h.c->braw, h.c->bout,
+                         [&]() { store_band(h.c, h.c->bout, g_hat, g.dim); });
+    } else {
+      op_set_velocity(h.c, h.c->braw);
+      op_gradient(h.c, h.c->bout);
+      store_band(h.c, h.c->bout, g_hat, g.nodes * g.dim);
+      check_flag(h.c, "gradient");
+    }
     if (energy) *energy = h.c->E;
     h.ok = true;
     return BL_OK;
@@ -1609,7 +1655,7 @@ int bl_kernel_timing_enable(bl_ctx* c, int32_t on) {
 int bl_kernel_timing_read(bl_ctx* c, int32_t kclass, int64_t* launches, double* ms) {
   t_err.clear();
   if (!c || !launches || !ms) return fail(BL_E_INVALID, "NULL pointer argument");
-  if (kclass < 0 || kclass > 2) return fail(BL_E_INVALID, "kernel class must be 0, 1 or 2");
+  if (kclass < 0 || kclass > 6) return fail(BL_E_INVALID, "kernel class must be in [0, 6]");
   return guarded([&]() {
     HIP_TRY(hipSetDevice(c->device));
     t_collect(c);

@@ -325,6 +325,11 @@ __global__ __launch_bounds__(256) void k_add_scaled_dev(float2* __restrict__ y,
   }
 }
 
+// the non-finite flag of the band kernels into host-mapped memory (read after one sync)
+__global__ void k_publish_flag(const int* __restrict__ flag, double* __restrict__ host_flag) {
+  if (threadIdx.x == 0) host_flag[0] = (double)flag[0];
+}
+
 inline int blocks_for(int64_t n) {
   (void)n;
   return kRedBlocks;
@@ -368,6 +373,9 @@ void maxabs_partial(const float2* a, int64_t n, double* partial, hipStream_t s, 
 void axpy(float2* y, const float2* x, double alpha, int64_t n, hipStream_t s, const Batch& bt) {
   hipLaunchKernelGGL(k_axpy, batch_grid(dim3(blocks_for(n)), bt), dim3(256), 0, s, y, x, alpha, n,
                      bt);
+}
+void publish_flag(const int* flag, double* host_flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_publish_flag, dim3(1), dim3(64), 0, s, flag, host_flag);
 }
 void zero_band(float2* y, int64_t n, hipStream_t s, const Batch& bt) {
   hipLaunchKernelGGL(k_zero, batch_grid(dim3(blocks_for(n)), bt), dim3(256), 0, s, y, n, bt);

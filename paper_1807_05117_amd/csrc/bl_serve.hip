@@ -20,6 +20,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -69,6 +70,7 @@ struct Resident {
   int phase = 0;         // 0 free, 1 initial evaluation pending, 2 Gauss-Newton iterations
   int it = 0;            // current Gauss-Newton iteration
   bool pcg_open = false; // PCG of iteration `it` runs
+  int last_pcg = 0;      // PCG iterations of the previous Gauss-Newton iteration (0: none yet)
   double ginf0 = 0, g0n = 0, gg = 0, ginf = 0;
 };
 
@@ -347,6 +349,7 @@ void advance(bl_server* srv, CohortEntry& ce, int s) {
     st.pcg_iters[R.it] = out.iters;
     st.pcg_total += out.iters;
     R.pcg_open = false;
+    R.last_pcg = out.iters;
   }
   if (out.accepted) {
     st.ls_trials[R.it] = out.trials;
@@ -402,6 +405,8 @@ void admit_batched(bl_server* srv, int max_pairs) {
     std::vector<int> fresh_used;
     for (auto it = srv->queue.begin(); it != srv->queue.end();) {
       Request* r = *it;
+      // at most max_pairs pairs resident over all cohorts
+      if (srv->resident >= max_pairs) break;
       bool placed = false, defer = false;
       if (bl::batch::batchable(r->prob)) {
         for (size_t i = 0; i < srv->cohorts.size() && !placed; ++i) {
@@ -442,7 +447,8 @@ void admit_batched(bl_server* srv, int max_pairs) {
             }
           }
           const uint64_t room = srv->budget - std::min(srv->budget, srv->in_use);
-          const int cap = (int)std::min<uint64_t>((uint64_t)max_pairs, room / r->bytes);
+          const int cap = (int)std::min<uint64_t>(
+              (uint64_t)std::min(max_pairs, Cohort::llc_capacity(r->g)), room / r->bytes);
           if (cap >= 1) {
             Fresh f{r->prob, r->g, cap, nullptr};
             fresh.push_back(std::move(f));
@@ -539,9 +545,30 @@ void admit_batched(bl_server* srv, int max_pairs) {
   }
 }
 
+// PCG iterations of a cohort's next step: enough for the pair expected to need the most
+// (each pair's previous Gauss-Newton iteration's count, at least one more), so that few
+// gated-off iterations run; 0 when no pair is in PCG (initial evaluations, line-search
+// retries).  BL_COHORT_PCG_PER_STEP fixes the number instead.
+int pcg_per_step(const CohortEntry& ce) {
+  static const int fixed = []() {
+    const char* e = std::getenv("BL_COHORT_PCG_PER_STEP");
+    return e ? std::atoi(e) : -1;
+  }();
+  int k = 0;
+  for (size_t s = 0; s < ce.res.size(); ++s) {
+    const Resident& R = ce.res[s];
+    if (!R.r || R.phase != 2 || !R.pcg_open) continue;
+    const Ctl& in = ce.co->ctl_in((int)s);
+    const int left = in.max_pcg - in.iters;
+    const int guess = std::max(1, (R.last_pcg > 0 ? R.last_pcg : 2) - in.iters);
+    k = std::max(k, std::min(left, guess));
+  }
+  if (k > 0 && fixed >= 1) k = fixed;
+  return std::min(k, bl::batch::kMaxPcgPerStep);
+}
+
 void scheduler(bl_server* srv, int max_pairs) {
   hipSetDevice(srv->device);
-  std::deque<CohortEntry*> order;   // cohorts in flight, in launch order
   for (;;) {
     {
       std::unique_lock<std::mutex> lk(srv->mu);
@@ -554,11 +581,15 @@ void scheduler(bl_server* srv, int max_pairs) {
       }
     }
     admit_batched(srv, max_pairs);
+    bool in_flight = false;
     for (auto& up : srv->cohorts) {
       CohortEntry& ce = *up;
-      if (ce.active == 0 || ce.launched) continue;
+      if (ce.active == 0 || ce.launched) {
+        in_flight = in_flight || ce.launched;
+        continue;
+      }
       const int rc = guarded([&]() {
-        ce.co->launch();
+        ce.co->launch(pcg_per_step(ce));
         return BL_OK;
       });
       if (rc != BL_OK) {
@@ -568,21 +599,29 @@ void scheduler(bl_server* srv, int max_pairs) {
         continue;
       }
       ce.launched = true;
-      order.push_back(&ce);
+      in_flight = true;
     }
-    if (order.empty()) continue;
-    CohortEntry& ce = *order.front();
-    order.pop_front();
-    ce.launched = false;
-    const int rc = guarded([&]() {
-      ce.co->wait();
-      return BL_OK;
-    });
-    for (int s = 0; s < (int)ce.res.size(); ++s) {
-      if (!ce.res[s].r) continue;
-      if (rc != BL_OK) fail_resident(srv, ce, s, rc, bl_lddmm_last_error());
-      else advance(srv, ce, s);
+    if (!in_flight) continue;
+    // the cohorts whose steps have ended, in any order
+    bool progressed = false;
+    for (auto& up : srv->cohorts) {
+      CohortEntry& ce = *up;
+      if (!ce.launched) continue;
+      bool ended = false;
+      const int rc = guarded([&]() {
+        ended = ce.co->poll();
+        return BL_OK;
+      });
+      if (rc == BL_OK && !ended) continue;
+      ce.launched = false;
+      progressed = true;
+      for (int s = 0; s < (int)ce.res.size(); ++s) {
+        if (!ce.res[s].r) continue;
+        if (rc != BL_OK) fail_resident(srv, ce, s, rc, bl_lddmm_last_error());
+        else advance(srv, ce, s);
+      }
     }
+    if (!progressed) std::this_thread::yield();
   }
 }
 
