@@ -35,12 +35,33 @@ BAND = (32, 32, 32)
 NT = 10
 DISP = 6.0
 HBM_PEAK_GBS = 8000.0
-# algorithmic FP32 bytes per voxel of one launch of each transport step kernel:
+# algorithmic FP32 bytes per voxel of one launch of each timed kernel class:
 #   state step      X (12) + m^n (4) read, m^{n+1} (4) written                 = 20
 #   incremental     X (12) + t^n (4) + m^{n+1} (4) + dv (12) read, t^{n+1} (4)  = 36
 #   adjoint step    (Y, a) packed (16) + lambda^{n+1} (4) read, lambda^n (4)    = 24
 #                   written (the body force is a separate pass over the stored lambda^n)
+#   iota z stage    3 grid planes written (12) + the kz >= 0 half-spectrum columns read
+#                   (3 kzh complex per column = 24 kzh / nz per voxel)
+#   pi z stage      the same bytes in the other direction
+#   body force      lambda^n, m^n read for n = 0..Nt (8 (Nt + 1)), b written (12)
+#   setup           v, r read (16), X (12) and (Y, a) (16) written              = 44
 KCLASS = {0: ("state_step", 20), 1: ("inc_step", 36), 2: ("adj_step", 24)}
+KNAMES = {3: "iota_z", 4: "pi_z", 5: "body_force", 6: "setup"}
+
+
+def class_bytes(k, grid, band, nt):
+    """algorithmic bytes per voxel of kernel class k"""
+    if k in KCLASS:
+        return KCLASS[k][1]
+    if k in (3, 4):
+        return 12.0 + 24.0 * (band[2] // 2) / grid[2]
+    if k == 5:
+        return 8.0 * (nt + 1) + 12.0
+    return 44.0
+
+
+def class_name(k):
+    return KCLASS[k][0] if k in KCLASS else KNAMES[k]
 
 
 def progress(msg):
@@ -66,6 +87,20 @@ def make_inputs(seed=0, grid=None, band=None, nt=None, disp=None, ncls=3, **mode
     vs = (raw * (disp / vmax)).astype(np.complex64)
     I1 = B.bl_lddmm_warp(p, I0, vs)
     return I0, I1, vs
+
+
+def kernel_table(kern, grid, band, nt):
+    """average launch time and algorithmic GB/s (fraction of the 8 TB/s peak) per class"""
+    M = int(np.prod(grid))
+    out = {}
+    for k, (n, ms) in kern.items():
+        if not n:
+            continue
+        avg = ms / 1000.0 / n
+        gbs = class_bytes(k, grid, band, nt) * M / avg / 1e9
+        out[class_name(k)] = {"launches": n, "avg_us": avg * 1e6, "gbs_algorithmic": gbs,
+                              "frac_of_peak": gbs / HBM_PEAK_GBS}
+    return out
 
 
 def gpu_leg(steps, warmup, n_hv=200, n_lat=50, n_grad=20, precision=B.BL_FP32, inputs=None,
@@ -157,7 +192,7 @@ def gpu_leg(steps, warmup, n_hv=200, n_lat=50, n_grad=20, precision=B.BL_FP32, i
         ctx.bl_lddmm_ctx_hessvec(dv, out)
     torch.cuda.synchronize()
     kern = {}
-    for k in (0, 1, 2):
+    for k in range(7):
         n, ms = ctx.bl_kernel_timing_read(k)
         kern[k] = (n, ms)
     ctx.bl_kernel_timing_enable(False)
@@ -197,9 +232,10 @@ def gpu_leg(steps, warmup, n_hv=200, n_lat=50, n_grad=20, precision=B.BL_FP32, i
                 t_host=t_host)
 
 
-def cpu_leg(stats):
-    """The FP64 oracle on the host: one energy evaluation, one gradient and one
-    Hessian-vector product at 128^3, scaled by the registration's operation counts."""
+def cpu_leg(stats, repeats=3):
+    """The FP64 oracle on the host: an energy evaluation, a gradient and a Hessian-vector
+    product at 128^3 (median of `repeats` runs each), scaled by the registration's operation
+    counts."""
     from threadpoolctl import threadpool_limits
 
     import oracle as O
@@ -210,26 +246,55 @@ def cpu_leg(stats):
         vs = O.project(phantoms.raw_band_velocity(0, 3, BAND), prob)
         vs *= DISP / O.max_displacement_voxels(vs, prob)
         I1 = O.warp(I0, vs, prob).astype(np.float32).astype(np.float64)
-        t = time.perf_counter()
-        st = O.evaluate(0.5 * vs, I0, I1, prob)
-        t_eval = time.perf_counter() - t
-        t = time.perf_counter()
-        O.gradient(st)
-        t_grad = time.perf_counter() - t
         d = O.project(phantoms.random_band_direction(1, 3, BAND), prob)
-        t = time.perf_counter()
-        O.hessvec(st, d)
-        t_hv = time.perf_counter() - t
-    progress(f"oracle: evaluation {t_eval:.1f} s, gradient {t_grad:.1f} s, product {t_hv:.1f} s")
+        te, tg, th = [], [], []
+        for _ in range(repeats):
+            t = time.perf_counter()
+            st = O.evaluate(0.5 * vs, I0, I1, prob)
+            te.append(time.perf_counter() - t)
+            t = time.perf_counter()
+            O.gradient(st)
+            tg.append(time.perf_counter() - t)
+            t = time.perf_counter()
+            O.hessvec(st, d)
+            th.append(time.perf_counter() - t)
+    t_eval, t_grad, t_hv = (float(np.median(x)) for x in (te, tg, th))
+    progress(f"oracle: evaluation {t_eval:.1f} s, gradient {t_grad:.1f} s, product {t_hv:.1f} s "
+             f"(medians of {repeats})")
     t_reg = (stats["evaluations"] * t_eval + stats["gradients"] * t_grad
              + stats["hessvecs"] * t_hv)
     return {"value": 60.0 / t_reg, "unit": "registrations/min", "cores": 1, "kind": "oracle",
-            "sample": (f"one energy evaluation ({t_eval:.1f} s), one gradient ({t_grad:.1f} s) "
-                       f"and one Hessian-vector product ({t_hv:.1f} s) at 128^3/32^3/Nt=10, "
-                       f"FP64 NumPy on 1 thread, scaled by the registration's counts "
-                       f"({stats['evaluations']} evaluations, {stats['gradients']} gradients, "
-                       f"{stats['hessvecs']} products)"),
-            "hv_per_s": 1.0 / t_hv}
+            "sample": (f"medians of {repeats} runs each of an energy evaluation ({t_eval:.1f} s), "
+                       f"a gradient ({t_grad:.1f} s) and a Hessian-vector product ({t_hv:.1f} s) "
+                       f"at 128^3/32^3/Nt=10, FP64 NumPy on 1 thread, scaled by the "
+                       f"registration's counts ({stats['evaluations']} evaluations, "
+                       f"{stats['gradients']} gradients, {stats['hessvecs']} products)"),
+            "runs_s": {"evaluation": te, "gradient": tg, "hessvec": th},
+            "hv_per_s": 1.0 / t_hv, "gradients_per_s": 1.0 / (t_eval + t_grad)}
+
+
+def oracle_register_leg():
+    """One full FP64 oracle registration of the headline pair (10 GN x <= 10 PCG), timed."""
+    from threadpoolctl import threadpool_limits
+
+    import oracle as O
+
+    progress("oracle: one full registration at 128^3 (minutes)")
+    with threadpool_limits(limits=1):
+        prob = O.Problem(3, GRID, BAND, NT)
+        I0 = phantoms.shells_3d(0, GRID, n_classes=3).astype(np.float32).astype(np.float64)
+        vs = O.project(phantoms.raw_band_velocity(0, 3, BAND), prob)
+        vs *= DISP / O.max_displacement_voxels(vs, prob)
+        I1 = O.warp(I0, vs, prob).astype(np.float32).astype(np.float64)
+        t = time.perf_counter()
+        _, _, st = O.register(
+            I0, I1, np.zeros_like(vs), prob, O.SolverOpts(),
+            on_iteration=lambda s: progress(f"oracle registration: iteration {s['gn_iters']} "
+                                            f"({s['pcg_iters'][-1]} PCG steps) at "
+                                            f"{time.perf_counter() - t:.0f} s"))
+        dt = time.perf_counter() - t
+    return {"seconds": dt, "registrations_per_min": 60.0 / dt, "gn_iters": st["gn_iters"],
+            "pcg_iters": st["pcg_iters"], "final_mse_rel": st["mse_rel"][-1], "cores": 1}
 
 
 SERVE_SIZES = [(96, 96, 96), (128, 128, 128), (160, 192, 160)]
@@ -359,6 +424,114 @@ def traffic_record(kernel):
     return rec["kernels"][kernel]["bytes_per_launch"]
 
 
+# the brain-shaped instance: 160x192x160, five tissue classes, band 40x48x40, Nt = 10
+C3 = dict(grid=(160, 192, 160), band=(40, 48, 40), nt=10, disp=6.0, ncls=5)
+BF16_DENSE_PEAK_TFLOPS = 2500.0
+
+
+def zstage_rates(kern, grid, band, precision):
+    """The z stages of the transforms (classes 3, 4, timed inside Gauss-Newton products):
+    algorithmic rate of the stage's real products (2 flops per multiply-add: a
+    [nz x 2 kzh] x [2 kzh x nx ny] product per component, 3 components) and, for the mixed
+    form, the rate the matrix cores issue (3 split BF16 products per term, tiles padded to
+    the 32 x 32 x 16 instruction) against the dense BF16 peak."""
+    nq, nz, kzh, C = grid[0] * grid[1], grid[2], band[2] // 2, 3
+    nq32 = (nq + 31) // 32 * 32
+    out = {}
+    for k, nm in ((3, "iota_z"), (4, "pi_z")):
+        n, ms = kern.get(k, (0, 0.0))
+        if not n:
+            continue
+        avg = ms / 1000.0 / n
+        rec = {"avg_us": avg * 1e6,
+               "tflops_algorithmic": 4.0 * nz * kzh * nq * C / avg / 1e12}
+        if precision == B.BL_MIXED:
+            if k == 3:
+                kp = (2 * kzh + 15) // 16 * 16
+                issued = 3 * 2.0 * ((nz + 31) // 32 * 32) * kp * nq32 * C
+            else:
+                jt = (2 * kzh + 31) // 32
+                issued = 3 * 2.0 * (32 * jt) * ((nz + 15) // 16 * 16) * nq32 * C
+            rec["mfma_issued_tflops"] = issued / avg / 1e12
+            rec["mfma_util_of_bf16_dense_peak"] = issued / avg / 1e12 / BF16_DENSE_PEAK_TFLOPS
+        out[nm + "_rates"] = rec
+    return out
+
+
+def rel_errs(got, ref, lv=None):
+    """2-norm error relative to |ref| (gradient: to |L v| + |ref - L v|), and the largest entry
+    error relative to the largest reference entry"""
+    got = np.asarray(got, np.complex128)
+    d = np.linalg.norm((got - ref).ravel())
+    den = (np.linalg.norm(lv.ravel()) + np.linalg.norm((ref - lv).ravel())) if lv is not None \
+        else np.linalg.norm(ref.ravel())
+    return {"rel_2norm": float(d / den),
+            "rel_maxabs": float(np.abs(got - ref).max() / np.abs(ref).max())}
+
+
+def c3_leg(reps, with_oracle):
+    """160x192x160 (band 40x48x40, Nt = 10, five tissue classes): plain FP32 and mixed form,
+    registrations/min, Hv/s, the z stages' GB/s and matrix-core rate, and -- with the oracle --
+    the gradient's and the product's errors against the FP64 oracle at a mid-optimisation
+    velocity for both precisions."""
+    size = dict(C3)
+    ncls = size.pop("ncls")
+    progress("C3 160x192x160: inputs")
+    inputs = make_inputs(0, ncls=ncls, **size)
+    I0, I1, vs = inputs
+    grid, band, nt = size["grid"], size["band"], size["nt"]
+    out = {"workload": "160x192x160 5-class shell phantom, 6 vox, band 40x48x40, Nt = 10"}
+    gen = np.random.default_rng(7)
+    dv = (gen.standard_normal(vs.shape) + 1j * gen.standard_normal(vs.shape)).astype(np.complex64)
+    vh = (0.5 * vs).astype(np.complex64)
+    gh = {}
+    for name, prec in (("fp32", B.BL_FP32), ("mixed", B.BL_MIXED)):
+        progress(f"C3: {name}")
+        r = gpu_leg(3, 1, *reps, precision=prec, inputs=inputs, size=size)
+        kern = kernel_table(r["kern"], grid, band, nt)
+        kern.update(zstage_rates(r["kern"], grid, band, prec))
+        out[name] = {"registrations_per_min": 60000.0 / (1000.0 * r["elapsed"] / 3),
+                     "hv_per_s": r["hv_s"], "hv_p50_ms": percentile(r["hv_lat"], 50),
+                     "gradients_per_s": r["grad_s"], "gn_iters": r["stats"]["gn_iters"],
+                     "hessvecs": r["stats"]["hessvecs"],
+                     "final_mse_rel": r["stats"]["mse_rel"][-1], "kernels": kern}
+        p = B.make_problem(3, grid, band, nt, precision=prec)
+        g, _ = B.bl_lddmm_gradient(p, I0, I1, vh)
+        H = B.bl_lddmm_hessvec(p, I0, I1, vh, dv)
+        gh[name] = (g, H)
+    if with_oracle:
+        from threadpoolctl import threadpool_limits
+
+        import oracle as O
+
+        progress("C3: FP64 oracle gradient and product (host)")
+        with threadpool_limits(limits=1):
+            prob = O.Problem(3, grid, band, nt)
+            st = O.evaluate(vh.astype(np.complex128), I0.astype(np.float64),
+                            I1.astype(np.float64), prob)
+            gref = O.gradient(st)
+            dvp = O.project(dv.astype(np.complex128), prob)
+            Href = O.hessvec(st, dvp)
+            lv = O.L_hat(prob)[None] * O.project(vh.astype(np.complex128), prob)
+        out["errors_vs_fp64_oracle"] = {
+            name: {"gradient": rel_errs(g, gref, lv), "hessvec": rel_errs(H, Href)}
+            for name, (g, H) in gh.items()}
+    return out
+
+
+def hbm_resident_leg():
+    """The transports on fields that do not fit the last-level cache: one registration and a
+    few products at 256^3 (band 64^3, Nt = 20), per-class HIP-event timing."""
+    size = dict(LARGE)
+    ncls = size.pop("ncls")
+    progress("256^3: inputs")
+    inputs = make_inputs(0, ncls=ncls, **size)
+    r = gpu_leg(1, 0, 10, 3, 2, inputs=inputs, size=size)
+    return {"workload": "256^3 6-class shell phantom, 8 vox, band 64^3, Nt = 20",
+            "kernels": kernel_table(r["kern"], size["grid"], size["band"], size["nt"]),
+            "hv_per_s": r["hv_s"]}
+
+
 def large_main(steps, warmup, reps):
     """256^3 single instance (band 64^3, Nt = 20): plain FP32 and the mixed form on the same
     pair, registrations/min, Hv/s, final mismatch, and the transports' HBM GB/s from HIP-event
@@ -367,19 +540,14 @@ def large_main(steps, warmup, reps):
     ncls = size.pop("ncls")
     progress("large instance: inputs")
     inputs = make_inputs(0, ncls=ncls, **size)
-    M = int(np.prod(size["grid"]))
     out = {"metric": "registrations/min and GN Hv/s at 256^3, plain FP32 vs mixed form",
            "workload": "256^3 6-class shell phantom, 8 vox, band 64^3, Nt = 20, 10 GN x <= 10 PCG",
            "data": "synthetic", "n_gpus": 1}
     for name, prec in (("fp32", B.BL_FP32), ("mixed", B.BL_MIXED)):
         progress(f"large instance: {name}")
         r = gpu_leg(steps, warmup, *reps, precision=prec, inputs=inputs, size=size)
-        kern = {}
-        for k, (n, ms) in r["kern"].items():
-            cname, bpv = KCLASS[k]
-            avg = ms / 1000.0 / max(n, 1)
-            kern[cname] = {"avg_us": avg * 1e6, "gbs_algorithmic": bpv * M / avg / 1e9 if n else None,
-                           "frac_of_peak": bpv * M / avg / 1e9 / HBM_PEAK_GBS if n else None}
+        kern = kernel_table(r["kern"], size["grid"], size["band"], size["nt"])
+        kern.update(zstage_rates(r["kern"], size["grid"], size["band"], prec))
         out[name] = {"registrations_per_min": 60000.0 / (1000.0 * r["elapsed"] / steps),
                      "hv_per_s": r["hv_s"], "hv_p50_ms": percentile(r["hv_lat"], 50),
                      "gradients_per_s": r["grad_s"], "gn_iters": r["stats"]["gn_iters"],
@@ -391,58 +559,20 @@ def large_main(steps, warmup, reps):
     print(json.dumps(out), flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
-    ap.add_argument("--quick", action="store_true",
-                    help="fewer Hessian-vector repetitions (for profiler passes)")
-    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
-    ap.add_argument("--large", action="store_true",
-                    help="the 256^3 single instance instead (plain FP32 vs mixed form)")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the registration path has no multi-GPU mode "
-              "(pairs are independent; see the design notes for how it would shard).",
-              file=sys.stderr)
-        sys.exit(2)
-    B.load()
-    if not B.device_available():
-        raise RuntimeError("no HIP device visible")
-    reps = (20, 5, 2) if args.quick else (200, 50, 20)
-    if args.large:
-        large_main(args.steps, args.warmup, (20, 5, 3) if args.quick else (50, 20, 5))
-        return
-    r = gpu_leg(args.steps, args.warmup, *reps)
-    progress("mixed-precision form")
-    rm = gpu_leg(max(1, args.steps // 2), 1, *reps, precision=B.BL_MIXED, inputs=r["inputs"])
-    progress("incompressible H1 model")
-    h1 = dict(alpha=5e-3, s=1, gamma=1)
-    ri = gpu_leg(max(1, args.steps // 2), 1, *reps, model=h1)
-    progress("full Newton Hessian")
-    rn = gpu_leg(max(1, args.steps // 2), 1, *reps, model=dict(newton=True), inputs=r["inputs"])
-    progress("non-stationary velocity")
-    I0r, I1r, vsr = r["inputs"]
-    rns = gpu_leg(max(1, args.steps // 2), 1, *reps, model=dict(nonstationary=True),
-                  inputs=(I0r, I1r, np.stack([vsr] * (NT + 1))))
-    progress("deformation state equation")
-    rd = gpu_leg(max(1, args.steps // 2), 1, *reps, model=dict(deformation=True),
-                 inputs=r["inputs"])
+def headline_line(args, r):
+    """The JSON line of the headline leg (128^3 FP32 registrations and products)."""
     ms_step = 1000.0 * r["elapsed"] / args.steps
-    value = 60000.0 / ms_step
     M = GRID[0] * GRID[1] * GRID[2]
     # dominant kernel: largest total time among the transport step kernels
-    kc = max(r["kern"], key=lambda k: r["kern"][k][1])
+    kc = max(KCLASS, key=lambda k: r["kern"][k][1])
     n_launch, ms_tot = r["kern"][kc]
     name, bpv = KCLASS[kc]
     avg_s = ms_tot / 1000.0 / max(n_launch, 1)
     achieved = bpv * M / avg_s / 1e9
     hv_bytes = (64 * NT + 36) * M
-    line = {
+    return {
         "metric": "GN Hessian-vec products/s and registrations/min at 128^3; p50/p99 latency",
-        "value": value,
+        "value": 60000.0 / ms_step,
         "unit": "registrations/min",
         "n_gpus": 1,
         "steps": args.steps,
@@ -471,59 +601,110 @@ def main():
         "hv_p99_ms": percentile(r["hv_lat"], 99),
         "hv_hbm_gbs_algorithmic": hv_bytes * r["hv_s"] / 1e9,
         "gradients_per_s": r["grad_s"],
-        "kernels": {KCLASS[k][0]: {"launches": r["kern"][k][0],
-                                   "avg_us": 1000.0 * r["kern"][k][1] / max(r["kern"][k][0], 1)}
-                    for k in r["kern"]},
-        "mixed": {"precision": "bf16 split hi/lo MFMA band<->grid z contractions, fp32 "
-                               "transports, fp64 reductions",
-                  "registrations_per_min": 60000.0 / (1000.0 * rm["elapsed"] / max(1, args.steps // 2)),
-                  "hv_per_s": rm["hv_s"], "hv_p50_ms": percentile(rm["hv_lat"], 50),
-                  "hv_p99_ms": percentile(rm["hv_lat"], 99), "gradients_per_s": rm["grad_s"],
-                  "final_mse_rel": rm["stats"]["mse_rel"][-1],
-                  "final_mse_rel_fp32": r["stats"]["mse_rel"][-1],
-                  "warped_max_abs_diff_vs_fp32": float(np.abs(rm["warped"] - r["warped"]).max())},
-        "incompressible_h1": {"model": "gamma = 1, s = 1, alpha = 5e-3 (divergence-free "
-                                       "velocities, H1 regulariser), same grid, band, Nt, FP32",
-                              "registrations_per_min": 60000.0 / (1000.0 * ri["elapsed"] / max(1, args.steps // 2)),
-                              "hv_per_s": ri["hv_s"], "hv_p50_ms": percentile(ri["hv_lat"], 50),
-                              "gradients_per_s": ri["grad_s"],
-                              "gn_iters": ri["stats"]["gn_iters"], "hessvecs": ri["stats"]["hessvecs"],
-                              "final_mse_rel": ri["stats"]["mse_rel"][-1],
-                              "status": ri["stats"]["status"]},
-        "full_newton": {"hessian": "full Newton products (adjoint source and lambda grad dm kept)",
-                        "registrations_per_min": 60000.0 / (1000.0 * rn["elapsed"] / max(1, args.steps // 2)),
-                        "hv_per_s": rn["hv_s"], "hv_p50_ms": percentile(rn["hv_lat"], 50),
-                        "gn_iters": rn["stats"]["gn_iters"], "hessvecs": rn["stats"]["hessvecs"],
-                        "final_mse_rel": rn["stats"]["mse_rel"][-1], "status": rn["stats"]["status"]},
-        "nonstationary": {"velocity": f"one band field per time node ({NT + 1} nodes)",
-                          "registrations_per_min": 60000.0 / (1000.0 * rns["elapsed"] / max(1, args.steps // 2)),
-                          "hv_per_s": rns["hv_s"], "hv_p50_ms": percentile(rns["hv_lat"], 50),
-                          "gradients_per_s": rns["grad_s"],
-                          "gn_iters": rns["stats"]["gn_iters"], "hessvecs": rns["stats"]["hessvecs"],
-                          "final_mse_rel": rns["stats"]["mse_rel"][-1], "status": rns["stats"]["status"]},
-        "deformation_state": {"method": "band deformation state equation: RK4 on the band "
-                                        "displacement, truncated convolutions on a 48^3 product "
-                                        "grid, Gauss-Newton products",
-                              "registrations_per_min": 60000.0 / (1000.0 * rd["elapsed"] / max(1, args.steps // 2)),
-                              "hv_per_s": rd["hv_s"], "hv_p50_ms": percentile(rd["hv_lat"], 50),
-                              "gradients_per_s": rd["grad_s"],
-                              "gn_iters": rd["stats"]["gn_iters"], "hessvecs": rd["stats"]["hessvecs"],
-                              "final_mse_rel": rd["stats"]["mse_rel"][-1],
-                              "status": rd["stats"]["status"]},
+        "kernels": kernel_table(r["kern"], GRID, BAND, NT),
         "roofline": {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic_record(name),
                      "bytes_per_voxel": bpv, "avg_launch_us": avg_s * 1e6,
+                     "llc_assisted": True,
+                     "note": ("at 128^3 the fields one time step re-reads (offsets, dv) stay in "
+                              "the 256 MiB last-level cache between steps; hbm_resident_256 "
+                              "gives the same kernels on 256^3 fields, which do not"),
                      "copy_gbs": r["copy_gbs"], "frac_of_copy": achieved / r["copy_gbs"],
-                     "inplace_rmw_gbs": r["rmw_gbs"], "frac_of_inplace_rmw": achieved / r["rmw_gbs"]},
+                     "inplace_rmw_gbs": r["rmw_gbs"],
+                     "frac_of_inplace_rmw": achieved / r["rmw_gbs"]},
         "cpu_baseline": None,
     }
+
+
+def model_record(r, steps, **extra):
+    rec = dict(extra)
+    rec.update({"registrations_per_min": 60000.0 / (1000.0 * r["elapsed"] / steps),
+                "hv_per_s": r["hv_s"], "hv_p50_ms": percentile(r["hv_lat"], 50),
+                "gradients_per_s": r["grad_s"], "gn_iters": r["stats"]["gn_iters"],
+                "hessvecs": r["stats"]["hessvecs"], "final_mse_rel": r["stats"]["mse_rel"][-1],
+                "status": r["stats"]["status"]})
+    return rec
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
+    ap.add_argument("--quick", action="store_true",
+                    help="fewer Hessian-vector repetitions (for profiler passes)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--large", action="store_true",
+                    help="the 256^3 single instance instead (plain FP32 vs mixed form)")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 160x192x160 leg")
+    ap.add_argument("--no-hbm", action="store_true", help="skip the 256^3 transport timing")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline leg (128^3 FP32 registrations and products), for "
+                         "profiler passes")
+    ap.add_argument("--oracle-register", action="store_true",
+                    help="also time one full FP64 oracle registration at 128^3 (minutes)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the registration path has no multi-GPU mode "
+              "(pairs are independent; see the design notes for how it would shard).",
+              file=sys.stderr)
+        sys.exit(2)
+    B.load()
+    if not B.device_available():
+        raise RuntimeError("no HIP device visible")
+    reps = (20, 5, 2) if args.quick else (200, 50, 20)
+    if args.large:
+        large_main(args.steps, args.warmup, (20, 5, 3) if args.quick else (50, 20, 5))
+        return
+    r = gpu_leg(args.steps, args.warmup, *reps)
+    line = headline_line(args, r)
+    if args.headline_only:
+        print(json.dumps(line), flush=True)
+        return
+    half = max(1, args.steps // 2)
+    progress("mixed-precision form")
+    rm = gpu_leg(half, 1, *reps, precision=B.BL_MIXED, inputs=r["inputs"])
+    line["mixed"] = model_record(
+        rm, half, precision="bf16 split hi/lo MFMA band<->grid z contractions, fp32 "
+                            "transports, fp64 reductions",
+        hv_p99_ms=percentile(rm["hv_lat"], 99), final_mse_rel_fp32=r["stats"]["mse_rel"][-1],
+        warped_max_abs_diff_vs_fp32=float(np.abs(rm["warped"] - r["warped"]).max()))
+    progress("incompressible H1 model")
+    ri = gpu_leg(half, 1, *reps, model=dict(alpha=5e-3, s=1, gamma=1))
+    line["incompressible_h1"] = model_record(
+        ri, half, model="gamma = 1, s = 1, alpha = 5e-3 (divergence-free velocities, H1 "
+                        "regulariser), same grid, band, Nt, FP32")
+    progress("full Newton Hessian")
+    rn = gpu_leg(half, 1, *reps, model=dict(newton=True), inputs=r["inputs"])
+    line["full_newton"] = model_record(
+        rn, half, hessian="full Newton products (adjoint source and lambda grad dm kept)")
+    progress("non-stationary velocity")
+    I0r, I1r, vsr = r["inputs"]
+    rns = gpu_leg(half, 1, *reps, model=dict(nonstationary=True),
+                  inputs=(I0r, I1r, np.stack([vsr] * (NT + 1))))
+    line["nonstationary"] = model_record(
+        rns, half, velocity=f"one band field per time node ({NT + 1} nodes)")
+    progress("deformation state equation")
+    rd = gpu_leg(half, 1, *reps, model=dict(deformation=True), inputs=r["inputs"])
+    line["deformation_state"] = model_record(
+        rd, half, method="band deformation state equation: RK4 on the band displacement, "
+                         "truncated convolutions on a 48^3 product grid, Gauss-Newton products")
+    if not args.no_hbm:
+        B.bl_lddmm_release_cached()
+        line["roofline"]["hbm_resident_256"] = hbm_resident_leg()
+    if not args.no_c3:
+        B.bl_lddmm_release_cached()
+        line["c3"] = c3_leg(reps, not args.no_cpu)
     if not args.no_serve:
         B.bl_lddmm_release_cached()
         line["serving"] = serve_leg()
     if not args.no_cpu:
         progress("oracle baseline on the host")
         line["cpu_baseline"] = cpu_leg(r["stats"])
+        if args.oracle_register:
+            line["cpu_baseline"]["full_registration"] = oracle_register_leg()
     print(json.dumps(line), flush=True)
 
 

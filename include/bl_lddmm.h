@@ -255,10 +255,10 @@ int bl_lddmm_device_count(void);
  * Per-kernel timing with HIP events on the library's stream, for benchmarks: while enabled,
  * each run of consecutive launches of a transport step kernel is bracketed by one event
  * pair (no per-launch event overhead); bl_kernel_timing_read
- * returns the number of launches (runs for classes 3 and 4) and the summed milliseconds per
- * class and resets: 0 = forward state step, 1 = incremental forward step, 2 = adjoint step,
- * 3 = iota of the direction in a Gauss-Newton product (its three stages), 4 = pi of the
- * product's body force (its three stages), 5 = body-force pass, 6 = departure-point setup.
+ * returns the number of launches (timed runs for classes 3 and 4) and the summed milliseconds
+ * per class and resets: 0 = forward state step, 1 = incremental forward step, 2 = adjoint step,
+ * 3 = z stage of iota of the direction in a Gauss-Newton product, 4 = z stage of pi of the
+ * product's body force, 5 = body-force pass, 6 = departure-point setup.
  * Classes 3-5 are timed in Gauss-Newton products and gradients of the stationary state
  * equation only.  Errors: BL_E_INVALID for a NULL argument or a class outside [0, 6].
  */

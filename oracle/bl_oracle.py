@@ -569,12 +569,13 @@ class SolverOpts:
     newton: bool = False        # full Newton products (reading R-N) instead of Gauss-Newton
 
 
-def register(I0, I1, vh0, prob: Problem, opts: SolverOpts = SolverOpts()):
+def register(I0, I1, vh0, prob: Problem, opts: SolverOpts = SolverOpts(), on_iteration=None):
     """Reduced-space Gauss-Newton-Krylov registration in the band (Section 3.4):
     PCG with preconditioner K^ = 1/L^ on H dv~ = -g~, then v~ <- v~ + eps dv~ with Armijo
     backtracking (readings R-LS, R-PCG).
 
-    Returns (v~, m(1), stats) with stats a dict of per-iteration lists.
+    Returns (v~, m(1), stats) with stats a dict of per-iteration lists.  on_iteration (if not
+    None) is called with stats after every accepted iteration (progress reports only).
     """
     I0 = np.asarray(I0, dtype=np.float64)
     I1 = np.asarray(I1, dtype=np.float64)
@@ -649,6 +650,8 @@ def register(I0, I1, vh0, prob: Problem, opts: SolverOpts = SolverOpts()):
         stats["E"].append(st.E)
         stats["mse_rel"].append(mse_rel(st.m[-1], I0, I1))
         stats["ginf_rel"].append(norm_inf(g) / ginf0)
+        if on_iteration is not None:
+            on_iteration(stats)
     else:
         stats["status"] = MAXITER
         if norm_inf(g) / ginf0 < opts.gtol:

@@ -575,24 +575,40 @@ void z_stage(const Geo& g, const DftPlan& p, const float2* F2, float* out, int C
 
 }  // namespace
 
-void iota(const Geo& g, const DftPlan& p, const float2* band, int C, float* out, hipStream_t s) {
+void iota_xy(const Geo& g, const DftPlan& p, const float2* band, int C, hipStream_t s) {
   const int xb = (g.nx + 63) / 64;
   hipLaunchKernelGGL(k_iota_x, batch_grid(dim3(xb, g.ky, C * g.kzh), g.bat), dim3(64), 0, s, g,
                      band, p.tw_x, p.bufA);
   hipLaunchKernelGGL(k_iota_y, batch_grid(dim3(xb, p.nyp / kYG, C * g.kzh), g.bat), dim3(64), 0,
                      s, g, p.bufA, p.tw_y, p.nyp, p.bufB);
+}
+
+void iota_z(const Geo& g, const DftPlan& p, int C, float* out, hipStream_t s) {
   if (p.mixed)
     iota_z_mixed(g, p, p.bufB, C, out, s);
   else
     z_stage(g, p, p.bufB, out, C, nullptr, nullptr, s, true);
 }
 
+void iota(const Geo& g, const DftPlan& p, const float2* band, int C, float* out, hipStream_t s) {
+  iota_xy(g, p, band, C, s);
+  iota_z(g, p, C, out, s);
+}
+
 void pi_half(const Geo& g, const DftPlan& p, const float* grid, int C, float2* P, hipStream_t s) {
-  const int xb = (g.nx + 63) / 64;
+  pi_z(g, p, grid, C, s);
+  pi_yx(g, p, C, P, s);
+}
+
+void pi_z(const Geo& g, const DftPlan& p, const float* grid, int C, hipStream_t s) {
   if (p.mixed)
     pi_z_mixed(g, p, grid, C, p.bufA, s);
   else
     z_stage(g, p, nullptr, nullptr, C, grid, p.bufA, s, false);
+}
+
+void pi_yx(const Geo& g, const DftPlan& p, int C, float2* P, hipStream_t s) {
+  const int xb = (g.nx + 63) / 64;
   const int yseg = ((g.ny + kYS - 1) / kYS + kUY - 1) / kUY * kUY;
   hipLaunchKernelGGL(k_pi_y, batch_grid(dim3(xb, p.kyp / kJG, C * g.kzh), g.bat), dim3(64, kYS),
                      0, s, g, p.bufA, p.tw_yT, p.kyp, yseg, p.bufB);

@@ -117,6 +117,12 @@ constexpr int kRedBlocks = 512;   // partial sums per deterministic FP64 reducti
 void iota(const Geo& g, const DftPlan& p, const float2* band, int C, float* out, hipStream_t s);
 // pi without the 1/M scale: P[c][h][ky][kx] for h = 0..kzh-1 (half spectrum)
 void pi_half(const Geo& g, const DftPlan& p, const float* grid, int C, float2* P, hipStream_t s);
+// the stages separately: iota = iota_xy (band -> p.bufB) then iota_z (p.bufB -> out);
+// pi_half = pi_z (grid -> p.bufA) then pi_yx (p.bufA -> P)
+void iota_xy(const Geo& g, const DftPlan& p, const float2* band, int C, hipStream_t s);
+void iota_z(const Geo& g, const DftPlan& p, int C, float* out, hipStream_t s);
+void pi_z(const Geo& g, const DftPlan& p, const float* grid, int C, hipStream_t s);
+void pi_yx(const Geo& g, const DftPlan& p, int C, float2* P, hipStream_t s);
 
 // ---- mixed-precision z stages on BF16 matrix cores (bl_mixed.hip)
 int mixed_kp(const Geo& g);   // padded contraction length of the iota z stage: 2 kzh -> x16

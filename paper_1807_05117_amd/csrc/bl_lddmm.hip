@@ -1016,8 +1016,9 @@ void op_hessvec(bl_ctx* c, const float2* draw, float2* hout) {
   hipStream_t s = c->stream;
   const size_t M = (size_t)g.M;
   bl::band_prep(g, draw, c->bd, 0, nullptr, nullptr, s);
+  bl::iota_xy(g, c->plan, c->bd, g.dim, s);
   if (c->timing) t_begin(c);
-  bl::iota(g, c->plan, c->bd, g.dim, c->DV, s);
+  bl::iota_z(g, c->plan, g.dim, c->DV, s);
   if (c->timing) t_end(c, 3, 1);
   bl::inc_init(g, c->m, c->DV, c->T0, s);
   float* tin = c->T0;
@@ -1031,8 +1032,9 @@ void op_hessvec(bl_ctx* c, const float2* draw, float2* hout) {
   bl::inc_last(g, tin, c->X, c->m + g.nt * M, c->DV, c->L + g.nt * M, s);
   backward_and_body_force(c);
   if (c->timing) t_begin(c);
-  bl::pi_half(g, c->plan, c->Bf, g.dim, c->P, s);
+  bl::pi_z(g, c->plan, c->Bf, g.dim, s);
   if (c->timing) t_end(c, 4, 1);
+  bl::pi_yx(g, c->plan, g.dim, c->P, s);
   bl::band_finalize(g, g.dim, c->bd, c->Lhat, c->P, (float)(1.0 / (double)g.M), hout, c->flag, s,
                     1);
   check_launch("hessvec");
