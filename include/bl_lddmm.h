@@ -176,6 +176,24 @@ int bl_lddmm_hessvec(const bl_problem* prob, const float* I0, const float* I1,
                      const float* v_hat, const float* dv_hat, float* hv_hat);
 
 /*
+ * bl_lddmm_hessvec for callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same product, arguments,
+ * layouts and results, computed in a fixed device scratch array that the library holds on
+ * each GPU it runs on until the process ends (bl_lddmm_noalloc_limit() bytes, 512 MiB:
+ * enough for 128^3 with Nt = 10).  The call allocates no device, pinned-host or runtime
+ * memory and creates no stream or event; with BL_DEVICE_PTRS it runs on problem->stream,
+ * else on the null stream, and returns when the result is in hv_hat.  Launch shapes are the
+ * ones tuned earlier in the process for the grid (else the defaults); they never change
+ * results.  Calls on one GPU share the scratch array and must not overlap: a call while
+ * another runs on the same GPU races.  Errors as bl_lddmm_hessvec, plus BL_E_NOMEM (checked
+ * on the host before any device work) when the problem's working set exceeds the limit and
+ * BL_E_UNSUPPORTED for BL_NONSTATIONARY or BL_DEFORMATION.
+ */
+int bl_lddmm_hessvec_noalloc(const bl_problem* prob, const float* I0, const float* I1,
+                             const float* v_hat, const float* dv_hat, float* hv_hat);
+uint64_t bl_lddmm_noalloc_limit(void);
+
+/*
  * Registration by reduced-space Gauss-Newton-Krylov in the band (Section 3.4, equations
  * BLNewton and BLKKT): PCG on H dv~ = -g~ preconditioned by K~ = L~^-1, then
  * v~ <- v~ + eps dv~ with Armijo backtracking (eps = 1, 1/2, ...).

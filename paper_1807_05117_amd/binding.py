@@ -108,6 +108,8 @@ def load():
     sig = {
         "bl_lddmm_gradient": (C.c_int, [PP, _P, _P, _P, _P, C.POINTER(C.c_double)]),
         "bl_lddmm_hessvec": (C.c_int, [PP, _P, _P, _P, _P, _P]),
+        "bl_lddmm_hessvec_noalloc": (C.c_int, [PP, _P, _P, _P, _P, _P]),
+        "bl_lddmm_noalloc_limit": (C.c_uint64, []),
         "bl_lddmm_register": (C.c_int, [PP, C.POINTER(SolverOpts), _P, _P, _P, _P, C.POINTER(Stats)]),
         "bl_lddmm_warp": (C.c_int, [PP, _P, _P, _P]),
         "bl_band_to_grid": (C.c_int, [PP, C.c_int32, _P, _P]),
@@ -237,6 +239,23 @@ def bl_lddmm_hessvec(p, I0, I1, v_hat, dv_hat):
     h = np.empty(band_shape(p), np.complex64)
     _check(lib.bl_lddmm_hessvec(C.byref(p), _ptr(I0), _ptr(I1), _ptr(v), _ptr(d), _ptr(h)))
     return h
+
+
+def bl_lddmm_hessvec_noalloc(p, I0, I1, v_hat, dv_hat):
+    """bl_lddmm_hessvec in the library's fixed device scratch array (allocates nothing)"""
+    lib = load()
+    I0 = _f32(I0, grid_shape(p))
+    I1 = _f32(I1, grid_shape(p))
+    v = _c64(v_hat, band_shape(p))
+    d = _c64(dv_hat, band_shape(p))
+    h = np.empty(band_shape(p), np.complex64)
+    _check(lib.bl_lddmm_hessvec_noalloc(C.byref(p), _ptr(I0), _ptr(I1), _ptr(v), _ptr(d),
+                                        _ptr(h)))
+    return h
+
+
+def bl_lddmm_noalloc_limit():
+    return int(load().bl_lddmm_noalloc_limit())
 
 
 def bl_lddmm_register(p, I0, I1, v0, opts=None):

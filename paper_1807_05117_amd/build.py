@@ -19,7 +19,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libbl_lddmm.so")
 
 SOURCES = ["bl_dft.hip", "bl_transport.hip", "bl_reduce.hip", "bl_mixed.hip", "bl_deform.hip",
-           "bl_deform_fused.hip", "bl_lddmm.hip", "bl_batch.hip", "bl_serve.hip"]
+           "bl_deform_fused.hip", "bl_lddmm.hip", "bl_batch.hip", "bl_serve.hip",
+           "bl_noalloc.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

@@ -138,11 +138,18 @@ namespace host {
 size_t ctx_bytes(const Geo& g, bool transport, bool solver, bool mixed);
 // A context on the current device.  With arena != nullptr the caller provides (and keeps
 // owning) at least ctx_bytes() of device memory and the stream, and host_scalars (64 doubles
-// from alloc_host_scalars) if not NULL; nothing is allocated then.
+// from alloc_host_scalars) if not NULL; no device memory is allocated then.  host_mirror =
+// false: no host-mapped scalars at all (hscal = hdev = NULL, nothing published to the host;
+// only operation sequences that read no published scalar may run on such a context).
 bl_ctx* create_ctx(const bl_problem* prob, const Geo& g, bool transport, bool solver,
                    void* arena = nullptr, size_t arena_bytes = 0, hipStream_t stream = nullptr,
-                   double* host_scalars = nullptr);
+                   double* host_scalars = nullptr, bool host_mirror = true);
 void destroy_ctx(bl_ctx* c);
+// owns a context until the end of a scope
+struct CtxHolder {
+  bl_ctx* c = nullptr;
+  ~CtxHolder() { destroy_ctx(c); }
+};
 // 64 doubles of pinned, coherent, device-mapped host memory for published scalars
 double* alloc_host_scalars();
 void sync(bl_ctx* c);
@@ -159,6 +166,9 @@ void op_gradient(bl_ctx* c, float2* gout);
 void op_hessvec(bl_ctx* c, const float2* draw, float2* hout);
 void vec_dot_partial(bl_ctx* c, const float2* a, const float2* b, double* pa);
 void choose_launch_shapes(bl_ctx* c);
+// the launch shapes chosen earlier in the process for this grid shape, else the defaults;
+// no timing, no allocation
+void apply_known_launch_shapes(bl_ctx* c);
 
 template <class F>
 int guarded(F&& f) {

@@ -352,7 +352,8 @@ void destroy_ctx(bl_ctx* c) {
 }
 
 bl_ctx* create_ctx(const bl_problem* prob, const bl::Geo& g, bool transport, bool solver,
-                   void* arena, size_t arena_bytes, hipStream_t stream, double* host_scalars) {
+                   void* arena, size_t arena_bytes, hipStream_t stream, double* host_scalars,
+                   bool host_mirror) {
   bl_ctx* c = new bl_ctx();
   try {
     c->g = g;
@@ -440,13 +441,17 @@ bl_ctx* create_ctx(const bl_problem* prob, const bl::Geo& g, bool transport, boo
       c->sv = s; c->sg = s + nb; c->sdelta = s + 2 * nb; c->sr = s + 3 * nb; c->sz = s + 4 * nb;
       c->sp = s + 5 * nb; c->sHp = s + 6 * nb; c->stry = s + 7 * nb;
     }
-    if (host_scalars) {
+    if (!host_mirror) {
+      c->hscal = nullptr;
+      c->hdev = nullptr;
+      c->own_hscal = false;
+    } else if (host_scalars) {
       c->hscal = host_scalars;
       c->own_hscal = false;
     } else {
       c->hscal = alloc_host_scalars();
     }
-    HIP_TRY(hipHostGetDevicePointer((void**)&c->hdev, c->hscal, 0));
+    if (c->hscal) HIP_TRY(hipHostGetDevicePointer((void**)&c->hdev, c->hscal, 0));
     // host tables: twiddles of exactly reduced angles, the symbol of L
     std::vector<float2> tw;
     auto upload = [&](float2* dst) {
@@ -548,6 +553,17 @@ void t_collect(bl_ctx* c) {
 // the planes they write (T0, T1, Bf) are work space that every operation rewrites before use.
 std::mutex g_shape_mu;
 std::map<std::array<int, 4>, std::array<int, 4>> g_shapes;
+
+void apply_known_launch_shapes(bl_ctx* c) {
+  c->tuned = true;
+  bl::Geo& g = c->g;
+  if (g.dim != 3 || !c->transport) return;
+  const std::array<int, 4> key = {g.dim, g.nx, g.ny, g.nz};
+  std::lock_guard<std::mutex> lk(g_shape_mu);
+  auto it = g_shapes.find(key);
+  if (it != g_shapes.end())
+    for (int k = 0; k < 4; ++k) g.zv[k] = it->second[k];
+}
 
 void choose_launch_shapes(bl_ctx* c) {
   c->tuned = true;
@@ -849,7 +865,9 @@ void op_hessvec_def(bl_ctx* c, const float2* draw, float2* hout) {
 
 // host-mapped mirror of a device scalar slot, for single-problem launches (a batched launch
 // publishes nothing to host memory: its scalars are read by the device control kernels)
-double* publish(bl_ctx* c, int slot) { return c->g.bat.count > 1 ? nullptr : c->hdev + slot; }
+double* publish(bl_ctx* c, int slot) {
+  return (c->g.bat.count > 1 || !c->hdev) ? nullptr : c->hdev + slot;
+}
 
 // setup + forward state + energy sums at the raw band vector `vraw` (stationary state
 // equation), enqueued only: the regulariser and data sums land in scal[S_REG], scal[S_DATA]
@@ -1260,11 +1278,6 @@ void solve(bl_ctx* c, const bl_solver_opts& o, bl_stats* st) {
 size_t ctx_bytes(const bl::Geo& g, bool transport, bool solver, bool mixed) {
   return plan_layout(g, transport, solver, mixed).total;
 }
-
-struct CtxHolder {
-  bl_ctx* c = nullptr;
-  ~CtxHolder() { destroy_ctx(c); }
-};
 
 // ---------------------------------------------------------------- idle context cache
 // The one-shot calls (register, gradient, H v, warp) take an idle context of the same problem

@@ -157,3 +157,16 @@ def test_server_arguments_rejected(lib):
     assert lib.bl_server_wait(None, 1, 0.0, None, None, None, None) == B.BL_E_INVALID
     assert lib.bl_server_cancel(None, 1) == B.BL_E_INVALID
     lib.bl_server_destroy(None)
+
+
+def test_noalloc_product_checks_on_the_host(lib):
+    """the allocation-free product refuses a problem beyond its scratch limit, models it does
+    not serve and NULL pointers before any device call"""
+    big = B.make_problem(3, (256, 256, 256), (64, 64, 64), 20)
+    z = C.c_void_p(1)
+    assert lib.bl_lddmm_hessvec_noalloc(C.byref(big), z, z, z, z, z) == B.BL_E_NOMEM
+    assert b"limited to" in lib.bl_lddmm_last_error()
+    ns = _p(nonstationary=True)
+    assert lib.bl_lddmm_hessvec_noalloc(C.byref(ns), z, z, z, z, z) == B.BL_E_UNSUPPORTED
+    assert lib.bl_lddmm_hessvec_noalloc(C.byref(_p()), None, z, z, z, z) == B.BL_E_INVALID
+    assert lib.bl_lddmm_noalloc_limit() == 512 << 20
