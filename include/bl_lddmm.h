@@ -54,7 +54,8 @@ extern "C" {
 /* return codes */
 #define BL_OK             0
 #define BL_E_INVALID     -1   /* bad dim, n, k, nt, alpha, s, sigma, opts or NULL pointer     */
-#define BL_E_UNSUPPORTED -2   /* unknown precision                                              */
+#define BL_E_UNSUPPORTED -2   /* unknown precision, a flag combination or model the call does
+                                 not serve (see the flags and the individual calls)             */
 #define BL_E_NOMEM       -3   /* the working set does not fit in free device memory         */
 #define BL_E_DEVICE      -4   /* a HIP runtime error                                          */
 #define BL_E_NONFINITE   -5   /* NaN/Inf in an input, in E, in the gradient or in H v         */
@@ -294,6 +295,19 @@ int bl_kernel_timing_read(bl_ctx* ctx, int32_t kclass, int64_t* launches, double
  * defaults before the first velocity).  Errors: BL_E_INVALID for NULL arguments.
  */
 int bl_lddmm_ctx_launch_shapes(bl_ctx* ctx, int32_t zv_out[4]);
+
+/*
+ * The autotuner: besides the transports' zv, it chooses the setup kernel's voxels per thread,
+ * the z-chunking of the FP32 iota z stage and the iota x/y stages (two kernels, or one fused
+ * kernel with 32 or 16 rows per block),
+ * all bitwise-invariant, by timing at the first velocity of each (GPU architecture, grid,
+ * band, precision).  Choices are kept for the process and appended to a cache file read by
+ * later processes: BL_TUNE_CACHE (a path, or "off"), else $XDG_CACHE_HOME/bl_lddmm/
+ * launch_shapes_v1.txt or ~/.cache/bl_lddmm/launch_shapes_v1.txt.  BL_LAUNCH_SHAPES="s0,...,s6"
+ * fixes all classes (state, incremental, adjoint, body force, setup, iota z, iota x/y).
+ * bl_lddmm_tune_reload forgets the choices of this process and reads the cache file again.
+ */
+void bl_lddmm_tune_reload(void);
 
 /*
  * Serving: a request loop for many registrations on one GPU (continuous batching).

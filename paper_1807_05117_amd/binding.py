@@ -121,6 +121,7 @@ def load():
         "bl_lddmm_ctx_destroy": (None, [_P]),
         "bl_lddmm_footprint": (C.c_uint64, [PP]),
         "bl_lddmm_release_cached": (None, []),
+        "bl_lddmm_tune_reload": (None, []),
         "bl_lddmm_last_error": (C.c_char_p, []),
         "bl_lddmm_device_count": (C.c_int, []),
         "bl_lddmm_default_opts": (None, [C.POINTER(SolverOpts)]),

@@ -242,10 +242,10 @@ void Cohort::prepare(int s) {
   bl_ctx* c0 = ctx_[s];
   op_set_velocity(c0, c0->sv);
   for (bl_ctx* c : ctx_) {
-    for (int k = 0; k < 4; ++k) c->g.zv[k] = c0->g.zv[k];
+    for (int k = 0; k < bl::TR_CLASSES; ++k) c->g.zv[k] = c0->g.zv[k];
     c->tuned = true;
   }
-  for (int k = 0; k < 4; ++k) g_.zv[k] = c0->g.zv[k];
+  for (int k = 0; k < bl::TR_CLASSES; ++k) g_.zv[k] = c0->g.zv[k];
   exec_.assign(kMaxPcgPerStep + 1, nullptr);
   prepared_ = true;
 }

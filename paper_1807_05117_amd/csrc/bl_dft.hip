@@ -109,6 +109,94 @@ __global__ __launch_bounds__(64) void k_iota_y(Geo g, const float2* __restrict__
     if (y0 + u < g.ny) dst[(size_t)u * g.nx] = acc[u];
 }
 
+// Fused x and y stages: one block per (c*kzh + h, tile of kFX columns, chunk of kFY rows).
+// The band plane is staged in LDS (every lane of a wavefront reads the same entry), the x
+// stage writes the block's columns of F1 for every ky to LDS, and the y stage forms the block's
+// rows of F2 from them; F1 never goes through memory.  Each output is accumulated in exactly
+// the order of k_iota_x / k_iota_y (two alternating partial sums over kx in chunks of kU; one
+// sum over ky in chunks of kU, rows past ky against zero twiddle rows), so the results are
+// bitwise those of the two separate stages.  A launch shape: the autotuner times it (16 or 32
+// rows per block) against the two separate stages when the band plane and the block's F1
+// tile fit kFusedLds bytes; every choice computes the same values.
+constexpr int kFX = 64;
+constexpr size_t kFusedLds = 64 * 1024;
+
+template <int kFY>
+__global__ __launch_bounds__(256) void k_iota_xy(Geo g, const float2* __restrict__ band,
+                                                 const float2* __restrict__ tw_x,
+                                                 const float2* __restrict__ tw_y, int nyp,
+                                                 float2* __restrict__ F2) {
+  BL_BATCH(g.bat)
+  BL_AT(band, g.bat);
+  BL_AT(F2, g.bat);
+  extern __shared__ float2 lds_xy[];
+  const int KX = g.kx, KY = g.ky;
+  float2* S = lds_xy;                    // [KY][KX] band plane
+  float2* T = S + (size_t)KY * KX;       // [KY][kFX] x-stage outputs of the block's columns
+  const int ch = batch_bz(g.bat, bpair_);
+  const int c = ch / g.kzh, h = ch - c * g.kzh;
+  const float2* plane = band + (size_t)(c * g.kz + g.kz0 + h) * KY * KX;
+  for (int i = threadIdx.x; i < KY * KX; i += 256) S[i] = plane[i];
+  __syncthreads();
+  const int xl = threadIdx.x & (kFX - 1);
+  const int wq = wave_uniform(threadIdx.x >> 6);   // 4 wavefronts
+  const int x = blockIdx.x * kFX + xl;
+  const int xc = x < g.nx ? x : g.nx - 1;          // clamped column: loads stay in bounds
+  // x stage: T[jy][xl] for jy = wq + 4 r, kNJ rows of a thread per pass sharing each twiddle
+  // load (one round of kU loads per chunk for all of them)
+  constexpr int kNJ = 8;
+  for (int jb = wq; jb < KY; jb += 4 * kNJ) {
+    float2 a0[kNJ], a1[kNJ];
+#pragma unroll
+    for (int r = 0; r < kNJ; ++r) a0[r] = a1[r] = make_float2(0.f, 0.f);
+    for (int j0 = 0; j0 < KX; j0 += kU) {
+      float2 t[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) t[u] = tw_x[(size_t)(j0 + u) * g.nx + xc];
+#pragma unroll
+      for (int r = 0; r < kNJ; ++r) {
+        const float2* row = S + (size_t)min(jb + 4 * r, KY - 1) * KX;
+#pragma unroll
+        for (int u = 0; u < kU; u += 2) {
+          cmac(a0[r], row[min(j0 + u, KX - 1)], t[u]);
+          cmac(a1[r], row[min(j0 + u + 1, KX - 1)], t[u + 1]);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kNJ; ++r) {
+      const int jy = jb + 4 * r;
+      if (jy < KY) T[jy * kFX + xl] = make_float2(a0[r].x + a1[r].x, a0[r].y + a1[r].y);
+    }
+  }
+  __syncthreads();
+  // y stage: rows y0 + wq + 4 v (v < kFY / 4) of the block's chunk, together per ky term
+  constexpr int NV = kFY / 4;
+  const int y0 = blockIdx.y * kFY + wq;
+  float2 acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = make_float2(0.f, 0.f);
+  for (int j0 = 0; j0 < KY; j0 += kU) {
+    float2 f[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) f[u] = T[min(j0 + u, KY - 1) * kFX + xl];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const float2* tw = tw_y + (size_t)(j0 + u) * nyp + y0;   // zero past ny and ky
+#pragma unroll
+      for (int v = 0; v < NV; ++v) cmac(acc[v], f[u], tw[4 * v]);
+    }
+  }
+  if (x < g.nx) {
+    float2* dst = F2 + (size_t)ch * g.ny * g.nx + x;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int y = y0 + 4 * v;
+      if (y < g.ny) dst[(size_t)y * g.nx] = acc[v];
+    }
+  }
+}
+
 // z stage (real output): one thread per (column q, chunk of z, component); the half-spectrum
 // column is held in registers.  Planes z and nz - z share their twiddles up to conjugation,
 // so one pass over z <= nz/2 forms A = sum_h f.x t.x and B = sum_h f.y t.y and writes A - B
@@ -401,7 +489,6 @@ __global__ __launch_bounds__(256) void k_band_prep(Geo g, const float2* __restri
   BL_AT(out, g.bat);
   BL_AT(Lhat64, g.bat);
   BL_AT(reg_partial, g.bat);
-  __shared__ double sh[256];
   double acc = 0.0;
   const int B = (int)g.B;
   raw += blockIdx.y * nstride;   // node blockIdx.y (nodes > 1 only without the regulariser sum)
@@ -443,14 +530,9 @@ __global__ __launch_bounds__(256) void k_band_prep(Geo g, const float2* __restri
     }
   }
   if (reg_partial) {
-    sh[threadIdx.x] = acc;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-      __syncthreads();
-    }
+    const double tot = block_reduce_256<false>(acc);
     if (threadIdx.x == 0) {
-      const double v = reg_weight == 1.0 ? sh[0] : reg_weight * sh[0];
+      const double v = reg_weight == 1.0 ? tot : reg_weight * tot;
       reg_partial[blockIdx.x] = reg_accumulate ? reg_partial[blockIdx.x] + v : v;
     }
   }
@@ -547,6 +629,8 @@ void launch_z_pair(const Geo& g, const DftPlan& p, const float2* F2, float* out,
     const int qblocks = (nq + 255) / 256;
     int nchunk = (npair + 63) / 64;
     while (qblocks * nchunk * C < 768 && nchunk * 8 < npair) nchunk *= 2;
+    // launch shape: more z chunks per column (each output's arithmetic is unchanged)
+    for (int m = g.zv[TR_IOTA_Z]; m > 1 && nchunk * 4 <= npair; m /= 2) nchunk *= 2;
     const int zchunk = (npair + nchunk - 1) / nchunk;
     nchunk = (npair + zchunk - 1) / zchunk;
     const size_t lds = (size_t)zchunk * (KZH == 1 ? 2 : KZH) * sizeof(float2);
@@ -576,6 +660,23 @@ void z_stage(const Geo& g, const DftPlan& p, const float2* F2, float* out, int C
 }  // namespace
 
 void iota_xy(const Geo& g, const DftPlan& p, const float2* band, int C, hipStream_t s) {
+  const size_t lds = ((size_t)g.ky * g.kx + (size_t)g.ky * kFX) * sizeof(float2);
+  // launch shape 16 or 32: the fused stage with that many rows per block; 0: the two stages
+  // (nyp is a multiple of 32: the rows of every block are in the table)
+  if (g.zv[TR_IOTA_XY] != 0 && lds <= kFusedLds) {
+    const dim3 b(256);
+    if (g.zv[TR_IOTA_XY] == 16)
+      hipLaunchKernelGGL(k_iota_xy<16>,
+                         batch_grid(dim3((g.nx + kFX - 1) / kFX, (g.ny + 15) / 16, C * g.kzh),
+                                    g.bat),
+                         b, lds, s, g, band, p.tw_x, p.tw_y, p.nyp, p.bufB);
+    else
+      hipLaunchKernelGGL(k_iota_xy<32>,
+                         batch_grid(dim3((g.nx + kFX - 1) / kFX, (g.ny + 31) / 32, C * g.kzh),
+                                    g.bat),
+                         b, lds, s, g, band, p.tw_x, p.tw_y, p.nyp, p.bufB);
+    return;
+  }
   const int xb = (g.nx + 63) / 64;
   hipLaunchKernelGGL(k_iota_x, batch_grid(dim3(xb, g.ky, C * g.kzh), g.bat), dim3(64), 0, s, g,
                      band, p.tw_x, p.bufA);

@@ -49,6 +49,30 @@ inline dim3 batch_grid(dim3 d, const Batch& b) {
   if (::bl::batch_gated_off(bt, bpair_)) return;
 #define BL_AT(p, bt) p = ::bl::batch_ptr(p, bt, bpair_)
 
+// Sum (MAX: maximum) of one double per thread of a 1D block of 256 threads, in a fixed order:
+// within each 64-lane wavefront by shuffles (offsets 32, 16, ..., 1; lane 0 ends with its
+// wavefront's value), then the four wavefront values in order by thread 0, which alone returns
+// the result.  Every thread of the block must call it (it has two barriers).
+template <bool MAX>
+__device__ __forceinline__ double block_reduce_256(double v) {
+  __shared__ double part[4];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double w = __shfl_down(v, (unsigned)o, 64);
+    v = MAX ? fmax(v, w) : v + w;
+  }
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+    r = part[0];
+#pragma unroll
+    for (int w = 1; w < 4; ++w) r = MAX ? fmax(r, part[w]) : r + part[w];
+  }
+  __syncthreads();   // part may be reused by a following reduction of the same kernel
+  return r;
+}
+
 // Geometry and weights of one problem, passed by value to every kernel.
 struct Geo {
   int dim;            // 2 or 3
@@ -73,15 +97,16 @@ struct Geo {
   // nine grid fields an incremental step touches exceed the 256 MiB last-level cache: there
   // the hint speeds the steps up, below it the next step's reads of the output would miss.
   int stream_out;
-  // voxels per thread along z of the transport launches, per kernel class (TR_*): a launch
-  // shape only, every choice computes bitwise the same values
-  int zv[4];
+  // launch shapes per kernel class (TR_*): voxels per thread along z of the transports and
+  // the setup, the z-chunk multiplier of the iota z stage, the rows per block of the fused
+  // iota x/y stage.  Every choice computes bitwise the same values.
+  int zv[8];
   // several problems of this shape in one launch (default: one)
   Batch bat;
 };
 
-// kernel classes of the transport launch shapes (Geo::zv)
-enum { TR_STATE = 0, TR_INC, TR_ADJ, TR_FORCE };
+// kernel classes of the launch shapes (Geo::zv)
+enum { TR_STATE = 0, TR_INC, TR_ADJ, TR_FORCE, TR_SETUP, TR_IOTA_Z, TR_IOTA_XY, TR_CLASSES };
 
 // Work buffers and twiddle tables of the band<->grid transforms.
 constexpr int kYG = 4;     // y outputs per thread in the iota y stage

@@ -20,6 +20,8 @@
 #include <string>
 #include <vector>
 
+#include <sys/stat.h>
+
 #include "bl_host.h"
 
 namespace bl {
@@ -94,6 +96,10 @@ int validate(const bl_problem* p, bl::Geo* g) {
     g->zv[bl::TR_INC] = d3 ? 2 : 1;
     g->zv[bl::TR_ADJ] = d3 ? 2 : 1;
     g->zv[bl::TR_FORCE] = 1;
+    g->zv[bl::TR_SETUP] = 1;
+    g->zv[bl::TR_IOTA_Z] = 1;
+    g->zv[bl::TR_IOTA_XY] = 0;
+    g->zv[bl::TR_CLASSES] = 0;
     g->stream_out = 9 * 4 * g->M > (int64_t(256) << 20) ? 1 : 0;
   }
   return BL_OK;
@@ -547,44 +553,141 @@ void t_collect(bl_ctx* c) {
 
 // ------------------------------------------------------------------------------ operators
 // ------------------------------------------------------------------ transport launch shapes
-// Tiles of 64 x 4 x zv voxels; zv only changes how many voxels one thread handles, never the
-// arithmetic of a voxel.  Candidates are timed on the context's own offset fields right after
-// the first setup on a grid shape (the gathers' cache behaviour depends on the real offsets);
-// the planes they write (T0, T1, Bf) are work space that every operation rewrites before use.
+// Launch shapes, chosen per problem shape by timing and remembered (the autotuner).
+//
+// Every class's candidates compute bitwise the same values -- they only change how work is
+// split over threads and blocks -- so tuning never changes a result:
+//   transports (state, incremental, adjoint, body force) and setup: voxels per thread along z
+//     (tiles of 64 x 4 x zv voxels), 1, 2, 4 or 8;
+//   iota z stage (FP32): the z-chunk multiplier of its grid, 1, 2 or 4;
+//   iota x and y stages: two kernels (0) or one fused kernel with 32 or 16 rows per block.
+// Candidates are timed on the context's own fields right after the first setup on a problem
+// shape (the gathers' cache behaviour depends on the real offsets); the planes they write
+// (T0, T1, Bf, DV, X, YA with the same values, the transform buffers) are work space that every
+// operation rewrites before use.  Choices are kept per (GPU architecture, grid, band,
+// precision) for the process and in a cache file -- BL_TUNE_CACHE, else
+// $XDG_CACHE_HOME/bl_lddmm/launch_shapes_v1.txt or ~/.cache/bl_lddmm/launch_shapes_v1.txt -- read at
+// the first tuning and appended to after each new choice, so later processes skip the timing.
+// BL_TUNE_CACHE=off disables the file; BL_TRANSPORT_ZV = 1, 2, 4 or 8 fixes the transports'
+// and the setup's voxels per thread and skips the timing, BL_LAUNCH_SHAPES fixes every class.
 std::mutex g_shape_mu;
-std::map<std::array<int, 4>, std::array<int, 4>> g_shapes;
+std::map<std::string, std::array<int, bl::TR_CLASSES>> g_shapes;
+bool g_shapes_file_read = false;
+
+std::string tune_cache_path() {
+  const char* e = std::getenv("BL_TUNE_CACHE");
+  if (e && *e) return std::string(e) == "off" ? std::string() : std::string(e);
+  if (const char* x = std::getenv("XDG_CACHE_HOME"))
+    if (*x) return std::string(x) + "/bl_lddmm/launch_shapes_v1.txt";
+  if (const char* h = std::getenv("HOME"))
+    if (*h) return std::string(h) + "/.cache/bl_lddmm/launch_shapes_v1.txt";
+  return std::string();
+}
+
+std::string shape_key(const bl_ctx* c) {
+  static std::string arch = []() {
+    hipDeviceProp_t pr{};
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess || hipGetDeviceProperties(&pr, d) != hipSuccess)
+      return std::string("unknown");
+    std::string a = pr.gcnArchName;
+    return a.substr(0, a.find(':'));
+  }();
+  const bl::Geo& g = c->g;
+  char buf[160];
+  std::snprintf(buf, sizeof(buf), "%s %d %d %d %d %d %d %d %d", arch.c_str(), g.dim, g.nx, g.ny,
+                g.nz, g.kx, g.ky, g.kz, c->plan.mixed);
+  return buf;
+}
+
+// the cache file's lines: "<arch> dim nx ny nz kx ky kz mixed : s0 ... s6"; malformed lines are
+// skipped (caller holds g_shape_mu)
+void read_shape_file() {
+  g_shapes_file_read = true;
+  const std::string path = tune_cache_path();
+  if (path.empty()) return;
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return;
+  char line[512];
+  while (std::fgets(line, sizeof(line), f)) {
+    char* colon = std::strchr(line, ':');
+    if (!colon) continue;
+    std::string key(line, colon - line);
+    while (!key.empty() && key.back() == ' ') key.pop_back();
+    std::array<int, bl::TR_CLASSES> v{};
+    int n = 0, off = 0;
+    const char* q = colon + 1;
+    while (n < bl::TR_CLASSES && std::sscanf(q, "%d%n", &v[n], &off) == 1) {
+      q += off;
+      ++n;
+    }
+    if (n == bl::TR_CLASSES) g_shapes[key] = v;
+  }
+  std::fclose(f);
+}
+
+void append_shape_file(const std::string& key, const std::array<int, bl::TR_CLASSES>& v) {
+  const std::string path = tune_cache_path();
+  if (path.empty()) return;
+  const size_t slash = path.find_last_of('/');
+  if (slash != std::string::npos) {   // create the directory chain (errors ignored)
+    for (size_t i = 1; i <= slash; ++i)
+      if (path[i] == '/' || i == slash) ::mkdir(path.substr(0, i == slash ? slash : i).c_str(), 0755);
+  }
+  FILE* f = std::fopen(path.c_str(), "a");
+  if (!f) return;
+  std::fprintf(f, "%s :", key.c_str());
+  for (int k = 0; k < bl::TR_CLASSES; ++k) std::fprintf(f, " %d", v[k]);
+  std::fprintf(f, "\n");
+  std::fclose(f);
+}
+
+bool lookup_shapes(bl_ctx* c) {
+  const std::string key = shape_key(c);
+  std::lock_guard<std::mutex> lk(g_shape_mu);
+  if (!g_shapes_file_read) read_shape_file();
+  auto it = g_shapes.find(key);
+  if (it == g_shapes.end()) return false;
+  for (int k = 0; k < bl::TR_CLASSES; ++k) c->g.zv[k] = it->second[k];
+  return true;
+}
 
 void apply_known_launch_shapes(bl_ctx* c) {
   c->tuned = true;
-  bl::Geo& g = c->g;
-  if (g.dim != 3 || !c->transport) return;
-  const std::array<int, 4> key = {g.dim, g.nx, g.ny, g.nz};
-  std::lock_guard<std::mutex> lk(g_shape_mu);
-  auto it = g_shapes.find(key);
-  if (it != g_shapes.end())
-    for (int k = 0; k < 4; ++k) g.zv[k] = it->second[k];
+  if (c->g.dim != 3 || !c->transport) return;
+  lookup_shapes(c);
 }
 
 void choose_launch_shapes(bl_ctx* c) {
   c->tuned = true;
   bl::Geo& g = c->g;
   if (g.dim != 3 || !c->transport) return;
+  // BL_LAUNCH_SHAPES = "s0,...,s6" fixes every class (tests of the shapes' equivalence);
+  // an invalid list keeps the defaults
+  if (const char* all = std::getenv("BL_LAUNCH_SHAPES")) {
+    int v[bl::TR_CLASSES], n = 0, off = 0;
+    const char* q = all;
+    while (n < bl::TR_CLASSES && std::sscanf(q, "%d%n", &v[n], &off) == 1) {
+      q += off;
+      if (*q == ',') ++q;
+      ++n;
+    }
+    bool ok = n == bl::TR_CLASSES;
+    for (int k = 0; ok && k <= bl::TR_SETUP; ++k) ok = v[k] == 1 || v[k] == 2 || v[k] == 4 || v[k] == 8;
+    ok = ok && (v[bl::TR_IOTA_Z] == 1 || v[bl::TR_IOTA_Z] == 2 || v[bl::TR_IOTA_Z] == 4);
+    ok = ok && (v[bl::TR_IOTA_XY] == 0 || v[bl::TR_IOTA_XY] == 16 || v[bl::TR_IOTA_XY] == 32);
+    if (ok)
+      for (int k = 0; k < bl::TR_CLASSES; ++k) g.zv[k] = v[k];
+    return;
+  }
   const char* env = std::getenv("BL_TRANSPORT_ZV");
   if (env && *env) {
     const int v = std::atoi(env);
     if (v == 1 || v == 2 || v == 4 || v == 8)
-      for (int k = 0; k < 4; ++k) g.zv[k] = v;
+      for (int k = 0; k <= bl::TR_SETUP; ++k) g.zv[k] = v;
     return;  // any other value keeps the defaults
   }
-  const std::array<int, 4> key = {g.dim, g.nx, g.ny, g.nz};
-  {
-    std::lock_guard<std::mutex> lk(g_shape_mu);
-    auto it = g_shapes.find(key);
-    if (it != g_shapes.end()) {
-      for (int k = 0; k < 4; ++k) g.zv[k] = it->second[k];
-      return;
-    }
-  }
+  if (lookup_shapes(c)) return;
   hipStream_t s = c->stream;
   const size_t M = (size_t)g.M;
   hipEvent_t e0, e1;
@@ -599,17 +702,34 @@ void choose_launch_shapes(bl_ctx* c) {
       case bl::TR_STATE: bl::state_step(g, c->m, c->X, c->T0, s); break;
       case bl::TR_INC: bl::inc_step(g, c->T0, c->X, c->m + M, c->DV, c->T1, s); break;
       case bl::TR_ADJ: bl::adj_step(g, c->T0, c->YA, c->T1, s); break;
-      default: bl::body_force(g, c->L, c->m, c->Bf, s); break;
+      case bl::TR_FORCE: bl::body_force(g, c->L, c->m, c->Bf, s); break;
+      case bl::TR_SETUP: bl::setup(g, c->V, c->X, c->YA, s); break;   // same values again
+      case bl::TR_IOTA_Z: bl::iota_z(g, c->plan, g.dim, c->DV, s); break;
+      default: bl::iota_xy(g, c->plan, c->bv, g.dim, s); break;
+    }
+  };
+  auto candidates = [&](int cls) -> std::vector<int> {
+    switch (cls) {
+      // (a non-stationary velocity has per-step offsets from its own setup kernel: the
+      // stationary setup is not timed on its fields)
+      case bl::TR_SETUP: return g.nodes > 1 ? std::vector<int>{} : std::vector<int>{1, 2, 4};
+      case bl::TR_IOTA_Z: return c->plan.mixed ? std::vector<int>{} : std::vector<int>{1, 2, 4};
+      case bl::TR_IOTA_XY: return {0, 32, 16};
+      default: return {1, 2, 4, 8};
     }
   };
   constexpr int kReps = 4;
-  std::array<int, 4> best;
-  for (int cls = 0; cls < 4; ++cls) {
+  std::array<int, bl::TR_CLASSES> best;
+  for (int cls = 0; cls < bl::TR_CLASSES; ++cls) {
     const int dflt = g.zv[cls];
-    float t_best = 0.f;
     best[cls] = dflt;
-    for (int zv : {dflt, 1, 2, 4, 8}) {
-      if (zv == dflt && t_best > 0.f) continue;
+    const std::vector<int> cand = candidates(cls);
+    if (cand.empty()) continue;
+    float t_best = 0.f;
+    std::vector<int> order{dflt};
+    for (int v : cand)
+      if (v != dflt) order.push_back(v);
+    for (int zv : order) {
       g.zv[cls] = zv;
       launch(cls);  // warm-up
       HIP_TRY(hipEventRecord(e0, s));
@@ -625,8 +745,9 @@ void choose_launch_shapes(bl_ctx* c) {
     }
     g.zv[cls] = best[cls];
   }
+  const std::string key = shape_key(c);
   std::lock_guard<std::mutex> lk(g_shape_mu);
-  g_shapes.emplace(key, best);
+  if (g_shapes.emplace(key, best).second) append_shape_file(key, best);
 }
 
 // ------------------------------------------------ non-stationary velocity (one field per node)
@@ -1391,6 +1512,12 @@ int bl_lddmm_device_count(void) {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess) return 0;
   return n;
+}
+
+void bl_lddmm_tune_reload(void) {
+  std::lock_guard<std::mutex> lk(g_shape_mu);
+  g_shapes.clear();
+  read_shape_file();
 }
 
 void bl_lddmm_release_cached(void) {

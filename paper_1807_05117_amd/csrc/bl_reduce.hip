@@ -2,8 +2,9 @@
 // (paper Section 3.4: PCG on H dv~ = -g~ with preconditioner K~ = L~^-1).
 //
 // Every reduction runs on a fixed grid of kRedBlocks blocks of 256 threads; each thread
-// accumulates a fixed strided subset in FP64, each block reduces through a fixed LDS tree,
-// and one block sums the partials in order.  No atomics, so results are bitwise repeatable.
+// accumulates a fixed strided subset in FP64, each block reduces its threads' values by
+// wavefront shuffles and one fixed-order step across its four wavefronts, and one block sums
+// the partials the same way.  No atomics, so results are bitwise repeatable.
 #include "bl_internal.h"
 
 namespace bl {
@@ -19,25 +20,13 @@ __device__ __forceinline__ double node_weight(const Geo& g, int64_t i) {
 }
 
 __device__ __forceinline__ void block_sum_store(double acc, double* __restrict__ partial) {
-  __shared__ double sh[256];
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+  const double r = block_reduce_256<false>(acc);
+  if (threadIdx.x == 0) partial[blockIdx.x] = r;
 }
 
 __device__ __forceinline__ void block_max_store(double acc, double* __restrict__ partial) {
-  __shared__ double sh[256];
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+  const double r = block_reduce_256<true>(acc);
+  if (threadIdx.x == 0) partial[blockIdx.x] = r;
 }
 
 #define GRID_STRIDE(i, n) \
@@ -59,19 +48,12 @@ __global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__
   BL_AT(partial, bt);
   BL_AT(out, bt);
   BL_AT(flag, bt);
-  __shared__ double sh[256];
   double acc = 0.0;
   for (int i = threadIdx.x; i < n; i += 256) acc = MAX ? fmax(acc, partial[i]) : acc + partial[i];
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o)
-      sh[threadIdx.x] = MAX ? fmax(sh[threadIdx.x], sh[threadIdx.x + o]) : sh[threadIdx.x] + sh[threadIdx.x + o];
-    __syncthreads();
-  }
+  const double r = block_reduce_256<MAX>(acc);
   if (threadIdx.x == 0) {
-    out[0] = sh[0];
-    if (host) host[0] = sh[0];
+    out[0] = r;
+    if (host) host[0] = r;
     if (flag) host_flag[0] = (double)flag[0];
   }
 }

@@ -184,7 +184,7 @@ __device__ __forceinline__ void store_out(const Geo& g, float* out, uint32_t p, 
     if (live) store_out(g, (out), p, (val)[zz]);           \
   }
 
-template <int DIM>
+template <int DIM, int ZV>
 __global__ __launch_bounds__(BX* GBY) void k_setup(Geo g, const float* __restrict__ v,
                                                    float* __restrict__ X,
                                                    float4* __restrict__ YA) {
@@ -192,32 +192,44 @@ __global__ __launch_bounds__(BX* GBY) void k_setup(Geo g, const float* __restric
   BL_AT(v, g.bat);
   BL_AT(X, g.bat);
   BL_AT(YA, g.bat);
-  constexpr int ZV = 1;
   GATHER_XY
-  GATHER_Z(0)
-  (void)live;
   const size_t M = (size_t)g.M;
   const float s = g.dt * (float)g.nref;
-  float u[3] = {0.f, 0.f, 0.f};
-  for (int c = 0; c < DIM; ++c) u[c] = s * v[c * M + p];
-  // forward: X = -(u + Interp(u, i - u)) / 2
-  const Tap<DIM> tf = make_tap<DIM>(g, x, y, z, -u[0], -u[1], -u[2]);
-  // backward: Y = +(u + Interp(u, i + u)) / 2
-  const Tap<DIM> tb = make_tap<DIM>(g, x, y, z, u[0], u[1], u[2]);
-  float xo[3] = {0.f, 0.f, 0.f}, yo[3] = {0.f, 0.f, 0.f};
-  for (int c = 0; c < DIM; ++c) {
-    const __amdgpu_buffer_rsrc_t vc = field_rsrc(v + c * M, g);
-    xo[c] = -0.5f * (u[c] + s * apply<DIM>(vc, tf));
-    yo[c] = 0.5f * (u[c] + s * apply<DIM>(vc, tb));
+  // the ZV voxels of the thread are computed first and stored afterwards (their gathers can
+  // all be in flight)
+  float xo[ZV][3], yo[ZV][3], av[ZV];
+#pragma unroll
+  for (int zz = 0; zz < ZV; ++zz) {
+    GATHER_Z(zz)
+    (void)live;
+    float u[3] = {0.f, 0.f, 0.f};
+    for (int c = 0; c < DIM; ++c) u[c] = s * v[c * M + p];
+    // forward: X = -(u + Interp(u, i - u)) / 2
+    const Tap<DIM> tf = make_tap<DIM>(g, x, y, z, -u[0], -u[1], -u[2]);
+    // backward: Y = +(u + Interp(u, i + u)) / 2
+    const Tap<DIM> tb = make_tap<DIM>(g, x, y, z, u[0], u[1], u[2]);
+    xo[zz][0] = xo[zz][1] = xo[zz][2] = 0.f;
+    yo[zz][0] = yo[zz][1] = yo[zz][2] = 0.f;
+    for (int c = 0; c < DIM; ++c) {
+      const __amdgpu_buffer_rsrc_t vc = field_rsrc(v + c * M, g);
+      xo[zz][c] = -0.5f * (u[c] + s * apply<DIM>(vc, tf));
+      yo[zz][c] = 0.5f * (u[c] + s * apply<DIM>(vc, tb));
+    }
+    // reaction factor of the adjoint along the backward characteristic (Heun)
+    const float* r = v + DIM * M;
+    const Tap<DIM> ty = make_tap<DIM>(g, x, y, z, yo[zz][0], yo[zz][1], yo[zz][2]);
+    const float R = apply<DIM>(field_rsrc(r, g), ty);
+    const float ri = r[p];
+    av[zz] = 1.0f + 0.5f * g.dt * (R + (1.0f + g.dt * R) * ri);
   }
-  // reaction factor of the adjoint along the backward characteristic (Heun)
-  const float* r = v + DIM * M;
-  const Tap<DIM> ty = make_tap<DIM>(g, x, y, z, yo[0], yo[1], yo[2]);
-  const float R = apply<DIM>(field_rsrc(r, g), ty);
-  const float ri = r[p];
-  const float a = 1.0f + 0.5f * g.dt * (R + (1.0f + g.dt * R) * ri);
-  for (int c = 0; c < DIM; ++c) X[c * M + p] = xo[c];
-  YA[p] = make_float4(yo[0], yo[1], yo[2], a);
+#pragma unroll
+  for (int zz = 0; zz < ZV; ++zz) {
+    GATHER_Z(zz)
+    if (live) {
+      for (int c = 0; c < DIM; ++c) X[c * M + p] = xo[zz][c];
+      YA[p] = make_float4(yo[zz][0], yo[zz][1], yo[zz][2], av[zz]);
+    }
+  }
 }
 
 // Non-stationary step t_n -> t_{n+1}: the Heun characteristics take the velocity at both
@@ -722,7 +734,7 @@ __global__ __launch_bounds__(BX* GBY) void k_body_node(Geo g, const float* __res
 }
 
 // Deterministic partial sums of (mT - I1)^2: a fixed grid of kRedBlocks blocks, each thread
-// a fixed strided subset, then a fixed tree in LDS.
+// a fixed strided subset, then the fixed-order block reduction (wavefront shuffles).
 __global__ __launch_bounds__(256) void k_energy_partial(int64_t n, const float* __restrict__ a,
                                                         const float* __restrict__ b,
                                                         double* __restrict__ partial, Batch bt) {
@@ -730,20 +742,14 @@ __global__ __launch_bounds__(256) void k_energy_partial(int64_t n, const float* 
   BL_AT(a, bt);
   BL_AT(b, bt);
   BL_AT(partial, bt);
-  __shared__ double sh[256];
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * 256) {
     const double d = (double)a[i] - (double)b[i];
     acc = fma(d, d, acc);
   }
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+  const double r = block_reduce_256<false>(acc);
+  if (threadIdx.x == 0) partial[blockIdx.x] = r;
 }
 
 // One component of packed float4 data into a plane.
@@ -793,7 +799,7 @@ inline dim3 gather_grid(const Geo& g, int zv) {
                          __VA_ARGS__);                                                     \
   } while (0)
 void setup(const Geo& g, const float* v, float* X, float4* YA, hipStream_t s) {
-  DISPATCH_ONE(k_setup, g, v, X, YA);
+  DISPATCH_GATHER(k_setup, TR_SETUP, g, v, X, YA);
 }
 void setup_ns(const Geo& g, const float* V, float* X, float4* YA, int steps, hipStream_t s) {
   const dim3 grid = batch_grid(dim3(gather_grid(g, 1).x, (unsigned)steps), g.bat);
