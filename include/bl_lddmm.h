@@ -271,10 +271,10 @@ const char* bl_lddmm_last_error(void);
 int bl_lddmm_device_count(void);
 
 /*
- * Per-kernel timing with HIP events on the library's stream, for benchmarks: while enabled,
- * each run of consecutive launches of a transport step kernel is bracketed by one event
- * pair (no per-launch event overhead); bl_kernel_timing_read
- * returns the number of launches (timed runs for classes 3 and 4) and the summed milliseconds
+ * Per-kernel timing with HIP events, for benchmarks: while enabled, each launch of a timed
+ * kernel records an event pair at its own dispatch's start and end (kernel time alone, no gap
+ * to its neighbours; up to 4096 launches between reads, later ones are not timed).
+ * bl_kernel_timing_read returns the number of timed launches and their summed milliseconds
  * per class and resets: 0 = forward state step, 1 = incremental forward step, 2 = adjoint step,
  * 3 = z stage of iota of the direction in a Gauss-Newton product, 4 = z stage of pi of the
  * product's body force, 5 = body-force pass, 6 = departure-point setup.

@@ -634,11 +634,11 @@ void launch_z_pair(const Geo& g, const DftPlan& p, const float2* F2, float* out,
     const int zchunk = (npair + nchunk - 1) / nchunk;
     nchunk = (npair + zchunk - 1) / zchunk;
     const size_t lds = (size_t)zchunk * (KZH == 1 ? 2 : KZH) * sizeof(float2);
-    hipLaunchKernelGGL(k_iota_z<KZH>, batch_grid(dim3(qblocks, nchunk, C), g.bat), dim3(256), lds,
-                       s, g, F2, p.tw_zT, out, zchunk);
+    BL_LAUNCH(k_iota_z<KZH>, batch_grid(dim3(qblocks, nchunk, C), g.bat), dim3(256), lds, s, g,
+              F2, p.tw_zT, out, zchunk);
   } else {
-    hipLaunchKernelGGL(k_pi_z<KZH>, batch_grid(dim3((nq + 63) / 64, C), g.bat), dim3(64, kNW), 0,
-                       s, g, f, p.tw_zT, G);
+    BL_LAUNCH(k_pi_z<KZH>, batch_grid(dim3((nq + 63) / 64, C), g.bat), dim3(64, kNW), 0, s, g,
+              f, p.tw_zT, G);
   }
 }
 

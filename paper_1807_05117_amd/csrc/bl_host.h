@@ -123,10 +123,11 @@ struct bl_ctx {
   // kernel timing
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
+  std::vector<bl::LaunchEvents> ev_pairs;   // event pairs armed for single launches
   struct Run { int cls, ev, count; };
   std::vector<Run> ev_used;  // timed runs: class, pool index of the start event, launches
   size_t ev_next = 0;
-  int ev_open = -1;
+
   int64_t t_launch[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   double t_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstddef>
 #include <cstdint>
@@ -72,6 +73,24 @@ __device__ __forceinline__ double block_reduce_256(double v) {
   __syncthreads();   // part may be reused by a following reduction of the same kernel
   return r;
 }
+
+// Kernel timing for the benchmark: a pair of HIP events that the next launch through
+// BL_LAUNCH on the calling host thread records at its kernel's own start and end (the
+// dispatch's timestamps, no gap to a neighbouring launch).  set_launch_events(e) arms it;
+// BL_LAUNCH takes and clears it.
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+void set_launch_events(LaunchEvents* e);
+LaunchEvents* take_launch_events();
+#define BL_LAUNCH(KERNEL, GRID, BLOCK, SHMEM, STREAM, ...)                                   \
+  do {                                                                                     \
+    if (::bl::LaunchEvents* ev_ = ::bl::take_launch_events())                              \
+      hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, ev_->start, ev_->stop, 0,  \
+                            __VA_ARGS__);                                                  \
+    else                                                                                   \
+      hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);                  \
+  } while (0)
 
 // Geometry and weights of one problem, passed by value to every kernel.
 struct Geo {

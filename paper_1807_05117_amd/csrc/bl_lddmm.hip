@@ -348,12 +348,13 @@ double* alloc_host_scalars() {
 
 void destroy_ctx(bl_ctx* c) {
   if (!c) return;
-  hipSetDevice(c->device);
-  if (c->stream) hipStreamSynchronize(c->stream);
-  for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
-  if (c->arena && c->own_arena) hipFree(c->arena);
-  if (c->hscal && c->own_hscal) hipHostFree(c->hscal);
-  if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+  // best-effort teardown: errors here have nowhere to go
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->arena && c->own_arena) (void)hipFree(c->arena);
+  if (c->hscal && c->own_hscal) (void)hipHostFree(c->hscal);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
 
@@ -521,22 +522,27 @@ inline hipMemcpyKind in_kind(const bl_ctx* c) {
 void sync(bl_ctx* c) { HIP_TRY(hipStreamSynchronize(c->stream)); }
 
 // -------------------------------------------------------------------------------- timing
-// A run of `count` consecutive launches of one kernel class is bracketed by one event pair,
-// so the per-launch average carries no event overhead.
-void t_begin(bl_ctx* c) {
-  if (!c->timing || c->ev_next + 2 > c->ev_pool.size()) {
-    c->ev_open = -1;
-    return;
-  }
-  c->ev_open = (int)c->ev_next;
-  c->ev_next += 2;
-  HIP_TRY(hipEventRecord(c->ev_pool[c->ev_open], c->stream));
+// Timed launches record a HIP event pair at their kernel's own start and end (the dispatch
+// timestamps): the durations are those of the kernels alone, as a kernel trace reports them.
+}  // namespace host
+thread_local LaunchEvents* t_next_launch = nullptr;
+void set_launch_events(LaunchEvents* e) { t_next_launch = e; }
+LaunchEvents* take_launch_events() {
+  LaunchEvents* e = t_next_launch;
+  t_next_launch = nullptr;
+  return e;
 }
-void t_end(bl_ctx* c, int cls, int count) {
-  if (!c->timing || c->ev_open < 0) return;
-  HIP_TRY(hipEventRecord(c->ev_pool[c->ev_open + 1], c->stream));
-  c->ev_used.push_back({cls, c->ev_open, count});
-  c->ev_open = -1;
+namespace host {
+
+// arm the next BL_LAUNCH on this thread with an event pair of the pool, counted for class cls
+void t_arm(bl_ctx* c, int cls) {
+  if (!c->timing || c->ev_next + 2 > c->ev_pool.size()) return;
+  bl::LaunchEvents& e = c->ev_pairs[c->ev_next / 2];
+  e.start = c->ev_pool[c->ev_next];
+  e.stop = c->ev_pool[c->ev_next + 1];
+  bl::set_launch_events(&e);
+  c->ev_used.push_back({cls, (int)c->ev_next, 1});
+  c->ev_next += 2;
 }
 void t_collect(bl_ctx* c) {
   if (c->ev_used.empty()) return;
@@ -695,7 +701,10 @@ void choose_launch_shapes(bl_ctx* c) {
   HIP_TRY(hipEventCreate(&e1));
   struct Ev {
     hipEvent_t a, b;
-    ~Ev() { hipEventDestroy(a); hipEventDestroy(b); }
+    ~Ev() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
   } ev{e0, e1};
   auto launch = [&](int cls) {
     switch (cls) {
@@ -999,14 +1008,14 @@ void enqueue_set_velocity(bl_ctx* c, const float2* vraw) {
   double* red_data = c->red + RED_DATA * bl::kRedBlocks;
   bl::band_prep(g, vraw, c->bv, 1, c->Lhat64, red_reg, s);
   bl::iota(g, c->plan, c->bv, g.dim + 1, c->V, s);
-  if (c->timing) t_begin(c);
+  if (c->timing) t_arm(c, 6);
   bl::setup(g, c->V, c->X, c->YA, s);
-  if (c->timing) t_end(c, 6, 1);
   if (!c->tuned) choose_launch_shapes(c);
   const size_t M = (size_t)g.M;
-  if (c->timing) t_begin(c);
-  for (int n = 0; n < g.nt; ++n) bl::state_step(g, c->m + n * M, c->X, c->m + (n + 1) * M, s);
-  if (c->timing) t_end(c, 0, g.nt);
+  for (int n = 0; n < g.nt; ++n) {
+    if (c->timing) t_arm(c, 0);
+    bl::state_step(g, c->m + n * M, c->X, c->m + (n + 1) * M, s);
+  }
   bl::energy_partial(g, c->m + g.nt * M, c->I1, red_data, s);
   bl::reduce_final(red_reg, bl::kRedBlocks, c->scal + S_REG, s, publish(c, S_REG), nullptr,
                    nullptr, g.bat);
@@ -1068,12 +1077,12 @@ void backward_and_body_force(bl_ctx* c) {
   const bl::Geo& g = c->g;
   hipStream_t s = c->stream;
   const size_t M = (size_t)g.M;
-  if (c->timing) t_begin(c);
-  for (int n = g.nt - 1; n >= 0; --n) bl::adj_step(g, c->L + (n + 1) * M, c->YA, c->L + n * M, s);
-  if (c->timing) t_end(c, 2, g.nt);
-  if (c->timing) t_begin(c);
+  for (int n = g.nt - 1; n >= 0; --n) {
+    if (c->timing) t_arm(c, 2);
+    bl::adj_step(g, c->L + (n + 1) * M, c->YA, c->L + n * M, s);
+  }
+  if (c->timing) t_arm(c, 5);
   bl::body_force(g, c->L, c->m, c->Bf, s);
-  if (c->timing) t_end(c, 5, 1);
 }
 
 // gradient at the current velocity into gout (device, dim components)
@@ -1156,23 +1165,20 @@ void op_hessvec(bl_ctx* c, const float2* draw, float2* hout) {
   const size_t M = (size_t)g.M;
   bl::band_prep(g, draw, c->bd, 0, nullptr, nullptr, s);
   bl::iota_xy(g, c->plan, c->bd, g.dim, s);
-  if (c->timing) t_begin(c);
+  if (c->timing) t_arm(c, 3);
   bl::iota_z(g, c->plan, g.dim, c->DV, s);
-  if (c->timing) t_end(c, 3, 1);
   bl::inc_init(g, c->m, c->DV, c->T0, s);
   float* tin = c->T0;
   float* tout = c->T1;
-  if (c->timing && g.nt > 1) t_begin(c);
   for (int n = 0; n + 1 < g.nt; ++n) {
+    if (c->timing) t_arm(c, 1);
     bl::inc_step(g, tin, c->X, c->m + (n + 1) * M, c->DV, tout, s);
     std::swap(tin, tout);
   }
-  if (c->timing && g.nt > 1) t_end(c, 1, g.nt - 1);
   bl::inc_last(g, tin, c->X, c->m + g.nt * M, c->DV, c->L + g.nt * M, s);
   backward_and_body_force(c);
-  if (c->timing) t_begin(c);
+  if (c->timing) t_arm(c, 4);
   bl::pi_z(g, c->plan, c->Bf, g.dim, s);
-  if (c->timing) t_end(c, 4, 1);
   bl::pi_yx(g, c->plan, g.dim, c->P, s);
   bl::band_finalize(g, g.dim, c->bd, c->Lhat, c->P, (float)(1.0 / (double)g.M), hout, c->flag, s,
                     1);
@@ -1470,11 +1476,11 @@ struct CachedCtx {
       return;
     }
     if (c->timing) {
-      for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
+      for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
       c->ev_pool.clear();
       c->ev_used.clear();
+      c->ev_pairs.clear();
       c->ev_next = 0;
-      c->ev_open = -1;
       c->timing = false;
     }
     if (c->devptr) c->stream = nullptr;   // the caller's stream is not kept
@@ -1786,6 +1792,7 @@ int bl_kernel_timing_enable(bl_ctx* c, int32_t on) {
     HIP_TRY(hipSetDevice(c->device));
     if (on && c->ev_pool.empty()) {
       c->ev_pool.resize(8192);
+      c->ev_pairs.resize(4096);
       for (auto& e : c->ev_pool) HIP_TRY(hipEventCreate(&e));
     }
     t_collect(c);

@@ -223,7 +223,7 @@ void iota_z_mixed(const Geo& g, const DftPlan& p, const float2* F2, int C, float
   const dim3 grid = batch_grid(dim3((nqt + 3) / 4, C), g.bat);
   const int ks = mixed_kp(g) / 16;
 #define L_IOTA(K)                                                                             \
-  hipLaunchKernelGGL(k_iota_z_mfma<K>, grid, dim3(256), 0, s, g, F2, p.wi_bf16, p.nzp32, out, \
+  BL_LAUNCH(k_iota_z_mfma<K>, grid, dim3(256), 0, s, g, F2, p.wi_bf16, p.nzp32, out,          \
                      nqt)
   switch (ks) {
     case 1: L_IOTA(1); break;
@@ -243,16 +243,16 @@ void pi_z_mixed(const Geo& g, const DftPlan& p, const float* f, int C, float2* G
   const dim3 grid = batch_grid(dim3((nq + 31) / 32, C), g.bat);
   switch (mixed_jt(g)) {
     case 1:
-      hipLaunchKernelGGL(k_pi_z_mfma<1>, grid, dim3(256), 0, s, g, f, p.wp_bf16, p.nzp16, G);
+      BL_LAUNCH(k_pi_z_mfma<1>, grid, dim3(256), 0, s, g, f, p.wp_bf16, p.nzp16, G);
       break;
     case 2:
-      hipLaunchKernelGGL(k_pi_z_mfma<2>, grid, dim3(256), 0, s, g, f, p.wp_bf16, p.nzp16, G);
+      BL_LAUNCH(k_pi_z_mfma<2>, grid, dim3(256), 0, s, g, f, p.wp_bf16, p.nzp16, G);
       break;
     case 3:
-      hipLaunchKernelGGL(k_pi_z_mfma<3>, grid, dim3(256), 0, s, g, f, p.wp_bf16, p.nzp16, G);
+      BL_LAUNCH(k_pi_z_mfma<3>, grid, dim3(256), 0, s, g, f, p.wp_bf16, p.nzp16, G);
       break;
     default:
-      hipLaunchKernelGGL(k_pi_z_mfma<4>, grid, dim3(256), 0, s, g, f, p.wp_bf16, p.nzp16, G);
+      BL_LAUNCH(k_pi_z_mfma<4>, grid, dim3(256), 0, s, g, f, p.wp_bf16, p.nzp16, G);
       break;
   }
 }

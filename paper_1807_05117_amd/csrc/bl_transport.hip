@@ -777,15 +777,15 @@ inline dim3 gather_grid(const Geo& g, int zv) {
     if (g.dim == 3) {                                                                           \
       const int zv_ = g.zv[CLS];                                                                \
       if (zv_ == 8)                                                                             \
-        hipLaunchKernelGGL((KERNEL<3, 8>), GRID_N(8, NY), dim3(BX, GBY), 0, s, __VA_ARGS__);    \
+        BL_LAUNCH((KERNEL<3, 8>), GRID_N(8, NY), dim3(BX, GBY), 0, s, __VA_ARGS__);    \
       else if (zv_ == 4)                                                                        \
-        hipLaunchKernelGGL((KERNEL<3, 4>), GRID_N(4, NY), dim3(BX, GBY), 0, s, __VA_ARGS__);    \
+        BL_LAUNCH((KERNEL<3, 4>), GRID_N(4, NY), dim3(BX, GBY), 0, s, __VA_ARGS__);    \
       else if (zv_ == 2)                                                                        \
-        hipLaunchKernelGGL((KERNEL<3, 2>), GRID_N(2, NY), dim3(BX, GBY), 0, s, __VA_ARGS__);    \
+        BL_LAUNCH((KERNEL<3, 2>), GRID_N(2, NY), dim3(BX, GBY), 0, s, __VA_ARGS__);    \
       else                                                                                      \
-        hipLaunchKernelGGL((KERNEL<3, 1>), GRID_N(1, NY), dim3(BX, GBY), 0, s, __VA_ARGS__);    \
+        BL_LAUNCH((KERNEL<3, 1>), GRID_N(1, NY), dim3(BX, GBY), 0, s, __VA_ARGS__);    \
     } else {                                                                                    \
-      hipLaunchKernelGGL((KERNEL<2, 1>), GRID_N(1, NY), dim3(BX, GBY), 0, s, __VA_ARGS__);     \
+      BL_LAUNCH((KERNEL<2, 1>), GRID_N(1, NY), dim3(BX, GBY), 0, s, __VA_ARGS__);     \
     }                                                                                           \
   } while (0)
 #define DISPATCH_GATHER(KERNEL, CLS, ...) DISPATCH_GATHER_N(KERNEL, CLS, 1, __VA_ARGS__)
