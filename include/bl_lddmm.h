@@ -297,14 +297,17 @@ int bl_kernel_timing_read(bl_ctx* ctx, int32_t kclass, int64_t* launches, double
 int bl_lddmm_ctx_launch_shapes(bl_ctx* ctx, int32_t zv_out[4]);
 
 /*
- * The autotuner: besides the transports' zv, it chooses the setup kernel's voxels per thread,
- * the z-chunking of the FP32 iota z stage and the iota x/y stages (two kernels, or one fused
- * kernel with 32 or 16 rows per block),
- * all bitwise-invariant, by timing at the first velocity of each (GPU architecture, grid,
- * band, precision).  Choices are kept for the process and appended to a cache file read by
- * later processes: BL_TUNE_CACHE (a path, or "off"), else $XDG_CACHE_HOME/bl_lddmm/
- * launch_shapes_v1.txt or ~/.cache/bl_lddmm/launch_shapes_v1.txt.  BL_LAUNCH_SHAPES="s0,...,s6"
- * fixes all classes (state, incremental, adjoint, body force, setup, iota z, iota x/y).
+ * The autotuner: besides the transports' zv, it chooses the setup kernel's voxels per thread
+ * and the z-chunking of the FP32 iota z stage, all bitwise-invariant, by timing at the first
+ * velocity of each (GPU architecture, grid, band, precision): every candidate is launched
+ * once, then all are timed in turn three times over and each keeps its fastest round; another
+ * shape must beat the default by 3%.  BL_TUNE_LOG=1 prints the times and choices to stderr.
+ * Choices are kept for the process and appended to a cache file read by later processes:
+ * BL_TUNE_CACHE (a path, or "off"), else $XDG_CACHE_HOME/bl_lddmm/launch_shapes_v2.txt or
+ * ~/.cache/bl_lddmm/launch_shapes_v2.txt.  BL_LAUNCH_SHAPES="s0,...,s6" fixes all classes
+ * (state, incremental, adjoint, body force, setup, iota z, iota x/y); only through it can the
+ * iota x/y stages run as one fused kernel with 32 or 16 rows per block (s6 = 32 or 16; 0 = the
+ * two separate stages, the default), which times faster alone but runs slower in products.
  * bl_lddmm_tune_reload forgets the choices of this process and reads the cache file again.
  */
 void bl_lddmm_tune_reload(void);

@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <mutex>
 #include <new>
@@ -572,7 +573,7 @@ void t_collect(bl_ctx* c) {
 // (T0, T1, Bf, DV, X, YA with the same values, the transform buffers) are work space that every
 // operation rewrites before use.  Choices are kept per (GPU architecture, grid, band,
 // precision) for the process and in a cache file -- BL_TUNE_CACHE, else
-// $XDG_CACHE_HOME/bl_lddmm/launch_shapes_v1.txt or ~/.cache/bl_lddmm/launch_shapes_v1.txt -- read at
+// $XDG_CACHE_HOME/bl_lddmm/launch_shapes_v2.txt or ~/.cache/bl_lddmm/launch_shapes_v2.txt -- read at
 // the first tuning and appended to after each new choice, so later processes skip the timing.
 // BL_TUNE_CACHE=off disables the file; BL_TRANSPORT_ZV = 1, 2, 4 or 8 fixes the transports'
 // and the setup's voxels per thread and skips the timing, BL_LAUNCH_SHAPES fixes every class.
@@ -584,9 +585,9 @@ std::string tune_cache_path() {
   const char* e = std::getenv("BL_TUNE_CACHE");
   if (e && *e) return std::string(e) == "off" ? std::string() : std::string(e);
   if (const char* x = std::getenv("XDG_CACHE_HOME"))
-    if (*x) return std::string(x) + "/bl_lddmm/launch_shapes_v1.txt";
+    if (*x) return std::string(x) + "/bl_lddmm/launch_shapes_v2.txt";
   if (const char* h = std::getenv("HOME"))
-    if (*h) return std::string(h) + "/.cache/bl_lddmm/launch_shapes_v1.txt";
+    if (*h) return std::string(h) + "/.cache/bl_lddmm/launch_shapes_v2.txt";
   return std::string();
 }
 
@@ -723,36 +724,61 @@ void choose_launch_shapes(bl_ctx* c) {
       // stationary setup is not timed on its fields)
       case bl::TR_SETUP: return g.nodes > 1 ? std::vector<int>{} : std::vector<int>{1, 2, 4};
       case bl::TR_IOTA_Z: return c->plan.mixed ? std::vector<int>{} : std::vector<int>{1, 2, 4};
-      case bl::TR_IOTA_XY: return {0, 32, 16};
+      // the fused iota x/y kernel times faster alone than the two stages (15.0 against
+      // 17.4 us per launch at 128^3) but runs slower inside products and registrations (25 us
+      // per call in a kernel trace, 2% fewer products per second), so timing it alone would
+      // choose wrongly: not a candidate (BL_LAUNCH_SHAPES still selects it)
+      case bl::TR_IOTA_XY: return {};
       default: return {1, 2, 4, 8};
     }
   };
-  constexpr int kReps = 4;
+  // Every candidate is launched once first; then the candidates are timed in turn, kRounds
+  // times over, and each keeps its fastest round.  Interleaving keeps a clock ramp or a
+  // neighbour's load from favouring whichever candidate is timed last.
+  constexpr int kReps = 4, kRounds = 3;
+  // BL_TUNE_LOG=1 prints every class's candidate times (per launch) and the choice to stderr
+  const char* log_env = std::getenv("BL_TUNE_LOG");
+  const bool log = log_env && *log_env && std::strcmp(log_env, "0") != 0;
   std::array<int, bl::TR_CLASSES> best;
   for (int cls = 0; cls < bl::TR_CLASSES; ++cls) {
     const int dflt = g.zv[cls];
     best[cls] = dflt;
     const std::vector<int> cand = candidates(cls);
     if (cand.empty()) continue;
-    float t_best = 0.f;
     std::vector<int> order{dflt};
     for (int v : cand)
       if (v != dflt) order.push_back(v);
     for (int zv : order) {
       g.zv[cls] = zv;
       launch(cls);  // warm-up
-      HIP_TRY(hipEventRecord(e0, s));
-      for (int r = 0; r < kReps; ++r) launch(cls);
-      HIP_TRY(hipEventRecord(e1, s));
-      check_launch("launch shape timing");
-      HIP_TRY(hipEventSynchronize(e1));
-      float ms = 0.f;
-      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-      // another shape must beat the default by 3% to replace it (timing noise)
-      if (zv == dflt) t_best = ms;
-      else if (ms < 0.97f * t_best) { t_best = ms; best[cls] = zv; }
     }
+    std::vector<float> t_min(order.size(), std::numeric_limits<float>::infinity());
+    for (int round = 0; round < kRounds; ++round)
+      for (size_t i = 0; i < order.size(); ++i) {
+        g.zv[cls] = order[i];
+        HIP_TRY(hipEventRecord(e0, s));
+        for (int r = 0; r < kReps; ++r) launch(cls);
+        HIP_TRY(hipEventRecord(e1, s));
+        check_launch("launch shape timing");
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        t_min[i] = std::min(t_min[i], ms);
+      }
+    // another shape must beat the default by 3% to replace it (timing noise)
+    float t_best = t_min[0];
+    for (size_t i = 1; i < order.size(); ++i)
+      if (t_min[i] < 0.97f * t_best) {
+        t_best = t_min[i];
+        best[cls] = order[i];
+      }
     g.zv[cls] = best[cls];
+    if (log) {
+      std::fprintf(stderr, "[bl_lddmm tune] class %d:", cls);
+      for (size_t i = 0; i < order.size(); ++i)
+        std::fprintf(stderr, " %d=%.2fus", order[i], 1e3f * t_min[i] / kReps);
+      std::fprintf(stderr, " -> %d\n", best[cls]);
+    }
   }
   const std::string key = shape_key(c);
   std::lock_guard<std::mutex> lk(g_shape_mu);

@@ -126,6 +126,61 @@ __device__ __forceinline__ float apply(__amdgpu_buffer_rsrc_t f, const Tap<DIM>&
   return fmaf(t.wz, pb - pa, pa);
 }
 
+// apply() at the ZV taps of a thread, with the same loaded values and arithmetic, but the
+// second loads of wrapped pairs issued only by waves in which some lane wraps (one
+// wave-uniform branch after every 8-byte row load of the thread is in flight): waves away
+// from the x boundary skip them.  The taps are all formed before the call, so no load of the
+// thread waits behind the branch.
+template <int DIM, int ZV>
+__device__ __forceinline__ void gather_zv(__amdgpu_buffer_rsrc_t f, const Tap<DIM> (&t)[ZV],
+                                          float (&out)[ZV]) {
+  constexpr int R = DIM == 3 ? 4 : 2;
+  f2v v[ZV][R];
+  float w[ZV][R];
+  bool any = false;
+#pragma unroll
+  for (int zz = 0; zz < ZV; ++zz) {
+    const uint32_t rows[4] = {t[zz].r00, t[zz].r01, t[zz].r10, t[zz].r11};
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      v[zz][r] = __builtin_bit_cast(
+          f2v, __builtin_amdgcn_raw_buffer_load_b64(f, (int)((rows[r] + (uint32_t)t[zz].x0) * 4u),
+                                                    0, 0));
+      w[zz][r] = 0.0f;
+    }
+    any |= t[zz].x1 != t[zz].x0 + 1;
+  }
+  if (__builtin_amdgcn_ballot_w64(any) != 0) {
+#pragma unroll
+    for (int zz = 0; zz < ZV; ++zz) {
+      const uint32_t rows[4] = {t[zz].r00, t[zz].r01, t[zz].r10, t[zz].r11};
+      const bool wrapped = t[zz].x1 != t[zz].x0 + 1;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const uint32_t off = wrapped ? (rows[r] + (uint32_t)t[zz].x1) * 4u : kPastEnd;
+        w[zz][r] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(f, (int)off, 0, 0));
+      }
+    }
+  }
+#pragma unroll
+  for (int zz = 0; zz < ZV; ++zz) {
+    const bool wrapped = t[zz].x1 != t[zz].x0 + 1;
+    float rr[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const float lo = v[zz][r].x, hi = wrapped ? w[zz][r] : v[zz][r].y;
+      rr[r] = fmaf(t[zz].wx, hi - lo, lo);
+    }
+    const float pa = fmaf(t[zz].wy, rr[1] - rr[0], rr[0]);
+    if (DIM == 2) {
+      out[zz] = pa;
+    } else {
+      const float pb = fmaf(t[zz].wy, rr[3] - rr[2], rr[2]);
+      out[zz] = fmaf(t[zz].wz, pb - pa, pa);
+    }
+  }
+}
+
 // ------------------------------------------------------------------ gather kernels (64 x 4)
 // One thread per ZV voxels along z; z is clamped to the grid so that every load stays in
 // bounds and the ZV voxels' loads can be issued together; only the stores are guarded.
@@ -197,31 +252,53 @@ __global__ __launch_bounds__(BX* GBY) void k_setup(Geo g, const float* __restric
   const float s = g.dt * (float)g.nref;
   // the ZV voxels of the thread are computed first and stored afterwards (their gathers can
   // all be in flight)
-  float xo[ZV][3], yo[ZV][3], av[ZV];
+  float u[ZV][3];
+  Tap<DIM> tf[ZV], tb[ZV];
 #pragma unroll
   for (int zz = 0; zz < ZV; ++zz) {
     GATHER_Z(zz)
     (void)live;
-    float u[3] = {0.f, 0.f, 0.f};
-    for (int c = 0; c < DIM; ++c) u[c] = s * v[c * M + p];
+    u[zz][0] = u[zz][1] = u[zz][2] = 0.f;
+    for (int c = 0; c < DIM; ++c) u[zz][c] = s * v[c * M + p];
     // forward: X = -(u + Interp(u, i - u)) / 2
-    const Tap<DIM> tf = make_tap<DIM>(g, x, y, z, -u[0], -u[1], -u[2]);
+    tf[zz] = make_tap<DIM>(g, x, y, z, -u[zz][0], -u[zz][1], -u[zz][2]);
     // backward: Y = +(u + Interp(u, i + u)) / 2
-    const Tap<DIM> tb = make_tap<DIM>(g, x, y, z, u[0], u[1], u[2]);
+    tb[zz] = make_tap<DIM>(g, x, y, z, u[zz][0], u[zz][1], u[zz][2]);
+  }
+  float xo[ZV][3], yo[ZV][3], av[ZV];
+#pragma unroll
+  for (int zz = 0; zz < ZV; ++zz) {
     xo[zz][0] = xo[zz][1] = xo[zz][2] = 0.f;
     yo[zz][0] = yo[zz][1] = yo[zz][2] = 0.f;
-    for (int c = 0; c < DIM; ++c) {
-      const __amdgpu_buffer_rsrc_t vc = field_rsrc(v + c * M, g);
-      xo[zz][c] = -0.5f * (u[c] + s * apply<DIM>(vc, tf));
-      yo[zz][c] = 0.5f * (u[c] + s * apply<DIM>(vc, tb));
-    }
-    // reaction factor of the adjoint along the backward characteristic (Heun)
-    const float* r = v + DIM * M;
-    const Tap<DIM> ty = make_tap<DIM>(g, x, y, z, yo[zz][0], yo[zz][1], yo[zz][2]);
-    const float R = apply<DIM>(field_rsrc(r, g), ty);
-    const float ri = r[p];
-    av[zz] = 1.0f + 0.5f * g.dt * (R + (1.0f + g.dt * R) * ri);
   }
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    const __amdgpu_buffer_rsrc_t vc = field_rsrc(v + c * M, g);
+    float gf[ZV], gb[ZV];
+    gather_zv<DIM, ZV>(vc, tf, gf);
+    gather_zv<DIM, ZV>(vc, tb, gb);
+#pragma unroll
+    for (int zz = 0; zz < ZV; ++zz) {
+      xo[zz][c] = -0.5f * (u[zz][c] + s * gf[zz]);
+      yo[zz][c] = 0.5f * (u[zz][c] + s * gb[zz]);
+    }
+  }
+  // reaction factor of the adjoint along the backward characteristic (Heun)
+  const float* r = v + DIM * M;
+  Tap<DIM> ty[ZV];
+  float ri[ZV];
+#pragma unroll
+  for (int zz = 0; zz < ZV; ++zz) {
+    GATHER_Z(zz)
+    (void)live;
+    ty[zz] = make_tap<DIM>(g, x, y, z, yo[zz][0], yo[zz][1], yo[zz][2]);
+    ri[zz] = r[p];
+  }
+  float R[ZV];
+  gather_zv<DIM, ZV>(field_rsrc(r, g), ty, R);
+#pragma unroll
+  for (int zz = 0; zz < ZV; ++zz)
+    av[zz] = 1.0f + 0.5f * g.dt * (R[zz] + (1.0f + g.dt * R[zz]) * ri[zz]);
 #pragma unroll
   for (int zz = 0; zz < ZV; ++zz) {
     GATHER_Z(zz)
@@ -262,16 +339,22 @@ __global__ __launch_bounds__(BX* GBY) void k_setup_ns(Geo g, const float* __rest
     u0[c] = s * v0[c * M + p];
     u1[c] = s * v1[c * M + p];
   }
-  const Tap<DIM> tf = make_tap<DIM>(g, x, y, z, -u1[0], -u1[1], -u1[2]);
-  const Tap<DIM> tb = make_tap<DIM>(g, x, y, z, u0[0], u0[1], u0[2]);
+  const Tap<DIM> tf[1] = {make_tap<DIM>(g, x, y, z, -u1[0], -u1[1], -u1[2])};
+  const Tap<DIM> tb[1] = {make_tap<DIM>(g, x, y, z, u0[0], u0[1], u0[2])};
   float xo[3] = {0.f, 0.f, 0.f}, yo[3] = {0.f, 0.f, 0.f};
+#pragma unroll
   for (int c = 0; c < DIM; ++c) {
-    xo[c] = -0.5f * (u1[c] + s * apply<DIM>(field_rsrc(v0 + c * M, g), tf));
-    yo[c] = 0.5f * (u0[c] + s * apply<DIM>(field_rsrc(v1 + c * M, g), tb));
+    float gf[1], gb[1];
+    gather_zv<DIM, 1>(field_rsrc(v0 + c * M, g), tf, gf);
+    gather_zv<DIM, 1>(field_rsrc(v1 + c * M, g), tb, gb);
+    xo[c] = -0.5f * (u1[c] + s * gf[0]);
+    yo[c] = 0.5f * (u0[c] + s * gb[0]);
   }
-  const Tap<DIM> ty = make_tap<DIM>(g, x, y, z, yo[0], yo[1], yo[2]);
-  const float R = apply<DIM>(field_rsrc(v1 + DIM * M, g), ty);
+  const Tap<DIM> ty[1] = {make_tap<DIM>(g, x, y, z, yo[0], yo[1], yo[2])};
   const float ri = v0[DIM * M + p];
+  float Rv[1];
+  gather_zv<DIM, 1>(field_rsrc(v1 + DIM * M, g), ty, Rv);
+  const float R = Rv[0];
   const float a = 1.0f + 0.5f * g.dt * (R + (1.0f + g.dt * R) * ri);
   for (int c = 0; c < DIM; ++c) X[c * M + p] = xo[c];
   YA[p] = make_float4(yo[0], yo[1], yo[2], a);
@@ -287,14 +370,16 @@ __global__ __launch_bounds__(BX* GBY) void k_state_step(Geo g, const float* __re
   BL_AT(m_out, g.bat);
   GATHER_XY
   const size_t M = (size_t)g.M;
-  float val[ZV];
+  Tap<DIM> tp[ZV];
 #pragma unroll
   for (int zz = 0; zz < ZV; ++zz) {
     GATHER_Z(zz)
     (void)live;
     const float ox = X[p], oy = X[M + p], oz = DIM == 3 ? X[2 * M + p] : 0.f;
-    val[zz] = apply<DIM>(field_rsrc(m_in, g), make_tap<DIM>(g, x, y, z, ox, oy, oz));
+    tp[zz] = make_tap<DIM>(g, x, y, z, ox, oy, oz);
   }
+  float val[ZV];
+  gather_zv<DIM, ZV>(field_rsrc(m_in, g), tp, val);
   STORE_ZV(m_out, val)
 }
 
@@ -307,14 +392,20 @@ __global__ __launch_bounds__(BX* GBY) void k_adj_step(Geo g, const float* __rest
   BL_AT(YA, g.bat);
   BL_AT(lam_out, g.bat);
   GATHER_XY
-  float val[ZV];
+  Tap<DIM> tp[ZV];
+  float aw[ZV];
 #pragma unroll
   for (int zz = 0; zz < ZV; ++zz) {
     GATHER_Z(zz)
     (void)live;
     const float4 o = YA[p];
-    val[zz] = o.w * apply<DIM>(field_rsrc(lam_in, g), make_tap<DIM>(g, x, y, z, o.x, o.y, o.z));
+    tp[zz] = make_tap<DIM>(g, x, y, z, o.x, o.y, o.z);
+    aw[zz] = o.w;
   }
+  float val[ZV];
+  gather_zv<DIM, ZV>(field_rsrc(lam_in, g), tp, val);
+#pragma unroll
+  for (int zz = 0; zz < ZV; ++zz) val[zz] = aw[zz] * val[zz];
   STORE_ZV(lam_out, val)
 }
 
@@ -400,15 +491,20 @@ __global__ __launch_bounds__(BX* GBY) void k_inc_step(Geo g, const float* __rest
   BL_AT(t_out, g.bat);
   GATHER_XY
   const size_t M = (size_t)g.M;
-  float val[ZV];
+  Tap<DIM> tp[ZV];
+  float src[ZV];
 #pragma unroll
   for (int zz = 0; zz < ZV; ++zz) {
     GATHER_Z(zz)
     (void)live;
     const float ox = X[p], oy = X[M + p], oz = DIM == 3 ? X[2 * M + p] : 0.f;
-    const float tr = apply<DIM>(field_rsrc(t_in, g), make_tap<DIM>(g, x, y, z, ox, oy, oz));
-    val[zz] = fmaf(g.dt, source_f<DIM>(g, m_next, dv, x, y, z, p), tr);
+    tp[zz] = make_tap<DIM>(g, x, y, z, ox, oy, oz);
+    src[zz] = source_f<DIM>(g, m_next, dv, x, y, z, p);
   }
+  float val[ZV];
+  gather_zv<DIM, ZV>(field_rsrc(t_in, g), tp, val);
+#pragma unroll
+  for (int zz = 0; zz < ZV; ++zz) val[zz] = fmaf(g.dt, src[zz], val[zz]);
   STORE_ZV(t_out, val)
 }
 
@@ -426,16 +522,20 @@ __global__ __launch_bounds__(BX* GBY) void k_inc_last(Geo g, const float* __rest
   BL_AT(dlam, g.bat);
   GATHER_XY
   const size_t M = (size_t)g.M;
-  float val[ZV];
+  Tap<DIM> tp[ZV];
+  float src[ZV];
 #pragma unroll
   for (int zz = 0; zz < ZV; ++zz) {
     GATHER_Z(zz)
     (void)live;
     const float ox = X[p], oy = X[M + p], oz = DIM == 3 ? X[2 * M + p] : 0.f;
-    const float tr = apply<DIM>(field_rsrc(t_in, g), make_tap<DIM>(g, x, y, z, ox, oy, oz));
-    const float dm = fmaf(0.5f * g.dt, source_f<DIM>(g, mT, dv, x, y, z, p), tr);
-    val[zz] = g.lam_scale * dm;
+    tp[zz] = make_tap<DIM>(g, x, y, z, ox, oy, oz);
+    src[zz] = source_f<DIM>(g, mT, dv, x, y, z, p);
   }
+  float val[ZV];
+  gather_zv<DIM, ZV>(field_rsrc(t_in, g), tp, val);
+#pragma unroll
+  for (int zz = 0; zz < ZV; ++zz) val[zz] = g.lam_scale * fmaf(0.5f * g.dt, src[zz], val[zz]);
   STORE_ZV(dlam, val)
 }
 
