@@ -292,6 +292,7 @@ void Cohort::enqueue_step(int k_pcg) {
   const int64_t st = (int64_t)stride_;
   double* pa = c->red + RED_A * bl::kRedBlocks;
   double* pb = c->red + RED_B * bl::kRedBlocks;
+  double* pc = c->red + RED_C * bl::kRedBlocks;
   auto use = [&](const int* gate) {
     c->g = g0;
     c->g.bat = gated(gate);
@@ -313,20 +314,19 @@ void Cohort::enqueue_step(int k_pcg) {
   bl::zero_band(c->sr, nb, s, b);
   bl::axpy(c->sr, c->sg, -1.0, nb, s, b);
   bl::precond_dots(c->g, c->sr, c->Lhat, c->sz, pa, pb, s);
-  bl::reduce_final(pa, bl::kRedBlocks, c->scal + S_RR, s, nullptr, nullptr, nullptr, b);
-  bl::reduce_final(pb, bl::kRedBlocks, c->scal + S_RZ0, s, nullptr, nullptr, nullptr, b);
+  bl::reduce_final2(pa, c->scal + S_RR, nullptr, pb, c->scal + S_RZ0, nullptr, bl::kRedBlocks, s,
+                    false, nullptr, nullptr, b);
   bl::copy_band(c->sp, c->sz, nb, s, b);
 
   // PCG iterations
   for (int j = 0; j < k_pcg; ++j) {
     b = use(&ctl0->g_pcg);
     op_hessvec(c, c->sp, c->sHp);
-    vec_dot_partial(c, c->sp, c->sHp, pa);
-    bl::reduce_final(pa, bl::kRedBlocks, c->scal + S_PHP, s, nullptr, nullptr, nullptr, b);
-    bl::pcg_step(c->g, c->sp, c->sHp, c->scal + S_RZ0, c->scal + S_PHP, c->sdelta, c->sr,
-                 c->Lhat, c->sz, pa, pb, s);
-    bl::reduce_final(pa, bl::kRedBlocks, c->scal + S_RR, s, nullptr, nullptr, nullptr, b);
-    bl::reduce_final(pb, bl::kRedBlocks, c->scal + S_RZ1, s, nullptr, nullptr, nullptr, b);
+    vec_dot_partial(c, c->sp, c->sHp, pc);
+    bl::pcg_step(c->g, c->sp, c->sHp, c->scal + S_RZ0, pc, c->scal + S_PHP, nullptr, c->sdelta,
+                 c->sr, c->Lhat, c->sz, pa, pb, s);
+    bl::reduce_final2(pa, c->scal + S_RR, nullptr, pb, c->scal + S_RZ1, nullptr, bl::kRedBlocks,
+                      s, false, nullptr, nullptr, b);
     hipLaunchKernelGGL(k_ctl_pcg, one, lanes, 0, s, scal0, st, cap_);
     bl::xpby_dev(c->sp, c->sz, c->scal + S_RZ1, c->scal + S_RZ0, nb, s, b);
     hipLaunchKernelGGL(k_ctl_swap, one, lanes, 0, s, scal0, st, cap_);
@@ -353,9 +353,9 @@ void Cohort::enqueue_step(int k_pcg) {
   bl::copy_band(c->sv, c->bv, nb, s, b);
   op_gradient(c, c->sg);
   vec_dot_partial(c, c->sg, c->sg, pa);
-  bl::reduce_final(pa, bl::kRedBlocks, c->scal + S_GG, s, nullptr, nullptr, nullptr, b);
   bl::maxabs_partial(c->sg, nb, pb, s, b);
-  bl::reduce_max_final(pb, bl::kRedBlocks, c->scal + S_GINF, s, nullptr, nullptr, nullptr, b);
+  bl::reduce_final2(pa, c->scal + S_GG, nullptr, pb, c->scal + S_GINF, nullptr, bl::kRedBlocks, s,
+                    true, nullptr, nullptr, b);
   hipLaunchKernelGGL(k_ctl_grad, one, lanes, 0, s, scal0, st, cap_,
                      reinterpret_cast<char*>(c->flag));
 

@@ -31,7 +31,7 @@ struct NonFinite {
   const char* what;
 };
 
-enum { RED_REG = 0, RED_DATA, RED_A, RED_B, RED_SLOTS };
+enum { RED_REG = 0, RED_DATA, RED_A, RED_B, RED_C, RED_SLOTS };
 // slots of the device scalars (bl_ctx::scal) and of their host-mapped mirror (bl_ctx::hscal)
 enum {
   S_REG = 0, S_DATA, S_GG, S_GINF, S_PHP, S_SLOPE, S_RR, S_RZ0, S_RZ1, S_SQD, S_FLAG, S_SLOTS

@@ -317,6 +317,12 @@ void maxabs_partial(const float2* a, int64_t n, double* partial, hipStream_t s,
 void reduce_max_final(const double* partial, int n, double* out, hipStream_t s,
                       double* host = nullptr, const int* flag = nullptr,
                       double* host_flag = nullptr, const Batch& bt = Batch{});
+// reduce_final of pa and, in the same launch, reduce_final (max_b: reduce_max_final) of pb with
+// the flag published beside it; the same values as the two separate calls
+void reduce_final2(const double* pa, double* outa, double* hosta, const double* pb, double* outb,
+                   double* hostb, int n, hipStream_t s, bool max_b = false,
+                   const int* flag = nullptr, double* host_flag = nullptr,
+                   const Batch& bt = Batch{});
 // y = alpha x + y
 void axpy(float2* y, const float2* x, double alpha, int64_t n, hipStream_t s,
           const Batch& bt = Batch{});
@@ -330,11 +336,13 @@ void add_scaled_dev(float2* y, const float2* x, const float2* d, const double* e
                     hipStream_t s, const Batch& bt = Batch{});
 // y = x + beta y
 void xpby(float2* y, const float2* x, double beta, int64_t n, hipStream_t s);
-// one PCG step: alpha = rz / pHp (0 unless pHp > 0), delta += alpha p, r -= alpha Hp,
-// z = r / Lhat, kRedBlocks partials of <r, r> (p0) and <r, z> (p1)
+// one PCG step: pHp = <p, Hp> from its kRedBlocks partials php_part (the same value as
+// reduce_final of them; stored to pHp[0] and, when not NULL, host-mapped pHp_host[0]),
+// alpha = rz / pHp (0 unless pHp > 0), delta += alpha p, r -= alpha Hp, z = r / Lhat,
+// kRedBlocks partials of <r, r> (p0) and <r, z> (p1); php_part must not alias p0 or p1
 void pcg_step(const Geo& g, const float2* p, const float2* Hp, const double* rz,
-              const double* pHp, float2* delta, float2* r, const float* Lhat, float2* z,
-              double* p0, double* p1, hipStream_t s);
+              const double* php_part, double* pHp, double* pHp_host, float2* delta, float2* r,
+              const float* Lhat, float2* z, double* p0, double* p1, hipStream_t s);
 // y = x + (num[0] / den[0]) y with device scalars
 void xpby_dev(float2* y, const float2* x, const double* num, const double* den, int64_t n,
               hipStream_t s, const Batch& bt = Batch{});

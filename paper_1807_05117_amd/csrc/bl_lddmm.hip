@@ -809,8 +809,8 @@ void op_set_velocity_ns(bl_ctx* c, const float2* vraw) {
   for (int n = 0; n < g.nt; ++n)
     bl::state_step(g, c->m + n * M, c->X + (size_t)n * d * M, c->m + (n + 1) * M, s);
   bl::energy_partial(g, c->m + g.nt * M, c->I1, red_data, s);
-  bl::reduce_final(red_reg, bl::kRedBlocks, c->scal + S_REG, s, c->hdev + S_REG);
-  bl::reduce_final(red_data, bl::kRedBlocks, c->scal + S_DATA, s, c->hdev + S_DATA);
+  bl::reduce_final2(red_reg, c->scal + S_REG, c->hdev + S_REG, red_data, c->scal + S_DATA,
+                    c->hdev + S_DATA, bl::kRedBlocks, s);
   check_launch("set_velocity (non-stationary)");
   sync(c);
   c->reg = c->hscal[S_REG];
@@ -977,8 +977,8 @@ void op_set_velocity_def(bl_ctx* c, const float2* vraw) {
   bl::iota(g, c->plan, u1, g.dim, c->UG, s);
   bl::def_warp(g, c->UG, c->IG, c->mfinal, c->GP, s);
   bl::energy_partial(g, c->mfinal, c->I1, red_data, s);
-  bl::reduce_final(red_reg, bl::kRedBlocks, c->scal + S_REG, s, c->hdev + S_REG);
-  bl::reduce_final(red_data, bl::kRedBlocks, c->scal + S_DATA, s, c->hdev + S_DATA);
+  bl::reduce_final2(red_reg, c->scal + S_REG, c->hdev + S_REG, red_data, c->scal + S_DATA,
+                    c->hdev + S_DATA, bl::kRedBlocks, s);
   check_launch("set_velocity (deformation)");
   sync(c);
   c->reg = c->hscal[S_REG];
@@ -1043,10 +1043,8 @@ void enqueue_set_velocity(bl_ctx* c, const float2* vraw) {
     bl::state_step(g, c->m + n * M, c->X, c->m + (n + 1) * M, s);
   }
   bl::energy_partial(g, c->m + g.nt * M, c->I1, red_data, s);
-  bl::reduce_final(red_reg, bl::kRedBlocks, c->scal + S_REG, s, publish(c, S_REG), nullptr,
-                   nullptr, g.bat);
-  bl::reduce_final(red_data, bl::kRedBlocks, c->scal + S_DATA, s, publish(c, S_DATA), nullptr,
-                   nullptr, g.bat);
+  bl::reduce_final2(red_reg, c->scal + S_REG, publish(c, S_REG), red_data, c->scal + S_DATA,
+                    publish(c, S_DATA), bl::kRedBlocks, s, false, nullptr, nullptr, g.bat);
   check_launch("set_velocity");
 }
 
@@ -1245,10 +1243,9 @@ void grad_stats(bl_ctx* c, const float2* gvec, double* gg, double* ginf) {
   double* pa = c->red + RED_A * bl::kRedBlocks;
   double* pb = c->red + RED_B * bl::kRedBlocks;
   vec_dot_partial(c, gvec, gvec, pa);
-  bl::reduce_final(pa, bl::kRedBlocks, c->scal + S_GG, c->stream, c->hdev + S_GG);
   bl::maxabs_partial(gvec, n, pb, c->stream);
-  bl::reduce_max_final(pb, bl::kRedBlocks, c->scal + S_GINF, c->stream, c->hdev + S_GINF, c->flag,
-                       c->hdev + S_FLAG);
+  bl::reduce_final2(pa, c->scal + S_GG, c->hdev + S_GG, pb, c->scal + S_GINF, c->hdev + S_GINF,
+                    bl::kRedBlocks, c->stream, true, c->flag, c->hdev + S_FLAG);
   check_launch("gradient norms");
   sync(c);
   if (c->hscal[S_FLAG] != 0.0) {
@@ -1265,8 +1262,8 @@ void enqueue_precond(bl_ctx* c, int rz_slot) {
   double* pa = c->red + RED_A * bl::kRedBlocks;
   double* pb = c->red + RED_B * bl::kRedBlocks;
   bl::precond_dots(c->g, c->sr, c->Lhat, c->sz, pa, pb, c->stream);
-  bl::reduce_final(pa, bl::kRedBlocks, c->scal + S_RR, c->stream, c->hdev + S_RR);
-  bl::reduce_final(pb, bl::kRedBlocks, c->scal + rz_slot, c->stream);
+  bl::reduce_final2(pa, c->scal + S_RR, c->hdev + S_RR, pb, c->scal + rz_slot, nullptr,
+                    bl::kRedBlocks, c->stream);
 }
 
 double dev_sqdiff(bl_ctx* c, const float* a, const float* b) {
@@ -1321,6 +1318,7 @@ void solve(bl_ctx* c, const bl_solver_opts& o, bl_stats* st) {
   const int64_t nb = (int64_t)g.nodes * g.dim * g.B;
   double* pa = c->red + RED_A * bl::kRedBlocks;
   double* pb = c->red + RED_B * bl::kRedBlocks;
+  double* pc = c->red + RED_C * bl::kRedBlocks;
   const double den = dev_sqdiff(c, c->m, c->I1);  // |I0 - I1|^2
   auto mse = [&]() { return den > 0 ? 100.0 * c->data_sum / den : 0.0; };
 
@@ -1363,14 +1361,13 @@ void solve(bl_ctx* c, const bl_solver_opts& o, bl_stats* st) {
     for (int j = 0; j < o.max_pcg; ++j) {
       op_hessvec(c, c->sp, c->sHp);
       st->hessvecs += 1;
-      vec_dot_partial(c, c->sp, c->sHp, pa);
-      bl::reduce_final(pa, bl::kRedBlocks, c->scal + S_PHP, s, c->hdev + S_PHP);
-      // alpha = <r, z> / <p, Hp>, zero when <p, Hp> <= 0 (then neither vector moves);
+      vec_dot_partial(c, c->sp, c->sHp, pc);
+      // <p, Hp>, alpha = <r, z> / <p, Hp>, zero when <p, Hp> <= 0 (then neither vector moves);
       // delta, r, z = K r and the partials of <r, r>, <r, z> in one launch
-      bl::pcg_step(g, c->sp, c->sHp, c->scal + rz_cur, c->scal + S_PHP, c->sdelta, c->sr, c->Lhat,
-                   c->sz, pa, pb, s);
-      bl::reduce_final(pa, bl::kRedBlocks, c->scal + S_RR, s, c->hdev + S_RR);
-      bl::reduce_final(pb, bl::kRedBlocks, c->scal + rz_next, s);
+      bl::pcg_step(g, c->sp, c->sHp, c->scal + rz_cur, pc, c->scal + S_PHP, c->hdev + S_PHP,
+                   c->sdelta, c->sr, c->Lhat, c->sz, pa, pb, s);
+      bl::reduce_final2(pa, c->scal + S_RR, c->hdev + S_RR, pb, c->scal + rz_next, nullptr,
+                        bl::kRedBlocks, s);
       check_launch("pcg");
       sync(c);
       const double pHp = c->hscal[S_PHP];

@@ -37,6 +37,21 @@ __device__ __forceinline__ void block_max_store(double acc, double* __restrict__
 // memory, so the host reads it after a stream synchronisation without a separate copy.  With
 // `flag` not NULL the non-finite flag of the band kernels is published beside it as a double.
 template <bool MAX>
+__device__ __forceinline__ void reduce_block(const double* __restrict__ partial, int n,
+                                             double* __restrict__ out, double* __restrict__ host,
+                                             const int* __restrict__ flag,
+                                             double* __restrict__ host_flag) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc = MAX ? fmax(acc, partial[i]) : acc + partial[i];
+  const double r = block_reduce_256<MAX>(acc);
+  if (threadIdx.x == 0) {
+    out[0] = r;
+    if (host) host[0] = r;
+    if (flag) host_flag[0] = (double)flag[0];
+  }
+}
+
+template <bool MAX>
 __global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__ partial, int n,
                                                       double* __restrict__ out,
                                                       double* __restrict__ host,
@@ -48,14 +63,30 @@ __global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__
   BL_AT(partial, bt);
   BL_AT(out, bt);
   BL_AT(flag, bt);
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) acc = MAX ? fmax(acc, partial[i]) : acc + partial[i];
-  const double r = block_reduce_256<MAX>(acc);
-  if (threadIdx.x == 0) {
-    out[0] = r;
-    if (host) host[0] = r;
-    if (flag) host_flag[0] = (double)flag[0];
-  }
+  reduce_block<MAX>(partial, n, out, host, flag, host_flag);
+}
+
+// Two final passes in one launch: block 0 sums the partials pa, block 1 sums (MAXB: takes the
+// maximum of) the partials pb and publishes the flag; each exactly as k_reduce_final.
+template <bool MAXB>
+__global__ __launch_bounds__(256) void k_reduce_final2(const double* __restrict__ pa,
+                                                       double* __restrict__ outa,
+                                                       double* __restrict__ hosta,
+                                                       const double* __restrict__ pb,
+                                                       double* __restrict__ outb,
+                                                       double* __restrict__ hostb, int n,
+                                                       const int* __restrict__ flag,
+                                                       double* __restrict__ host_flag, Batch bt) {
+  BL_BATCH(bt)
+  BL_AT(pa, bt);
+  BL_AT(outa, bt);
+  BL_AT(pb, bt);
+  BL_AT(outb, bt);
+  BL_AT(flag, bt);
+  if (blockIdx.x == 0)
+    reduce_block<false>(pa, n, outa, hosta, nullptr, nullptr);
+  else
+    reduce_block<MAXB>(pb, n, outb, hostb, flag, host_flag);
 }
 
 // One PCG step after the product Hp, in one launch: alpha = rz / pHp (0 unless pHp > 0),
@@ -64,7 +95,9 @@ __global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__
 __global__ __launch_bounds__(256) void k_pcg_step(Geo g, const float2* __restrict__ p,
                                                   const float2* __restrict__ Hp,
                                                   const double* __restrict__ rz,
-                                                  const double* __restrict__ pHp,
+                                                  const double* __restrict__ php_part,
+                                                  double* __restrict__ pHp,
+                                                  double* __restrict__ pHp_host,
                                                   float2* __restrict__ delta,
                                                   float2* __restrict__ r,
                                                   const float* __restrict__ Lhat,
@@ -75,6 +108,7 @@ __global__ __launch_bounds__(256) void k_pcg_step(Geo g, const float2* __restric
   BL_AT(p, g.bat);
   BL_AT(Hp, g.bat);
   BL_AT(rz, g.bat);
+  BL_AT(php_part, g.bat);
   BL_AT(pHp, g.bat);
   BL_AT(delta, g.bat);
   BL_AT(r, g.bat);
@@ -83,7 +117,23 @@ __global__ __launch_bounds__(256) void k_pcg_step(Geo g, const float2* __restric
   BL_AT(p0, g.bat);
   BL_AT(p1, g.bat);
   const int64_t n = (int64_t)g.nodes * g.dim * g.B;
-  const double d = pHp[0];
+  // <p, Hp> from its kRedBlocks partials, summed by every block in the order of the final
+  // reduction pass; block 0 stores it
+  __shared__ double s_php;
+  {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < kRedBlocks; i += 256) acc += php_part[i];
+    const double t = block_reduce_256<false>(acc);
+    if (threadIdx.x == 0) {
+      s_php = t;
+      if (blockIdx.x == 0) {
+        pHp[0] = t;
+        if (pHp_host) pHp_host[0] = t;
+      }
+    }
+    __syncthreads();
+  }
+  const double d = s_php;
   const double alpha = d > 0.0 ? rz[0] / d : 0.0;
   const double nalpha = d > 0.0 ? -1.0 * (rz[0] / d) : 0.0;
   double rr = 0.0, rzn = 0.0;
@@ -329,11 +379,21 @@ void reduce_max_final(const double* partial, int n, double* out, hipStream_t s, 
   hipLaunchKernelGGL(k_reduce_final<true>, batch_grid(dim3(1), bt), dim3(256), 0, s, partial, n,
                      out, host, flag, host_flag, bt);
 }
+void reduce_final2(const double* pa, double* outa, double* hosta, const double* pb, double* outb,
+                   double* hostb, int n, hipStream_t s, bool max_b, const int* flag,
+                   double* host_flag, const Batch& bt) {
+  if (max_b)
+    hipLaunchKernelGGL(k_reduce_final2<true>, batch_grid(dim3(2), bt), dim3(256), 0, s, pa, outa,
+                       hosta, pb, outb, hostb, n, flag, host_flag, bt);
+  else
+    hipLaunchKernelGGL(k_reduce_final2<false>, batch_grid(dim3(2), bt), dim3(256), 0, s, pa, outa,
+                       hosta, pb, outb, hostb, n, flag, host_flag, bt);
+}
 void pcg_step(const Geo& g, const float2* p, const float2* Hp, const double* rz,
-              const double* pHp, float2* delta, float2* r, const float* Lhat, float2* z,
-              double* p0, double* p1, hipStream_t s) {
+              const double* php_part, double* pHp, double* pHp_host, float2* delta, float2* r,
+              const float* Lhat, float2* z, double* p0, double* p1, hipStream_t s) {
   hipLaunchKernelGGL(k_pcg_step, batch_grid(dim3(kRedBlocks), g.bat), dim3(256), 0, s, g, p, Hp,
-                     rz, pHp, delta, r, Lhat, z, p0, p1);
+                     rz, php_part, pHp, pHp_host, delta, r, Lhat, z, p0, p1);
 }
 void xpby_dev(float2* y, const float2* x, const double* num, const double* den, int64_t n,
               hipStream_t s, const Batch& bt) {
