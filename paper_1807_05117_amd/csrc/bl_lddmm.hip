@@ -535,15 +535,39 @@ LaunchEvents* take_launch_events() {
 }
 namespace host {
 
-// arm the next BL_LAUNCH on this thread with an event pair of the pool, counted for class cls
-void t_arm(bl_ctx* c, int cls) {
-  if (!c->timing || c->ev_next + 2 > c->ev_pool.size()) return;
+// arm the next BL_LAUNCH on this thread with an event pair of the pool, counted for class cls;
+// false when the pool is used up (the launch is then not timed)
+bool t_arm(bl_ctx* c, int cls) {
+  if (!c->timing || c->ev_next + 2 > c->ev_pool.size()) return false;
   bl::LaunchEvents& e = c->ev_pairs[c->ev_next / 2];
   e.start = c->ev_pool[c->ev_next];
   e.stop = c->ev_pool[c->ev_next + 1];
   bl::set_launch_events(&e);
   c->ev_used.push_back({cls, (int)c->ev_next, 1});
   c->ev_next += 2;
+  return true;
+}
+
+// f() with its first BL_LAUNCH timed for class cls while timing is on.  A pair that f did not
+// use (it threw first, or launched nothing through BL_LAUNCH) is disarmed and forgotten, so it
+// can neither time an unrelated later launch nor be read unrecorded.
+template <class F>
+void timed(bl_ctx* c, int cls, F&& f) {
+  if (!c->timing) {
+    f();
+    return;
+  }
+  struct Disarm {
+    bl_ctx* c;
+    bool armed;
+    ~Disarm() {
+      if (bl::take_launch_events() != nullptr && armed) {
+        c->ev_used.pop_back();
+        c->ev_next -= 2;
+      }
+    }
+  } d{c, t_arm(c, cls)};
+  f();
 }
 void t_collect(bl_ctx* c) {
   if (c->ev_used.empty()) return;
@@ -1034,14 +1058,11 @@ void enqueue_set_velocity(bl_ctx* c, const float2* vraw) {
   double* red_data = c->red + RED_DATA * bl::kRedBlocks;
   bl::band_prep(g, vraw, c->bv, 1, c->Lhat64, red_reg, s);
   bl::iota(g, c->plan, c->bv, g.dim + 1, c->V, s);
-  if (c->timing) t_arm(c, 6);
-  bl::setup(g, c->V, c->X, c->YA, s);
+  timed(c, 6, [&] { bl::setup(g, c->V, c->X, c->YA, s); });
   if (!c->tuned) choose_launch_shapes(c);
   const size_t M = (size_t)g.M;
-  for (int n = 0; n < g.nt; ++n) {
-    if (c->timing) t_arm(c, 0);
-    bl::state_step(g, c->m + n * M, c->X, c->m + (n + 1) * M, s);
-  }
+  for (int n = 0; n < g.nt; ++n)
+    timed(c, 0, [&] { bl::state_step(g, c->m + n * M, c->X, c->m + (n + 1) * M, s); });
   bl::energy_partial(g, c->m + g.nt * M, c->I1, red_data, s);
   bl::reduce_final2(red_reg, c->scal + S_REG, publish(c, S_REG), red_data, c->scal + S_DATA,
                     publish(c, S_DATA), bl::kRedBlocks, s, false, nullptr, nullptr, g.bat);
@@ -1101,12 +1122,9 @@ void backward_and_body_force(bl_ctx* c) {
   const bl::Geo& g = c->g;
   hipStream_t s = c->stream;
   const size_t M = (size_t)g.M;
-  for (int n = g.nt - 1; n >= 0; --n) {
-    if (c->timing) t_arm(c, 2);
-    bl::adj_step(g, c->L + (n + 1) * M, c->YA, c->L + n * M, s);
-  }
-  if (c->timing) t_arm(c, 5);
-  bl::body_force(g, c->L, c->m, c->Bf, s);
+  for (int n = g.nt - 1; n >= 0; --n)
+    timed(c, 2, [&] { bl::adj_step(g, c->L + (n + 1) * M, c->YA, c->L + n * M, s); });
+  timed(c, 5, [&] { bl::body_force(g, c->L, c->m, c->Bf, s); });
 }
 
 // gradient at the current velocity into gout (device, dim components)
@@ -1189,20 +1207,17 @@ void op_hessvec(bl_ctx* c, const float2* draw, float2* hout) {
   const size_t M = (size_t)g.M;
   bl::band_prep(g, draw, c->bd, 0, nullptr, nullptr, s);
   bl::iota_xy(g, c->plan, c->bd, g.dim, s);
-  if (c->timing) t_arm(c, 3);
-  bl::iota_z(g, c->plan, g.dim, c->DV, s);
+  timed(c, 3, [&] { bl::iota_z(g, c->plan, g.dim, c->DV, s); });
   bl::inc_init(g, c->m, c->DV, c->T0, s);
   float* tin = c->T0;
   float* tout = c->T1;
   for (int n = 0; n + 1 < g.nt; ++n) {
-    if (c->timing) t_arm(c, 1);
-    bl::inc_step(g, tin, c->X, c->m + (n + 1) * M, c->DV, tout, s);
+    timed(c, 1, [&] { bl::inc_step(g, tin, c->X, c->m + (n + 1) * M, c->DV, tout, s); });
     std::swap(tin, tout);
   }
   bl::inc_last(g, tin, c->X, c->m + g.nt * M, c->DV, c->L + g.nt * M, s);
   backward_and_body_force(c);
-  if (c->timing) t_arm(c, 4);
-  bl::pi_z(g, c->plan, c->Bf, g.dim, s);
+  timed(c, 4, [&] { bl::pi_z(g, c->plan, c->Bf, g.dim, s); });
   bl::pi_yx(g, c->plan, g.dim, c->P, s);
   bl::band_finalize(g, g.dim, c->bd, c->Lhat, c->P, (float)(1.0 / (double)g.M), hout, c->flag, s,
                     1);
