@@ -116,6 +116,7 @@ struct bl_ctx {
   // state of the last velocity
   bool have_v = false;
   bool have_lambda = false;   // L holds the adjoint lambda^n of the current velocity
+  bool lamT_valid = false;    // L[nt] holds lambda^Nt of the current velocity (with the energy)
   double E = 0, reg = 0, data_sum = 0;
   // solver vectors (dim * B complex each)
   float2 *sv = nullptr, *sg = nullptr, *sdelta = nullptr, *sr = nullptr, *sz = nullptr,

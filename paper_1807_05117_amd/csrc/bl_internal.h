@@ -210,8 +210,10 @@ void setup_ns(const Geo& g, const float* V, float* X, float4* YA, int steps, hip
 void body_nodes(const Geo& g, const float* lam, const float* m, float* b, int nodes,
                 hipStream_t s);
 void state_step(const Geo& g, const float* m_in, const float* X, float* m_out, hipStream_t s);
+// kRedBlocks partials of sum (mT - I1)^2 in FP64; with lam not NULL also the terminal adjoint
+// lam = lam_scale (mT - I1), the values terminal() writes
 void energy_partial(const Geo& g, const float* mT, const float* I1, double* partial,
-                    hipStream_t s);
+                    hipStream_t s, float* lam = nullptr);
 void terminal(const Geo& g, const float* mT, const float* I1, float* lam, hipStream_t s);
 void adj_step(const Geo& g, const float* lam_in, const float4* YA, float* lam_out,
               hipStream_t s);

@@ -898,6 +898,7 @@ void op_hessvec_ns(bl_ctx* c, const float2* draw, float2* hout) {
                c->DV + (size_t)g.nt * d * M, c->L + g.nt * M, s);
   backward_ns(c);
   c->have_lambda = false;   // L holds the incremental adjoint now
+  c->lamT_valid = false;
   per_node_outputs(c, c->bd, (size_t)d * B, hout);
   check_launch("hessvec (non-stationary)");
 }
@@ -1063,7 +1064,9 @@ void enqueue_set_velocity(bl_ctx* c, const float2* vraw) {
   const size_t M = (size_t)g.M;
   for (int n = 0; n < g.nt; ++n)
     timed(c, 0, [&] { bl::state_step(g, c->m + n * M, c->X, c->m + (n + 1) * M, s); });
-  bl::energy_partial(g, c->m + g.nt * M, c->I1, red_data, s);
+  // the energy's data term and, in the same pass, the terminal adjoint lambda^Nt into L[nt]
+  bl::energy_partial(g, c->m + g.nt * M, c->I1, red_data, s, c->L + g.nt * M);
+  c->lamT_valid = true;
   bl::reduce_final2(red_reg, c->scal + S_REG, publish(c, S_REG), red_data, c->scal + S_DATA,
                     publish(c, S_DATA), bl::kRedBlocks, s, false, nullptr, nullptr, g.bat);
   check_launch("set_velocity");
@@ -1071,6 +1074,7 @@ void enqueue_set_velocity(bl_ctx* c, const float2* vraw) {
 
 // setup + forward state + energy at the raw band vector `vraw` (device, dim components)
 void op_set_velocity(bl_ctx* c, const float2* vraw) {
+  c->lamT_valid = false;   // set again by the stationary energy pass, which writes lambda^Nt
   if (c->g.deform) {
     op_set_velocity_def(c, vraw);
     return;
@@ -1140,7 +1144,7 @@ void op_gradient(bl_ctx* c, float2* gout) {
   const bl::Geo& g = c->g;
   hipStream_t s = c->stream;
   const size_t M = (size_t)g.M;
-  bl::terminal(g, c->m + g.nt * M, c->I1, c->L + g.nt * M, s);
+  if (!c->lamT_valid) bl::terminal(g, c->m + g.nt * M, c->I1, c->L + g.nt * M, s);
   backward_and_body_force(c);
   c->have_lambda = true;
   bl::pi_half(g, c->plan, c->Bf, g.dim, c->P, s);
@@ -1216,6 +1220,7 @@ void op_hessvec(bl_ctx* c, const float2* draw, float2* hout) {
     std::swap(tin, tout);
   }
   bl::inc_last(g, tin, c->X, c->m + g.nt * M, c->DV, c->L + g.nt * M, s);
+  c->lamT_valid = false;   // L[nt] holds the incremental terminal adjoint now
   backward_and_body_force(c);
   timed(c, 4, [&] { bl::pi_z(g, c->plan, c->Bf, g.dim, s); });
   bl::pi_yx(g, c->plan, g.dim, c->P, s);

@@ -837,16 +837,21 @@ __global__ __launch_bounds__(BX* GBY) void k_body_node(Geo g, const float* __res
 // a fixed strided subset, then the fixed-order block reduction (wavefront shuffles).
 __global__ __launch_bounds__(256) void k_energy_partial(int64_t n, const float* __restrict__ a,
                                                         const float* __restrict__ b,
-                                                        double* __restrict__ partial, Batch bt) {
+                                                        double* __restrict__ partial,
+                                                        float* __restrict__ lam, float lam_scale,
+                                                        Batch bt) {
   BL_BATCH(bt)
   BL_AT(a, bt);
   BL_AT(b, bt);
   BL_AT(partial, bt);
+  BL_AT(lam, bt);
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * 256) {
-    const double d = (double)a[i] - (double)b[i];
+    const float ai = a[i], bi = b[i];
+    const double d = (double)ai - (double)bi;
     acc = fma(d, d, acc);
+    if (lam) lam[i] = lam_scale * (ai - bi);   // the terminal adjoint, as k_terminal forms it
   }
   const double r = block_reduce_256<false>(acc);
   if (threadIdx.x == 0) partial[blockIdx.x] = r;
@@ -953,9 +958,9 @@ void body_force_n(const Geo& g, const float* dlam, const float* m, const float* 
   DISPATCH_GATHER(k_body_force_n, TR_FORCE, g, dlam, m, lam, dm, b);
 }
 void energy_partial(const Geo& g, const float* mT, const float* I1, double* partial,
-                    hipStream_t s) {
+                    hipStream_t s, float* lam) {
   hipLaunchKernelGGL(k_energy_partial, batch_grid(dim3(kRedBlocks), g.bat), dim3(256), 0, s, g.M,
-                     mT, I1, partial, g.bat);
+                     mT, I1, partial, lam, g.lam_scale, g.bat);
 }
 void unpack4(const Geo& g, int comp, const float4* in, float* plane, hipStream_t s) {
   hipLaunchKernelGGL(k_unpack4, dim3((unsigned)((g.M + 255) / 256)), dim3(256), 0, s, g.M, comp,
