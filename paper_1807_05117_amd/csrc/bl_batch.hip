@@ -209,22 +209,22 @@ Cohort::Cohort(const bl_problem& prob, const Geo& g, int capacity)
 Cohort::~Cohort() { release(); }
 
 void Cohort::release() {
-  if (stream_) hipStreamSynchronize(stream_);
+  if (stream_) (void)hipStreamSynchronize(stream_);
   for (hipGraphExec_t& e : exec_)
-    if (e) hipGraphExecDestroy(e);
+    if (e) (void)hipGraphExecDestroy(e);
   exec_.clear();
   for (bl_ctx* c : ctx_) destroy_ctx(c);   // does not own the arena, stream or host scalars
   ctx_.clear();
-  for (double* h : hscal_) hipHostFree(h);
+  for (double* h : hscal_) (void)hipHostFree(h);
   hscal_.clear();
-  if (hin_) hipHostFree(hin_);
-  if (hout_) hipHostFree(hout_);
+  if (hin_) (void)hipHostFree(hin_);
+  if (hout_) (void)hipHostFree(hout_);
   hin_ = hout_ = nullptr;
-  if (arena_) hipFree(arena_);
+  if (arena_) (void)hipFree(arena_);
   arena_ = nullptr;
-  if (done_) hipEventDestroy(done_);
+  if (done_) (void)hipEventDestroy(done_);
   done_ = nullptr;
-  if (stream_) hipStreamDestroy(stream_);
+  if (stream_) (void)hipStreamDestroy(stream_);
   stream_ = nullptr;
 }
 
@@ -258,14 +258,14 @@ hipGraphExec_t Cohort::graph(int k) {
   try {
     enqueue_step(k);
   } catch (...) {
-    hipStreamEndCapture(stream_, &graph);
-    if (graph) hipGraphDestroy(graph);
+    (void)hipStreamEndCapture(stream_, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
     throw;
   }
   HIP_TRY(hipStreamEndCapture(stream_, &graph));
   hipGraphExec_t ex = nullptr;
   const hipError_t e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
-  hipGraphDestroy(graph);
+  (void)hipGraphDestroy(graph);
   if (e != hipSuccess) throw DeviceError{e, "hipGraphInstantiate (cohort step)"};
   exec_[k] = ex;
   return ex;

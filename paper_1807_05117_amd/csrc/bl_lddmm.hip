@@ -859,7 +859,7 @@ void backward_ns(bl_ctx* c) {
 void per_node_outputs(bl_ctx* c, const float2* vproj, size_t vstride, float2* out) {
   const bl::Geo& g = c->g;
   hipStream_t s = c->stream;
-  const size_t M = (size_t)g.M, B = (size_t)g.B;
+  const size_t B = (size_t)g.B;
   const int d = g.dim;
   bl::body_nodes(g, c->L, c->m, c->Bf, g.nt + 1, s);
   bl::pi_half(g, c->plan, c->Bf, (g.nt + 1) * d, c->P, s);
@@ -1476,7 +1476,7 @@ void free_idle(std::vector<bl_ctx*>& v) {
   const bool have_dev = hipGetDevice(&dev) == hipSuccess;
   for (bl_ctx* c : v) destroy_ctx(c);   // switches to each context's device
   v.clear();
-  if (have_dev) hipSetDevice(dev);
+  if (have_dev) (void)hipSetDevice(dev);
 }
 
 struct CachedCtx {

@@ -162,7 +162,7 @@ void run_request(bl_server* srv, Slot& slot, int slot_index, Request* r) {
 void release_slot_memory(bl_server* srv, Slot& slot) {
   destroy_ctx(slot.ctx);
   slot.ctx = nullptr;
-  if (slot.arena) hipFree(slot.arena);
+  if (slot.arena) (void)hipFree(slot.arena);
   slot.arena = nullptr;
   std::lock_guard<std::mutex> lk(srv->mu);
   srv->in_use -= slot.arena_bytes;
@@ -195,7 +195,7 @@ void admit_locked(bl_server* srv, Request* r, int slot_index) {
 // enough idle memory is returned.
 void worker(bl_server* srv, int index) {
   Slot& slot = srv->slots[index];
-  hipSetDevice(srv->device);
+  (void)hipSetDevice(srv->device);
   for (;;) {
     Request* r = nullptr;
     size_t need = 0;
@@ -232,7 +232,7 @@ void worker(bl_server* srv, int index) {
       // a larger arena: the old one (and its context) first, then exactly the footprint
       destroy_ctx(slot.ctx);
       slot.ctx = nullptr;
-      if (slot.arena) hipFree(slot.arena);
+      if (slot.arena) (void)hipFree(slot.arena);
       slot.arena = nullptr;
       if (hipMalloc(&slot.arena, need) != hipSuccess) {
         slot.arena = nullptr;
@@ -568,7 +568,7 @@ int pcg_per_step(const CohortEntry& ce) {
 }
 
 void scheduler(bl_server* srv, int max_pairs) {
-  hipSetDevice(srv->device);
+  (void)hipSetDevice(srv->device);
   for (;;) {
     {
       std::unique_lock<std::mutex> lk(srv->mu);
@@ -785,15 +785,15 @@ void bl_server_destroy(bl_server* srv) {
   for (auto& sl : srv->slots)
     if (sl.th.joinable()) sl.th.join();
   if (srv->sched.joinable()) srv->sched.join();
-  hipSetDevice(srv->device);
+  (void)hipSetDevice(srv->device);
   srv->cohorts.clear();
   for (auto& sl : srv->slots) {
-    if (sl.stream) hipStreamSynchronize(sl.stream);
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
     destroy_ctx(sl.ctx);   // does not own the arena, stream or host scalars
     sl.ctx = nullptr;
-    if (sl.arena) hipFree(sl.arena);
-    if (sl.hscal) hipHostFree(sl.hscal);
-    if (sl.stream) hipStreamDestroy(sl.stream);
+    if (sl.arena) (void)hipFree(sl.arena);
+    if (sl.hscal) (void)hipHostFree(sl.hscal);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
   }
   delete srv;
 }
