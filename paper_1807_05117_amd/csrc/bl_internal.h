@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <type_traits>
 
 namespace bl {
 
@@ -33,12 +34,13 @@ __device__ __forceinline__ int batch_bz(const Batch& b, int pair) {
 __device__ __forceinline__ bool batch_gated_off(const Batch& b, int pair) {
   return b.gate != nullptr && b.gate[(size_t)pair * b.gate_stride] == 0;
 }
-// problem pair's copy of a buffer of problem 0 (null stays null)
+// problem pair's copy of a buffer of problem 0 (null stays null).  Byte-pointer arithmetic,
+// not an integer round trip: the compiler then still knows the result points to global memory
+// (global and scalar loads; through an integer it can only use flat loads).
 template <class T>
 __device__ __forceinline__ T* batch_ptr(T* p, const Batch& b, int pair) {
-  if (p == nullptr || pair == 0) return p;
-  return reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) +
-                              (uintptr_t)((int64_t)pair * b.stride));
+  using Byte = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+  return p == nullptr ? p : reinterpret_cast<T*>(reinterpret_cast<Byte*>(p) + (int64_t)pair * b.stride);
 }
 inline dim3 batch_grid(dim3 d, const Batch& b) {
   d.z *= (unsigned)b.count;
