@@ -301,7 +301,7 @@ int bl_lddmm_ctx_launch_shapes(bl_ctx* ctx, int32_t zv_out[4]);
  * and the z-chunking of the FP32 iota z stage, all bitwise-invariant, by timing at the first
  * velocity of each (GPU architecture, grid, band, precision): every candidate is launched
  * once, then all are timed in turn three times over and each keeps its fastest round; another
- * shape must beat the default by 3%.  BL_TUNE_LOG=1 prints the times and choices to stderr.
+ * shape must beat the default by 5%.  BL_TUNE_LOG=1 prints the times and choices to stderr.
  * Choices are kept for the process and appended to a cache file read by later processes:
  * BL_TUNE_CACHE (a path, or "off"), else $XDG_CACHE_HOME/bl_lddmm/launch_shapes_v2.txt or
  * ~/.cache/bl_lddmm/launch_shapes_v2.txt.  BL_LAUNCH_SHAPES="s0,...,s6" fixes all classes
