@@ -256,7 +256,10 @@ constexpr int kNW = 8;
 constexpr int kZU = 16;
 
 template <int KZH>
-__global__ __launch_bounds__(64 * kNW) void k_pi_z(Geo g, const float* __restrict__ f,
+// (up to 16 stored kz planes: at least 6 wavefronts per SIMD, i.e. three blocks of 8 per compute
+// unit; unbounded, the compiler used 83 registers, two blocks fit and a 128^3 call took 15.3
+// instead of 12.7 us)
+__global__ __launch_bounds__(64 * kNW, KZH <= 16 ? 6 : 1) void k_pi_z(Geo g, const float* __restrict__ f,
                                                    const float2* __restrict__ tw_zT,
                                                    float2* __restrict__ G) {
   BL_BATCH(g.bat)
