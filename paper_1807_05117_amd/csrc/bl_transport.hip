@@ -845,13 +845,32 @@ __global__ __launch_bounds__(256) void k_energy_partial(int64_t n, const float* 
   BL_AT(b, bt);
   BL_AT(partial, bt);
   BL_AT(lam, bt);
+  // the thread's elements i, i + stride, ... in that order; kEU of them per round with all of
+  // the round's loads issued before its stores (a loop that loads and stores one element per
+  // iteration waits for each iteration's loads)
+  constexpr int kEU = 8;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * 256) {
+  for (; i + (kEU - 1) * stride < n; i += kEU * stride) {
+    float av[kEU], bv[kEU];
+#pragma unroll
+    for (int u = 0; u < kEU; ++u) {
+      av[u] = a[i + u * stride];
+      bv[u] = b[i + u * stride];
+    }
+#pragma unroll
+    for (int u = 0; u < kEU; ++u) {
+      const double d = (double)av[u] - (double)bv[u];
+      acc = fma(d, d, acc);
+      if (lam) lam[i + u * stride] = lam_scale * (av[u] - bv[u]);   // as k_terminal forms it
+    }
+  }
+  for (; i < n; i += stride) {
     const float ai = a[i], bi = b[i];
     const double d = (double)ai - (double)bi;
     acc = fma(d, d, acc);
-    if (lam) lam[i] = lam_scale * (ai - bi);   // the terminal adjoint, as k_terminal forms it
+    if (lam) lam[i] = lam_scale * (ai - bi);
   }
   const double r = block_reduce_256<false>(acc);
   if (threadIdx.x == 0) partial[blockIdx.x] = r;
