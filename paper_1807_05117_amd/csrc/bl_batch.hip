@@ -321,10 +321,11 @@ void Cohort::enqueue_step(int k_pcg) {
   // PCG iterations
   for (int j = 0; j < k_pcg; ++j) {
     b = use(&ctl0->g_pcg);
-    op_hessvec(c, c->sp, c->sHp);
-    vec_dot_partial(c, c->sp, c->sHp, pc);
-    bl::pcg_step(c->g, c->sp, c->sHp, c->scal + S_RZ0, pc, c->scal + S_PHP, nullptr, c->sdelta,
-                 c->sr, c->Lhat, c->sz, pa, pb, s);
+    const bool fused = op_hessvec(c, c->sp, c->sHp, pc);
+    if (!fused) vec_dot_partial(c, c->sp, c->sHp, pc);
+    bl::pcg_step(c->g, c->sp, c->sHp, c->scal + S_RZ0, pc,
+                 fused ? bl::finalize_blocks(c->g) : bl::kRedBlocks, c->scal + S_PHP, nullptr,
+                 c->sdelta, c->sr, c->Lhat, c->sz, pa, pb, s);
     bl::reduce_final2(pa, c->scal + S_RR, nullptr, pb, c->scal + S_RZ1, nullptr, bl::kRedBlocks,
                       s, false, nullptr, nullptr, b);
     hipLaunchKernelGGL(k_ctl_pcg, one, lanes, 0, s, scal0, st, cap_);

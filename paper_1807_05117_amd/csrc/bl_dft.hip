@@ -549,13 +549,18 @@ __global__ __launch_bounds__(256) void k_band_finalize(Geo g,
                                                        float scale, float2* __restrict__ out,
                                                        int* __restrict__ nonfinite, int leray_on,
                                                        size_t vstride, size_t pstride,
-                                                       size_t ostride) {
+                                                       size_t ostride,
+                                                       const float2* __restrict__ dotp,
+                                                       double* __restrict__ dot_part) {
   BL_BATCH(g.bat)
   BL_AT(vproj, g.bat);
   BL_AT(Lhat, g.bat);
   BL_AT(P, g.bat);
   BL_AT(out, g.bat);
   BL_AT(nonfinite, g.bat);
+  BL_AT(dotp, g.bat);
+  BL_AT(dot_part, g.bat);
+  double dacc = 0.0;
   const int B = (int)g.B;
   if (vproj) vproj += blockIdx.y * vstride;   // node blockIdx.y
   P += blockIdx.y * pstride;
@@ -614,6 +619,18 @@ __global__ __launch_bounds__(256) void k_band_finalize(Geo g,
       out[c * B + b] = o[c];
     }
     if (bad) *nonfinite = 1;
+    if (dot_part) {   // Re conj(dotp) o, the components of this band index in order
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const float2 d = dotp[c * B + b];
+        dacc = fma((double)d.x, (double)o[c].x, dacc);
+        dacc = fma((double)d.y, (double)o[c].y, dacc);
+      }
+    }
+  }
+  if (dot_part) {   // the whole block (a kernel argument decides)
+    const double r = block_reduce_256<false>(dacc);
+    if (threadIdx.x == 0) dot_part[blockIdx.x] = r;
   }
 }
 
@@ -746,22 +763,19 @@ void band_prep_nodes(const Geo& g, const float2* raw, float2* out, int nodes, si
                        1.0, 0, stride);
 }
 
-void band_finalize(const Geo& g, int C, const float2* vproj, const float* Lhat,
-                   const float2* P, float scale, float2* out, int* nonfinite, hipStream_t s,
-                   int leray) {
-  band_finalize_nodes(g, C, vproj, 0, Lhat, P, 0, scale, out, 0, 1, nonfinite, s, leray);
-}
+int finalize_blocks(const Geo& g) { return (int)std::min<int64_t>(kRedBlocks, (g.B + 255) / 256); }
 
-void band_finalize_nodes(const Geo& g, int C, const float2* vproj, size_t vstride,
-                         const float* Lhat, const float2* P, size_t pstride, float scale,
-                         float2* out, size_t ostride, int nodes, int* nonfinite, hipStream_t s,
-                         int leray) {
-  const dim3 blocks((unsigned)std::min(4096, (int)((g.B + 255) / 256)), (unsigned)nodes);
+namespace {
+void finalize_launch(const Geo& g, int C, const float2* vproj, size_t vstride, const float* Lhat,
+                     const float2* P, size_t pstride, float scale, float2* out, size_t ostride,
+                     int nodes, int* nonfinite, hipStream_t s, int leray, const float2* dotp,
+                     double* dot_part) {
+  const dim3 blocks((unsigned)finalize_blocks(g), (unsigned)nodes);
   const int on = (leray && g.gamma && C == g.dim) ? 1 : 0;
 #define BF_LAUNCH(D, CC)                                                                        \
   hipLaunchKernelGGL((k_band_finalize<D, CC>), batch_grid(blocks, g.bat), dim3(256), 0, s, g,     \
                      vproj, Lhat, P,                                                            \
-                     scale, out, nonfinite, on, vstride, pstride, ostride)
+                     scale, out, nonfinite, on, vstride, pstride, ostride, dotp, dot_part)
   if (g.dim == 3) {
     switch (C) {
       case 1: BF_LAUNCH(3, 1); break;
@@ -778,6 +792,22 @@ void band_finalize_nodes(const Geo& g, int C, const float2* vproj, size_t vstrid
     }
   }
 #undef BF_LAUNCH
+}
+}  // namespace
+
+void band_finalize(const Geo& g, int C, const float2* vproj, const float* Lhat,
+                   const float2* P, float scale, float2* out, int* nonfinite, hipStream_t s,
+                   int leray, const float2* dotp, double* dot_part) {
+  finalize_launch(g, C, vproj, 0, Lhat, P, 0, scale, out, 0, 1, nonfinite, s, leray, dotp,
+                  dot_part);
+}
+
+void band_finalize_nodes(const Geo& g, int C, const float2* vproj, size_t vstride,
+                         const float* Lhat, const float2* P, size_t pstride, float scale,
+                         float2* out, size_t ostride, int nodes, int* nonfinite, hipStream_t s,
+                         int leray) {
+  finalize_launch(g, C, vproj, vstride, Lhat, P, pstride, scale, out, ostride, nodes, nonfinite, s,
+                  leray, nullptr, nullptr);
 }
 
 }  // namespace bl

@@ -165,7 +165,9 @@ void enqueue_set_velocity(bl_ctx* c, const float2* vraw);   // stationary state 
 void op_set_velocity(bl_ctx* c, const float2* vraw);        // enqueue, synchronise, read E
 void finish_set_velocity(bl_ctx* c);   // E from the published sums (after a sync)
 void op_gradient(bl_ctx* c, float2* gout);
-void op_hessvec(bl_ctx* c, const float2* draw, float2* hout);
+// H draw into hout; with dot_part not NULL, also the finalize_blocks partials of <draw, hout>
+// where the product's last kernel can form them (returns true then; false: not formed)
+bool op_hessvec(bl_ctx* c, const float2* draw, float2* hout, double* dot_part = nullptr);
 void vec_dot_partial(bl_ctx* c, const float2* a, const float2* b, double* pa);
 void choose_launch_shapes(bl_ctx* c);
 // the launch shapes chosen earlier in the process for this grid shape, else the defaults;

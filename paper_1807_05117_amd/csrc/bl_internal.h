@@ -191,9 +191,14 @@ void band_prep_nodes(const Geo& g, const float2* raw, float2* out, int nodes, si
                      hipStream_t s);
 // out[c][k] = Lhat(k) vproj[c][k] + scale * P (Hermitian-completed), zero on unpaired planes;
 // leray (C == dim): then projected divergence-free per index k.
+// With dot_part not NULL (one node), also the finalize_blocks(g) block partials of
+// Re sum conj(dotp) out over all C components (each thread sums its band index's components in
+// order, then its block in the fixed order of block_reduce_256).
 void band_finalize(const Geo& g, int C, const float2* vproj, const float* Lhat,
                    const float2* P, float scale, float2* out, int* nonfinite, hipStream_t s,
-                   int leray = 0);
+                   int leray = 0, const float2* dotp = nullptr, double* dot_part = nullptr);
+// blocks of a band_finalize launch (at most kRedBlocks)
+int finalize_blocks(const Geo& g);
 // band_finalize of `nodes` vectors in one launch: node n reads vproj + n vstride and
 // P + n pstride and writes out + n ostride
 void band_finalize_nodes(const Geo& g, int C, const float2* vproj, size_t vstride,
@@ -340,13 +345,13 @@ void add_scaled_dev(float2* y, const float2* x, const float2* d, const double* e
                     hipStream_t s, const Batch& bt = Batch{});
 // y = x + beta y
 void xpby(float2* y, const float2* x, double beta, int64_t n, hipStream_t s);
-// one PCG step: pHp = <p, Hp> from its kRedBlocks partials php_part (the same value as
-// reduce_final of them; stored to pHp[0] and, when not NULL, host-mapped pHp_host[0]),
+// one PCG step: pHp = <p, Hp> from its nphp partials php_part (the same value as reduce_final
+// of them; stored to pHp[0] and, when not NULL, host-mapped pHp_host[0]),
 // alpha = rz / pHp (0 unless pHp > 0), delta += alpha p, r -= alpha Hp, z = r / Lhat,
 // kRedBlocks partials of <r, r> (p0) and <r, z> (p1); php_part must not alias p0 or p1
 void pcg_step(const Geo& g, const float2* p, const float2* Hp, const double* rz,
-              const double* php_part, double* pHp, double* pHp_host, float2* delta, float2* r,
-              const float* Lhat, float2* z, double* p0, double* p1, hipStream_t s);
+              const double* php_part, int nphp, double* pHp, double* pHp_host, float2* delta,
+              float2* r, const float* Lhat, float2* z, double* p0, double* p1, hipStream_t s);
 // y = x + (num[0] / den[0]) y with device scalars
 void xpby_dev(float2* y, const float2* x, const double* num, const double* den, int64_t n,
               hipStream_t s, const Batch& bt = Batch{});

@@ -1159,7 +1159,7 @@ void op_gradient(bl_ctx* c, float2* gout) {
 // Full Newton Hessian-vector product: the Gauss-Newton one plus the incremental adjoint's
 // source div(lambda dv) and pi(sum w_n lambda^n grad dm^n); lambda^n (kept in L) comes from the
 // gradient at this velocity, or is computed here if no gradient was taken.
-void op_hessvec_newton(bl_ctx* c, const float2* draw, float2* hout) {
+void op_hessvec_newton(bl_ctx* c, const float2* draw, float2* hout, double* dot_part) {
   const bl::Geo& g = c->g;
   hipStream_t s = c->stream;
   const size_t M = (size_t)g.M;
@@ -1191,23 +1191,23 @@ void op_hessvec_newton(bl_ctx* c, const float2* draw, float2* hout) {
   bl::body_force_n(g, c->DL, c->m, c->L, c->DM, c->Bf, s);
   bl::pi_half(g, c->plan, c->Bf, g.dim, c->P, s);
   bl::band_finalize(g, g.dim, c->bd, c->Lhat, c->P, (float)(1.0 / (double)g.M), hout, c->flag, s,
-                    1);
+                    1, draw, dot_part);
   check_launch("hessvec (Newton)");
 }
 
 // Gauss-Newton Hessian-vector product of the raw direction draw into hout
-void op_hessvec(bl_ctx* c, const float2* draw, float2* hout) {
+bool op_hessvec(bl_ctx* c, const float2* draw, float2* hout, double* dot_part) {
   if (c->g.deform) {
     op_hessvec_def(c, draw, hout);
-    return;
+    return false;
   }
   if (c->g.nodes > 1) {
     op_hessvec_ns(c, draw, hout);
-    return;
+    return false;
   }
   if (c->g.newton) {
-    op_hessvec_newton(c, draw, hout);
-    return;
+    op_hessvec_newton(c, draw, hout, dot_part);
+    return dot_part != nullptr;
   }
   const bl::Geo& g = c->g;
   hipStream_t s = c->stream;
@@ -1228,8 +1228,9 @@ void op_hessvec(bl_ctx* c, const float2* draw, float2* hout) {
   timed(c, 4, [&] { bl::pi_z(g, c->plan, c->Bf, g.dim, s); });
   bl::pi_yx(g, c->plan, g.dim, c->P, s);
   bl::band_finalize(g, g.dim, c->bd, c->Lhat, c->P, (float)(1.0 / (double)g.M), hout, c->flag, s,
-                    1);
+                    1, draw, dot_part);
   check_launch("hessvec");
+  return dot_part != nullptr;
 }
 
 void check_flag(bl_ctx* c, const char* what) {
@@ -1382,13 +1383,15 @@ void solve(bl_ctx* c, const bl_solver_opts& o, bl_stats* st) {
     HIP_TRY(hipMemcpyAsync(c->sp, c->sz, nb * sizeof(float2), hipMemcpyDeviceToDevice, s));
     int iters = 0;
     for (int j = 0; j < o.max_pcg; ++j) {
-      op_hessvec(c, c->sp, c->sHp);
+      // the partials of <p, Hp> come with the product's last kernel where it can form them
+      const bool fused = op_hessvec(c, c->sp, c->sHp, pc);
       st->hessvecs += 1;
-      vec_dot_partial(c, c->sp, c->sHp, pc);
+      if (!fused) vec_dot_partial(c, c->sp, c->sHp, pc);
       // <p, Hp>, alpha = <r, z> / <p, Hp>, zero when <p, Hp> <= 0 (then neither vector moves);
       // delta, r, z = K r and the partials of <r, r>, <r, z> in one launch
-      bl::pcg_step(g, c->sp, c->sHp, c->scal + rz_cur, pc, c->scal + S_PHP, c->hdev + S_PHP,
-                   c->sdelta, c->sr, c->Lhat, c->sz, pa, pb, s);
+      bl::pcg_step(g, c->sp, c->sHp, c->scal + rz_cur, pc,
+                   fused ? bl::finalize_blocks(g) : bl::kRedBlocks, c->scal + S_PHP,
+                   c->hdev + S_PHP, c->sdelta, c->sr, c->Lhat, c->sz, pa, pb, s);
       bl::reduce_final2(pa, c->scal + S_RR, c->hdev + S_RR, pb, c->scal + rz_next, nullptr,
                         bl::kRedBlocks, s);
       check_launch("pcg");

@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void k_pcg_step(Geo g, const float2* __restric
                                                   const float2* __restrict__ Hp,
                                                   const double* __restrict__ rz,
                                                   const double* __restrict__ php_part,
-                                                  double* __restrict__ pHp,
+                                                  int nphp, double* __restrict__ pHp,
                                                   double* __restrict__ pHp_host,
                                                   float2* __restrict__ delta,
                                                   float2* __restrict__ r,
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void k_pcg_step(Geo g, const float2* __restric
   __shared__ double s_php;
   {
     double acc = 0.0;
-    for (int i = threadIdx.x; i < kRedBlocks; i += 256) acc += php_part[i];
+    for (int i = threadIdx.x; i < nphp; i += 256) acc += php_part[i];
     const double t = block_reduce_256<false>(acc);
     if (threadIdx.x == 0) {
       s_php = t;
@@ -390,10 +390,10 @@ void reduce_final2(const double* pa, double* outa, double* hosta, const double* 
                        hosta, pb, outb, hostb, n, flag, host_flag, bt);
 }
 void pcg_step(const Geo& g, const float2* p, const float2* Hp, const double* rz,
-              const double* php_part, double* pHp, double* pHp_host, float2* delta, float2* r,
-              const float* Lhat, float2* z, double* p0, double* p1, hipStream_t s) {
+              const double* php_part, int nphp, double* pHp, double* pHp_host, float2* delta,
+              float2* r, const float* Lhat, float2* z, double* p0, double* p1, hipStream_t s) {
   hipLaunchKernelGGL(k_pcg_step, batch_grid(dim3(kRedBlocks), g.bat), dim3(256), 0, s, g, p, Hp,
-                     rz, php_part, pHp, pHp_host, delta, r, Lhat, z, p0, p1);
+                     rz, php_part, nphp, pHp, pHp_host, delta, r, Lhat, z, p0, p1);
 }
 void xpby_dev(float2* y, const float2* x, const double* num, const double* den, int64_t n,
               hipStream_t s, const Batch& bt) {
