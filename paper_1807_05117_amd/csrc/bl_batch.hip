@@ -352,11 +352,14 @@ void Cohort::enqueue_step(int k_pcg) {
   // accepted: v = projected trial, gradient and its norms
   b = use(&ctl0->g_grad);
   bl::copy_band(c->sv, c->bv, nb, s, b);
-  op_gradient(c, c->sg);
-  vec_dot_partial(c, c->sg, c->sg, pa);
-  bl::maxabs_partial(c->sg, nb, pb, s, b);
-  bl::reduce_final2(pa, c->scal + S_GG, nullptr, pb, c->scal + S_GINF, nullptr, bl::kRedBlocks, s,
-                    true, nullptr, nullptr, b);
+  const bool norms = op_gradient(c, c->sg, pa, pb);   // with the partials of its norms
+  if (!norms) {
+    vec_dot_partial(c, c->sg, c->sg, pa);
+    bl::maxabs_partial(c->sg, nb, pb, s, b);
+  }
+  bl::reduce_final2(pa, c->scal + S_GG, nullptr, pb, c->scal + S_GINF, nullptr,
+                    norms ? bl::finalize_blocks(c->g) : bl::kRedBlocks, s, true, nullptr, nullptr,
+                    b);
   hipLaunchKernelGGL(k_ctl_grad, one, lanes, 0, s, scal0, st, cap_,
                      reinterpret_cast<char*>(c->flag));
 

@@ -551,7 +551,9 @@ __global__ __launch_bounds__(256) void k_band_finalize(Geo g,
                                                        size_t vstride, size_t pstride,
                                                        size_t ostride,
                                                        const float2* __restrict__ dotp,
-                                                       double* __restrict__ dot_part) {
+                                                       double* __restrict__ dot_part,
+                                                       double* __restrict__ sq_part,
+                                                       double* __restrict__ max_part) {
   BL_BATCH(g.bat)
   BL_AT(vproj, g.bat);
   BL_AT(Lhat, g.bat);
@@ -560,7 +562,9 @@ __global__ __launch_bounds__(256) void k_band_finalize(Geo g,
   BL_AT(nonfinite, g.bat);
   BL_AT(dotp, g.bat);
   BL_AT(dot_part, g.bat);
-  double dacc = 0.0;
+  BL_AT(sq_part, g.bat);
+  BL_AT(max_part, g.bat);
+  double dacc = 0.0, sacc = 0.0, macc = 0.0;
   const int B = (int)g.B;
   if (vproj) vproj += blockIdx.y * vstride;   // node blockIdx.y
   P += blockIdx.y * pstride;
@@ -627,10 +631,25 @@ __global__ __launch_bounds__(256) void k_band_finalize(Geo g,
         dacc = fma((double)d.y, (double)o[c].y, dacc);
       }
     }
+    if (sq_part) {   // |o|^2 and max |o| (the gradient's norms)
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        sacc = fma((double)o[c].x, (double)o[c].x, sacc);
+        sacc = fma((double)o[c].y, (double)o[c].y, sacc);
+        macc = fmax(macc, sqrt((double)o[c].x * o[c].x + (double)o[c].y * o[c].y));
+      }
+    }
   }
-  if (dot_part) {   // the whole block (a kernel argument decides)
+  // (the whole block takes these branches: kernel arguments decide)
+  if (dot_part) {
     const double r = block_reduce_256<false>(dacc);
     if (threadIdx.x == 0) dot_part[blockIdx.x] = r;
+  }
+  if (sq_part) {
+    const double r = block_reduce_256<false>(sacc);
+    if (threadIdx.x == 0) sq_part[blockIdx.x] = r;
+    const double m = block_reduce_256<true>(macc);
+    if (threadIdx.x == 0) max_part[blockIdx.x] = m;
   }
 }
 
@@ -769,13 +788,14 @@ namespace {
 void finalize_launch(const Geo& g, int C, const float2* vproj, size_t vstride, const float* Lhat,
                      const float2* P, size_t pstride, float scale, float2* out, size_t ostride,
                      int nodes, int* nonfinite, hipStream_t s, int leray, const float2* dotp,
-                     double* dot_part) {
+                     double* dot_part, double* sq_part, double* max_part) {
   const dim3 blocks((unsigned)finalize_blocks(g), (unsigned)nodes);
   const int on = (leray && g.gamma && C == g.dim) ? 1 : 0;
 #define BF_LAUNCH(D, CC)                                                                        \
   hipLaunchKernelGGL((k_band_finalize<D, CC>), batch_grid(blocks, g.bat), dim3(256), 0, s, g,     \
                      vproj, Lhat, P,                                                            \
-                     scale, out, nonfinite, on, vstride, pstride, ostride, dotp, dot_part)
+                     scale, out, nonfinite, on, vstride, pstride, ostride, dotp, dot_part,     \
+                     sq_part, max_part)
   if (g.dim == 3) {
     switch (C) {
       case 1: BF_LAUNCH(3, 1); break;
@@ -797,9 +817,10 @@ void finalize_launch(const Geo& g, int C, const float2* vproj, size_t vstride, c
 
 void band_finalize(const Geo& g, int C, const float2* vproj, const float* Lhat,
                    const float2* P, float scale, float2* out, int* nonfinite, hipStream_t s,
-                   int leray, const float2* dotp, double* dot_part) {
+                   int leray, const float2* dotp, double* dot_part, double* sq_part,
+                   double* max_part) {
   finalize_launch(g, C, vproj, 0, Lhat, P, 0, scale, out, 0, 1, nonfinite, s, leray, dotp,
-                  dot_part);
+                  dot_part, sq_part, max_part);
 }
 
 void band_finalize_nodes(const Geo& g, int C, const float2* vproj, size_t vstride,
@@ -807,7 +828,7 @@ void band_finalize_nodes(const Geo& g, int C, const float2* vproj, size_t vstrid
                          float2* out, size_t ostride, int nodes, int* nonfinite, hipStream_t s,
                          int leray) {
   finalize_launch(g, C, vproj, vstride, Lhat, P, pstride, scale, out, ostride, nodes, nonfinite, s,
-                  leray, nullptr, nullptr);
+                  leray, nullptr, nullptr, nullptr, nullptr);
 }
 
 }  // namespace bl

@@ -164,7 +164,9 @@ void solve(bl_ctx* c, const bl_solver_opts& o, bl_stats* st);
 void enqueue_set_velocity(bl_ctx* c, const float2* vraw);   // stationary state equation only
 void op_set_velocity(bl_ctx* c, const float2* vraw);        // enqueue, synchronise, read E
 void finish_set_velocity(bl_ctx* c);   // E from the published sums (after a sync)
-void op_gradient(bl_ctx* c, float2* gout);
+// gradient into gout; with sq_part / max_part not NULL, also the finalize_blocks partials of
+// |g|^2 and max |g| where the last kernel can form them (returns true then)
+bool op_gradient(bl_ctx* c, float2* gout, double* sq_part = nullptr, double* max_part = nullptr);
 // H draw into hout; with dot_part not NULL, also the finalize_blocks partials of <draw, hout>
 // where the product's last kernel can form them (returns true then; false: not formed)
 bool op_hessvec(bl_ctx* c, const float2* draw, float2* hout, double* dot_part = nullptr);

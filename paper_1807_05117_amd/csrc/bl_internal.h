@@ -193,10 +193,12 @@ void band_prep_nodes(const Geo& g, const float2* raw, float2* out, int nodes, si
 // leray (C == dim): then projected divergence-free per index k.
 // With dot_part not NULL (one node), also the finalize_blocks(g) block partials of
 // Re sum conj(dotp) out over all C components (each thread sums its band index's components in
-// order, then its block in the fixed order of block_reduce_256).
+// order, then its block in the fixed order of block_reduce_256); with sq_part and max_part not
+// NULL likewise the partials of sum |out|^2 and of max |out|.
 void band_finalize(const Geo& g, int C, const float2* vproj, const float* Lhat,
                    const float2* P, float scale, float2* out, int* nonfinite, hipStream_t s,
-                   int leray = 0, const float2* dotp = nullptr, double* dot_part = nullptr);
+                   int leray = 0, const float2* dotp = nullptr, double* dot_part = nullptr,
+                   double* sq_part = nullptr, double* max_part = nullptr);
 // blocks of a band_finalize launch (at most kRedBlocks)
 int finalize_blocks(const Geo& g);
 // band_finalize of `nodes` vectors in one launch: node n reads vproj + n vstride and

@@ -1135,14 +1135,14 @@ void backward_and_body_force(bl_ctx* c) {
 }
 
 // gradient at the current velocity into gout (device, dim components)
-void op_gradient(bl_ctx* c, float2* gout) {
+bool op_gradient(bl_ctx* c, float2* gout, double* sq_part, double* max_part) {
   if (c->g.deform) {
     op_gradient_def(c, gout);
-    return;
+    return false;
   }
   if (c->g.nodes > 1) {
     op_gradient_ns(c, gout);
-    return;
+    return false;
   }
   const bl::Geo& g = c->g;
   hipStream_t s = c->stream;
@@ -1152,8 +1152,9 @@ void op_gradient(bl_ctx* c, float2* gout) {
   c->have_lambda = true;
   bl::pi_half(g, c->plan, c->Bf, g.dim, c->P, s);
   bl::band_finalize(g, g.dim, c->bv, c->Lhat, c->P, (float)(1.0 / (double)g.M), gout, c->flag, s,
-                    1);
+                    1, nullptr, nullptr, sq_part, max_part);
   check_launch("gradient");
+  return sq_part != nullptr && max_part != nullptr;
 }
 
 // Full Newton Hessian-vector product: the Gauss-Newton one plus the incremental adjoint's
@@ -1262,14 +1263,19 @@ void copy_projected_velocity(bl_ctx* c, float2* dst) {
                            band_bytes(g) * g.dim, hipMemcpyDeviceToDevice, c->stream));
 }
 
-void grad_stats(bl_ctx* c, const float2* gvec, double* gg, double* ginf) {
+// |g|^2 and max |g| of gvec (published) with the non-finite flag; have_partials: the gradient's
+// band finalisation already wrote their partials to RED_A / RED_B
+void grad_stats(bl_ctx* c, const float2* gvec, double* gg, double* ginf, bool have_partials) {
   const int64_t n = (int64_t)c->g.nodes * c->g.dim * c->g.B;
   double* pa = c->red + RED_A * bl::kRedBlocks;
   double* pb = c->red + RED_B * bl::kRedBlocks;
-  vec_dot_partial(c, gvec, gvec, pa);
-  bl::maxabs_partial(gvec, n, pb, c->stream);
+  if (!have_partials) {
+    vec_dot_partial(c, gvec, gvec, pa);
+    bl::maxabs_partial(gvec, n, pb, c->stream);
+  }
   bl::reduce_final2(pa, c->scal + S_GG, c->hdev + S_GG, pb, c->scal + S_GINF, c->hdev + S_GINF,
-                    bl::kRedBlocks, c->stream, true, c->flag, c->hdev + S_FLAG);
+                    have_partials ? bl::finalize_blocks(c->g) : bl::kRedBlocks, c->stream, true,
+                    c->flag, c->hdev + S_FLAG);
   check_launch("gradient norms");
   sync(c);
   if (c->hscal[S_FLAG] != 0.0) {
@@ -1348,9 +1354,8 @@ void solve(bl_ctx* c, const bl_solver_opts& o, bl_stats* st) {
 
   op_set_velocity(c, c->sv);
   copy_projected_velocity(c, c->sv);
-  op_gradient(c, c->sg);
   double gg, ginf0;
-  grad_stats(c, c->sg, &gg, &ginf0);
+  grad_stats(c, c->sg, &gg, &ginf0, op_gradient(c, c->sg, pa, pb));
   double E = c->E;
   const double g0n = std::sqrt(std::max(gg, 0.0));
   st->E[0] = E;
@@ -1440,8 +1445,7 @@ void solve(bl_ctx* c, const bl_solver_opts& o, bl_stats* st) {
     st->eps[it] = eps;
     copy_projected_velocity(c, c->sv);
     E = c->E;
-    op_gradient(c, c->sg);
-    grad_stats(c, c->sg, &gg, &ginf);
+    grad_stats(c, c->sg, &gg, &ginf, op_gradient(c, c->sg, pa, pb));
     st->gradients += 1;
     st->gn_iters += 1;
     st->E[st->gn_iters] = E;
