@@ -28,6 +28,16 @@ CASES = {
     # a strongly anisotropic band (2 x 66 x 4): the deformation method's fused yx kernels then
     # give each thread two band entries (ky * 4 > 256), within their LDS limits
     "aniso_band_3d": (3, (8, 72, 12), (2, 66, 4), 4, 1.0, 3),
+    # degenerate cases of the method: one time step (no incremental steps between the first
+    # and the last), the full band k = n (the unpaired Nyquist planes are the only ones
+    # dropped), the smallest band k = 2 (one frequency pair per axis, of which only the zero
+    # frequency survives the projection), and the smallest grids the library accepts
+    "nt1_3d": (3, (24, 20, 12), (8, 8, 4), 1, 1.0, 3),
+    "fullband_2d": (2, (16, 16), (16, 16), 4, 1.0, 0),
+    "fullband_3d": (3, (12, 10, 8), (12, 10, 8), 2, 0.5, 3),
+    "minband_3d": (3, (16, 12, 10), (2, 2, 2), 3, 0.5, 3),
+    "tiny_3d": (3, (8, 8, 8), (4, 4, 4), 2, 0.5, 3),
+    "min_grid_2d": (2, (4, 4), (4, 4), 2, 0.5, 0),
 }
 # regulariser and flow model per case (default alpha = 1e-3, s = 2, gamma = 0)
 MODEL = {
