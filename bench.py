@@ -196,11 +196,13 @@ def gpu_leg(steps, warmup, n_hv=200, n_lat=50, n_grad=20, precision=B.BL_FP32, i
         n, ms = ctx.bl_kernel_timing_read(k)
         kern[k] = (n, ms)
     ctx.bl_kernel_timing_enable(False)
+    shapes = dict(zip(("state", "incremental", "adjoint", "body_force"),
+                      ctx.bl_lddmm_ctx_launch_shapes()))
     ctx.close()
     if precision != B.BL_FP32 or model or size:
         return dict(elapsed=elapsed, lat=lat, stats=stats, hv_s=hv_s, hv_lat=hv_lat,
-                    grad_s=grad_s, kern=kern, E=E, inputs=(I0, I1, vs), warped=warped,
-                    t_host=t_host)
+                    grad_s=grad_s, kern=kern, shapes=shapes, E=E, inputs=(I0, I1, vs),
+                    warped=warped, t_host=t_host)
     # achievable HBM bandwidth: a plain 1 GiB device-to-device copy (also the reference
     # kernel for scaling the FETCH_SIZE / WRITE_SIZE counters)
     src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -228,7 +230,7 @@ def gpu_leg(steps, warmup, n_hv=200, n_lat=50, n_grad=20, precision=B.BL_FP32, i
     rmw_gbs = 10 * 2 * dst.numel() * 4 / (e0.elapsed_time(e1) / 1000.0) / 1e9
     del src, dst
     return dict(copy_gbs=copy_gbs, rmw_gbs=rmw_gbs, inputs=(I0, I1, vs), warped=warped, elapsed=elapsed, lat=lat,
-                stats=stats, hv_s=hv_s, hv_lat=hv_lat, grad_s=grad_s, kern=kern, E=E,
+                stats=stats, hv_s=hv_s, hv_lat=hv_lat, grad_s=grad_s, kern=kern, shapes=shapes, E=E,
                 t_host=t_host)
 
 
@@ -529,7 +531,7 @@ def hbm_resident_leg():
     r = gpu_leg(1, 0, 10, 3, 2, inputs=inputs, size=size)
     return {"workload": "256^3 6-class shell phantom, 8 vox, band 64^3, Nt = 20",
             "kernels": kernel_table(r["kern"], size["grid"], size["band"], size["nt"]),
-            "hv_per_s": r["hv_s"]}
+            "transport_voxels_per_thread": r["shapes"], "hv_per_s": r["hv_s"]}
 
 
 def large_main(steps, warmup, reps):
@@ -602,6 +604,7 @@ def headline_line(args, r):
         "hv_hbm_gbs_algorithmic": hv_bytes * r["hv_s"] / 1e9,
         "gradients_per_s": r["grad_s"],
         "kernels": kernel_table(r["kern"], GRID, BAND, NT),
+        "transport_voxels_per_thread": r["shapes"],
         "roofline": {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic_record(name),
