@@ -304,7 +304,8 @@ int bl_lddmm_ctx_launch_shapes(bl_ctx* ctx, int32_t zv_out[4]);
  * shape must beat the default by 5%.  BL_TUNE_LOG=1 prints the times and choices to stderr.
  * Choices are kept for the process and appended to a cache file read by later processes:
  * BL_TUNE_CACHE (a path, or "off"), else $XDG_CACHE_HOME/bl_lddmm/launch_shapes_v2.txt or
- * ~/.cache/bl_lddmm/launch_shapes_v2.txt.  BL_LAUNCH_SHAPES="s0,...,s6" fixes all classes
+ * ~/.cache/bl_lddmm/launch_shapes_v2.txt (lines with a value a class does not accept are
+ * skipped).  BL_LAUNCH_SHAPES="s0,...,s6" fixes all classes
  * (state, incremental, adjoint, body force, setup, iota z, iota x/y); only through it can the
  * iota x/y stages run as one fused kernel with 32 or 16 rows per block (s6 = 32 or 16; 0 = the
  * two separate stages, the default), which times faster alone but runs slower in products.

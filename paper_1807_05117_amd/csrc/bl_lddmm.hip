@@ -631,8 +631,17 @@ std::string shape_key(const bl_ctx* c) {
   return buf;
 }
 
-// the cache file's lines: "<arch> dim nx ny nz kx ky kz mixed : s0 ... s6"; malformed lines are
-// skipped (caller holds g_shape_mu)
+// a launch-shape list every class accepts: voxels per thread 1, 2, 4 or 8 for the transports
+// and the setup, 1, 2 or 4 for the iota z chunking, 0, 16 or 32 for the iota x/y stages
+bool valid_shapes(const int* v) {
+  bool ok = true;
+  for (int k = 0; ok && k <= bl::TR_SETUP; ++k) ok = v[k] == 1 || v[k] == 2 || v[k] == 4 || v[k] == 8;
+  ok = ok && (v[bl::TR_IOTA_Z] == 1 || v[bl::TR_IOTA_Z] == 2 || v[bl::TR_IOTA_Z] == 4);
+  return ok && (v[bl::TR_IOTA_XY] == 0 || v[bl::TR_IOTA_XY] == 16 || v[bl::TR_IOTA_XY] == 32);
+}
+
+// the cache file's lines: "<arch> dim nx ny nz kx ky kz mixed : s0 ... s6"; malformed lines and
+// lines with a value outside valid_shapes are skipped (caller holds g_shape_mu)
 void read_shape_file() {
   g_shapes_file_read = true;
   const std::string path = tune_cache_path();
@@ -652,7 +661,7 @@ void read_shape_file() {
       q += off;
       ++n;
     }
-    if (n == bl::TR_CLASSES) g_shapes[key] = v;
+    if (n == bl::TR_CLASSES && valid_shapes(v.data())) g_shapes[key] = v;
   }
   std::fclose(f);
 }
@@ -703,11 +712,7 @@ void choose_launch_shapes(bl_ctx* c) {
       if (*q == ',') ++q;
       ++n;
     }
-    bool ok = n == bl::TR_CLASSES;
-    for (int k = 0; ok && k <= bl::TR_SETUP; ++k) ok = v[k] == 1 || v[k] == 2 || v[k] == 4 || v[k] == 8;
-    ok = ok && (v[bl::TR_IOTA_Z] == 1 || v[bl::TR_IOTA_Z] == 2 || v[bl::TR_IOTA_Z] == 4);
-    ok = ok && (v[bl::TR_IOTA_XY] == 0 || v[bl::TR_IOTA_XY] == 16 || v[bl::TR_IOTA_XY] == 32);
-    if (ok)
+    if (n == bl::TR_CLASSES && valid_shapes(v))
       for (int k = 0; k < bl::TR_CLASSES; ++k) g.zv[k] = v[k];
     return;
   }

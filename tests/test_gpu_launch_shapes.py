@@ -118,3 +118,49 @@ def test_tuned_shapes_persist_in_the_cache_file(gpu_lib, tmp_path):
         else:
             os.environ["BL_TUNE_CACHE"] = old
         B.load().bl_lddmm_tune_reload()
+
+
+def test_cache_file_lines_are_validated(gpu_lib, tmp_path):
+    """a cache line with a value no class accepts is skipped (the shape is tuned again and a
+    valid line appended); a valid line is used as written, without timing"""
+    import oracle as O
+    from paper_1807_05117_amd import phantoms
+
+    cache = tmp_path / "shapes.txt"
+    old = os.environ.get("BL_TUNE_CACHE")
+    os.environ["BL_TUNE_CACHE"] = str(cache)
+    for k in ("BL_TRANSPORT_ZV", "BL_LAUNCH_SHAPES"):
+        os.environ.pop(k, None)
+    try:
+        bad = O.Problem(3, (36, 20, 14), (8, 8, 6), 4)    # shapes no other test uses
+        good = O.Problem(3, (36, 20, 16), (8, 8, 6), 4)
+        arch = None
+
+        def run(prob):
+            I0 = phantoms.shells_3d(5, prob.n).astype(np.float32)
+            vh = (0.1 * O.project(phantoms.raw_band_velocity(5, 3, prob.k), prob)).astype(np.complex64)
+            ctx = B.Ctx(bl_problem(prob), I0, I0)
+            ctx.bl_lddmm_ctx_set_velocity(vh)
+            out = ctx.bl_lddmm_ctx_launch_shapes()
+            ctx.close()
+            return out
+
+        # learn the key format (architecture name) from a first tuning of the bad shape
+        run(bad)
+        arch = cache.read_text().split()[0]
+        cache.write_text(f"{arch} 3 36 20 14 8 8 6 0 : 3 2 2 2 1 1 0\n"
+                         f"{arch} 3 36 20 16 8 8 6 0 : 1 4 1 8 2 1 0\n")
+        B.load().bl_lddmm_tune_reload()
+        got_bad = run(bad)
+        assert all(v in (1, 2, 4, 8) for v in got_bad), got_bad
+        lines = cache.read_text().splitlines()
+        assert len(lines) == 3, lines                      # re-tuned: one valid line appended
+        assert lines[2].startswith(f"{arch} 3 36 20 14 ")
+        assert run(good) == (1, 4, 1, 8)                   # taken from the file as written
+        assert len(cache.read_text().splitlines()) == 3    # no timing, nothing appended
+    finally:
+        if old is None:
+            os.environ.pop("BL_TUNE_CACHE", None)
+        else:
+            os.environ["BL_TUNE_CACHE"] = old
+        B.load().bl_lddmm_tune_reload()
