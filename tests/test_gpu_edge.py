@@ -1,8 +1,9 @@
 """GPU parity on the degenerate cases of the method, against the FP64 oracle on the same seeded
 float32 inputs: one time step, the full band k = n, the smallest band k = 2, and the smallest
-grids the library accepts (see parity_cases.CASES).  Same bar as the other parity tests:
-gradient and H v within relative 1e-5 in the 2-norm and element by element, the energy within
-1e-5, and a full registration with the oracle's solver decisions reproduced exactly."""
+grids the library accepts (see parity_cases.CASES).  Same bar as the other parity tests: the
+transforms within 2e-6, gradient and H v within relative 1e-5 in the 2-norm and element by
+element, the energy within 1e-5, and a full registration with the oracle's solver decisions
+reproduced exactly."""
 import numpy as np
 import pytest
 
@@ -19,6 +20,27 @@ EDGE = ["nt1_3d", "fullband_2d", "fullband_3d", "minband_3d", "tiny_3d", "min_gr
 
 def _log(*a):
     print(*a, flush=True)
+
+
+@pytest.mark.parametrize("name", EDGE)
+def test_edge_band_to_grid_and_back(gpu_lib, name):
+    """iota and pi at the degenerate band sizes, element by element against the oracle (same
+    bound as the other transform tests), and pi's output exactly Hermitian with zero unpaired
+    planes"""
+    prob, I0, I1, vs, vh, dv = case(name)
+    p = bl_problem(prob)
+    _log("case", name, "band_to_grid / grid_to_band")
+    grid = B.bl_band_to_grid(p, vh)
+    for c in range(prob.dim):
+        ref = O.iota(O.project(vh[c], prob), prob)
+        assert np.abs(grid[c] - ref).max() <= 2e-6 * np.abs(ref).max(), c
+    f = np.stack([I0, I1]).astype(np.float32)
+    band = B.bl_grid_to_band(p, f)
+    for c in range(2):
+        ref = O.pi_(f[c].astype(np.float64), prob)
+        assert rel2(band[c], ref) < 2e-6
+        assert np.array_equal(O.project(band[c].astype(np.complex128), prob),
+                              band[c].astype(np.complex128))
 
 
 @pytest.mark.parametrize("name", EDGE)
