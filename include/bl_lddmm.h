@@ -324,7 +324,10 @@ void bl_lddmm_tune_reload(void);
  * the moment its pair finishes.  Every result is identical to bl_lddmm_register's on the same
  * inputs (same kernels, same launch shapes, fixed-order reductions).
  *   server_create   budget_bytes: device memory the resident pairs may use (0: 80% of free);
- *                   max_slots: pairs resident at once (1..64)
+ *                   max_slots: pairs resident at once (1..64); the slots' streams share
+ *                   the process's hardware queues (GPU_MAX_HW_QUEUES, 4 unless set), and
+ *                   more slots than queues contend: on MI355X four slots served the most
+ *                   pairs per second
  *   server_submit   validates, copies I0, I1 (and v_hat if not NULL: initial guess; zero
  *                   otherwise) and returns a ticket; opts may be NULL (defaults); flags must
  *                   not contain BL_DEVICE_PTRS.  BL_E_NOMEM if the footprint exceeds the budget.
