@@ -40,6 +40,8 @@ BAD = [
     (dict(dim=1), B.BL_E_INVALID),
     (dict(n=(2, 12, 10)), B.BL_E_INVALID),
     (dict(n=(4096, 12, 10)), B.BL_E_INVALID),
+    (dict(n=(2048, 2048, 256)), B.BL_E_INVALID),          # 2^30 voxels: one past the largest grid
+    (dict(n=(16, 12, 256), k=(8, 6, 130)), B.BL_E_INVALID),   # kz above 128
     (dict(k=(7, 6, 4)), B.BL_E_INVALID),
     (dict(k=(0, 6, 4)), B.BL_E_INVALID),
     (dict(k=(18, 6, 4)), B.BL_E_INVALID),

@@ -76,3 +76,22 @@ def test_edge_register(gpu_lib, name):
     check_mse_rel(st, st_ref, 1e-5, name)
     assert rel2(v_gpu, v_ref) < 1e-3
     assert np.abs(m_gpu - m_ref).max() < 1e-3 * np.abs(m_ref).max()
+
+
+def test_edge_largest_grid_over_device_memory(gpu_lib):
+    """the largest grid the library accepts (2048 x 2048 x 255 voxels, just under 2^30) with
+    Nt = 256 needs far more device memory than one GPU has: the call fails with BL_E_NOMEM
+    before any device work (the inputs are never read), and the next call works as before"""
+    prob = O.Problem(3, (2048, 2048, 255), (8, 8, 8), 256)
+    p = bl_problem(prob)
+    assert B.bl_lddmm_footprint(p) > 300 * 2 ** 30
+    I0 = np.zeros(prob.shape, np.float32)   # untouched pages: no host memory is used
+    vh = np.zeros((3,) + prob.bshape, np.complex64)
+    with pytest.raises(B.BLError) as e:
+        B.bl_lddmm_gradient(p, I0, I0, vh)
+    assert e.value.code == B.BL_E_NOMEM, e.value
+    del I0
+    name = "tiny_3d"
+    prob, I0, I1, vs, vh, dv = case(name)
+    g, E = B.bl_lddmm_gradient(bl_problem(prob), I0, I1, vh)
+    check_gradient(g, oracle_gradient(name), prob, vh, 1e-5, name)
