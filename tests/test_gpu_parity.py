@@ -232,6 +232,34 @@ def test_nonfinite_input_reported(gpu_lib):
     assert e.value.code == B.BL_E_NONFINITE
 
 
+@pytest.mark.parametrize("where", ["velocity", "direction", "source", "register"])
+def test_nonfinite_inputs_of_every_call(gpu_lib, where):
+    """a NaN or Inf in any input of the path is reported as BL_E_NONFINITE (through the
+    non-finite flag of the band outputs or the energy), and the next call on clean inputs gives
+    the oracle's result again (the flag is cleared)"""
+    name = "ragged_3d"
+    prob, I0, I1, vs, vh, dv = case(name)
+    p = bl_problem(prob)
+    v_bad = vh.astype(np.complex64).copy()
+    v_bad[1, 2, 3, 4] = np.nan
+    d_bad = dv.astype(np.complex64).copy()
+    d_bad[0, 1, 2, 3] = np.inf
+    src_bad = I0.astype(np.float32).copy()
+    src_bad[5, 6, 7] = -np.inf
+    with pytest.raises(B.BLError) as e:
+        if where == "velocity":
+            B.bl_lddmm_gradient(p, I0, I1, v_bad)
+        elif where == "direction":
+            B.bl_lddmm_hessvec(p, I0, I1, vh, d_bad)
+        elif where == "source":
+            B.bl_lddmm_hessvec(p, src_bad, I1, vh, dv)
+        else:
+            B.bl_lddmm_register(p, I0, I1, v_bad)
+    assert e.value.code == B.BL_E_NONFINITE, e.value
+    H = B.bl_lddmm_hessvec(p, I0, I1, vh, dv)
+    check_hessvec(H, oracle_hessvec(name), 1e-5, name)
+
+
 def test_device_pointer_mode_matches_host_mode(gpu_lib):
     """torch tensors and a torch stream through BL_DEVICE_PTRS give the host-mode results
     bit for bit (same kernels, same launch configuration)."""
