@@ -260,6 +260,31 @@ def test_nonfinite_inputs_of_every_call(gpu_lib, where):
     check_hessvec(H, oracle_hessvec(name), 1e-5, name)
 
 
+def test_one_shot_calls_from_several_threads(gpu_lib):
+    """the one-shot calls share a pool of cached contexts: gradients and products of two
+    problems called from four host threads at once (the binding releases the GIL during a
+    call) give bitwise the results of the same calls made one after another"""
+    from concurrent.futures import ThreadPoolExecutor
+
+    names = ["ragged_3d", "brainlike_small"]
+    args = {n: case(n) for n in names}
+
+    def call(job):
+        n, kind = job
+        prob, I0, I1, vs, vh, dv = args[n]
+        p = bl_problem(prob)
+        if kind == "g":
+            return B.bl_lddmm_gradient(p, I0, I1, vh)[0]
+        return B.bl_lddmm_hessvec(p, I0, I1, vh, dv)
+
+    jobs = [(n, k) for n in names for k in ("g", "h")] * 3
+    ref = {j: call(j) for j in set(jobs)}
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        got = list(ex.map(call, jobs))
+    for j, r in zip(jobs, got):
+        assert np.array_equal(r, ref[j]), j
+
+
 def test_device_pointer_mode_matches_host_mode(gpu_lib):
     """torch tensors and a torch stream through BL_DEVICE_PTRS give the host-mode results
     bit for bit (same kernels, same launch configuration)."""
