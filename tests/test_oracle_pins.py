@@ -609,6 +609,41 @@ def test_c1_recovery_of_known_warp():
     assert stats["ginf_rel"][-1] < 1e-3
 
 
+def test_leray_projection_of_one_mode_by_hand():
+    """Leray projection (gamma = 1) of a single band mode on a non-cubic 2D domain: 16 x 8
+    voxels, so l = (1, 1/2) and the mode k = (1, 1) has wave vector k / l = (1, 2).  For the
+    amplitude a = (1, 0) the divergence-free part is a - q (q . a) / |q|^2 with q = (1, 2):
+    (1 - 1/5, -2/5) = (0.8, -0.4), worked by hand.  Its Hermitian partner maps to the
+    conjugate, the zero mode is left alone, and every other entry stays zero."""
+    prob = O.Problem(2, (16, 8), (8, 8), 4, gamma=1)
+    vh = np.zeros((2, 8, 8), np.complex128)       # [component][ky + 4][kx + 4]
+    vh[0, 5, 5] = 1.0                              # k = (kx, ky) = (1, 1), x component
+    vh[0, 3, 3] = 1.0                              # its partner -k (conjugate of a real amplitude)
+    vh[:, 4, 4] = (0.3, -0.7)                      # k = 0: no divergence, kept as is
+    P = O.leray(vh, prob)
+    assert np.allclose(P[:, 5, 5], [0.8, -0.4], rtol=0, atol=1e-15)
+    assert np.allclose(P[:, 3, 3], [0.8, -0.4], rtol=0, atol=1e-15)
+    assert np.allclose(P[:, 4, 4], [0.3, -0.7], rtol=0, atol=1e-15)
+    rest = np.ones((8, 8), bool)
+    rest[5, 5] = rest[3, 3] = rest[4, 4] = False
+    assert np.all(P[:, rest] == 0)
+
+
+def test_leray_projection_is_an_orthogonal_projection():
+    """on a random band vector of a non-cubic 3D problem: idempotent, self-adjoint in the l2
+    product, output with zero spectral divergence, divergence-free input unchanged"""
+    prob = O.Problem(3, (12, 10, 8), (8, 6, 4), 3, gamma=1)
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal((3,) + prob.bshape) + 1j * rng.standard_normal((3,) + prob.bshape)
+    b = rng.standard_normal((3,) + prob.bshape) + 1j * rng.standard_normal((3,) + prob.bshape)
+    Pa, Pb = O.leray(a, prob), O.leray(b, prob)
+    scale = np.abs(a).max()
+    assert np.allclose(O.leray(Pa, prob), Pa, rtol=0, atol=1e-14 * scale)
+    assert abs(O.dot(Pa, b) - O.dot(a, Pb)) <= 1e-12 * O.norm2(a) * O.norm2(b)
+    assert np.abs(O.div_band(Pa, prob)).max() <= 1e-12 * scale * 2 * np.pi * 8
+    assert O.norm2(Pa) <= O.norm2(a) * (1 + 1e-14)
+
+
 def test_incompressible_registration_of_divergence_free_warp():
     """gamma = 1 with H^1 (s = 1): a target made by a divergence-free velocity is registered
     with energies decreasing, a divergence-free result, a reaction factor of exactly 1 along
