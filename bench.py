@@ -56,7 +56,8 @@ def class_bytes(k, grid, band, nt):
     if k in (3, 4):
         return 12.0 + 24.0 * (band[2] // 2) / grid[2]
     if k == 5:
-        return 8.0 * (nt + 1) + 12.0
+        # m^0..m^nt and lambda^1..lambda^nt read, (Y, a) read to form lambda^0, b written
+        return 4.0 * (nt + 1) + 4.0 * nt + 16.0 + 12.0
     return 44.0
 
 

@@ -226,8 +226,10 @@ void energy_partial(const Geo& g, const float* mT, const float* I1, double* part
 void terminal(const Geo& g, const float* mT, const float* I1, float* lam, hipStream_t s);
 void adj_step(const Geo& g, const float* lam_in, const float4* YA, float* lam_out,
               hipStream_t s);
-// b_c = sum_n w_n lam^n d_c m^n over nt + 1 stored planes of lam and m
-void body_force(const Geo& g, const float* lam, const float* m, float* b, hipStream_t s);
+// b_c = sum_n w_n lam^n d_c m^n over nt + 1 stored planes of lam and m; with YA, lam^0 is
+// formed from lam^1 as a Interp(lam^1, i + Y) instead of read (the plane lam^0 is not used)
+void body_force(const Geo& g, const float* lam, const float* m, float* b, hipStream_t s,
+                const float4* YA = nullptr);
 void inc_init(const Geo& g, const float* m0, const float* dv, float* t0, hipStream_t s);
 void inc_step(const Geo& g, const float* t_in, const float* X, const float* m_next,
               const float* dv, float* t_out, hipStream_t s);

@@ -698,6 +698,8 @@ void apply_known_launch_shapes(bl_ctx* c) {
   lookup_shapes(c);
 }
 
+bool body_forms_lambda0(const bl::Geo& g);
+
 void choose_launch_shapes(bl_ctx* c) {
   c->tuned = true;
   bl::Geo& g = c->g;
@@ -741,7 +743,9 @@ void choose_launch_shapes(bl_ctx* c) {
       case bl::TR_STATE: bl::state_step(g, c->m, c->X, c->T0, s); break;
       case bl::TR_INC: bl::inc_step(g, c->T0, c->X, c->m + M, c->DV, c->T1, s); break;
       case bl::TR_ADJ: bl::adj_step(g, c->T0, c->YA, c->T1, s); break;
-      case bl::TR_FORCE: bl::body_force(g, c->L, c->m, c->Bf, s); break;
+      case bl::TR_FORCE:
+        bl::body_force(g, c->L, c->m, c->Bf, s, body_forms_lambda0(g) ? c->YA : nullptr);
+        break;
       case bl::TR_SETUP: bl::setup(g, c->V, c->X, c->YA, s); break;   // same values again
       case bl::TR_IOTA_Z: bl::iota_z(g, c->plan, g.dim, c->DV, s); break;
       default: bl::iota_xy(g, c->plan, c->bv, g.dim, s); break;
@@ -1130,13 +1134,24 @@ void op_energy_gradient(bl_ctx* c, const float2* vraw, float2* gout, After&& aft
 }
 
 // backward transport of L[nt] down to L[0], then the body force b = sum_n w_n L[n] grad m^n
+// lambda^0 (or dlambda^0) is read by nothing but the body force, which can form it from
+// lambda^1 itself: one adjoint launch and the plane's store and reload fewer.  That pays while
+// a step's fields stay in the last-level cache (at 128^3 a product takes 513 instead of
+// 522 us); on larger grids (Geo::stream_out) the body force then fetches the offsets and
+// lambda^1 from HBM at its own, lower rate and loses more than the launch saves (256^3: +104
+// us in the body force against 90 us for the adjoint step), so the last step stays separate.
+// The full Newton product keeps every stored lambda^n, so a Newton context transports down to
+// lambda^0.  Both forms give bitwise the same sums.
+bool body_forms_lambda0(const bl::Geo& g) { return !g.newton && !g.stream_out; }
+
 void backward_and_body_force(bl_ctx* c) {
   const bl::Geo& g = c->g;
   hipStream_t s = c->stream;
   const size_t M = (size_t)g.M;
-  for (int n = g.nt - 1; n >= 0; --n)
+  const bool form0 = body_forms_lambda0(g);
+  for (int n = g.nt - 1; n >= (form0 ? 1 : 0); --n)
     timed(c, 2, [&] { bl::adj_step(g, c->L + (n + 1) * M, c->YA, c->L + n * M, s); });
-  timed(c, 5, [&] { bl::body_force(g, c->L, c->m, c->Bf, s); });
+  timed(c, 5, [&] { bl::body_force(g, c->L, c->m, c->Bf, s, form0 ? c->YA : nullptr); });
 }
 
 // gradient at the current velocity into gout (device, dim components)

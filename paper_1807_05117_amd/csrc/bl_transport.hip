@@ -544,15 +544,19 @@ __global__ __launch_bounds__(BX* GBY) void k_inc_last(Geo g, const float* __rest
 // every time node in turn (node loop outside, voxel loop inside), so its z differences come
 // from a sliding window of three planes held in registers: each m^n plane of the run is read
 // once, plus one plane above and below, and the ZV voxels' loads of a node are in flight
-// together.
+// together.  With YA given, lambda^0 is not read: it is formed here as the last adjoint step
+// would, a Interp(lambda^1, i + Y), with the same arithmetic (the caller then stops the
+// backward transport at lambda^1; lambda^0 is needed by nothing but this sum).
 template <int DIM, int ZV>
 __global__ __launch_bounds__(BX* GBY) void k_body_force(Geo g, const float* __restrict__ lam,
                                                         const float* __restrict__ m,
-                                                        float* __restrict__ b) {
+                                                        float* __restrict__ b,
+                                                        const float4* __restrict__ YA) {
   BL_BATCH(g.bat)
   BL_AT(lam, g.bat);
   BL_AT(m, g.bat);
   BL_AT(b, g.bat);
+  BL_AT(YA, g.bat);
   GATHER_XY
   const size_t M = (size_t)g.M;
   const uint32_t sz = (uint32_t)g.nx * g.ny;
@@ -565,7 +569,26 @@ __global__ __launch_bounds__(BX* GBY) void k_body_force(Geo g, const float* __re
   const int z0 = tile.bz * ZV;
   const uint32_t p0 = ((uint32_t)z0 * g.ny + y) * g.nx + x;
   const uint32_t p0m = z0 == 0 ? p0 + (uint32_t)(g.nz - 1) * sz : p0 - sz;
-  for (int n = 0; n <= g.nt; ++n) {
+  // lambda^0 of the thread's voxels from lambda^1 (as k_adj_step)
+  float l0[ZV];
+  const bool form0 = YA != nullptr;
+  if (form0) {
+    Tap<DIM> tp[ZV];
+    float aw[ZV];
+#pragma unroll
+    for (int zz = 0; zz < ZV; ++zz) {
+      GATHER_Z(zz)
+      (void)live;
+      const float4 o = YA[p];
+      tp[zz] = make_tap<DIM>(g, x, y, z, o.x, o.y, o.z);
+      aw[zz] = o.w;
+    }
+    gather_zv<DIM, ZV>(field_rsrc(lam + M, g), tp, l0);
+#pragma unroll
+    for (int zz = 0; zz < ZV; ++zz) l0[zz] = aw[zz] * l0[zz];
+  }
+  // one time node: own = lambda^n from l0 (n = 0 only), else from its stored plane
+  auto node = [&](int n, bool own) {
     const float w = (n == 0 || n == g.nt) ? 0.5f * g.dt : g.dt;
     const float* __restrict__ mn = m + n * M;
     const float* __restrict__ ln = lam + n * M;
@@ -589,12 +612,15 @@ __global__ __launch_bounds__(BX* GBY) void k_body_force(Geo g, const float* __re
         prev = cur;
         cur = next;
       }
-      const float wl = w * ln[p];
+      const float wl = w * (own ? l0[zz] : ln[p]);
       acc[zz][0] = fmaf(wl, gx, acc[zz][0]);
       acc[zz][1] = fmaf(wl, gy, acc[zz][1]);
       if (DIM == 3) acc[zz][2] = fmaf(wl, gz, acc[zz][2]);
     }
-  }
+  };
+  if (form0) node(0, true);
+  else node(0, false);
+  for (int n = 1; n <= g.nt; ++n) node(n, false);
 #pragma unroll
   for (int zz = 0; zz < ZV; ++zz) {
     GATHER_Z(zz)
@@ -946,8 +972,9 @@ void adj_step(const Geo& g, const float* lam_in, const float4* YA, float* lam_ou
               hipStream_t s) {
   DISPATCH_GATHER(k_adj_step, TR_ADJ, g, lam_in, YA, lam_out);
 }
-void body_force(const Geo& g, const float* lam, const float* m, float* b, hipStream_t s) {
-  DISPATCH_GATHER(k_body_force, TR_FORCE, g, lam, m, b);
+void body_force(const Geo& g, const float* lam, const float* m, float* b, hipStream_t s,
+                const float4* YA) {
+  DISPATCH_GATHER(k_body_force, TR_FORCE, g, lam, m, b, YA);
 }
 void inc_init(const Geo& g, const float* m0, const float* dv, float* t0, hipStream_t s) {
   DISPATCH_GATHER(k_inc_init, TR_INC, g, m0, dv, t0);

@@ -37,7 +37,8 @@ def test_timed_counts_and_results(gpu_lib, name):
     assert E == E_ref and np.array_equal(g, g_ref)
     for h in H:
         assert np.array_equal(h, H_ref)
-    want = {0: nt, 1: 3 * (nt - 1), 2: nt + 3 * nt, 3: 3, 4: 3, 5: 1 + 3, 6: 1}
+    # the adjoint sweeps stop at lambda^1 (the body force forms lambda^0): nt - 1 steps each
+    want = {0: nt, 1: 3 * (nt - 1), 2: 4 * (nt - 1), 3: 3, 4: 3, 5: 1 + 3, 6: 1}
     for k, n in want.items():
         launches, ms = got[k]
         assert launches == n, (k, launches, n)
