@@ -215,9 +215,10 @@ void setup(const Geo& g, const float* v, float* X, float4* YA, hipStream_t s);
 // node (dim + 1 planes each); step n writes X + n dim M and YA + n M
 void setup_ns(const Geo& g, const float* V, float* X, float4* YA, int steps, hipStream_t s);
 // b^n = lambda^n grad m^n for the time nodes n < nodes (lam, m: one plane per node; b: dim
-// planes per node), one launch
+// planes per node), one launch; with YA0 (the first step's (Y, a)), lambda^0 is formed from
+// lambda^1 as a Interp(lambda^1, i + Y) instead of read (the plane lambda^0 is not used)
 void body_nodes(const Geo& g, const float* lam, const float* m, float* b, int nodes,
-                hipStream_t s);
+                hipStream_t s, const float4* YA0 = nullptr);
 void state_step(const Geo& g, const float* m_in, const float* X, float* m_out, hipStream_t s);
 // kRedBlocks partials of sum (mT - I1)^2 in FP64; with lam not NULL also the terminal adjoint
 // lam = lam_scale (mT - I1), the values terminal() writes

@@ -858,11 +858,13 @@ void op_set_velocity_ns(bl_ctx* c, const float2* vraw) {
   if (!std::isfinite(c->E)) throw NonFinite{"energy"};
 }
 
-// adjoint from L[nt] down to L[0] with the per-step (Y, a)
+// adjoint from L[nt] down to L[1] with the per-step (Y, a): lambda^0 is read by nothing but
+// the per-node body force, whose node-0 blocks form it from lambda^1 (per_node_outputs) in
+// parallel with the other nodes' blocks -- one launch and the plane's store and reload fewer
 void backward_ns(bl_ctx* c) {
   const bl::Geo& g = c->g;
   const size_t M = (size_t)g.M;
-  for (int n = g.nt - 1; n >= 0; --n)
+  for (int n = g.nt - 1; n >= 1; --n)
     bl::adj_step(g, c->L + (n + 1) * M, c->YA + (size_t)n * M, c->L + n * M, c->stream);
 }
 
@@ -873,7 +875,7 @@ void per_node_outputs(bl_ctx* c, const float2* vproj, size_t vstride, float2* ou
   hipStream_t s = c->stream;
   const size_t B = (size_t)g.B;
   const int d = g.dim;
-  bl::body_nodes(g, c->L, c->m, c->Bf, g.nt + 1, s);
+  bl::body_nodes(g, c->L, c->m, c->Bf, g.nt + 1, s, c->YA);   // YA of step 0: lambda^0
   bl::pi_half(g, c->plan, c->Bf, (g.nt + 1) * d, c->P, s);
   const size_t ph = (size_t)g.kzh * g.ky * g.kx;
   bl::band_finalize_nodes(g, d, vproj, vstride, c->Lhat, c->P, (size_t)d * ph,

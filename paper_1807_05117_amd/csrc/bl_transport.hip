@@ -831,13 +831,34 @@ __global__ __launch_bounds__(BX* GBY) void k_body_force_n(Geo g, const float* __
 template <int DIM, int ZV>
 __global__ __launch_bounds__(BX* GBY) void k_body_node(Geo g, const float* __restrict__ lam,
                                                        const float* __restrict__ m,
-                                                       float* __restrict__ b) {
+                                                       float* __restrict__ b,
+                                                       const float4* __restrict__ YA0) {
   BL_BATCH(g.bat)
   BL_AT(lam, g.bat);
   BL_AT(m, g.bat);
   BL_AT(b, g.bat);
+  BL_AT(YA0, g.bat);
   GATHER_XY
   const size_t M = (size_t)g.M;
+  // with YA0 (the first step's (Y, a)), the blocks of node 0 form lambda^0 = a Interp(lambda^1,
+  // i + Y) as the adjoint step would, with the same arithmetic, instead of reading it
+  const bool form0 = YA0 != nullptr && blockIdx.y == 0;
+  float l0[ZV];
+  if (form0) {
+    Tap<DIM> tp[ZV];
+    float aw[ZV];
+#pragma unroll
+    for (int zz = 0; zz < ZV; ++zz) {
+      GATHER_Z(zz)
+      (void)live;
+      const float4 o = YA0[p];
+      tp[zz] = make_tap<DIM>(g, x, y, z, o.x, o.y, o.z);
+      aw[zz] = o.w;
+    }
+    gather_zv<DIM, ZV>(field_rsrc(lam + M, g), tp, l0);
+#pragma unroll
+    for (int zz = 0; zz < ZV; ++zz) l0[zz] = aw[zz] * l0[zz];
+  }
   lam += blockIdx.y * M;
   m += blockIdx.y * M;
   b += blockIdx.y * (size_t)DIM * M;
@@ -848,7 +869,7 @@ __global__ __launch_bounds__(BX* GBY) void k_body_node(Geo g, const float* __res
     (void)live;
     float gr[3];
     grad_c<DIM>(g, m, x, y, z, p, gr);
-    const float l = lam[p];
+    const float l = form0 ? l0[zz] : lam[p];
     for (int c = 0; c < DIM; ++c) acc[zz][c] = l * gr[c];
   }
 #pragma unroll
@@ -959,8 +980,8 @@ void setup_ns(const Geo& g, const float* V, float* X, float4* YA, int steps, hip
     hipLaunchKernelGGL(k_setup_ns<2>, grid, dim3(BX, GBY), 0, s, g, V, X, YA);
 }
 void body_nodes(const Geo& g, const float* lam, const float* m, float* b, int nodes,
-                hipStream_t s) {
-  DISPATCH_GATHER_N(k_body_node, TR_FORCE, nodes, g, lam, m, b);
+                hipStream_t s, const float4* YA0) {
+  DISPATCH_GATHER_N(k_body_node, TR_FORCE, nodes, g, lam, m, b, YA0);
 }
 void state_step(const Geo& g, const float* m_in, const float* X, float* m_out, hipStream_t s) {
   DISPATCH_GATHER(k_state_step, TR_STATE, g, m_in, X, m_out);
